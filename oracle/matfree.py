@@ -1,0 +1,246 @@
+"""Matrix-free CPU reference: H.X by FFTs and the block LOBPCG of sec. 3.
+
+TEST INFRASTRUCTURE ONLY (oracle).  Plain numpy/scipy, FP64/complex128.
+
+* `MatFreeH.apply` -- the Hamiltonian apply that sec. 2.2 (iii) and sec. 4.1
+  describe: place the plane-wave coefficients on the FFT grid (zero padding
+  outside the sphere), transform to real space, multiply by the local potential,
+  transform back, add the kinetic diagonal, add the non-local projector term in
+  reciprocal space.  Full (unpruned) library FFTs; equal to the dense matrix of
+  oracle.pw.dense_hamiltonian in exact arithmetic.
+* `lobpcg_block` -- Algorithm 1 (sec. 3.2): Rayleigh quotients, residuals
+  R = H Psi - Psi Upsilon, preconditioned W = K(R), Rayleigh-Ritz on
+  span{Psi, W, P}, Psi <- Psi Delta + W Lambda + P Gamma, P <- W Lambda + P Gamma,
+  with the current block kept orthogonal to the previously computed bands
+  (identity overlap).
+* `solve` -- the multiband-by-multiband sweep over M/m blocks followed by the
+  final Rayleigh-Ritz over all M bands (end of sec. 3.2; sec. 2.1 step 4).
+* `certificate` -- residual-based eigenvalue error bounds for Hermitian H.
+
+The preconditioner K is called "PW optimized" in sec. 3.1 without a formula;
+the Teter-Payne-Allan rational function in T_g / E_kin is used.  K changes the
+iteration count, never the fixed point.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import scipy.fft
+import scipy.linalg
+
+from . import pw
+
+
+class MatFreeH:
+    """H = T + V_loc + sum_p D_p |beta_p><beta_p| on one sphere (sec. 2.1, 2.2)."""
+
+    def __init__(self, cell, kfrac, miller, vgrid, pos=None, lm=(), D=None,
+                 workers: int = -1):
+        self.miller = np.asarray(miller, np.int64)
+        self.vgrid = np.asarray(vgrid, float)
+        self.shape = self.vgrid.shape
+        self.idx = tuple(np.mod(self.miller[:, a], self.shape[a]) for a in range(3))
+        self.T = pw.kinetic(cell, kfrac, self.miller)
+        self.npw = self.miller.shape[0]
+        self.workers = workers
+        if lm and pos is not None and len(pos):
+            self.B = pw.projectors(cell, kfrac, self.miller, pos, lm)
+            self.D = np.asarray(D, float)
+        else:
+            self.B = None
+            self.D = None
+        self.napply = 0
+
+    def apply_local(self, X, chunk: int = 8):
+        """Kinetic + local part: T X + FFT^-1[ V . FFT[X on grid] ] restricted to the sphere."""
+        X = np.asarray(X, np.complex128)
+        Y = self.T[:, None] * X
+        N3 = float(np.prod(self.shape))
+        for c0 in range(0, X.shape[1], chunk):
+            c1 = min(X.shape[1], c0 + chunk)
+            grid = np.zeros((c1 - c0,) + self.shape, np.complex128)
+            grid[(slice(None),) + self.idx] = X[:, c0:c1].T
+            # psi(r_j) = sum_n c(n) exp(+2 pi i n.j / N)   (no normalisation)
+            psi = scipy.fft.ifftn(grid, axes=(1, 2, 3), workers=self.workers) * N3
+            psi *= self.vgrid[None]
+            # (V psi)(n) = N^-3 sum_j (V psi)(r_j) exp(-2 pi i n.j / N)
+            out = scipy.fft.fftn(psi, axes=(1, 2, 3), workers=self.workers) / N3
+            Y[:, c0:c1] += out[(slice(None),) + self.idx].T
+        return Y
+
+    def apply(self, X):
+        Y = self.apply_local(X)
+        if self.B is not None:
+            Y += self.B @ (self.D[:, None] * (self.B.conj().T @ X))
+        self.napply += X.shape[1]
+        return Y
+
+
+def tpa_precondition(T, X, R, ekin_floor: float = 1e-3):
+    """W = K(R), K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4), x = T_g/E_kin,n.
+
+    E_kin,n = <x_n| -1/2 Laplacian |x_n> / <x_n|x_n> per band, floored at ekin_floor.
+    """
+    ekin = np.einsum("g,gn->n", T, np.abs(X) ** 2) / np.einsum("gn->n", np.abs(X) ** 2)
+    ekin = np.maximum(ekin, ekin_floor)
+    x = T[:, None] / ekin[None, :]
+    num = 27 + 18 * x + 12 * x ** 2 + 8 * x ** 3
+    return (num / (num + 16 * x ** 4)) * R
+
+
+def rayleigh_ritz(Z, HZ, nwant: int, drop_rel: float = 1e-14):
+    """Rayleigh-Ritz on span(Z): lowest `nwant` Ritz pairs as coefficients C.
+
+    The Gram pair A = Z^H H Z, B = Z^H Z is reduced through an orthonormal
+    basis of span(Z) taken from the eigenvectors of B (directions with
+    eigenvalue below drop_rel * max are outside the numerically spanned space),
+    then A is diagonalised.  Returns (theta[nwant], C[ncol, nwant]).
+    """
+    A = Z.conj().T @ HZ
+    B = Z.conj().T @ Z
+    A = 0.5 * (A + A.conj().T)
+    B = 0.5 * (B + B.conj().T)
+    bv, bu = scipy.linalg.eigh(B)
+    keep = bv > drop_rel * bv.max()
+    S = bu[:, keep] / np.sqrt(bv[keep])[None, :]
+    Ah = S.conj().T @ A @ S
+    Ah = 0.5 * (Ah + Ah.conj().T)
+    theta, U = scipy.linalg.eigh(Ah)
+    return theta[:nwant], S @ U[:, :nwant]
+
+
+def _orth_against(V, Y):
+    if Y is None or Y.shape[1] == 0:
+        return V
+    return V - Y @ (Y.conj().T @ V)
+
+
+def lobpcg_block(H: MatFreeH, Psi0, Y=None, tol=1e-8, maxit=300, history=None, nconv=None):
+    """Algorithm 1 of sec. 3.2 for one block, O-orthogonal (here: orthogonal) to Y.
+
+    Iterates all m columns of Psi0; stops when the lowest `nconv` (default m)
+    residuals are <= tol.  Returns (eps[m], Psi[npw, m], HPsi, res[m], iterations).
+    """
+    m = Psi0.shape[1]
+    nconv = m if nconv is None else nconv
+    Psi = _orth_against(np.asarray(Psi0, np.complex128), Y)
+    HPsi = H.apply(Psi)
+    eps, C = rayleigh_ritz(Psi, HPsi, m)
+    Psi, HPsi = Psi @ C, HPsi @ C
+    P = HP = None
+    it = 0
+    res = None
+    for it in range(1, maxit + 1):
+        # step 1: Upsilon = diag of Rayleigh quotients (Eq. 1 with O = I)
+        nrm2 = np.einsum("gn,gn->n", Psi.conj(), Psi).real
+        eps = np.einsum("gn,gn->n", Psi.conj(), HPsi).real / nrm2
+        # step 2: residuals
+        R = HPsi - Psi * eps[None, :]
+        res = np.linalg.norm(R, axis=0) / np.sqrt(nrm2)
+        if history is not None:
+            history.append(eps.copy())
+        if np.all(res[:nconv] <= tol):
+            it -= 1
+            break
+        # step 3: preconditioned residuals, constrained to the earlier blocks
+        W = _orth_against(tpa_precondition(H.T, Psi, R), Y)
+        W = W / np.linalg.norm(W, axis=0)[None, :]      # scaling is irrelevant
+        HW = H.apply(W)
+        # step 4: Rayleigh-Ritz in span{Psi, W, P}
+        if P is None:
+            Z, HZ = np.hstack([Psi, W]), np.hstack([HPsi, HW])
+        else:
+            s = np.linalg.norm(P, axis=0)
+            s[s == 0] = 1.0
+            P, HP = P / s[None, :], HP / s[None, :]
+            Z, HZ = np.hstack([Psi, W, P]), np.hstack([HPsi, HW, HP])
+        eps, C = rayleigh_ritz(Z, HZ, m)
+        Delta = C[:m]
+        # Psi_new = Psi Delta + W Lambda + P Gamma ; P_new = W Lambda + P Gamma (step 5)
+        Pn = Z[:, m:] @ C[m:]
+        HPn = HZ[:, m:] @ C[m:]
+        Psi = Psi @ Delta + Pn
+        HPsi = HPsi @ Delta + HPn
+        P, HP = Pn, HPn
+    # normalise columns before returning
+    nrm = np.sqrt(np.einsum("gn,gn->n", Psi.conj(), Psi).real)
+    Psi, HPsi = Psi / nrm[None, :], HPsi / nrm[None, :]
+    return eps, Psi, HPsi, res, it
+
+
+def guard_count(block: int) -> int:
+    """Guard columns per block: iterated but neither required to converge nor kept."""
+    return block // 8
+
+
+def solve(H: MatFreeH, nbands: int, block: int, tol=1e-8, maxit=300, seed=0,
+          start=None, final_rr=True, log=None, guard=None):
+    """Multiband-by-multiband LOBPCG over the M bands, then a final Rayleigh-Ritz.
+
+    Each block iterates `block` columns; the lowest block - guard of them must
+    converge and are kept (the top `guard` columns only shield them from a
+    near-degenerate neighbour above the block); the last block keeps the rest.
+    `start(b, npw, m)` returns the starting block of block b (default: the
+    seeded complex normal blocks of workloads.start_block).  Returns a dict
+    with eigenvalues (ascending), vectors, residual norms and per-block
+    iteration counts.
+    """
+    g = guard_count(block) if guard is None else guard
+    if start is None:
+        from workloads import start_block
+
+        def start(b, npw, m):
+            return start_block(seed * 1000 + b, npw, m)
+    npw = H.npw
+    Xs, HXs, iters = [], [], []
+    t0 = time.perf_counter()
+    b, ib = 0, 0
+    while b < nbands:
+        keep = min(block - g, nbands - b)
+        width = min(block, keep + g, npw - b)
+        Y = np.hstack(Xs) if Xs else None
+        eps, Psi, HPsi, res, it = lobpcg_block(H, start(ib, npw, width), Y,
+                                               tol=tol, maxit=maxit, nconv=keep)
+        Xs.append(Psi[:, :keep])
+        HXs.append(HPsi[:, :keep])
+        iters.append(it)
+        if log:
+            log(f"block {ib}: {it} iterations, max res {res[:keep].max():.2e}, "
+                f"{time.perf_counter() - t0:.1f}s")
+        b += keep
+        ib += 1
+    X = np.hstack(Xs)
+    HX = np.hstack(HXs)
+    if final_rr:
+        eps, C = rayleigh_ritz(X, HX, nbands)
+        X, HX = X @ C, HX @ C
+    nrm = np.sqrt(np.einsum("gn,gn->n", X.conj(), X).real)
+    eps = np.einsum("gn,gn->n", X.conj(), HX).real / nrm ** 2
+    order = np.argsort(eps)
+    X, HX, eps = X[:, order], HX[:, order], eps[order]
+    R = HX - X * eps[None, :]
+    res = np.linalg.norm(R, axis=0) / np.linalg.norm(X, axis=0)
+    return dict(eig=eps, X=X, HX=HX, res=res, iters=iters,
+                seconds=time.perf_counter() - t0)
+
+
+def certificate(theta, res):
+    """Per-eigenvalue error bounds for Ritz pairs of a Hermitian operator.
+
+    Krylov-Bogolyubov: some eigenvalue lies within res_j of theta_j.
+    Kato-Temple: if the interval around theta_j is isolated from the other
+    Ritz intervals by a gap delta_j, the error is at most res_j^2 / delta_j.
+    Returns min of the two (the Kato-Temple bound only where delta_j > 0).
+    """
+    theta = np.asarray(theta, float)
+    res = np.asarray(res, float)
+    n = theta.size
+    out = res.copy()
+    for j in range(n):
+        others = [abs(theta[i] - theta[j]) - res[i] for i in range(n) if i != j]
+        if others:
+            delta = min(others)
+            if delta > 0:
+                out[j] = min(out[j], res[j] ** 2 / delta)
+    return out

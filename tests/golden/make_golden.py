@@ -1,0 +1,75 @@
+"""Write the stored expected eigenvalues under tests/golden/.
+
+Calls only `oracle/` (and the seeded input generators in `workloads/`):
+
+  gamma_l10   dense H (oracle.pw) diagonalised by the oracle's C Jacobi.
+  mid_nl      dense H diagonalised by the oracle's C Jacobi.
+  fcc32_l12   oracle.matfree.solve (block LOBPCG + final Rayleigh-Ritz), tol 1e-9.
+  fcc108_l20  oracle.matfree.solve, tol 1e-8 (34181 plane waves: no dense H).
+
+Each file lists index, eigenvalue (Ha) and, for the matrix-free runs, the
+residual norm and the residual certificate (oracle.matfree.certificate).
+
+Usage:  python tests/golden/make_golden.py [name ...]
+"""
+from __future__ import annotations
+
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import pw, matfree                      # noqa: E402
+from oracle.jacobi import eigh_jacobi              # noqa: E402
+from workloads import make_workload                # noqa: E402
+
+
+def dense_case(name):
+    w = make_workload(name)
+    mil = pw.sphere(w.cell, w.kfrac, w.ecut)
+    H = pw.dense_hamiltonian(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D)
+    ev, _, sweeps = eigh_jacobi(H)
+    path = os.path.join(HERE, f"{name}_eig.txt")
+    with open(path, "w") as f:
+        f.write(f"# {name}: npw={len(mil)}, dense H diagonalised by cyclic Jacobi "
+                f"({sweeps} sweeps), all {len(ev)} eigenvalues in Ha\n")
+        f.write("# written by tests/golden/make_golden.py (oracle only)\n")
+        for i, e in enumerate(ev):
+            f.write(f"{i} {e:.17e}\n")
+    print("wrote", path)
+
+
+def matfree_case(name, tol):
+    w = make_workload(name)
+    mil = pw.sphere(w.cell, w.kfrac, w.ecut)
+    H = matfree.MatFreeH(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D)
+    t0 = time.time()
+    r = matfree.solve(H, w.nbands, w.block, tol=tol, seed=w.seed,
+                      log=lambda s: print(name, s, flush=True))
+    cert = matfree.certificate(r["eig"], r["res"])
+    path = os.path.join(HERE, f"{name}_eig.txt")
+    with open(path, "w") as f:
+        f.write(f"# {name}: npw={len(mil)}, M={w.nbands}, m={w.block}, oracle block "
+                f"LOBPCG tol={tol:g} + final Rayleigh-Ritz, iterations per block "
+                f"{r['iters']}, {time.time() - t0:.0f} s\n")
+        f.write("# written by tests/golden/make_golden.py (oracle only)\n")
+        f.write("# columns: index, eigenvalue (Ha), residual norm, error bound\n")
+        for i, (e, s, c) in enumerate(zip(r["eig"], r["res"], cert)):
+            f.write(f"{i} {e:.17e} {s:.3e} {c:.3e}\n")
+    print("wrote", path)
+
+
+CASES = {
+    "gamma_l10": lambda: dense_case("gamma_l10"),
+    "mid_nl": lambda: dense_case("mid_nl"),
+    "fcc32_l12": lambda: matfree_case("fcc32_l12", 1e-9),
+    "fcc108_l20": lambda: matfree_case("fcc108_l20", 1e-8),
+}
+
+if __name__ == "__main__":
+    for n in (sys.argv[1:] or list(CASES)):
+        CASES[n]()

@@ -1,0 +1,126 @@
+"""Synthetic Gaussian-well cells (seeded, numpy PCG64).
+
+Every workload is a cubic cell of side L (bohr) holding Gaussian wells of depth
+2 Ha and width 1 bohr, periodically repeated:
+
+    V(r) = sum_a  -2 exp(-|r - R_a - T|^2 / 2),  T in L Z^3,
+
+sampled on the FFT grid r_j = L j / N (C order [x][y][z]).  The image sum is
+separable: each well contributes -2 g_x (x) g_y (x) g_z with
+g(x) = sum_{t=-3..3} exp(-(x - X_a - tL)^2 / 2); images farther than 3L are
+below 1e-40 of the peak for L >= 8 and are dropped.
+
+Kleinman-Bylander projector data (positions, (l, m) list, couplings D) is also
+drawn here; how a projector acts is the method's business and lives elsewhere.
+
+Random draws follow one fixed order per workload: positions (uniform, or fcc
+sites), fcc jitter, couplings D.  Starting blocks come from their own stream
+(`start_block`).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+import numpy as np
+
+# (l, m) of the four projectors per atom: one s and three real p harmonics.
+LM4 = ((0, 0), (1, -1), (1, 0), (1, 1))
+
+
+@dataclass
+class Workload:
+    name: str
+    seed: int
+    L: float                 # cubic cell side, bohr
+    ecut: float              # plane-wave cutoff, Ha
+    n: int                   # FFT grid points per axis
+    kfrac: tuple             # k in units of 2*pi/L
+    pos: np.ndarray          # [natom, 3] well centres, bohr
+    nbands: int              # M
+    block: int               # m
+    tol: float               # residual tolerance
+    lm: tuple = ()           # projector (l, m) list per atom (empty: local only)
+    D: np.ndarray | None = None   # [natom * len(lm)] couplings, Ha
+    vgrid: np.ndarray = field(default=None, repr=False)   # [n, n, n] float64
+
+    @property
+    def cell(self) -> np.ndarray:
+        return np.eye(3) * self.L
+
+    @property
+    def natom(self) -> int:
+        return int(self.pos.shape[0])
+
+    @property
+    def nproj(self) -> int:
+        return self.natom * len(self.lm)
+
+
+def well_potential(L: float, n: int, pos: np.ndarray, depth: float = 2.0,
+                   images: int = 3) -> np.ndarray:
+    """Periodic sum of Gaussian wells sampled on the n^3 grid, C order [x][y][z]."""
+    x = L * np.arange(n) / n
+    t = np.arange(-images, images + 1) * L
+    v = np.zeros((n, n, n))
+    for a in range(pos.shape[0]):
+        g = []
+        for ax in range(3):
+            d = x[:, None] - pos[a, ax] - t[None, :]
+            g.append(np.exp(-0.5 * d * d).sum(axis=1))
+        v -= depth * np.einsum("i,j,k->ijk", g[0], g[1], g[2])
+    return v
+
+
+def _fcc_sites(L: float, reps: int) -> np.ndarray:
+    a = L / reps
+    basis = np.array([[0, 0, 0], [0.5, 0.5, 0], [0.5, 0, 0.5], [0, 0.5, 0.5]])
+    sites = []
+    for i in range(reps):
+        for j in range(reps):
+            for k in range(reps):
+                for b in basis:
+                    sites.append(a * (np.array([i, j, k]) + b))
+    return np.array(sites)
+
+
+def make_workload(name: str) -> Workload:
+    spec = WORKLOADS[name]
+    rng = np.random.default_rng(spec["seed"])
+    L = spec["L"]
+    if spec.get("fcc"):
+        pos = _fcc_sites(L, spec["fcc"])
+        pos = pos + rng.uniform(-0.2, 0.2, pos.shape)
+        pos = np.mod(pos, L)
+    else:
+        pos = rng.uniform(0.0, L, (spec["natom"], 3))
+    lm = LM4 if spec.get("proj") else ()
+    D = rng.uniform(0.5, 1.5, pos.shape[0] * len(lm)) if lm else None
+    w = Workload(name=name, seed=spec["seed"], L=L, ecut=spec["ecut"],
+                 n=spec["n"], kfrac=tuple(spec["k"]), pos=pos,
+                 nbands=spec["M"], block=spec["m"], tol=spec["tol"],
+                 lm=lm, D=D)
+    w.vgrid = well_potential(L, w.n, pos)
+    return w
+
+
+def start_block(seed: int, npw: int, ncol: int) -> np.ndarray:
+    """Complex standard-normal block [npw, ncol] from its own PCG64 stream."""
+    rng = np.random.default_rng(10_000 + seed)
+    return (rng.standard_normal((npw, ncol))
+            + 1j * rng.standard_normal((npw, ncol))) / np.sqrt(2.0)
+
+
+# Workload table.  `gamma_l10` is the small Gamma-point FP64 case, `fcc108_l20`
+# the paper-scale single-k case (108 wells at jittered fcc sites, 432
+# projectors, 512 bands in blocks of 64).  The others are test cells.
+WORKLOADS = {
+    "gamma_l10": dict(seed=0, L=10.0, ecut=5.0, n=24, k=(0, 0, 0), natom=8,
+                      M=16, m=16, tol=1e-8),
+    "fcc108_l20": dict(seed=1, L=20.0, ecut=20.0, n=96, k=(0.25, 0.25, 0.25),
+                       fcc=3, proj=True, M=512, m=64, tol=1e-6),
+    "tiny_nl": dict(seed=7, L=8.0, ecut=4.0, n=20, k=(0.1, 0.2, 0.3), natom=2,
+                    proj=True, M=12, m=4, tol=1e-8),
+    "mid_nl": dict(seed=11, L=12.0, ecut=8.0, n=36, k=(0.25, 0.0, 0.5),
+                   natom=6, proj=True, M=48, m=16, tol=1e-7),
+    "fcc32_l12": dict(seed=5, L=12.0, ecut=12.0, n=48, k=(0.25, 0.25, 0.25),
+                      fcc=2, proj=True, M=128, m=32, tol=1e-6),
+}
