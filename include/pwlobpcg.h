@@ -1,0 +1,182 @@
+/*
+ * pwlobpcg.h -- C ABI of the MI355X (gfx950) plane-wave block-LOBPCG library.
+ *
+ * The library solves H c = eps c for the lowest bands of a plane-wave
+ * Kohn-Sham Hamiltonian at one k-point with identity overlap (Bottin, Leroux,
+ * Knyazev, Zerah, Comput. Mater. Sci. 2007 -- sec. 2.1: the wave-function is
+ * expanded over plane waves e^{i(k+G).r} and the projected eigenproblem is
+ * solved; with norm-conserving potentials the overlap operator is the
+ * identity).  The iteration is the block LOBPCG of sec. 3.2, Algorithm 1,
+ * run multiband-by-multiband with each block orthogonal to the previous ones,
+ * followed by a final Rayleigh-Ritz over all bands.
+ *
+ *   H = 1/2 |k+G|^2                                      kinetic diagonal
+ *     + FFT^-1 . diag(V(r)) . FFT                        local potential (sec. 2.2 iii)
+ *     + sum_p D_p |beta_p><beta_p|                       KB projectors (sec. 2.2 iv, 4.3)
+ *
+ * Conventions shared by every entry point:
+ *  - Complex arrays are interleaved (re, im): double2 in FP64, float2 where a
+ *    mixed-precision variant says so.  Block vectors are column-major
+ *    [npw x nb] with a leading dimension ld >= npw; column j is band j.
+ *  - The plane-wave order is the library's sphere order (pw_get_miller).
+ *  - Every call returns pw_status; no exception or abort crosses the ABI.  On
+ *    failure pw_last_error(ctx) describes the cause.
+ *  - Device pointers must stay valid until the context stream has completed
+ *    the call.  Calls that return host data synchronise the stream; the others
+ *    are asynchronous on the context stream.
+ *  - One context per host thread / stream.  Calls on one context are not
+ *    thread-safe.
+ *  - Ownership: the context owns its copies of the sphere tables, V(r) and the
+ *    projector table; the caller owns X, Y, the workspace and every host array.
+ *    The library never frees caller memory.
+ */
+#ifndef PWLOBPCG_H
+#define PWLOBPCG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pw_ctx_s *pw_ctx;
+
+typedef enum {
+    PW_OK = 0,
+    PW_ERR_ARG = 1,            /* invalid argument (null pointer, bad size, unsupported grid) */
+    PW_ERR_STATE = 2,          /* call out of order (e.g. apply before init/potential/workspace) */
+    PW_ERR_NOMEM = 3,          /* workspace too small or device allocation failed */
+    PW_ERR_DEVICE = 4,         /* HIP runtime error */
+    PW_ERR_NOT_CONVERGED = 5,  /* max_iter reached; best Ritz pairs and residuals still written */
+    PW_ERR_NUMERIC = 6         /* NaN/Inf or a breakdown the solver could not recover from */
+} pw_status;
+
+typedef enum {
+    PW_PREC_FP64 = 0,          /* every step in complex128 / float64 */
+    PW_PREC_MIXED = 1          /* reserved: FFT apply in complex64, FP64 small dense steps */
+} pw_precision;
+
+/* Per-solve counters and phase times (milliseconds, measured with HIP events
+ * on the context stream). */
+typedef struct {
+    int32_t iterations;        /* LOBPCG iterations summed over blocks */
+    int32_t blocks;            /* number of blocks */
+    int32_t h_applies;         /* number of H.X columns applied */
+    int32_t p_restarts;        /* iterations where the P direction was dropped */
+    double ms_total;           /* wall time of the solve on the stream */
+    double ms_apply;           /* H.X (FFT apply + projectors) */
+    double ms_gemm;            /* Gram, projection and block-update GEMMs */
+    double ms_dense;           /* small dense FP64 steps (Cholesky, eigensolver) */
+    double ms_vec;             /* residual / preconditioner / copies */
+    double ms_final_rr;        /* final Rayleigh-Ritz over all bands */
+} pw_stats;
+
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the legacy default stream). */
+pw_status pw_create(int device, void *hip_stream, pw_ctx *out);
+void pw_destroy(pw_ctx ctx);
+/* Text of the last error on ctx (valid until the next call on ctx). */
+const char *pw_last_error(pw_ctx ctx);
+
+/* Plane-wave sphere S = { n in Z^3 : 1/2 |B (n + kfrac)|^2 <= ecut } (sec. 2.1),
+ * B = 2 pi cell^-T.  cell: 3x3 row-major, rows = lattice vectors (bohr).
+ * kfrac: k in reduced coordinates.  ecut: Ha.  fft_n: grid points per axis;
+ * the grid must be cubic (n0 = n1 = n2), a supported size (see pw_fft_sizes)
+ * and hold the sphere without collisions (n >= 2 nmax + 1).  Writes npw.
+ * Sphere order: lexicographic in (n_x, n_y, n_z), so every z-column
+ * ("stick") of the sphere is contiguous.  Resets potential, projectors and
+ * workspace. */
+pw_status pw_init_basis(pw_ctx ctx, const double cell[9], const double kfrac[3],
+                        double ecut, const int32_t fft_n[3], int64_t *npw);
+/* Supported FFT sizes: writes up to `cap` sizes to `sizes`, returns the count
+ * in *count. */
+pw_status pw_fft_sizes(int32_t *sizes, int32_t cap, int32_t *count);
+/* Miller indices of the sphere, host int32 [npw][3], library order. */
+pw_status pw_get_miller(pw_ctx ctx, int32_t *miller);
+/* Kinetic diagonal 1/2 |k+G|^2 in Ha, host double [npw], library order. */
+pw_status pw_get_kinetic(pw_ctx ctx, double *kin);
+
+/* Local potential V(r_j) (Ha) on the grid, real, C order [j0][j1][j2] with
+ * r_j = cell^T (j / N).  Host pointer (on_device = 0) or device pointer. The
+ * context keeps its own permuted copy.  Non-finite values -> PW_ERR_NUMERIC. */
+pw_status pw_set_local_potential(pw_ctx ctx, const double *v, int on_device);
+
+/* Kleinman-Bylander projectors (sec. 2.2 iv, sec. 4.3): for atom a at pos[a]
+ * (bohr, Cartesian) and each (l, m) in lm[nproj_per_atom][2] (l in {0, 1},
+ * real harmonics Y00 = 1/(2 sqrt pi), (Y1-1, Y10, Y11) = sqrt(3/4pi)(y, z, x)/|q|),
+ *   beta_{a,lm}(q) = Omega^-1/2 c exp(-|q|^2/2) Y_lm(q/|q|) exp(-i q.R_a),
+ *   c = (32 pi^(5/2))^(1/2),  q = k + G,
+ * and the term sum_{a,p} D[a*nproj_per_atom + p] |beta><beta| is added to H.
+ * natom = 0 removes the projectors.  Host arrays. */
+pw_status pw_set_projectors(pw_ctx ctx, int32_t natom, const double *pos,
+                            int32_t nproj_per_atom, const int32_t *lm, const double *D);
+
+/* Device workspace the caller allocates: bytes needed by pw_lobpcg_solve for
+ * (nbands, block) and by pw_apply_H (which works in chunks of `block`
+ * columns). */
+pw_status pw_workspace_size(pw_ctx ctx, int32_t nbands, int32_t block, pw_precision prec,
+                            size_t *bytes);
+/* Hand the workspace to the context (device pointer, 256-byte aligned).  The
+ * plan of the last pw_workspace_size call must fit: else PW_ERR_NOMEM. */
+pw_status pw_set_workspace(pw_ctx ctx, void *dptr, size_t bytes);
+
+/* Y = H X on the context stream (rows a2-a7 of the hot path).  X, Y: device,
+ * complex128, column-major [npw x nb], ldx, ldy >= npw; X and Y must not
+ * overlap.  Needs basis, potential and workspace.  Asynchronous. */
+pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                     int32_t nb, pw_precision prec);
+
+/* Lowest `nbands` eigenpairs by block LOBPCG (sec. 3.2, Algorithm 1) in blocks
+ * of `block` bands, each block kept orthogonal to the previous ones, then a
+ * final Rayleigh-Ritz over all bands.  Convergence per block: every residual
+ * ||H x - theta x||_2 (||x||_2 = 1) <= tol.  X: device complex128
+ * [npw x nbands], ldx >= npw; on entry a starting guess if use_guess != 0,
+ * on exit the orthonormal eigenvectors.  eig: host double[nbands], ascending.
+ * Returns PW_ERR_NOT_CONVERGED (with the best pairs written) if a block hits
+ * max_iter or a final residual exceeds tol.  Synchronises the stream. */
+pw_status pw_lobpcg_solve(pw_ctx ctx, int32_t nbands, int32_t block, double tol,
+                          int32_t max_iter, pw_precision prec, void *X, int64_t ldx,
+                          int32_t use_guess, double *eig);
+/* Residual norms ||H x_j - theta_j x_j||_2 of the last solve, host double[nbands]. */
+pw_status pw_get_residuals(pw_ctx ctx, double *res);
+/* Counters and phase times of the last solve. */
+pw_status pw_get_stats(pw_ctx ctx, pw_stats *stats);
+
+/* ---- Building blocks of the iteration, exported for per-step parity tests ----
+ * All pointers are device pointers; complex128 column-major; asynchronous on
+ * the context stream; no workspace needed unless stated. */
+
+/* Gram block C = A^H B (sec. 4.1: Gram blocks by zgemm over the plane-wave
+ * coefficients; Algorithm 1 step 4).  A [K x p], B [K x q], C [p x q].
+ * Deterministic split-K reduction; needs the workspace (size from
+ * pw_workspace_size). */
+pw_status pw_gram(pw_ctx ctx, const void *A, int64_t lda, const void *B, int64_t ldb,
+                  int64_t K, int32_t p, int32_t q, void *C, int64_t ldc);
+/* Block update Y = alpha A C + beta Y (Algorithm 1 steps 4-5: Psi Delta +
+ * W Lambda + P Gamma).  A [K x p], C [p x q], Y [K x q]; alpha, beta real.
+ * Y must not overlap A unless q <= 64 and Y == A (in-place right multiply). */
+pw_status pw_block_update(pw_ctx ctx, const void *A, int64_t lda, const void *C, int64_t ldc,
+                          int64_t K, int32_t p, int32_t q, double alpha, double beta,
+                          void *Y, int64_t ldy);
+/* Lowest k eigenpairs of a Hermitian n x n matrix A (lda >= n) -- the small
+ * dense Rayleigh-Ritz eigenproblem of Algorithm 1 step 4 and of the final
+ * Rayleigh-Ritz (sec. 3.2, sec. 4.2).  Householder tridiagonalisation,
+ * bisection, inverse iteration, re-orthogonalisation, back-transform; one
+ * workgroup, FP64.  w: device double[k] ascending; V: device [n x k], ldv >= n.
+ * A is overwritten.  1 <= k <= n <= 1024.  Needs the workspace. */
+pw_status pw_small_eigh(pw_ctx ctx, void *A, int64_t lda, int32_t n, int32_t k,
+                        void *w, void *V, int64_t ldv);
+/* Residuals and preconditioned residuals (Eq. (1) with O = I; Algorithm 1
+ * steps 1-3): theta_j = Re(x_j^H Hx_j) (columns of X assumed unit norm),
+ * R = HX - X diag(theta), res_j = ||R_j||_2, and W = K(R) with the
+ * Teter-Payne-Allan factor K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4),
+ * x = T_g / max(E_kin,j, 1e-3), E_kin,j = sum_g T_g |x_gj|^2.
+ * theta, res: device double[nb].  W may be NULL (residual norms only). */
+pw_status pw_residuals(pw_ctx ctx, const void *X, int64_t ldx, const void *HX, int64_t ldhx,
+                       int32_t nb, void *theta, void *res, void *W, int64_t ldw);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PWLOBPCG_H */

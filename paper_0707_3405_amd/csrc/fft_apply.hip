@@ -1,0 +1,335 @@
+// Plane-wave H.X apply, kinetic + local part (hot-path rows a2-a6).
+//
+// Sec. 2.2 (iii) and sec. 4.1: the local potential is applied by transforming
+// each band to real space on the FFT grid (coefficients zero-padded outside
+// the sphere), multiplying by V(r), and transforming back.  Here the 3-D
+// transform is pruned to the sphere and split into three passes over a
+// "stick" buffer S[band][z][stick] (a stick is one (n_x, n_y) column of the
+// sphere):
+//
+//   pass 1 (k_zinv):  per (band, group of sticks): scatter the sphere
+//                     coefficients of each stick into LDS, inverse z-FFT,
+//                     write S (only sticks, not the full grid).
+//   pass 2 (k_plane): per (band, z-plane): scatter the plane's sticks into the
+//                     kept x-columns, inverse y-FFT on those columns, then row
+//                     by row inverse x-FFT, multiply by V(r)/N^3, forward
+//                     x-FFT (keeping only the kept columns), forward y-FFT,
+//                     gather the sticks back into S.
+//   pass 3 (k_zfwd):  per (band, group of sticks): forward z-FFT, gather the
+//                     sphere points, add the kinetic term 1/2|k+G|^2 X.
+//
+// Sign convention: grid <- G uses exp(+2 pi i n.j/N) with no scale, G <- grid
+// uses exp(-2 pi i n.j/N) with 1/N^3 (folded into the stored potential).
+#include "fft_core.h"
+#include "pw_internal.h"
+
+namespace pw {
+namespace {
+
+using namespace fft;
+
+constexpr int kThreads = 256;
+
+template <class T>
+__device__ __forceinline__ void load_twiddles(cpx<T> *tw_s, const double *tw_g, int n) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        tw_s[i] = cpx<T>{T(tw_g[2 * i]), T(tw_g[2 * i + 1])};
+}
+
+// ---- pass 1: inverse z-FFT per stick ---------------------------------------
+template <int N, class T>
+__global__ void __launch_bounds__(kThreads) k_zinv(SphereDev sp, const cpx<T> *__restrict__ X,
+                                                   int64_t ldx, cpx<T> *__restrict__ S, int spb) {
+    constexpr int LD = N + 1;
+    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *tw = reinterpret_cast<cpx<T> *>(smem_raw);
+    cpx<T> *buf = tw + N;
+
+    const int band = blockIdx.y;
+    const int s0 = blockIdx.x * spb;
+    const int ns = min(spb, sp.nst - s0);
+    if (ns <= 0) return;
+    const cpx<T> *Xb = X + (int64_t)band * ldx;
+
+    load_twiddles(tw, sp.twid, N);
+    for (int i = threadIdx.x; i < ns * LD; i += blockDim.x) buf[i] = cpx<T>{T(0), T(0)};
+    __syncthreads();
+    const int g0 = sp.st_start[s0];
+    const int g1 = sp.st_start[s0 + ns - 1] + sp.st_len[s0 + ns - 1];
+    for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+        const int pos = sp.g_map[g];
+        const int s = pos / N, z = pos - s * N;
+        buf[(s - s0) * LD + z] = Xb[g];
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < ns * R2; it += blockDim.x) {
+        const int seq = it % ns, n2 = it / ns;
+        dit_a<N, +1>(buf + seq * LD, n2, tw);
+    }
+    __syncthreads();
+    cpx<T> *Sb = S + (int64_t)band * N * sp.ldst + s0;
+    for (int it = threadIdx.x; it < ns * R1; it += blockDim.x) {
+        const int seq = it % ns, k1 = it / ns;
+        cpx<T> out[R2];
+        dit_b<N, +1>(buf + seq * LD, k1, out);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) Sb[(int64_t)(k1 + R1 * k2) * sp.ldst + seq] = out[k2];
+    }
+}
+
+// ---- pass 2: per z-plane xy transforms with the potential in between -------
+// XCD-aware mapping: consecutive hardware workgroup ids go round-robin over
+// the 8 XCDs; each XCD is given a contiguous range of (plane, band) work so
+// that all bands of one plane share that XCD's L2 copy of V(z, :, :).
+__device__ __forceinline__ int xcd_logical(int lin, int total) {
+    const int q = total / 8, r = total % 8;
+    const int xcd = lin % 8, local = lin / 8;
+    return xcd * q + min(xcd, r) + local;
+}
+
+template <int N, class T>
+__global__ void __launch_bounds__(kThreads) k_plane(SphereDev sp, const T *__restrict__ vperm,
+                                                    cpx<T> *__restrict__ S, int nb, int rb) {
+    constexpr int LD = N + 1;
+    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *tw = reinterpret_cast<cpx<T> *>(smem_raw);
+    cpx<T> *A = tw + N;                 // [ncx][LD], y along the row
+    cpx<T> *R = A + sp.ncx * LD;        // [rb][LD], x along the row
+
+    const int total = N * nb;
+    const int lid = xcd_logical(blockIdx.x, total);
+    const int z = lid / nb, band = lid % nb;
+    const int ncx = sp.ncx;
+    cpx<T> *Sp = S + ((int64_t)band * N + z) * sp.ldst;
+    const T *Vz = vperm + (int64_t)z * N * N;
+
+    load_twiddles(tw, sp.twid, N);
+    for (int i = threadIdx.x; i < ncx * LD; i += blockDim.x) A[i] = cpx<T>{T(0), T(0)};
+    __syncthreads();
+    for (int s = threadIdx.x; s < sp.nst; s += blockDim.x) A[sp.st_xc[s] * LD + sp.st_y[s]] = Sp[s];
+    __syncthreads();
+    // inverse y-FFT on the kept columns (natural -> digit-reversed)
+    for (int it = threadIdx.x; it < ncx * R2; it += blockDim.x) {
+        const int c = it % ncx, n2 = it / ncx;
+        dit_a<N, +1>(A + c * LD, n2, tw);
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < ncx * R1; it += blockDim.x) {
+        const int c = it % ncx, k1 = it / ncx;
+        cpx<T> out[R2];
+        dit_b<N, +1>(A + c * LD, k1, out);
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) A[c * LD + k1 * R2 + k2] = out[k2];
+    }
+    __syncthreads();
+    // rows: x-iFFT, * V, x-FFT, in chunks of rb rows
+    const int xmin_g = ((sp.xmin % N) + N) % N;
+    for (int y0 = 0; y0 < N; y0 += rb) {
+        const int nr = min(rb, N - y0);
+        for (int i = threadIdx.x; i < nr * N; i += blockDim.x) {
+            const int r = i / N, x = i - r * N;
+            int xc = x - xmin_g;
+            xc += (xc < 0) ? N : 0;
+            R[r * LD + x] = (xc < ncx) ? A[xc * LD + digit_rev<N>(y0 + r)] : cpx<T>{T(0), T(0)};
+        }
+        __syncthreads();
+        for (int it = threadIdx.x; it < nr * R2; it += blockDim.x) {
+            const int r = it % nr, n2 = it / nr;
+            dit_a<N, +1>(R + r * LD, n2, tw);
+        }
+        __syncthreads();
+        for (int it = threadIdx.x; it < nr * R1; it += blockDim.x) {
+            const int r = it % nr, k1 = it / nr;
+            cpx<T> out[R2];
+            dit_b<N, +1>(R + r * LD, k1, out);
+            const T *vrow = Vz + (int64_t)(y0 + r) * N + k1 * R2;
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) R[r * LD + k1 * R2 + k2] = cscale(out[k2], vrow[k2]);
+        }
+        __syncthreads();
+        for (int it = threadIdx.x; it < nr * R1; it += blockDim.x) {
+            const int r = it % nr, k1 = it / nr;
+            dif_b<N, -1>(R + r * LD, k1);
+        }
+        __syncthreads();
+        for (int it = threadIdx.x; it < nr * R2; it += blockDim.x) {
+            const int r = it % nr, n2 = it / nr;
+            cpx<T> out[R1];
+            dif_a<N, -1>(R + r * LD, n2, tw, out);
+            const int ypos = digit_rev<N>(y0 + r);
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) {
+                const int x = n1 * R2 + n2;
+                int xc = x - xmin_g;
+                xc += (xc < 0) ? N : 0;
+                if (xc < ncx) A[xc * LD + ypos] = out[n1];
+            }
+        }
+        __syncthreads();
+    }
+    // forward y-FFT on the kept columns (digit-reversed -> natural)
+    for (int it = threadIdx.x; it < ncx * R1; it += blockDim.x) {
+        const int c = it % ncx, k1 = it / ncx;
+        dif_b<N, -1>(A + c * LD, k1);
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < ncx * R2; it += blockDim.x) {
+        const int c = it % ncx, n2 = it / ncx;
+        cpx<T> out[R1];
+        dif_a<N, -1>(A + c * LD, n2, tw, out);
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) A[c * LD + n1 * R2 + n2] = out[n1];
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < sp.nst; s += blockDim.x) Sp[s] = A[sp.st_xc[s] * LD + sp.st_y[s]];
+}
+
+// ---- pass 3: forward z-FFT per stick, gather, kinetic -----------------------
+template <int N, class T>
+__global__ void __launch_bounds__(kThreads) k_zfwd(SphereDev sp, const cpx<T> *__restrict__ S,
+                                                   const cpx<T> *__restrict__ X, int64_t ldx,
+                                                   cpx<T> *__restrict__ Y, int64_t ldy, int spb) {
+    constexpr int LD = N + 1;
+    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *tw = reinterpret_cast<cpx<T> *>(smem_raw);
+    cpx<T> *buf = tw + N;
+
+    const int band = blockIdx.y;
+    const int s0 = blockIdx.x * spb;
+    const int ns = min(spb, sp.nst - s0);
+    if (ns <= 0) return;
+    load_twiddles(tw, sp.twid, N);
+    const cpx<T> *Sb = S + (int64_t)band * N * sp.ldst + s0;
+    for (int i = threadIdx.x; i < ns * N; i += blockDim.x) {
+        const int z = i / ns, seq = i - z * ns;
+        buf[seq * LD + digit_rev<N>(z)] = Sb[(int64_t)z * sp.ldst + seq];
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < ns * R1; it += blockDim.x) {
+        const int seq = it % ns, k1 = it / ns;
+        dif_b<N, -1>(buf + seq * LD, k1);
+    }
+    __syncthreads();
+    for (int it = threadIdx.x; it < ns * R2; it += blockDim.x) {
+        const int seq = it % ns, n2 = it / ns;
+        cpx<T> out[R1];
+        dif_a<N, -1>(buf + seq * LD, n2, tw, out);
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) buf[seq * LD + n1 * R2 + n2] = out[n1];
+    }
+    __syncthreads();
+    const int g0 = sp.st_start[s0];
+    const int g1 = sp.st_start[s0 + ns - 1] + sp.st_len[s0 + ns - 1];
+    const cpx<T> *Xb = X + (int64_t)band * ldx;
+    cpx<T> *Yb = Y + (int64_t)band * ldy;
+    for (int g = g0 + threadIdx.x; g < g1; g += blockDim.x) {
+        const int pos = sp.g_map[g];
+        const int s = pos / N, zz = pos - s * N;
+        const cpx<T> v = buf[(s - s0) * LD + zz];
+        const cpx<T> x = Xb[g];
+        const T t = T(sp.kin[g]);
+        Yb[g] = cpx<T>{v.x + t * x.x, v.y + t * x.y};
+    }
+}
+
+// ---- potential layout: vperm[z][y][p] = scale * V[x(p)][y][z] ---------------
+// p is the digit-reversed x position produced by the inverse x-FFT of pass 2,
+// so the multiply in pass 2 reads V contiguously.
+template <int N>
+__global__ void k_permute_v(const double *__restrict__ v, double scale, double *__restrict__ out,
+                            int *bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * N * N) return;
+    const int p = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / ((int64_t)N * N));
+    const int x = freq_at<N>(p);
+    const double val = v[((int64_t)x * N + y) * N + z];
+    if (!isfinite(val)) atomicOr(bad, 1);
+    out[i] = val * scale;
+}
+
+// ---- dispatch ---------------------------------------------------------------
+constexpr int kSticksPerBlock = 32;
+
+template <int N, class T>
+void run_apply(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
+               int64_t ldy, int nb, cpx<T> *S, hipStream_t st) {
+    const int spb = kSticksPerBlock;
+    const size_t e = sizeof(cpx<T>);
+    const size_t sm13 = (size_t)N * e + (size_t)spb * (N + 1) * e;
+    dim3 g13((sp.nst + spb - 1) / spb, nb);
+    // pass 2 LDS: twiddles + kept columns + row chunk; largest row chunk that
+    // keeps the workgroup under 150 KB.
+    const size_t base2 = (size_t)N * e + (size_t)sp.ncx * (N + 1) * e;
+    int rb = 32;
+    while (rb > 1 && base2 + (size_t)rb * (N + 1) * e > 150 * 1024) rb /= 2;
+    if (rb > N) rb = N;
+    const size_t sm2 = base2 + (size_t)rb * (N + 1) * e;
+    PW_REQUIRE(sm2 <= 160 * 1024, PW_ERR_ARG, "FFT plane does not fit in LDS");
+    PW_HIP(hipFuncSetAttribute((const void *)k_zinv<N, T>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm13));
+    PW_HIP(hipFuncSetAttribute((const void *)k_plane<N, T>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2));
+    PW_HIP(hipFuncSetAttribute((const void *)k_zfwd<N, T>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm13));
+    hipLaunchKernelGGL((k_zinv<N, T>), g13, dim3(kThreads), sm13, st, sp, X, ldx, S, spb);
+    hipLaunchKernelGGL((k_plane<N, T>), dim3(N * nb), dim3(kThreads), sm2, st, sp, vperm, S, nb,
+                       rb);
+    hipLaunchKernelGGL((k_zfwd<N, T>), g13, dim3(kThreads), sm13, st, sp, S, X, ldx, Y, ldy, spb);
+    PW_HIP(hipGetLastError());
+}
+
+#define PW_FFT_SIZES(X) X(16) X(20) X(24) X(32) X(36) X(40) X(48) X(60) X(64) X(72) X(80) X(96) X(108) X(120) X(128)
+
+}  // namespace
+
+bool fft_size_supported(int n) {
+#define PW_CASE(NN) if (n == NN) return true;
+    PW_FFT_SIZES(PW_CASE)
+#undef PW_CASE
+    return false;
+}
+
+std::vector<int> fft_supported_sizes() {
+    std::vector<int> v;
+#define PW_CASE(NN) v.push_back(NN);
+    PW_FFT_SIZES(PW_CASE)
+#undef PW_CASE
+    return v;
+}
+
+void launch_permute_potential(const double *v, int n, double scale, double *v_zyx, int *bad,
+                              hipStream_t st) {
+    const int64_t tot = (int64_t)n * n * n;
+    const dim3 grid((unsigned)((tot + 255) / 256));
+    switch (n) {
+#define PW_CASE(NN)                                                                      \
+    case NN:                                                                             \
+        hipLaunchKernelGGL(k_permute_v<NN>, grid, dim3(256), 0, st, v, scale, v_zyx, bad); \
+        break;
+        PW_FFT_SIZES(PW_CASE)
+#undef PW_CASE
+        default:
+            throw Error{PW_ERR_ARG, "unsupported FFT size"};
+    }
+    PW_HIP(hipGetLastError());
+}
+
+void launch_fft_apply_f64(const SphereDev &sp, const double *v_zyx, const cd *X, int64_t ldx,
+                          cd *Y, int64_t ldy, int nb, cd *S, hipStream_t st) {
+    if (nb <= 0) return;
+    switch (sp.n) {
+#define PW_CASE(NN)                                                          \
+    case NN:                                                                 \
+        run_apply<NN, double>(sp, v_zyx, X, ldx, Y, ldy, nb, S, st);         \
+        return;
+        PW_FFT_SIZES(PW_CASE)
+#undef PW_CASE
+        default:
+            throw Error{PW_ERR_ARG, "unsupported FFT size"};
+    }
+}
+
+}  // namespace pw

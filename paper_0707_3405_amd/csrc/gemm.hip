@@ -1,0 +1,271 @@
+// Complex FP64 GEMMs on the gfx950 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// Sec. 4.1: the Gram blocks of LOBPCG and the block updates are dense complex
+// matrix products over the plane-wave coefficients ("zgemm"), and sec. 5.1
+// finds them to dominate the run time.  Two shapes occur:
+//
+//   tn:  C[p x q] = A^H B   with A [K x p], B [K x q], K = npw large
+//        (Gram blocks, projector overlaps B^H X, constraint overlaps Y^H W).
+//        Split over K into chunks; each workgroup writes its partial tile,
+//        and a second kernel sums the partials in a fixed order, so results
+//        are bitwise reproducible (no floating-point atomics).
+//   nn:  Y[K x q] = alpha A C + beta Y   with C [p x q] small
+//        (block updates Psi Delta + W Lambda + P Gamma, projector add-back,
+//        orthonormalisation W <- W R^-1).
+//
+// A complex product is four real MFMAs (re.re, im.im, re.im, im.re).  The
+// MFMA contraction index is mapped so that lane group g = lane/16 consumes
+// k = kb + 4g + s in step s: each lane then reads four consecutive complex
+// elements of one column (64 contiguous bytes), and lanes 16 apart read the
+// neighbouring 64 bytes.
+//
+// MFMA operand layout (16x16x4 f64, wave64): A operand lane l holds
+// A[i = l%16][k = l/16]; B operand lane l holds B[k = l/16][j = l%16]; result
+// register r of lane l holds D[i = l/16 + 4r][j = l%16] (rows interleaved by 4,
+// as measured on gfx950).
+#include "pw_internal.h"
+
+namespace pw {
+namespace {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+constexpr int kTile = 64;      // workgroup tile (complex elements) per dimension
+constexpr int kThreads = 256;  // 4 waves in a 2 x 2 arrangement, 32 x 32 each
+
+__device__ __forceinline__ cd ldg_or_zero(const cd *p, bool ok) {
+    return ok ? *p : cd{0.0, 0.0};
+}
+
+// Map a hardware workgroup id to a logical id so that each XCD (ids are
+// dealt round-robin over 8 XCDs) receives a contiguous range.
+__device__ __forceinline__ int xcd_logical(int lin, int total) {
+    const int q = total / 8, r = total % 8;
+    const int xcd = lin % 8, local = lin / 8;
+    return xcd * q + min(xcd, r) + local;
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_gemm_tn(const cd *__restrict__ A, int64_t lda, const cd *__restrict__ B, int64_t ldb,
+              int64_t K, int p, int q, int64_t kchunk, int tiles_m, int tiles_n, int nsplit,
+              cd *__restrict__ part) {
+    const int total = tiles_m * tiles_n * nsplit;
+    const int lid = xcd_logical(blockIdx.x, total);
+    // split is the slow index so that the tiles sharing one K chunk run close
+    // together on one XCD and share its L2.
+    const int split = lid / (tiles_m * tiles_n);
+    const int tile = lid % (tiles_m * tiles_n);
+    const int tm = tile % tiles_m, tn = tile / tiles_m;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, g = lane >> 4;
+    const int i0 = tm * kTile + (wave & 1) * 32;
+    const int j0 = tn * kTile + (wave >> 1) * 32;
+    const int64_t kbeg = (int64_t)split * kchunk;
+    const int64_t kend = min(K, kbeg + kchunk);
+
+    f64x4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = f64x4{0, 0, 0, 0};
+
+    const cd *Ac[2];
+    const cd *Bc[2];
+    bool aok[2], bok[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const int ci = i0 + 16 * t + li, cj = j0 + 16 * t + li;
+        aok[t] = ci < p;
+        bok[t] = cj < q;
+        Ac[t] = A + (int64_t)(aok[t] ? ci : 0) * lda;
+        Bc[t] = B + (int64_t)(bok[t] ? cj : 0) * ldb;
+    }
+    for (int64_t kb = kbeg; kb < kend; kb += 16) {
+        cd a[2][4], b[2][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int64_t k = kb + 4 * g + s;
+            const bool kin = k < kend;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                a[t][s] = ldg_or_zero(Ac[t] + k, kin && aok[t]);
+                b[t][s] = ldg_or_zero(Bc[t] + k, kin && bok[t]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < 2; ++nj) {
+                    // conj(a) * b
+                    accr[mi][nj] = mfma(a[mi][s].x, b[nj][s].x, accr[mi][nj]);
+                    accr[mi][nj] = mfma(a[mi][s].y, b[nj][s].y, accr[mi][nj]);
+                    acci[mi][nj] = mfma(a[mi][s].x, b[nj][s].y, acci[mi][nj]);
+                    acci[mi][nj] = mfma(-a[mi][s].y, b[nj][s].x, acci[mi][nj]);
+                }
+    }
+    cd *P = part + (size_t)split * p * q;
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + 16 * mi + g + 4 * r;
+                const int j = j0 + 16 * nj + li;
+                if (i < p && j < q) P[(size_t)j * p + i] = cd{accr[mi][nj][r], acci[mi][nj][r]};
+            }
+}
+
+__global__ void k_reduce_parts(const cd *__restrict__ part, int nsplit, int p, int q, cd *C,
+                               int64_t ldc, const double *__restrict__ scale_row, double beta) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)p * q) return;
+    const int i = (int)(idx % p), j = (int)(idx / p);
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < nsplit; ++s) {
+        const cd v = part[(size_t)s * p * q + idx];
+        sr += v.x;
+        si += v.y;
+    }
+    if (scale_row) {
+        sr *= scale_row[i];
+        si *= scale_row[i];
+    }
+    cd *c = C + (int64_t)j * ldc + i;
+    if (beta != 0.0) {
+        sr += beta * c->x;
+        si += beta * c->y;
+    }
+    *c = cd{sr, si};
+}
+
+__global__ void __launch_bounds__(kThreads)
+    k_gemm_nn(const cd *__restrict__ A, int64_t lda, const cd *__restrict__ Cm, int64_t ldc,
+              int64_t K, int p, int q, double alpha, double beta, cd *Y, int64_t ldy,
+              int tiles_m) {
+    const int lid = xcd_logical(blockIdx.x, gridDim.x);
+    const int tm = lid % tiles_m, tn = lid / tiles_m;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, g = lane >> 4;
+    const int64_t r0 = (int64_t)tm * kTile + (wave & 1) * 32;
+    const int c0 = tn * kTile + (wave >> 1) * 32;
+
+    f64x4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = f64x4{0, 0, 0, 0};
+
+    bool rok[2], cok[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        rok[t] = r0 + 16 * t + li < K;
+        cok[t] = c0 + 16 * t + li < q;
+    }
+    for (int kb = 0; kb < p; kb += 16) {
+        cd a[2][4], b[2][4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const int kk = kb + 4 * g + s;
+            const bool kin = kk < p;
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                a[t][s] = ldg_or_zero(A + (int64_t)(kin ? kk : 0) * lda + (rok[t] ? r0 + 16 * t + li : 0),
+                                      kin && rok[t]);
+                b[t][s] = ldg_or_zero(Cm + (int64_t)(cok[t] ? c0 + 16 * t + li : 0) * ldc + (kin ? kk : 0),
+                                      kin && cok[t]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < 2; ++nj) {
+                    // a * c
+                    accr[mi][nj] = mfma(a[mi][s].x, b[nj][s].x, accr[mi][nj]);
+                    accr[mi][nj] = mfma(-a[mi][s].y, b[nj][s].y, accr[mi][nj]);
+                    acci[mi][nj] = mfma(a[mi][s].x, b[nj][s].y, acci[mi][nj]);
+                    acci[mi][nj] = mfma(a[mi][s].y, b[nj][s].x, acci[mi][nj]);
+                }
+    }
+    // every wave of the workgroup has read its rows of A before any writes:
+    // this makes the in-place form Y == A safe when one workgroup spans all q.
+    __syncthreads();
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = r0 + 16 * mi + g + 4 * r;
+                const int j = c0 + 16 * nj + li;
+                if (i < K && j < q) {
+                    cd *y = Y + (int64_t)j * ldy + i;
+                    double yr = alpha * accr[mi][nj][r], yi = alpha * acci[mi][nj][r];
+                    if (beta != 0.0) {
+                        const cd o = *y;
+                        yr += beta * o.x;
+                        yi += beta * o.y;
+                    }
+                    *y = cd{yr, yi};
+                }
+            }
+}
+
+int choose_split(int64_t K, int tiles) {
+    int64_t ns = (768 + tiles - 1) / tiles;
+    const int64_t kmax = (K + 255) / 256;
+    if (ns > kmax) ns = kmax;
+    if (ns < 1) ns = 1;
+    return (int)ns;
+}
+
+}  // namespace
+
+size_t gemm_tn_part_elems(int64_t K, int p, int q, int *nsplit_out) {
+    const int tiles = ((p + kTile - 1) / kTile) * ((q + kTile - 1) / kTile);
+    const int ns = choose_split(K, tiles);
+    if (nsplit_out) *nsplit_out = ns;
+    return (size_t)ns * p * q;
+}
+
+void launch_gemm_tn_f64(const cd *A, int64_t lda, const cd *B, int64_t ldb, int64_t K, int p,
+                        int q, cd *C, int64_t ldc, const double *scale_row, double beta,
+                        cd *part, size_t part_elems, hipStream_t st) {
+    if (p <= 0 || q <= 0) return;
+    const int tiles_m = (p + kTile - 1) / kTile, tiles_n = (q + kTile - 1) / kTile;
+    int ns = choose_split(K, tiles_m * tiles_n);
+    if ((size_t)ns * p * q > part_elems) ns = (int)(part_elems / ((size_t)p * q));
+    PW_REQUIRE(ns >= 1, PW_ERR_NOMEM, "GEMM partial buffer too small");
+    int64_t kchunk = (K + ns - 1) / ns;
+    kchunk = (kchunk + 15) / 16 * 16;
+    ns = (int)((K + kchunk - 1) / kchunk);
+    if (ns < 1) ns = 1;
+    const int total = tiles_m * tiles_n * ns;
+    hipLaunchKernelGGL(k_gemm_tn, dim3(total), dim3(kThreads), 0, st, A, lda, B, ldb, K, p, q,
+                       kchunk, tiles_m, tiles_n, ns, part);
+    const int64_t n = (int64_t)p * q;
+    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part,
+                       ns, p, q, C, ldc, scale_row, beta);
+    PW_HIP(hipGetLastError());
+}
+
+void launch_gemm_nn_f64(const cd *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p,
+                        int q, double alpha, double beta, cd *Y, int64_t ldy, hipStream_t st) {
+    if (K <= 0 || q <= 0) return;
+    const int tiles_m = (int)((K + kTile - 1) / kTile), tiles_n = (q + kTile - 1) / kTile;
+    PW_REQUIRE(!((const void *)A == (const void *)Y) || q <= kTile, PW_ERR_ARG,
+               "in-place block update needs q <= 64");
+    hipLaunchKernelGGL(k_gemm_nn, dim3(tiles_m * tiles_n), dim3(kThreads), 0, st, A, lda, C, ldc,
+                       K, p, q, alpha, beta, Y, ldy, tiles_m);
+    PW_HIP(hipGetLastError());
+}
+
+}  // namespace pw

@@ -1,0 +1,115 @@
+// Internal declarations shared by the host runtime and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "pwlobpcg.h"
+
+namespace pw {
+
+// Interleaved complex with natural alignment (16 B for double, 8 B for float).
+template <class T>
+struct alignas(2 * sizeof(T)) cpx {
+    T x, y;
+};
+using cd = cpx<double>;
+using cf = cpx<float>;
+
+// Error carrier used inside the runtime; converted to pw_status at the ABI.
+struct Error {
+    pw_status code;
+    std::string msg;
+};
+
+#define PW_HIP(call)                                                                  \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            throw ::pw::Error{PW_ERR_DEVICE, std::string(#call) + ": " +              \
+                                                 hipGetErrorString(e_)};              \
+    } while (0)
+
+#define PW_REQUIRE(cond, code, text)                                                  \
+    do {                                                                              \
+        if (!(cond)) throw ::pw::Error{code, text};                                   \
+    } while (0)
+
+// Device-side description of the plane-wave sphere and its z-sticks.
+// Sphere order is lexicographic (n_x, n_y, n_z): stick s holds the contiguous
+// range [st_start[s], st_start[s] + st_len[s]) with n_z = st_z0[s] + j.
+struct SphereDev {
+    int64_t npw = 0;
+    int32_t n = 0;            // cubic FFT size
+    int32_t nst = 0;          // number of sticks
+    int32_t ldst = 0;         // padded stick count (leading dim of stick buffers)
+    int32_t ncx = 0;          // kept x columns (n_x in [xmin, xmin + ncx))
+    int32_t xmin = 0;
+    int32_t *st_start = nullptr;  // [nst]
+    int32_t *st_len = nullptr;    // [nst]
+    int32_t *st_z0 = nullptr;     // [nst] signed n_z of the first element
+    int32_t *st_y = nullptr;      // [nst] grid y index (n_y mod n)
+    int32_t *st_xc = nullptr;     // [nst] kept-column index n_x - xmin
+    int32_t *g_map = nullptr;     // [npw] (stick * n + (n_z mod n))
+    double *kin = nullptr;        // [npw] 1/2 |k+G|^2
+    double *twid = nullptr;       // [n] exp(+2 pi i j / n), interleaved
+};
+
+// ---- kernel launchers (implemented in the .hip files) ----------------------
+
+// FFT apply (rows a2-a6): Y = T X + (V psi)(G) for nb columns.  S is the stick
+// buffer [nb][n][ldst] complex.  v_zyx is V / n^3 in [z][y][x] order.
+void launch_fft_apply_f64(const SphereDev &sp, const double *v_zyx, const cd *X, int64_t ldx,
+                          cd *Y, int64_t ldy, int nb, cd *S, hipStream_t st);
+bool fft_size_supported(int n);
+std::vector<int> fft_supported_sizes();
+
+// Complex FP64 GEMMs on MFMA.
+//   tn: part[s] = A^H B over K-chunk s; reduce: C = scale_row * sum_s part[s] (+ beta C)
+size_t gemm_tn_part_elems(int64_t K, int p, int q, int *nsplit_out);
+void launch_gemm_tn_f64(const cd *A, int64_t lda, const cd *B, int64_t ldb, int64_t K, int p,
+                        int q, cd *C, int64_t ldc, const double *scale_row, double beta,
+                        cd *part, size_t part_elems, hipStream_t st);
+//   nn: Y = alpha A C + beta Y
+void launch_gemm_nn_f64(const cd *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p,
+                        int q, double alpha, double beta, cd *Y, int64_t ldy, hipStream_t st);
+
+// Small dense FP64 (single workgroup).
+size_t heev_scratch_bytes(int n, int k);
+void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t ldv,
+                     void *scratch, int *status, hipStream_t st);
+// CholQR factor: G (n x n, Hermitian PD) -> Rinv (upper, G = R^H R, Rinv = R^-1)
+// with a diagonal shift for robustness; status[0] |= 1 on breakdown.
+void launch_chol_inv_f64(const cd *G, int64_t ldg, int n, cd *Rinv, int64_t ldr, int *status,
+                         hipStream_t st);
+
+// Vector kernels.
+size_t resid_part_elems(int64_t npw, int nb);
+// theta[nb]; ekin_nrm[2 nb] = (E_kin per band, |x|^2 per band)
+void launch_band_dots_f64(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
+                          int64_t npw, int nb, double *part, double *theta, double *ekin_nrm,
+                          hipStream_t st);
+void launch_resid_precond_f64(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx,
+                              const double *kin, int64_t npw, int nb, const double *theta,
+                              const double *ekin_nrm, cd *W, int64_t ldw, double *part, double *res,
+                              hipStream_t st);
+void launch_build_projectors_f64(const double *qvec, int64_t npw, int natom, const double *pos,
+                                 int nlm, const int *lm, double pref, cd *B, int64_t ldb,
+                                 hipStream_t st);
+void launch_permute_potential(const double *v, int n, double scale, double *v_zyx,
+                              int *bad, hipStream_t st);
+void launch_copy_cols_f64(const cd *A, int64_t lda, cd *B, int64_t ldb, int64_t rows, int cols,
+                          hipStream_t st);
+void launch_random_block_f64(cd *X, int64_t ldx, int64_t rows, int cols, uint64_t seed,
+                             const double *kin, hipStream_t st);
+void launch_zero_f64(cd *X, int64_t ldx, int64_t rows, int cols, hipStream_t st);
+// P-coefficient block: rows [0, m) of Cfull set to zero (the X rows), others copied.
+void launch_pcoef_f64(const cd *Cfull, int64_t ldc, int n, int m, cd *Cp, int64_t ldp,
+                      hipStream_t st);
+void launch_check_finite_f64(const double *a, int64_t n, int *status, hipStream_t st);
+
+}  // namespace pw

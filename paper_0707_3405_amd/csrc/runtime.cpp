@@ -1,0 +1,954 @@
+// Host runtime behind the C ABI: context, plane-wave sphere setup, potential
+// and projector tables, workspace plan, H.X apply and the block LOBPCG driver.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+
+#include "pw_internal.h"
+
+using pw::cd;
+using pw::Error;
+
+namespace {
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// Bump allocator over the caller's workspace (or a dry run that only sizes it).
+struct Arena {
+    char *base = nullptr;
+    size_t used = 0;
+    template <class T>
+    T *take(size_t count) {
+        used = align_up(used, 256);
+        T *p = base ? reinterpret_cast<T *>(base + used) : nullptr;
+        used += count * sizeof(T);
+        return p;
+    }
+};
+
+// Event pairs around phases; elapsed times are collected after a stream sync.
+struct PhaseTimer {
+    enum Phase { kApply = 0, kGemm, kDense, kVec, kFinal, kCount };
+    hipStream_t st = nullptr;
+    std::vector<hipEvent_t> pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> open;
+    size_t next = 0;
+    double ms[kCount] = {0, 0, 0, 0, 0};
+    hipEvent_t get() {
+        if (next == pool.size()) {
+            hipEvent_t e;
+            PW_HIP(hipEventCreate(&e));
+            pool.push_back(e);
+        }
+        return pool[next++];
+    }
+    hipEvent_t begin() {
+        hipEvent_t e = get();
+        PW_HIP(hipEventRecord(e, st));
+        return e;
+    }
+    void end(int phase, hipEvent_t b) {
+        hipEvent_t e = get();
+        PW_HIP(hipEventRecord(e, st));
+        open.push_back({phase, {b, e}});
+    }
+    // call after the stream has been synchronised
+    void collect() {
+        for (auto &o : open) {
+            float t = 0.f;
+            PW_HIP(hipEventElapsedTime(&t, o.second.first, o.second.second));
+            ms[o.first] += t;
+        }
+        open.clear();
+        next = 0;
+    }
+    ~PhaseTimer() {
+        for (auto e : pool) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace
+
+struct pw_ctx_s {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+
+    // basis
+    bool has_basis = false;
+    double cell[9] = {0}, kfrac[3] = {0}, ecut = 0;
+    int n = 0;
+    int64_t npw = 0, ldp = 0;   // ldp: padded leading dimension of internal blocks
+    std::vector<int32_t> miller;   // [npw][3]
+    std::vector<double> kin;       // [npw]
+    std::vector<double> qvec;      // [npw][3]
+    pw::SphereDev sp;
+    std::vector<void *> dev_allocs;   // context-owned device memory
+    double *d_qvec = nullptr;
+
+    // potential
+    bool has_v = false;
+    double *d_v = nullptr;
+
+    // projectors
+    int natom = 0, nlm = 0;
+    cd *d_B = nullptr;
+    double *d_D = nullptr;
+
+    // workspace
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    int plan_nbands = 0, plan_block = 0;
+
+    int *d_status = nullptr;
+    int nst_host = 0, ncx_host = 0;
+
+    // last solve
+    std::vector<double> res;
+    pw_stats stats{};
+
+    template <class T>
+    T *dev_alloc(size_t count) {
+        void *p = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc(&p, count * sizeof(T));
+        if (e != hipSuccess) throw Error{PW_ERR_NOMEM, "device allocation failed"};
+        dev_allocs.push_back(p);
+        return static_cast<T *>(p);
+    }
+    void dev_free(void *p) {
+        if (!p) return;
+        auto it = std::find(dev_allocs.begin(), dev_allocs.end(), p);
+        if (it != dev_allocs.end()) {
+            (void)hipFree(p);
+            dev_allocs.erase(it);
+        }
+    }
+    int nproj() const { return natom * nlm; }
+};
+
+namespace {
+
+// ---- workspace plan ----------------------------------------------------------
+struct Plan {
+    cd *S = nullptr;              // stick buffer [block][n][ldst]
+    cd *Z[2] = {nullptr, nullptr};    // [ldp x 3m] basis blocks [X | P | W]
+    cd *HZ[2] = {nullptr, nullptr};   // [ldp x 3m]
+    cd *HXall = nullptr;          // [ldp x M]
+    cd *T = nullptr;              // [ldp x M] rotation temp
+    cd *Pj = nullptr;             // projector overlaps [nproj x block]
+    cd *part = nullptr;           // GEMM split-K partials
+    size_t part_elems = 0;
+    cd *Agram = nullptr;          // [max(3m, M)]^2
+    cd *Cc = nullptr;             // [3m x 2m] coefficients [C | c_p]
+    cd *U = nullptr;              // [M x M] final eigenvectors (also [3m x m])
+    cd *Ov = nullptr;             // [M x m] overlaps
+    cd *Gs = nullptr;             // [m x m]
+    cd *Rinv = nullptr;           // [m x m]
+    cd *T1 = nullptr;             // [m x m]
+    double *theta = nullptr;      // [M]
+    double *ekin = nullptr;       // [2M]
+    double *res = nullptr;        // [M]
+    double *w = nullptr;          // [max(3m, M)]
+    double *rpart = nullptr;      // residual partials
+    void *heev_scratch = nullptr;
+    size_t bytes = 0;
+};
+
+Plan make_plan(const pw_ctx_s &c, int M, int m, char *base) {
+    Plan p;
+    Arena a;
+    a.base = base;
+    const int64_t ld = c.ldp;
+    const int nproj = c.nproj();
+    const int n3 = std::max(3 * m, M);
+    p.S = a.take<cd>((size_t)m * c.n * c.sp.ldst);
+    for (int i = 0; i < 2; ++i) {
+        p.Z[i] = a.take<cd>((size_t)ld * 3 * m);
+        p.HZ[i] = a.take<cd>((size_t)ld * 3 * m);
+    }
+    p.HXall = a.take<cd>((size_t)ld * M);
+    p.T = a.take<cd>((size_t)ld * M);
+    p.Pj = a.take<cd>((size_t)std::max(nproj, 1) * m);
+    size_t pe = 0;
+    auto upd = [&](int64_t K, int pp, int qq) {
+        pe = std::max(pe, pw::gemm_tn_part_elems(K, pp, qq, nullptr));
+    };
+    upd(c.npw, 3 * m, 3 * m);
+    upd(c.npw, 2 * m, m);
+    upd(c.npw, M, m);
+    upd(c.npw, m, m);
+    upd(c.npw, M, M);
+    if (nproj) upd(c.npw, nproj, m);
+    upd(3 * m, m, m);
+    p.part_elems = pe;
+    p.part = a.take<cd>(pe);
+    p.Agram = a.take<cd>((size_t)n3 * n3);
+    p.Cc = a.take<cd>((size_t)3 * m * 2 * m);
+    p.U = a.take<cd>((size_t)n3 * n3);
+    p.Ov = a.take<cd>((size_t)std::max(M, 3 * m) * m);
+    p.Gs = a.take<cd>((size_t)m * m);
+    p.Rinv = a.take<cd>((size_t)m * m);
+    p.T1 = a.take<cd>((size_t)m * m);
+    p.theta = a.take<double>(n3);
+    p.ekin = a.take<double>(2 * (size_t)n3);
+    p.res = a.take<double>(n3);
+    p.w = a.take<double>(n3);
+    p.rpart = a.take<double>(pw::resid_part_elems(c.npw, n3));
+    p.heev_scratch = a.take<char>(pw::heev_scratch_bytes(n3, n3));
+    p.bytes = align_up(a.used, 256);
+    return p;
+}
+
+void require_basis(const pw_ctx_s *c) {
+    PW_REQUIRE(c->has_basis, PW_ERR_STATE, "pw_init_basis has not been called");
+}
+void require_device(const pw_ctx_s *c) {
+    PW_REQUIRE(c->device >= 0, PW_ERR_STATE, "host-only context (device < 0) cannot run kernels");
+}
+
+Plan ready_plan(pw_ctx_s *c, int M, int m) {
+    require_basis(c);
+    require_device(c);
+    PW_REQUIRE(c->has_v, PW_ERR_STATE, "pw_set_local_potential has not been called");
+    PW_REQUIRE(c->ws != nullptr, PW_ERR_STATE, "pw_set_workspace has not been called");
+    Plan dry = make_plan(*c, M, m, nullptr);
+    PW_REQUIRE(dry.bytes <= c->ws_bytes, PW_ERR_NOMEM,
+               "workspace too small for this (nbands, block); query pw_workspace_size");
+    return make_plan(*c, M, m, c->ws);
+}
+
+// ---- H.X ------------------------------------------------------------------------
+void apply_H(pw_ctx_s *c, const Plan &p, int chunk, const cd *X, int64_t ldx, cd *Y, int64_t ldy,
+             int nb) {
+    for (int b0 = 0; b0 < nb; b0 += chunk) {
+        const int nc = std::min(chunk, nb - b0);
+        const cd *Xc = X + (int64_t)b0 * ldx;
+        cd *Yc = Y + (int64_t)b0 * ldy;
+        pw::launch_fft_apply_f64(c->sp, c->d_v, Xc, ldx, Yc, ldy, nc, p.S, c->stream);
+        const int np = c->nproj();
+        if (np > 0) {
+            // P = diag(D) B^H X ; Y += B P
+            pw::launch_gemm_tn_f64(c->d_B, c->ldp, Xc, ldx, c->npw, np, nc, p.Pj, np, c->d_D, 0.0,
+                                   p.part, p.part_elems, c->stream);
+            pw::launch_gemm_nn_f64(c->d_B, c->ldp, p.Pj, np, c->npw, np, nc, 1.0, 1.0, Yc, ldy,
+                                   c->stream);
+        }
+    }
+}
+
+struct Sync {
+    int status = 0;
+};
+
+int read_status(pw_ctx_s *c) {
+    int s = 0;
+    PW_HIP(hipMemcpyAsync(&s, c->d_status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    PW_HIP(hipStreamSynchronize(c->stream));
+    return s;
+}
+
+// CholQR of V [npw x nb] in place: G = V^H V, V <- V R^-1.
+void cholqr(pw_ctx_s *c, const Plan &p, PhaseTimer &tm, cd *V, int64_t ldv, int nb) {
+    auto e0 = tm.begin();
+    pw::launch_gemm_tn_f64(V, ldv, V, ldv, c->npw, nb, nb, p.Gs, nb, nullptr, 0.0, p.part,
+                           p.part_elems, c->stream);
+    tm.end(PhaseTimer::kGemm, e0);
+    auto e1 = tm.begin();
+    pw::launch_chol_inv_f64(p.Gs, nb, nb, p.Rinv, nb, c->d_status, c->stream);
+    tm.end(PhaseTimer::kDense, e1);
+    auto e2 = tm.begin();
+    pw::launch_gemm_nn_f64(V, ldv, p.Rinv, nb, c->npw, nb, nb, 1.0, 0.0, V, ldv, c->stream);
+    tm.end(PhaseTimer::kGemm, e2);
+}
+
+// V <- V - Q (Q^H V), Q [npw x nq]
+void project_out(pw_ctx_s *c, const Plan &p, PhaseTimer &tm, const cd *Q, int64_t ldq, int nq,
+                 cd *V, int64_t ldv, int nb) {
+    if (nq <= 0) return;
+    auto e0 = tm.begin();
+    pw::launch_gemm_tn_f64(Q, ldq, V, ldv, c->npw, nq, nb, p.Ov, nq, nullptr, 0.0, p.part,
+                           p.part_elems, c->stream);
+    pw::launch_gemm_nn_f64(Q, ldq, p.Ov, nq, c->npw, nq, nb, -1.0, 1.0, V, ldv, c->stream);
+    tm.end(PhaseTimer::kGemm, e0);
+}
+
+pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int64_t ldx,
+                 int use_guess, double *eig) {
+    Plan p = ready_plan(c, M, m);
+    hipStream_t st = c->stream;
+    const int64_t ld = c->ldp, npw = c->npw;
+    PhaseTimer tm;
+    tm.st = st;
+    pw_stats stats{};
+    hipEvent_t t_begin, t_end;
+    PW_HIP(hipEventCreate(&t_begin));
+    PW_HIP(hipEventCreate(&t_end));
+    PW_HIP(hipEventRecord(t_begin, st));
+    PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), st));
+    bool all_converged = true;
+    std::vector<double> hres(std::max(M, 3 * m));
+
+    // Each block iterates mb = min(m, keep + guard) columns; the lowest `keep`
+    // must converge and are stored, the top `guard` columns only shield them
+    // from a near-degenerate neighbour just above the block.
+    const int guard = m / 8;
+    for (int b0 = 0; b0 < M;) {
+        const int keep = std::min(m - guard, M - b0);
+        const int mb = (int)std::min<int64_t>(std::min(m, keep + guard), npw - b0);
+        ++stats.blocks;
+        int cur = 0;
+        cd *Z = p.Z[cur], *HZ = p.HZ[cur];
+        // start block: X in slot 0 (caller guess for the stored columns)
+        const int nguess = use_guess ? std::min(mb, M - b0) : 0;
+        if (nguess > 0) pw::launch_copy_cols_f64(X + (int64_t)b0 * ldx, ldx, Z, ld, npw, nguess, st);
+        if (nguess < mb)
+            pw::launch_random_block_f64(Z + (int64_t)nguess * ld, ld, npw, mb - nguess,
+                                        0x5EED0000ull + (uint64_t)b0, c->sp.kin, st);
+        // orthogonal to previous blocks, orthonormal (twice)
+        for (int pass = 0; pass < 2; ++pass) {
+            project_out(c, p, tm, X, ldx, b0, Z, ld, mb);
+            cholqr(c, p, tm, Z, ld, mb);
+        }
+        {
+            auto e = tm.begin();
+            apply_H(c, p, m, Z, ld, HZ, ld, mb);
+            tm.end(PhaseTimer::kApply, e);
+            stats.h_applies += mb;
+        }
+        // initial Rayleigh-Ritz on span(X)
+        {
+            auto e0 = tm.begin();
+            pw::launch_gemm_tn_f64(Z, ld, HZ, ld, npw, mb, mb, p.Agram, mb, nullptr, 0.0, p.part,
+                                   p.part_elems, st);
+            tm.end(PhaseTimer::kGemm, e0);
+            auto e1 = tm.begin();
+            pw::launch_heev_f64(p.Agram, mb, mb, mb, p.w, p.Cc, 3 * m, p.heev_scratch, c->d_status, st);
+            tm.end(PhaseTimer::kDense, e1);
+            auto e2 = tm.begin();
+            pw::launch_gemm_nn_f64(Z, ld, p.Cc, 3 * m, npw, mb, mb, 1.0, 0.0, p.Z[1 - cur], ld, st);
+            pw::launch_gemm_nn_f64(HZ, ld, p.Cc, 3 * m, npw, mb, mb, 1.0, 0.0, p.HZ[1 - cur], ld, st);
+            tm.end(PhaseTimer::kGemm, e2);
+            cur = 1 - cur;
+            Z = p.Z[cur];
+            HZ = p.HZ[cur];
+        }
+        bool havep = false, converged = false;
+        int it = 0;
+        for (it = 0; it < max_iter; ++it) {
+            // residuals and preconditioned directions (W written to slot 2 if P
+            // may be used, else slot 1)
+            const int wslot = havep ? 2 : 1;
+            cd *W = Z + (int64_t)wslot * mb * ld;
+            {
+                auto e = tm.begin();
+                pw::launch_band_dots_f64(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.rpart, p.theta, p.ekin, st);
+                pw::launch_resid_precond_f64(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.theta, p.ekin, W, ld,
+                                             p.rpart, p.res, st);
+                tm.end(PhaseTimer::kVec, e);
+            }
+            PW_HIP(hipMemcpyAsync(hres.data(), p.res, sizeof(double) * mb, hipMemcpyDeviceToHost, st));
+            const int status = read_status(c);
+            tm.collect();
+            if (status & 4) throw Error{PW_ERR_NUMERIC, "non-finite value in the iteration"};
+            bool pfail = (status & 1) != 0;
+            if (pfail) {
+                PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), st));
+                if (havep) {
+                    // P could not be orthonormalised: drop it, move W to slot 1
+                    pw::launch_copy_cols_f64(W, ld, Z + (int64_t)mb * ld, ld, npw, mb, st);
+                    havep = false;
+                    W = Z + (int64_t)mb * ld;
+                    ++stats.p_restarts;
+                }
+            }
+            bool done = true;
+            for (int j = 0; j < keep; ++j)
+                if (!(hres[j] <= tol)) done = false;
+            for (int j = 0; j < mb; ++j)
+                if (!std::isfinite(hres[j])) throw Error{PW_ERR_NUMERIC, "non-finite residual"};
+            if (done) {
+                converged = true;
+                break;
+            }
+            const int wcol = (havep ? 2 : 1) * mb;
+            // constraint to previous blocks, then orthogonal to [X P] (twice) and orthonormal
+            project_out(c, p, tm, X, ldx, b0, W, ld, mb);
+            for (int pass = 0; pass < 2; ++pass) {
+                project_out(c, p, tm, Z, ld, wcol, W, ld, mb);
+                cholqr(c, p, tm, W, ld, mb);
+            }
+            {
+                auto e = tm.begin();
+                apply_H(c, p, m, W, ld, HZ + (int64_t)wcol * ld, ld, mb);
+                tm.end(PhaseTimer::kApply, e);
+                stats.h_applies += mb;
+            }
+            const int nz = wcol + mb;
+            // Rayleigh-Ritz on span{X, P, W} (orthonormal basis)
+            {
+                auto e0 = tm.begin();
+                pw::launch_gemm_tn_f64(Z, ld, HZ, ld, npw, nz, nz, p.Agram, nz, nullptr, 0.0, p.part,
+                                       p.part_elems, st);
+                tm.end(PhaseTimer::kGemm, e0);
+                auto e1 = tm.begin();
+                pw::launch_heev_f64(p.Agram, nz, nz, mb, p.w, p.Cc, 3 * m, p.heev_scratch, c->d_status,
+                                    st);
+                tm.end(PhaseTimer::kDense, e1);
+            }
+            // P coefficients: C with the X rows removed, made orthogonal to C
+            // and orthonormal (all in coefficient space, the basis being orthonormal)
+            cd *Cp = p.Cc + (int64_t)mb * 3 * m;
+            {
+                auto e0 = tm.begin();
+                pw::launch_pcoef_f64(p.Cc, 3 * m, nz, mb, Cp, 3 * m, st);
+                for (int pass = 0; pass < 2; ++pass) {
+                    pw::launch_gemm_tn_f64(p.Cc, 3 * m, Cp, 3 * m, nz, mb, mb, p.T1, mb, nullptr, 0.0,
+                                           p.part, p.part_elems, st);
+                    pw::launch_gemm_nn_f64(p.Cc, 3 * m, p.T1, mb, nz, mb, mb, -1.0, 1.0, Cp, 3 * m, st);
+                    pw::launch_gemm_tn_f64(Cp, 3 * m, Cp, 3 * m, nz, mb, mb, p.Gs, mb, nullptr, 0.0,
+                                           p.part, p.part_elems, st);
+                    pw::launch_chol_inv_f64(p.Gs, mb, mb, p.Rinv, mb, c->d_status, st);
+                    pw::launch_gemm_nn_f64(Cp, 3 * m, p.Rinv, mb, nz, mb, mb, 1.0, 0.0, Cp, 3 * m, st);
+                }
+                tm.end(PhaseTimer::kDense, e0);
+            }
+            // [X P]_new = Z [C c_p], same for HZ
+            {
+                auto e = tm.begin();
+                pw::launch_gemm_nn_f64(Z, ld, p.Cc, 3 * m, npw, nz, 2 * mb, 1.0, 0.0, p.Z[1 - cur], ld, st);
+                pw::launch_gemm_nn_f64(HZ, ld, p.Cc, 3 * m, npw, nz, 2 * mb, 1.0, 0.0, p.HZ[1 - cur], ld,
+                                       st);
+                tm.end(PhaseTimer::kGemm, e);
+            }
+            cur = 1 - cur;
+            Z = p.Z[cur];
+            HZ = p.HZ[cur];
+            havep = true;
+        }
+        stats.iterations += it;
+        if (!converged) all_converged = false;
+        // store the converged columns of the block
+        pw::launch_copy_cols_f64(Z, ld, X + (int64_t)b0 * ldx, ldx, npw, keep, st);
+        pw::launch_copy_cols_f64(HZ, ld, p.HXall + (int64_t)b0 * ld, ld, npw, keep, st);
+        b0 += keep;
+    }
+
+    // final Rayleigh-Ritz over all M bands
+    auto ef = tm.begin();
+    pw::launch_gemm_tn_f64(X, ldx, p.HXall, ld, npw, M, M, p.Agram, M, nullptr, 0.0, p.part,
+                           p.part_elems, st);
+    pw::launch_heev_f64(p.Agram, M, M, M, p.w, p.U, M, p.heev_scratch, c->d_status, st);
+    pw::launch_gemm_nn_f64(X, ldx, p.U, M, npw, M, M, 1.0, 0.0, p.T, ld, st);
+    pw::launch_copy_cols_f64(p.T, ld, X, ldx, npw, M, st);
+    pw::launch_gemm_nn_f64(p.HXall, ld, p.U, M, npw, M, M, 1.0, 0.0, p.T, ld, st);
+    pw::launch_copy_cols_f64(p.T, ld, p.HXall, ld, npw, M, st);
+    pw::launch_band_dots_f64(X, ldx, p.HXall, ld, c->sp.kin, npw, M, p.rpart, p.theta, p.ekin, st);
+    pw::launch_resid_precond_f64(X, ldx, p.HXall, ld, c->sp.kin, npw, M, p.theta, p.ekin, nullptr, 0,
+                                 p.rpart, p.res, st);
+    tm.end(PhaseTimer::kFinal, ef);
+    PW_HIP(hipEventRecord(t_end, st));
+    c->res.assign(M, 0.0);
+    PW_HIP(hipMemcpyAsync(eig, p.theta, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+    PW_HIP(hipMemcpyAsync(c->res.data(), p.res, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+    const int status = read_status(c);
+    tm.collect();
+    float total = 0.f;
+    PW_HIP(hipEventElapsedTime(&total, t_begin, t_end));
+    (void)hipEventDestroy(t_begin);
+    (void)hipEventDestroy(t_end);
+    stats.ms_total = total;
+    stats.ms_apply = tm.ms[PhaseTimer::kApply];
+    stats.ms_gemm = tm.ms[PhaseTimer::kGemm];
+    stats.ms_dense = tm.ms[PhaseTimer::kDense];
+    stats.ms_vec = tm.ms[PhaseTimer::kVec];
+    stats.ms_final_rr = tm.ms[PhaseTimer::kFinal];
+    c->stats = stats;
+    if (status & 4) throw Error{PW_ERR_NUMERIC, "non-finite value in the final Rayleigh-Ritz"};
+    for (int j = 0; j < M; ++j) {
+        if (!std::isfinite(eig[j])) throw Error{PW_ERR_NUMERIC, "non-finite eigenvalue"};
+    }
+    bool res_ok = true;
+    for (int j = 0; j < M; ++j)
+        if (!(c->res[j] <= tol)) res_ok = false;
+    if (!all_converged || !res_ok) {
+        c->err = all_converged ? "a final residual exceeds tol after the final Rayleigh-Ritz"
+                               : "max_iter reached before every block converged";
+        return PW_ERR_NOT_CONVERGED;
+    }
+    return PW_OK;
+}
+
+// ---- basis setup -------------------------------------------------------------------
+void init_basis(pw_ctx_s *c, const double cell[9], const double kfrac[3], double ecut,
+                const int32_t fft_n[3], int64_t *npw_out) {
+    PW_REQUIRE(cell && kfrac && fft_n && npw_out, PW_ERR_ARG, "null argument");
+    PW_REQUIRE(ecut > 0 && std::isfinite(ecut), PW_ERR_ARG, "ecut must be positive");
+    PW_REQUIRE(fft_n[0] == fft_n[1] && fft_n[1] == fft_n[2], PW_ERR_ARG, "FFT grid must be cubic");
+    PW_REQUIRE(pw::fft_size_supported(fft_n[0]), PW_ERR_ARG, "unsupported FFT size");
+    // reset everything that depends on the basis
+    if (c->device >= 0)
+        for (void *p : c->dev_allocs) (void)hipFree(p);
+    c->dev_allocs.clear();
+    c->has_basis = c->has_v = false;
+    c->natom = c->nlm = 0;
+    c->d_B = nullptr;
+    c->d_D = nullptr;
+    c->d_v = nullptr;
+    c->d_qvec = nullptr;
+    c->ws = nullptr;
+    c->ws_bytes = 0;
+    c->plan_nbands = c->plan_block = 0;
+    c->d_status = nullptr;
+
+    std::memcpy(c->cell, cell, sizeof(c->cell));
+    std::memcpy(c->kfrac, kfrac, sizeof(c->kfrac));
+    c->ecut = ecut;
+    const int N = fft_n[0];
+    c->n = N;
+    // reciprocal rows b_i = 2 pi (cell^-1)^T rows
+    const double *a = cell;
+    const double det = a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                       a[2] * (a[3] * a[7] - a[4] * a[6]);
+    PW_REQUIRE(std::fabs(det) > 1e-12, PW_ERR_ARG, "singular cell");
+    double inv[9];
+    inv[0] = (a[4] * a[8] - a[5] * a[7]) / det;
+    inv[1] = (a[2] * a[7] - a[1] * a[8]) / det;
+    inv[2] = (a[1] * a[5] - a[2] * a[4]) / det;
+    inv[3] = (a[5] * a[6] - a[3] * a[8]) / det;
+    inv[4] = (a[0] * a[8] - a[2] * a[6]) / det;
+    inv[5] = (a[2] * a[3] - a[0] * a[5]) / det;
+    inv[6] = (a[3] * a[7] - a[4] * a[6]) / det;
+    inv[7] = (a[1] * a[6] - a[0] * a[7]) / det;
+    inv[8] = (a[0] * a[4] - a[1] * a[3]) / det;
+    double B[9];   // B[i][j] = 2 pi inv[j][i]
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) B[3 * i + j] = 2.0 * M_PI * inv[3 * j + i];
+    const double qmax = std::sqrt(2.0 * ecut);
+    int lim[3];
+    for (int i = 0; i < 3; ++i) {
+        const double an = std::sqrt(a[3 * i] * a[3 * i] + a[3 * i + 1] * a[3 * i + 1] +
+                                    a[3 * i + 2] * a[3 * i + 2]);
+        lim[i] = (int)std::ceil(an * qmax / (2.0 * M_PI) + std::fabs(kfrac[i])) + 1;
+    }
+    c->miller.clear();
+    c->kin.clear();
+    c->qvec.clear();
+    for (int nx = -lim[0]; nx <= lim[0]; ++nx)
+        for (int ny = -lim[1]; ny <= lim[1]; ++ny)
+            for (int nz = -lim[2]; nz <= lim[2]; ++nz) {
+                const double f[3] = {nx + kfrac[0], ny + kfrac[1], nz + kfrac[2]};
+                double q[3];
+                for (int j = 0; j < 3; ++j) q[j] = f[0] * B[j] + f[1] * B[3 + j] + f[2] * B[6 + j];
+                const double t = 0.5 * (q[0] * q[0] + q[1] * q[1] + q[2] * q[2]);
+                if (t <= ecut) {
+                    c->miller.insert(c->miller.end(), {nx, ny, nz});
+                    c->kin.push_back(t);
+                    c->qvec.insert(c->qvec.end(), {q[0], q[1], q[2]});
+                }
+            }
+    const int64_t npw = (int64_t)c->kin.size();
+    PW_REQUIRE(npw > 0, PW_ERR_ARG, "empty plane-wave sphere");
+    int mx[3] = {0, 0, 0};
+    int xmin = 1 << 30, xmax = -(1 << 30);
+    for (int64_t g = 0; g < npw; ++g) {
+        for (int j = 0; j < 3; ++j) mx[j] = std::max(mx[j], std::abs(c->miller[3 * g + j]));
+        xmin = std::min(xmin, c->miller[3 * g]);
+        xmax = std::max(xmax, c->miller[3 * g]);
+    }
+    for (int j = 0; j < 3; ++j)
+        PW_REQUIRE(N >= 2 * mx[j] + 1, PW_ERR_ARG, "FFT grid too small for the sphere (need n >= 2 nmax + 1)");
+    // sticks: runs of equal (n_x, n_y)
+    std::vector<int32_t> st_start, st_len, st_z0, st_y, st_xc, g_map(npw);
+    for (int64_t g = 0; g < npw; ++g) {
+        const int nx = c->miller[3 * g], ny = c->miller[3 * g + 1], nz = c->miller[3 * g + 2];
+        if (g == 0 || nx != c->miller[3 * (g - 1)] || ny != c->miller[3 * (g - 1) + 1]) {
+            st_start.push_back((int32_t)g);
+            st_len.push_back(0);
+            st_z0.push_back(nz);
+            st_y.push_back(((ny % N) + N) % N);
+            st_xc.push_back(nx - xmin);
+        }
+        const int s = (int)st_start.size() - 1;
+        ++st_len[s];
+        g_map[g] = s * N + ((nz % N) + N) % N;
+    }
+    const int nst = (int)st_start.size();
+    c->npw = npw;
+    c->nst_host = nst;
+    c->ncx_host = xmax - xmin + 1;
+    if (c->device < 0) {   // host-only context: tables stay on the host
+        c->has_basis = true;
+        *npw_out = npw;
+        return;
+    }
+    c->d_status = c->dev_alloc<int>(1);
+    PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
+    c->ldp = (int64_t)align_up((size_t)npw, 32);
+    pw::SphereDev &sp = c->sp;
+    sp.npw = npw;
+    sp.n = N;
+    sp.nst = nst;
+    sp.ldst = (int32_t)align_up((size_t)nst, 16);
+    sp.ncx = xmax - xmin + 1;
+    sp.xmin = xmin;
+    auto up_i = [&](const std::vector<int32_t> &v) {
+        int32_t *d = c->dev_alloc<int32_t>(v.size());
+        PW_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+        return d;
+    };
+    sp.st_start = up_i(st_start);
+    sp.st_len = up_i(st_len);
+    sp.st_z0 = up_i(st_z0);
+    sp.st_y = up_i(st_y);
+    sp.st_xc = up_i(st_xc);
+    sp.g_map = up_i(g_map);
+    sp.kin = c->dev_alloc<double>(npw);
+    PW_HIP(hipMemcpy(sp.kin, c->kin.data(), npw * sizeof(double), hipMemcpyHostToDevice));
+    std::vector<double> tw(2 * N);
+    for (int j = 0; j < N; ++j) {
+        const long double ang = 2.0L * 3.141592653589793238462643383279502884L * j / N;
+        tw[2 * j] = (double)std::cos(ang);
+        tw[2 * j + 1] = (double)std::sin(ang);
+    }
+    sp.twid = c->dev_alloc<double>(2 * N);
+    PW_HIP(hipMemcpy(sp.twid, tw.data(), 2 * N * sizeof(double), hipMemcpyHostToDevice));
+    c->d_qvec = c->dev_alloc<double>(3 * npw);
+    PW_HIP(hipMemcpy(c->d_qvec, c->qvec.data(), 3 * npw * sizeof(double), hipMemcpyHostToDevice));
+    c->has_basis = true;
+    *npw_out = npw;
+}
+
+void set_potential(pw_ctx_s *c, const double *v, int on_device) {
+    require_basis(c);
+    require_device(c);
+    PW_REQUIRE(v != nullptr, PW_ERR_ARG, "null potential");
+    const int N = c->n;
+    const size_t tot = (size_t)N * N * N;
+    double *src = nullptr;
+    double *tmp = c->dev_alloc<double>(tot);
+    if (on_device) {
+        src = const_cast<double *>(v);
+    } else {
+        PW_HIP(hipMemcpyAsync(tmp, v, tot * sizeof(double), hipMemcpyHostToDevice, c->stream));
+        src = tmp;
+    }
+    if (!c->d_v) c->d_v = c->dev_alloc<double>(tot);
+    PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
+    pw::launch_permute_potential(src, N, 1.0 / (double(N) * N * N), c->d_v, c->d_status, c->stream);
+    const int s = read_status(c);
+    c->dev_free(tmp);
+    PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
+    PW_REQUIRE(!(s & 1), PW_ERR_NUMERIC, "potential contains NaN or Inf");
+    c->has_v = true;
+}
+
+void set_projectors(pw_ctx_s *c, int natom, const double *pos, int nlm, const int32_t *lm,
+                    const double *D) {
+    require_basis(c);
+    require_device(c);
+    PW_REQUIRE(natom >= 0 && nlm >= 0, PW_ERR_ARG, "negative projector count");
+    c->dev_free(c->d_B);
+    c->dev_free(c->d_D);
+    c->d_B = nullptr;
+    c->d_D = nullptr;
+    c->natom = c->nlm = 0;
+    if (natom == 0 || nlm == 0) return;
+    PW_REQUIRE(pos && lm && D, PW_ERR_ARG, "null projector argument");
+    for (int p = 0; p < nlm; ++p) {
+        const int l = lm[2 * p], m = lm[2 * p + 1];
+        PW_REQUIRE((l == 0 && m == 0) || (l == 1 && m >= -1 && m <= 1), PW_ERR_ARG,
+                   "projectors support l = 0, 1 only");
+    }
+    for (int i = 0; i < natom * nlm; ++i) PW_REQUIRE(std::isfinite(D[i]), PW_ERR_NUMERIC, "non-finite D");
+    const int np = natom * nlm;
+    double *d_pos = c->dev_alloc<double>(3 * natom);
+    int *d_lm = c->dev_alloc<int>(2 * nlm);
+    PW_HIP(hipMemcpy(d_pos, pos, 3 * natom * sizeof(double), hipMemcpyHostToDevice));
+    PW_HIP(hipMemcpy(d_lm, lm, 2 * nlm * sizeof(int), hipMemcpyHostToDevice));
+    c->d_B = c->dev_alloc<cd>((size_t)c->ldp * np);
+    c->d_D = c->dev_alloc<double>(np);
+    PW_HIP(hipMemcpy(c->d_D, D, np * sizeof(double), hipMemcpyHostToDevice));
+    const double *a = c->cell;
+    const double omega = std::fabs(a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
+                                   a[2] * (a[3] * a[7] - a[4] * a[6]));
+    const double pref = std::sqrt(32.0 * std::pow(M_PI, 2.5)) / std::sqrt(omega);
+    pw::launch_zero_f64(c->d_B, c->ldp, c->ldp, np, c->stream);
+    pw::launch_build_projectors_f64(c->d_qvec, c->npw, natom, d_pos, nlm, lm ? d_lm : nullptr, pref,
+                                    c->d_B, c->ldp, c->stream);
+    PW_HIP(hipStreamSynchronize(c->stream));
+    c->dev_free(d_pos);
+    c->dev_free(d_lm);
+    c->natom = natom;
+    c->nlm = nlm;
+}
+
+template <class F>
+pw_status guard(pw_ctx c, F &&f) {
+    if (!c) return PW_ERR_ARG;
+    try {
+        c->err.clear();
+        return f();
+    } catch (const Error &e) {
+        c->err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc &) {
+        c->err = "host allocation failed";
+        return PW_ERR_NOMEM;
+    } catch (...) {
+        c->err = "unexpected exception";
+        return PW_ERR_DEVICE;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+pw_status pw_create(int device, void *hip_stream, pw_ctx *out) {
+    if (!out) return PW_ERR_ARG;
+    *out = nullptr;
+    if (device >= 0) {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || device >= ndev) return PW_ERR_DEVICE;
+        if (hipSetDevice(device) != hipSuccess) return PW_ERR_DEVICE;
+    }
+    pw_ctx c = new (std::nothrow) pw_ctx_s;
+    if (!c) return PW_ERR_NOMEM;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    *out = c;
+    return PW_OK;
+}
+
+void pw_destroy(pw_ctx c) {
+    if (!c) return;
+    if (c->device >= 0) {
+        (void)hipSetDevice(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        for (void *p : c->dev_allocs) (void)hipFree(p);
+    }
+    delete c;
+}
+
+const char *pw_last_error(pw_ctx c) { return c ? c->err.c_str() : "null context"; }
+
+pw_status pw_fft_sizes(int32_t *sizes, int32_t cap, int32_t *count) {
+    if (!count) return PW_ERR_ARG;
+    const std::vector<int> v = pw::fft_supported_sizes();
+    *count = (int32_t)v.size();
+    for (int i = 0; i < (int)v.size() && i < cap && sizes; ++i) sizes[i] = v[i];
+    return PW_OK;
+}
+
+pw_status pw_init_basis(pw_ctx c, const double cell[9], const double kfrac[3], double ecut,
+                        const int32_t fft_n[3], int64_t *npw) {
+    return guard(c, [&] {
+        if (c->device >= 0) PW_HIP(hipSetDevice(c->device));
+        init_basis(c, cell, kfrac, ecut, fft_n, npw);
+        return PW_OK;
+    });
+}
+
+pw_status pw_get_miller(pw_ctx c, int32_t *miller) {
+    return guard(c, [&] {
+        require_basis(c);
+        PW_REQUIRE(miller, PW_ERR_ARG, "null output");
+        std::memcpy(miller, c->miller.data(), c->miller.size() * sizeof(int32_t));
+        return PW_OK;
+    });
+}
+
+pw_status pw_get_kinetic(pw_ctx c, double *kin) {
+    return guard(c, [&] {
+        require_basis(c);
+        PW_REQUIRE(kin, PW_ERR_ARG, "null output");
+        std::memcpy(kin, c->kin.data(), c->kin.size() * sizeof(double));
+        return PW_OK;
+    });
+}
+
+pw_status pw_set_local_potential(pw_ctx c, const double *v, int on_device) {
+    return guard(c, [&] {
+        if (c->device >= 0) PW_HIP(hipSetDevice(c->device));
+        set_potential(c, v, on_device);
+        return PW_OK;
+    });
+}
+
+pw_status pw_set_projectors(pw_ctx c, int32_t natom, const double *pos, int32_t nproj_per_atom,
+                            const int32_t *lm, const double *D) {
+    return guard(c, [&] {
+        if (c->device >= 0) PW_HIP(hipSetDevice(c->device));
+        set_projectors(c, natom, pos, nproj_per_atom, lm, D);
+        return PW_OK;
+    });
+}
+
+pw_status pw_workspace_size(pw_ctx c, int32_t nbands, int32_t block, pw_precision prec, size_t *bytes) {
+    return guard(c, [&] {
+        require_basis(c);
+        PW_REQUIRE(bytes, PW_ERR_ARG, "null output");
+        PW_REQUIRE(prec == PW_PREC_FP64, PW_ERR_ARG, "only PW_PREC_FP64 is implemented");
+        PW_REQUIRE(nbands >= 1 && block >= 1 && block <= 64, PW_ERR_ARG, "need nbands >= 1 and 1 <= block <= 64");
+        PW_REQUIRE(nbands <= 1024 && nbands <= c->npw, PW_ERR_ARG, "nbands must be <= min(npw, 1024)");
+        const int m = std::min(block, nbands);
+        c->plan_nbands = nbands;
+        c->plan_block = m;
+        *bytes = make_plan(*c, nbands, m, nullptr).bytes;
+        return PW_OK;
+    });
+}
+
+pw_status pw_set_workspace(pw_ctx c, void *dptr, size_t bytes) {
+    return guard(c, [&] {
+        require_basis(c);
+        PW_REQUIRE(dptr, PW_ERR_ARG, "null workspace");
+        PW_REQUIRE(((uintptr_t)dptr & 255) == 0, PW_ERR_ARG, "workspace must be 256-byte aligned");
+        if (c->plan_nbands > 0) {
+            const size_t need = make_plan(*c, c->plan_nbands, c->plan_block, nullptr).bytes;
+            PW_REQUIRE(bytes >= need, PW_ERR_NOMEM, "workspace smaller than pw_workspace_size");
+        }
+        c->ws = static_cast<char *>(dptr);
+        c->ws_bytes = bytes;
+        return PW_OK;
+    });
+}
+
+pw_status pw_apply_H(pw_ctx c, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nb,
+                     pw_precision prec) {
+    return guard(c, [&] {
+        PW_REQUIRE(prec == PW_PREC_FP64, PW_ERR_ARG, "only PW_PREC_FP64 is implemented");
+        require_basis(c);
+        PW_REQUIRE(X && Y, PW_ERR_ARG, "null block");
+        PW_REQUIRE(nb >= 0, PW_ERR_ARG, "negative column count");
+        PW_REQUIRE(ldx >= c->npw && ldy >= c->npw, PW_ERR_ARG, "leading dimension < npw");
+        if (nb == 0) return PW_OK;
+        const int chunk = c->plan_block > 0 ? c->plan_block : 1;
+        Plan p = ready_plan(c, std::max(c->plan_nbands, 1), chunk);
+        apply_H(c, p, chunk, static_cast<const cd *>(X), ldx, static_cast<cd *>(Y), ldy, nb);
+        return PW_OK;
+    });
+}
+
+pw_status pw_lobpcg_solve(pw_ctx c, int32_t nbands, int32_t block, double tol, int32_t max_iter,
+                          pw_precision prec, void *X, int64_t ldx, int32_t use_guess, double *eig) {
+    return guard(c, [&] {
+        PW_REQUIRE(prec == PW_PREC_FP64, PW_ERR_ARG, "only PW_PREC_FP64 is implemented");
+        require_basis(c);
+        PW_REQUIRE(X && eig, PW_ERR_ARG, "null argument");
+        PW_REQUIRE(nbands >= 1 && block >= 1 && block <= 64, PW_ERR_ARG, "need nbands >= 1, 1 <= block <= 64");
+        PW_REQUIRE(nbands <= 1024 && nbands <= c->npw, PW_ERR_ARG, "nbands must be <= min(npw, 1024)");
+        PW_REQUIRE(3 * std::min(block, nbands) <= c->npw, PW_ERR_ARG, "3 * block must not exceed npw");
+        PW_REQUIRE(ldx >= c->npw, PW_ERR_ARG, "ldx < npw");
+        PW_REQUIRE(tol > 0 && max_iter >= 1, PW_ERR_ARG, "need tol > 0 and max_iter >= 1");
+        const int m = std::min(block, nbands);
+        PW_REQUIRE(c->plan_nbands >= nbands && c->plan_block == m, PW_ERR_STATE,
+                   "call pw_workspace_size with this (nbands, block) before the solve");
+        require_device(c);
+        PW_HIP(hipSetDevice(c->device));
+        return lobpcg(c, nbands, m, tol, max_iter, static_cast<cd *>(X), ldx, use_guess, eig);
+    });
+}
+
+pw_status pw_get_residuals(pw_ctx c, double *res) {
+    return guard(c, [&] {
+        PW_REQUIRE(res, PW_ERR_ARG, "null output");
+        PW_REQUIRE(!c->res.empty(), PW_ERR_STATE, "no solve has run");
+        std::memcpy(res, c->res.data(), c->res.size() * sizeof(double));
+        return PW_OK;
+    });
+}
+
+pw_status pw_get_stats(pw_ctx c, pw_stats *stats) {
+    return guard(c, [&] {
+        PW_REQUIRE(stats, PW_ERR_ARG, "null output");
+        *stats = c->stats;
+        return PW_OK;
+    });
+}
+
+pw_status pw_gram(pw_ctx c, const void *A, int64_t lda, const void *B, int64_t ldb, int64_t K,
+                  int32_t p, int32_t q, void *C, int64_t ldc) {
+    return guard(c, [&] {
+        require_device(c);
+        PW_REQUIRE(A && B && C, PW_ERR_ARG, "null argument");
+        PW_REQUIRE(K >= 0 && p >= 0 && q >= 0 && lda >= K && ldb >= K && ldc >= p, PW_ERR_ARG,
+                   "bad GEMM shape");
+        PW_REQUIRE(c->ws != nullptr, PW_ERR_STATE, "pw_set_workspace has not been called");
+        if (p == 0 || q == 0) return PW_OK;
+        const size_t need = pw::gemm_tn_part_elems(K, p, q, nullptr) * sizeof(cd);
+        PW_REQUIRE(need <= c->ws_bytes, PW_ERR_NOMEM, "workspace too small for this Gram");
+        if (K == 0) {
+            pw::launch_zero_f64(static_cast<cd *>(C), ldc, p, q, c->stream);
+            return PW_OK;
+        }
+        pw::launch_gemm_tn_f64(static_cast<const cd *>(A), lda, static_cast<const cd *>(B), ldb, K, p,
+                               q, static_cast<cd *>(C), ldc, nullptr, 0.0,
+                               reinterpret_cast<cd *>(c->ws), c->ws_bytes / sizeof(cd), c->stream);
+        return PW_OK;
+    });
+}
+
+pw_status pw_block_update(pw_ctx c, const void *A, int64_t lda, const void *C, int64_t ldc,
+                          int64_t K, int32_t p, int32_t q, double alpha, double beta, void *Y,
+                          int64_t ldy) {
+    return guard(c, [&] {
+        require_device(c);
+        PW_REQUIRE(A && C && Y, PW_ERR_ARG, "null argument");
+        PW_REQUIRE(K >= 0 && p >= 0 && q >= 0 && lda >= K && ldy >= K && ldc >= p, PW_ERR_ARG,
+                   "bad GEMM shape");
+        pw::launch_gemm_nn_f64(static_cast<const cd *>(A), lda, static_cast<const cd *>(C), ldc, K, p,
+                               q, alpha, beta, static_cast<cd *>(Y), ldy, c->stream);
+        return PW_OK;
+    });
+}
+
+pw_status pw_small_eigh(pw_ctx c, void *A, int64_t lda, int32_t n, int32_t k, void *w, void *V,
+                        int64_t ldv) {
+    return guard(c, [&] {
+        require_device(c);
+        PW_REQUIRE(A && w && V, PW_ERR_ARG, "null argument");
+        PW_REQUIRE(n >= 1 && n <= 1024 && k >= 1 && k <= n && lda >= n && ldv >= n, PW_ERR_ARG,
+                   "need 1 <= k <= n <= 1024");
+        PW_REQUIRE(c->ws != nullptr, PW_ERR_STATE, "pw_set_workspace has not been called");
+        PW_REQUIRE(c->d_status, PW_ERR_STATE, "pw_init_basis has not been called");
+        PW_REQUIRE(pw::heev_scratch_bytes(n, k) <= c->ws_bytes, PW_ERR_NOMEM, "workspace too small");
+        PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
+        pw::launch_heev_f64(static_cast<cd *>(A), lda, n, k, static_cast<double *>(w),
+                            static_cast<cd *>(V), ldv, c->ws, c->d_status, c->stream);
+        const int s = read_status(c);
+        PW_REQUIRE(!(s & 4), PW_ERR_NUMERIC, "non-finite eigenvalue");
+        return PW_OK;
+    });
+}
+
+pw_status pw_residuals(pw_ctx c, const void *X, int64_t ldx, const void *HX, int64_t ldhx,
+                       int32_t nb, void *theta, void *res, void *W, int64_t ldw) {
+    return guard(c, [&] {
+        require_device(c);
+        require_basis(c);
+        PW_REQUIRE(X && HX && theta && res, PW_ERR_ARG, "null argument");
+        PW_REQUIRE(nb >= 1 && ldx >= c->npw && ldhx >= c->npw && (!W || ldw >= c->npw), PW_ERR_ARG,
+                   "bad shape");
+        PW_REQUIRE(c->ws != nullptr, PW_ERR_STATE, "pw_set_workspace has not been called");
+        const size_t need = (pw::resid_part_elems(c->npw, nb) + 2 * (size_t)nb) * sizeof(double) + 512;
+        PW_REQUIRE(need <= c->ws_bytes, PW_ERR_NOMEM, "workspace too small");
+        double *part = reinterpret_cast<double *>(c->ws);
+        double *ekin = part + align_up(pw::resid_part_elems(c->npw, nb), 32);
+        pw::launch_band_dots_f64(static_cast<const cd *>(X), ldx, static_cast<const cd *>(HX), ldhx,
+                                 c->sp.kin, c->npw, nb, part, static_cast<double *>(theta), ekin,
+                                 c->stream);
+        pw::launch_resid_precond_f64(static_cast<const cd *>(X), ldx, static_cast<const cd *>(HX), ldhx,
+                                     c->sp.kin, c->npw, nb, static_cast<const double *>(theta), ekin,
+                                     static_cast<cd *>(W), ldw, part, static_cast<double *>(res),
+                                     c->stream);
+        return PW_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,96 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared entry
+point, and its host logic (sphere enumeration, sticks, argument and state
+checks) behaves as the header says.  No kernel is launched."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from conftest import ROOT
+from oracle import pw
+from workloads import make_workload
+
+
+def _header_functions():
+    text = open(os.path.join(ROOT, "include", "pwlobpcg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pw_[a-zA-Z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_0707_3405_amd as pk
+    lib = pk.load_library()
+    declared = _header_functions()
+    assert len(declared) >= 19
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert set(declared) == set(pk.EXPORTS)
+
+
+def test_library_is_gfx950_code_object():
+    import paper_0707_3405_amd as pk
+    blob = open(pk.library_path(), "rb").read()
+    assert b"gfx950" in blob
+
+
+def test_package_fails_loudly_without_library(tmp_path, monkeypatch):
+    import paper_0707_3405_amd._binding as b
+    monkeypatch.setattr(b, "_LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(b, "_lib", None)
+    with pytest.raises(ImportError):
+        b.load_library()
+
+
+def test_fft_sizes_cover_workloads():
+    import paper_0707_3405_amd as pk
+    sizes = pk.fft_sizes()
+    for name in ("gamma_l10", "fcc108_l20", "tiny_nl", "mid_nl", "fcc32_l12"):
+        assert make_workload(name).n in sizes
+
+
+@pytest.mark.parametrize("name", ["gamma_l10", "tiny_nl", "mid_nl", "fcc32_l12", "fcc108_l20"])
+def test_host_sphere_matches_oracle(name):
+    from paper_0707_3405_amd import Context
+    w = make_workload(name)
+    c = Context(-1)
+    npw = c.init_basis(w.cell, w.kfrac, w.ecut, (w.n,) * 3)
+    mil = pw.sphere(w.cell, w.kfrac, w.ecut)
+    assert npw == mil.shape[0]
+    assert (c.get_miller() == mil).all()
+    assert np.abs(c.get_kinetic() - pw.kinetic(w.cell, w.kfrac, mil)).max() <= 1e-13
+
+
+def test_host_sphere_general_cell():
+    """A non-cubic (but cubic-grid) cell: sphere set equals the oracle's."""
+    from paper_0707_3405_amd import Context
+    cell = np.array([[7.0, 0.0, 0.0], [1.5, 8.0, 0.0], [0.3, -0.7, 9.0]])
+    c = Context(-1)
+    c.init_basis(cell, (0.2, -0.1, 0.05), 6.0, (40, 40, 40))
+    mil = pw.sphere(cell, (0.2, -0.1, 0.05), 6.0)
+    assert (c.get_miller() == mil).all()
+
+
+def test_argument_and_state_errors():
+    from paper_0707_3405_amd import Context, PWError, PW_ERR_ARG, PW_ERR_STATE
+    w = make_workload("gamma_l10")
+    c = Context(-1)
+    with pytest.raises(PWError) as e:
+        c.get_miller()
+    assert e.value.status == PW_ERR_STATE
+    for bad_n in [(24, 24, 25), (25, 25, 25), (8, 8, 8)]:
+        with pytest.raises(PWError) as e:
+            c.init_basis(w.cell, w.kfrac, w.ecut, bad_n)
+        assert e.value.status == PW_ERR_ARG
+    with pytest.raises(PWError) as e:
+        c.init_basis(w.cell, w.kfrac, -1.0, (24, 24, 24))
+    assert e.value.status == PW_ERR_ARG
+    c.init_basis(w.cell, w.kfrac, w.ecut, (24, 24, 24))
+    # kernels are refused on a host-only context
+    with pytest.raises(PWError) as e:
+        c.set_local_potential(w.vgrid)
+    assert e.value.status == PW_ERR_STATE
+    with pytest.raises(PWError) as e:
+        c.workspace_size(16, 128)
+    assert e.value.status == PW_ERR_ARG
+    assert c.workspace_size(16, 16) > 0
