@@ -7,14 +7,13 @@
 //    Rayleigh-Ritz over all bands (sec. 3.2, sec. 4.2).  Householder
 //    reduction to real tridiagonal form, bisection with Sturm counts,
 //    inverse iteration, classical Gram-Schmidt applied twice, back-transform.
+#include <algorithm>
 #include <cfloat>
 
 #include "pw_internal.h"
 
 namespace pw {
 namespace {
-
-constexpr int kDenseThreads = 512;
 
 __device__ __forceinline__ cd cconj(cd a) { return {a.x, -a.y}; }
 __device__ __forceinline__ cd cmulz(cd a, cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
@@ -82,22 +81,25 @@ __global__ void __launch_bounds__(256) k_chol_inv(const cd *__restrict__ G, int6
         }
         __syncthreads();
     }
-    // R^-1 column by column: X_cc = 1/R_cc, X_ic = -(sum_{k=i+1..c} R_ik X_kc) / R_ii
-    for (int c = t; c < n; c += blockDim.x) {
-        for (int i = 0; i < n; ++i) Xs[i][c] = cd{0.0, 0.0};
-        Xs[c][c] = cd{1.0 / Rs[c][c].x, 0.0};
-        for (int i = c - 1; i >= 0; --i) {
-            double sr = 0.0, si = 0.0;
-            for (int k = i + 1; k <= c; ++k) {
-                const cd pr = cmulz(Rs[i][k], Xs[k][c]);
-                sr += pr.x;
-                si += pr.y;
+    // R^-1 by rows from the bottom, columns in parallel:
+    // X_ic = (delta_ic - sum_{k=i+1..c} R_ik X_kc) / R_ii
+    for (int i = n - 1; i >= 0; --i) {
+        for (int c = t; c < n; c += blockDim.x) {
+            if (c < i) {
+                Xs[i][c] = cd{0.0, 0.0};
+                continue;
+            }
+            double sr = (c == i) ? 1.0 : 0.0, si = 0.0;
+            for (int kk = i + 1; kk <= c; ++kk) {
+                const cd pr = cmulz(Rs[i][kk], Xs[kk][c]);
+                sr -= pr.x;
+                si -= pr.y;
             }
             const double inv = 1.0 / Rs[i][i].x;
-            Xs[i][c] = cd{-sr * inv, -si * inv};
+            Xs[i][c] = cd{sr * inv, si * inv};
         }
+        __syncthreads();
     }
-    __syncthreads();
     for (int i = t; i < n * n; i += blockDim.x) {
         const int r = i % n, c = i / n;
         Rinv[(int64_t)c * ldr + r] = Xs[r][c];
@@ -106,13 +108,145 @@ __global__ void __launch_bounds__(256) k_chol_inv(const cd *__restrict__ G, int6
 }
 
 // ---- Hermitian eigensolver ---------------------------------------------------
-struct HeevScratch {
-    cd *tau;        // [n]
-    double *d;      // [n]
-    double *e;      // [n]
-    double *Z;      // [n][k] tridiagonal eigenvectors, row i at Z + i*k
-    double *lu;     // [5][n][k] per-eigenvalue LU factors, interleaved by eigenvalue
-};
+// Five kernels on the stream:
+//   k_hetrd  (1 workgroup)   A = Q T Q^H, T real tridiagonal (lower Householder)
+//   k_stebz  (k/64 groups)   lowest k eigenvalues of T by 16-way multisection
+//   k_stein  (k/E groups)    eigenvectors of T by inverse iteration, LU in LDS
+//   k_orth   (1 workgroup)   Gram-Schmidt (twice) in eigenvalue order
+//   k_unmtr  (k/cw groups)   back-transform V = Q Z
+constexpr int kTrdThreads = 1024;
+
+// One fused pass per column j: the pending rank-2 update of step j-1 is
+// applied while y = A_trail v_j is accumulated, so the trailing lower
+// triangle is read and written once per step.  Row sums are kept per wave in
+// LDS and added in wave order (deterministic).
+template <int P>
+__global__ void __launch_bounds__(kTrdThreads)
+    k_hetrd(cd *__restrict__ A, int64_t lda, int n, double *__restrict__ dd,
+            double *__restrict__ ee, cd *__restrict__ tau_out) {
+    extern __shared__ unsigned char smem_raw[];
+    cd *vp = reinterpret_cast<cd *>(smem_raw);   // [n] previous v (absolute rows)
+    cd *wp = vp + n;                              // [n] previous w
+    cd *v = wp + n;                               // [n] current v
+    cd *y = v + n;                                // [n] A v
+    cd *ycol = y + n;                             // [n] column (transposed) sums
+    cd *ywave = ycol + n;                         // [P][n] per-wave row sums
+    double *red = reinterpret_cast<double *>(ywave + (size_t)P * n);   // [blockDim]
+    __shared__ cd s_tau, s_scale;
+    __shared__ double s_beta;
+    const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wave = t >> 6;
+    auto col = [&](int c) { return A + (int64_t)c * lda; };
+
+    for (int i = t; i < n; i += nt) vp[i] = wp[i] = cd{0.0, 0.0};
+    __syncthreads();
+    for (int j = 0; j < n; ++j) {
+        // pending update of the pivot column j (rows j..n-1)
+        {
+            const cd vj = vp[j], wj = wp[j];
+            cd *cj = col(j);
+            for (int i = j + t; i < n; i += nt) {
+                const cd u1 = cmulz(wp[i], cconj(vj)), u2 = cmulz(vp[i], cconj(wj));
+                cj[i].x -= u1.x + u2.x;
+                cj[i].y -= u1.y + u2.y;
+            }
+        }
+        __syncthreads();
+        if (t == 0) dd[j] = col(j)[j].x;
+        if (j == n - 1) break;
+        double part = 0.0;
+        for (int i = j + 2 + t; i < n; i += nt) {
+            const cd x = col(j)[i];
+            part += x.x * x.x + x.y * x.y;
+        }
+        const double sigma = block_sum(part, red);
+        if (t == 0) {
+            const cd alpha = col(j)[j + 1];
+            if (sigma == 0.0 && alpha.y == 0.0) {
+                s_tau = cd{0.0, 0.0};
+                s_beta = alpha.x;
+                s_scale = cd{0.0, 0.0};
+            } else {
+                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
+                const double beta = alpha.x >= 0.0 ? -nrm : nrm;
+                s_tau = cd{(beta - alpha.x) / beta, -alpha.y / beta};
+                const double dr = alpha.x - beta, di = alpha.y;
+                const double den = dr * dr + di * di;
+                s_scale = cd{dr / den, -di / den};
+                s_beta = beta;
+            }
+        }
+        __syncthreads();
+        const cd tau = s_tau, scale = s_scale;
+        const bool reflect = !(tau.x == 0.0 && tau.y == 0.0);
+        for (int i = j + 1 + t; i < n; i += nt) {
+            if (!reflect) {
+                v[i] = cd{0.0, 0.0};
+            } else if (i == j + 1) {
+                v[i] = cd{1.0, 0.0};
+            } else {
+                const cd vv = cmulz(col(j)[i], scale);
+                v[i] = vv;
+                col(j)[i] = vv;
+            }
+        }
+        for (int i = t; i < P * n; i += nt) ywave[i] = cd{0.0, 0.0};
+        for (int i = t; i < n; i += nt) ycol[i] = cd{0.0, 0.0};
+        if (t == 0) {
+            tau_out[j] = tau;
+            ee[j] = s_beta;
+            col(j)[j + 1] = cd{s_beta, 0.0};
+        }
+        __syncthreads();
+        if (wave < P) {
+            for (int c = j + 1 + wave; c < n; c += P) {
+                const cd vc = v[c], vpc = vp[c], wpc = wp[c];
+                cd *cc = col(c);
+                double cr = 0.0, ci = 0.0;
+                for (int i = c + lane; i < n; i += 64) {
+                    cd a = cc[i];
+                    const cd u1 = cmulz(wp[i], cconj(vpc)), u2 = cmulz(vp[i], cconj(wpc));
+                    a.x -= u1.x + u2.x;
+                    a.y -= u1.y + u2.y;
+                    cc[i] = a;
+                    const cd r = cmulz(a, vc);
+                    cd &yw = ywave[wave * n + i];
+                    yw.x += r.x;
+                    yw.y += r.y;
+                    if (i > c) {
+                        const cd vi = v[i];   // conj(a) v_i
+                        cr += a.x * vi.x + a.y * vi.y;
+                        ci += a.x * vi.y - a.y * vi.x;
+                    }
+                }
+                for (int off = 32; off > 0; off >>= 1) {
+                    cr += __shfl_xor(cr, off);
+                    ci += __shfl_xor(ci, off);
+                }
+                if (lane == 0) ycol[c] = cd{cr, ci};
+            }
+        }
+        __syncthreads();
+        for (int i = j + 1 + t; i < n; i += nt) {
+            double sr = ycol[i].x, si = ycol[i].y;
+            for (int q = 0; q < P; ++q) {
+                sr += ywave[q * n + i].x;
+                si += ywave[q * n + i].y;
+            }
+            y[i] = cd{sr, si};
+        }
+        __syncthreads();
+        double pv = 0.0;
+        for (int i = j + 1 + t; i < n; i += nt) pv += v[i].x * y[i].x + v[i].y * y[i].y;
+        const double vhy = block_sum(pv, red);
+        const double nu = 0.5 * (tau.x * tau.x + tau.y * tau.y) * vhy;
+        for (int i = j + 1 + t; i < n; i += nt) {
+            const cd ty = cmulz(tau, y[i]);
+            wp[i] = reflect ? cd{ty.x - nu * v[i].x, ty.y - nu * v[i].y} : cd{0.0, 0.0};
+            vp[i] = v[i];
+        }
+        __syncthreads();
+    }
+}
 
 __device__ int sturm_count(const double *d, const double *e2, int n, double x, double pivmin) {
     int cnt = 0;
@@ -127,323 +261,271 @@ __device__ int sturm_count(const double *d, const double *e2, int n, double x, d
     return cnt;
 }
 
-__global__ void __launch_bounds__(kDenseThreads)
-    k_heev(cd *__restrict__ A, int64_t lda, int n, int k, double *__restrict__ w,
-           cd *__restrict__ V, int64_t ldv, HeevScratch sc, int *status) {
-    extern __shared__ unsigned char smem_raw[];
-    cd *vs = reinterpret_cast<cd *>(smem_raw);   // [n]
-    cd *ys = vs + n;                              // [n]
-    cd *ws = ys + n;                              // [n]
-    cd *ps = ws + n;                              // [blockDim] matvec partials
-    double *red = reinterpret_cast<double *>(ps + blockDim.x);   // [blockDim]
-    double *ds = red + blockDim.x;                // [n]
-    double *e2 = ds + n;                          // [n]
-    __shared__ cd tau_s;
-    __shared__ double beta_s;
+struct TriBounds {
+    double gl, gu, pivmin, tnorm;
+};
 
-    const int t = threadIdx.x, nt = blockDim.x;
-    auto Aat = [&](int r, int c) -> cd & { return A[(int64_t)c * lda + r]; };
-
-    // ---- 1. Householder reduction to real tridiagonal (lower) ----
-    for (int j = 0; j + 1 < n; ++j) {
-        const int L = n - j - 1;
-        // norm of x[1:] where x = A[j+1:, j]
-        double part = 0.0;
-        for (int i = 1 + t; i < L; i += nt) {
-            const cd x = Aat(j + 1 + i, j);
-            part += x.x * x.x + x.y * x.y;
-        }
-        const double sigma = block_sum(part, red);
-        if (t == 0) {
-            const cd alpha = Aat(j + 1, j);
-            if (sigma == 0.0 && alpha.y == 0.0) {
-                tau_s = cd{0.0, 0.0};
-                beta_s = alpha.x;
-            } else {
-                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
-                const double beta = alpha.x >= 0.0 ? -nrm : nrm;
-                tau_s = cd{(beta - alpha.x) / beta, -alpha.y / beta};
-                // scale = 1 / (alpha - beta)
-                const double dr = alpha.x - beta, di = alpha.y;
-                const double den = dr * dr + di * di;
-                ys[0] = cd{dr / den, -di / den};
-                beta_s = beta;
-            }
-        }
-        __syncthreads();
-        const cd tau = tau_s;
-        const bool reflect = !(tau.x == 0.0 && tau.y == 0.0);
-        if (reflect) {
-            const cd scale = ys[0];
-            for (int i = t; i < L; i += nt) {
-                if (i == 0) {
-                    vs[0] = cd{1.0, 0.0};
-                } else {
-                    const cd x = Aat(j + 1 + i, j);
-                    const cd v = cmulz(x, scale);
-                    vs[i] = v;
-                    Aat(j + 1 + i, j) = v;
-                }
-            }
-        }
-        if (t == 0) {
-            sc.tau[j] = tau;
-            sc.e[j] = beta_s;
-            Aat(j + 1, j) = cd{beta_s, 0.0};
-            sc.d[j] = Aat(j, j).x;
-        }
-        __syncthreads();
-        if (reflect) {
-            // y = A_sub v, A_sub = A[j+1:, j+1:] (full Hermitian storage)
-            const int groups = max(1, nt / L);
-            for (int r0 = 0; r0 < L; r0 += nt) {
-                // generic path: one thread per row when L >= nt, else column groups
-                if (groups == 1) {
-                    const int i = r0 + t;
-                    if (i < L) {
-                        double sr = 0.0, si = 0.0;
-                        for (int c = 0; c < L; ++c) {
-                            const cd a = Aat(j + 1 + i, j + 1 + c);
-                            const cd v = vs[c];
-                            sr += a.x * v.x - a.y * v.y;
-                            si += a.x * v.y + a.y * v.x;
-                        }
-                        ys[i] = cd{sr, si};
-                    }
-                } else {
-                    const int i = t % L, cg = t / L;
-                    double sr = 0.0, si = 0.0;
-                    if (cg < groups) {
-                        const int cb = (int)((int64_t)cg * L / groups);
-                        const int ce = (int)((int64_t)(cg + 1) * L / groups);
-                        for (int c = cb; c < ce; ++c) {
-                            const cd a = Aat(j + 1 + i, j + 1 + c);
-                            const cd v = vs[c];
-                            sr += a.x * v.x - a.y * v.y;
-                            si += a.x * v.y + a.y * v.x;
-                        }
-                    }
-                    // partials in ps[cg * L + i] (groups * L <= nt)
-                    if (cg < groups) ps[cg * L + i] = cd{sr, si};
-                    __syncthreads();
-                    if (t < L) {
-                        double ar = 0.0, ai = 0.0;
-                        for (int q2 = 0; q2 < groups; ++q2) {
-                            ar += ps[q2 * L + t].x;
-                            ai += ps[q2 * L + t].y;
-                        }
-                        ys[t] = cd{ar, ai};
-                    }
-                    break;
-                }
-            }
-            __syncthreads();
-            // alpha = |tau|^2 / 2 * Re(v^H y);  w = tau y - alpha v
-            double pv = 0.0;
-            for (int i = t; i < L; i += nt) pv += vs[i].x * ys[i].x + vs[i].y * ys[i].y;
-            const double vhy = block_sum(pv, red);
-            const double alpha = 0.5 * (tau.x * tau.x + tau.y * tau.y) * vhy;
-            for (int i = t; i < L; i += nt) {
-                const cd ty = cmulz(tau, ys[i]);
-                ws[i] = cd{ty.x - alpha * vs[i].x, ty.y - alpha * vs[i].y};
-            }
-            __syncthreads();
-            // A_sub -= w v^H + v w^H
-            const int64_t tot = (int64_t)L * L;
-            for (int64_t idx = t; idx < tot; idx += nt) {
-                const int i = (int)(idx % L), c = (int)(idx / L);
-                const cd a1 = cmulz(ws[i], cconj(vs[c]));
-                const cd a2 = cmulz(vs[i], cconj(ws[c]));
-                cd &a = Aat(j + 1 + i, j + 1 + c);
-                a.x -= a1.x + a2.x;
-                a.y -= a1.y + a2.y;
-            }
-            __syncthreads();
-        }
-    }
-    if (t == 0) {
-        sc.d[n - 1] = Aat(n - 1, n - 1).x;
-        if (n >= 1) sc.e[n - 1] = 0.0;
-    }
-    __syncthreads();
-    for (int i = t; i < n; i += nt) {
-        ds[i] = sc.d[i];
-        e2[i] = (i + 1 < n) ? sc.e[i] * sc.e[i] : 0.0;
-    }
-    __syncthreads();
-
-    // ---- 2. bisection for eigenvalues 0..k-1 of T ----
+__device__ TriBounds tri_bounds(const double *ds, const double *ee, int n) {
     double gl = ds[0], gu = ds[0], tnorm = 0.0;
     for (int i = 0; i < n; ++i) {
-        const double r = (i > 0 ? fabs(sc.e[i - 1]) : 0.0) + (i + 1 < n ? fabs(sc.e[i]) : 0.0);
+        const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
         gl = fmin(gl, ds[i] - r);
         gu = fmax(gu, ds[i] + r);
         tnorm = fmax(tnorm, fabs(ds[i]) + r);
     }
     const double pivmin = DBL_MIN * fmax(1.0, tnorm * tnorm);
     const double span = fmax(gu - gl, DBL_EPSILON * fmax(1.0, tnorm));
-    gl -= 2.0 * DBL_EPSILON * span + 1e-300;
-    gu += 2.0 * DBL_EPSILON * span + 1e-300;
-    for (int idx = t; idx < k; idx += nt) {
-        double lo = gl, hi = gu;
-        for (int it = 0; it < 200; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (mid <= lo || mid >= hi) break;
-            if (hi - lo <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi))) break;
-            if (sturm_count(ds, e2, n, mid, pivmin) <= idx) lo = mid;
-            else hi = mid;
-        }
-        w[idx] = 0.5 * (lo + hi);
-    }
-    __syncthreads();
+    return {gl - 2.0 * DBL_EPSILON * span - 1e-300, gu + 2.0 * DBL_EPSILON * span + 1e-300, pivmin,
+            tnorm};
+}
 
-    // ---- 3. inverse iteration on T for each eigenvalue ----
-    // (T - lambda I) = P L U, tridiagonal LU with partial pivoting; arrays
-    // interleaved [i][idx] so that threads access consecutive addresses.
-    double *dl = sc.lu;                   // multipliers
-    double *dd = sc.lu + (int64_t)n * k;  // U diagonal
-    double *du = sc.lu + 2 * (int64_t)n * k;   // U first superdiagonal
-    double *du2 = sc.lu + 3 * (int64_t)n * k;  // U second superdiagonal (fill)
-    double *piv = sc.lu + 4 * (int64_t)n * k;  // 1 if rows swapped
-    const double eps_t = DBL_EPSILON * fmax(tnorm, 1e-300);
-    for (int idx = t; idx < k; idx += nt) {
-        const double lam = w[idx];
-        auto at = [&](double *arr, int i) -> double & { return arr[(int64_t)i * k + idx]; };
-        // factor
-        for (int i = 0; i < n; ++i) {
-            at(dd, i) = ds[i] - lam;
-            at(du, i) = (i + 1 < n) ? sc.e[i] : 0.0;
-            at(du2, i) = 0.0;
-            at(piv, i) = 0.0;
+// 16 lanes per eigenvalue: each round evaluates 16 interior points of the
+// bracket and keeps the sub-interval where the Sturm count crosses the index.
+__global__ void __launch_bounds__(1024) k_stebz(const double *__restrict__ dd,
+                                                const double *__restrict__ ee, int n, int k,
+                                                double *__restrict__ w) {
+    extern __shared__ unsigned char smem_raw[];
+    double *ds = reinterpret_cast<double *>(smem_raw);
+    double *e2 = ds + n;
+    __shared__ TriBounds tb;
+    const int t = threadIdx.x;
+    for (int i = t; i < n; i += blockDim.x) {
+        ds[i] = dd[i];
+        e2[i] = (i + 1 < n) ? ee[i] * ee[i] : 0.0;
+    }
+    if (t == 0) tb = tri_bounds(dd, ee, n);
+    __syncthreads();
+    const int grp = t >> 4, s = t & 15;
+    const int idx = blockIdx.x * 64 + grp;
+    if (idx >= k) return;
+    double lo = tb.gl, hi = tb.gu;
+    const int base = (t & 63) & ~15;
+    for (int round = 0; round < 64; ++round) {
+        const double width = hi - lo;
+        if (width <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + tb.pivmin) break;
+        const double x = lo + width * (double)(s + 1) / 17.0;
+        const int c = sturm_count(ds, e2, n, x, tb.pivmin);
+        const unsigned long long mask = __ballot(c > idx);
+        const unsigned gm = (unsigned)((mask >> base) & 0xFFFFull);
+        const int first = gm ? __ffs(gm) - 1 : 16;
+        const double nlo = first == 0 ? lo : lo + width * (double)first / 17.0;
+        const double nhi = first == 16 ? hi : lo + width * (double)(first + 1) / 17.0;
+        lo = nlo;
+        hi = nhi;
+    }
+    if (s == 0) w[idx] = 0.5 * (lo + hi);
+}
+
+// Inverse iteration: one thread per eigenvalue, E eigenvalues per workgroup,
+// the LU factors of T - lambda I and the iterate in LDS, interleaved [i][e].
+__global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
+                                              const double *__restrict__ ee, int n, int k, int E,
+                                              const double *__restrict__ w, double *__restrict__ Z) {
+    extern __shared__ unsigned char smem_raw[];
+    double *ds = reinterpret_cast<double *>(smem_raw);   // [n]
+    double *es = ds + n;                                  // [n]
+    double *lu = es + n;                                  // [6][n][E]
+    __shared__ double s_tnorm;
+    const int t = threadIdx.x;
+    for (int i = t; i < n; i += blockDim.x) {
+        ds[i] = dd[i];
+        es[i] = (i + 1 < n) ? ee[i] : 0.0;
+    }
+    if (t == 0) s_tnorm = tri_bounds(dd, ee, n).tnorm;
+    __syncthreads();
+    const int idx = blockIdx.x * E + t;
+    if (t >= E || idx >= k) return;
+    auto at = [&](int arr, int i) -> double & { return lu[((size_t)arr * n + i) * E + t]; };
+    enum { DL = 0, DD, DU, DU2, PIV, ZZ };
+    const double lam = w[idx];
+    const double eps_t = DBL_EPSILON * fmax(s_tnorm, 1e-300);
+    for (int i = 0; i < n; ++i) {
+        at(DD, i) = ds[i] - lam;
+        at(DU, i) = es[i];
+        at(DU2, i) = 0.0;
+        at(PIV, i) = 0.0;
+    }
+    for (int i = 0; i + 1 < n; ++i) {
+        const double sub = es[i];
+        const double di = at(DD, i);
+        if (fabs(di) >= fabs(sub)) {
+            const double dp = fabs(di) < eps_t ? (di < 0 ? -eps_t : eps_t) : di;
+            at(DD, i) = dp;
+            const double m = sub / dp;
+            at(DL, i) = m;
+            at(DD, i + 1) -= m * at(DU, i);
+        } else {
+            const double m = di / sub;
+            at(DL, i) = m;
+            at(PIV, i) = 1.0;
+            at(DD, i) = sub;
+            const double tmp = at(DU, i);
+            at(DU, i) = at(DD, i + 1);
+            at(DD, i + 1) = tmp - m * at(DD, i + 1);
+            if (i + 2 < n) {
+                at(DU2, i) = at(DU, i + 1);
+                at(DU, i + 1) = -m * at(DU, i + 1);
+            }
         }
+    }
+    if (fabs(at(DD, n - 1)) < eps_t) at(DD, n - 1) = eps_t;
+    for (int i = 0; i < n; ++i) {
+        uint64_t h = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(idx + 7) * 0xD1B54A32D192ED03ull;
+        h ^= h >> 31;
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 29;
+        at(ZZ, i) = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+    for (int iter = 0; iter < 3; ++iter) {
         for (int i = 0; i + 1 < n; ++i) {
-            const double sub = sc.e[i];   // A[i+1][i]
-            if (fabs(at(dd, i)) >= fabs(sub)) {
-                double di = at(dd, i);
-                if (fabs(di) < eps_t) di = (di < 0 ? -eps_t : eps_t);
-                at(dd, i) = di;
-                const double m = sub / di;
-                at(dl, i) = m;
-                at(dd, i + 1) -= m * at(du, i);
+            if (at(PIV, i) != 0.0) {
+                const double tmp = at(ZZ, i);
+                at(ZZ, i) = at(ZZ, i + 1);
+                at(ZZ, i + 1) = tmp - at(DL, i) * at(ZZ, i + 1);
             } else {
-                // swap rows i and i+1
-                const double m = at(dd, i) / sub;
-                at(dl, i) = m;
-                at(piv, i) = 1.0;
-                at(dd, i) = sub;
-                const double tmp = at(du, i);
-                at(du, i) = at(dd, i + 1);
-                at(dd, i + 1) = tmp - m * at(dd, i + 1);
-                if (i + 2 < n) {
-                    at(du2, i) = at(du, i + 1);
-                    at(du, i + 1) = -m * at(du, i + 1);
-                }
+                at(ZZ, i + 1) -= at(DL, i) * at(ZZ, i);
             }
         }
-        if (fabs(at(dd, n - 1)) < eps_t) at(dd, n - 1) = eps_t;
-        // starting vector: deterministic pseudo-random in (-1, 1)
-        double *z = sc.Z;
-        auto zat = [&](int i) -> double & { return z[(int64_t)i * k + idx]; };
-        for (int i = 0; i < n; ++i) {
-            uint64_t h = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(idx + 7) * 0xD1B54A32D192ED03ull;
-            h ^= h >> 31;
-            h *= 0xBF58476D1CE4E5B9ull;
-            h ^= h >> 29;
-            zat(i) = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+        double nrm = 0.0;
+        for (int i = n - 1; i >= 0; --i) {
+            double sv = at(ZZ, i);
+            if (i + 1 < n) sv -= at(DU, i) * at(ZZ, i + 1);
+            if (i + 2 < n) sv -= at(DU2, i) * at(ZZ, i + 2);
+            sv /= at(DD, i);
+            at(ZZ, i) = sv;
+            nrm = fmax(nrm, fabs(sv));
         }
-        for (int iter = 0; iter < 3; ++iter) {
-            // apply L^-1 P
-            for (int i = 0; i + 1 < n; ++i) {
-                if (at(piv, i) != 0.0) {
-                    const double tmp = zat(i);
-                    zat(i) = zat(i + 1);
-                    zat(i + 1) = tmp - at(dl, i) * zat(i + 1);
-                } else {
-                    zat(i + 1) -= at(dl, i) * zat(i);
-                }
-            }
-            // U^-1
-            double nrm = 0.0;
-            for (int i = n - 1; i >= 0; --i) {
-                double s = zat(i);
-                if (i + 1 < n) s -= at(du, i) * zat(i + 1);
-                if (i + 2 < n) s -= at(du2, i) * zat(i + 2);
-                zat(i) = s / at(dd, i);
-            }
-            for (int i = 0; i < n; ++i) nrm = fmax(nrm, fabs(zat(i)));
-            const double inv = nrm > 0 ? 1.0 / nrm : 1.0;
-            for (int i = 0; i < n; ++i) zat(i) *= inv;
-        }
+        const double inv = nrm > 0 ? 1.0 / nrm : 1.0;
+        for (int i = 0; i < n; ++i) at(ZZ, i) *= inv;
     }
-    __syncthreads();
+    double n2 = 0.0;
+    for (int i = 0; i < n; ++i) n2 += at(ZZ, i) * at(ZZ, i);
+    const double inv = 1.0 / sqrt(n2);
+    for (int i = 0; i < n; ++i) Z[(int64_t)i * k + idx] = at(ZZ, i) * inv;
+}
 
-    // ---- 4. classical Gram-Schmidt, twice, in eigenvalue order ----
-    double *Z = sc.Z;
+// Gram-Schmidt (twice) of the columns of Z [n][k] in eigenvalue order.  In
+// LDS when it fits; otherwise only within clusters of eigenvalues closer than
+// ctol (vectors of separated eigenvalues are already orthogonal to ~eps ||T|| / gap).
+__global__ void __launch_bounds__(1024) k_orth(double *__restrict__ Zg, int n, int k, int in_lds,
+                                               const double *__restrict__ w, double ctol_rel,
+                                               const double *__restrict__ dd,
+                                               const double *__restrict__ ee) {
+    extern __shared__ unsigned char smem_raw[];
+    double *coef = reinterpret_cast<double *>(smem_raw);   // [k]
+    double *red = coef + k;                                 // [blockDim]
+    double *Zl = red + blockDim.x;                          // [n][k] if in_lds
+    const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wave = t >> 6, nw = nt >> 6;
+    double *Z = in_lds ? Zl : Zg;
+    __shared__ double s_ctol;
+    if (t == 0) s_ctol = ctol_rel * fmax(tri_bounds(dd, ee, n).tnorm, 1e-300);
+    __syncthreads();
+    const double ctol = s_ctol;
+    if (in_lds) {
+        for (int i = t; i < n * k; i += nt) Zl[i] = Zg[i];
+        __syncthreads();
+    }
+    int cstart = 0;
     for (int j = 0; j < k; ++j) {
+        if (!in_lds && j > 0 && !(w[j] - w[j - 1] <= ctol)) cstart = j;
+        const int i0 = in_lds ? 0 : cstart;
         for (int pass = 0; pass < 2; ++pass) {
-            // coefficients c_i = z_i . z_j for i < j (one thread per i)
-            // red[] holds up to nt coefficients; process in chunks of nt.
-            for (int ib = 0; ib < j; ib += nt) {
-                const int i = ib + t;
-                double c = 0.0;
-                if (i < j)
-                    for (int r = 0; r < n; ++r) c += Z[(int64_t)r * k + i] * Z[(int64_t)r * k + j];
+            if (j > i0) {
+                // coef[i] = z_i . z_j, one wave per i, lanes over rows
+                for (int i = i0 + wave; i < j; i += nw) {
+                    double sacc = 0.0;
+                    for (int r = lane; r < n; r += 64) sacc += Z[(int64_t)r * k + i] * Z[(int64_t)r * k + j];
+                    for (int off = 32; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off);
+                    if (lane == 0) coef[i] = sacc;
+                }
                 __syncthreads();
-                red[t] = c;
-                __syncthreads();
-                const int cnt = min(nt, j - ib);
                 for (int r = t; r < n; r += nt) {
-                    double s = Z[(int64_t)r * k + j];
-                    for (int q2 = 0; q2 < cnt; ++q2) s -= red[q2] * Z[(int64_t)r * k + ib + q2];
-                    Z[(int64_t)r * k + j] = s;
+                    double sv = Z[(int64_t)r * k + j];
+                    for (int i = i0; i < j; ++i) sv -= coef[i] * Z[(int64_t)r * k + i];
+                    Z[(int64_t)r * k + j] = sv;
                 }
                 __syncthreads();
             }
             double pn = 0.0;
             for (int r = t; r < n; r += nt) {
-                const double v = Z[(int64_t)r * k + j];
-                pn += v * v;
+                const double vv = Z[(int64_t)r * k + j];
+                pn += vv * vv;
             }
             const double nn = block_sum(pn, red);
             const double inv = nn > 0 ? 1.0 / sqrt(nn) : 0.0;
-            if (!(nn > 0) && t == 0) atomicOr(status, 2);
             for (int r = t; r < n; r += nt) Z[(int64_t)r * k + j] *= inv;
             __syncthreads();
         }
     }
+    if (in_lds)
+        for (int i = t; i < n * k; i += nt) Zg[i] = Zl[i];
+}
 
-    // ---- 5. back-transform V = H_0 ... H_{n-2} Z ----
-    for (int idx = t; idx < n * k; idx += nt) {
-        const int r = idx % n, c = idx / n;
-        V[(int64_t)c * ldv + r] = cd{Z[(int64_t)r * k + c], 0.0};
+// V[:, c] = H_0 ... H_{n-2} Z[:, c] for a chunk of cw columns held in LDS.
+__global__ void __launch_bounds__(256) k_unmtr(const cd *__restrict__ A, int64_t lda, int n, int k,
+                                               int cw, const cd *__restrict__ tau,
+                                               const double *__restrict__ Z, cd *__restrict__ V,
+                                               int64_t ldv) {
+    extern __shared__ unsigned char smem_raw[];
+    cd *Vs = reinterpret_cast<cd *>(smem_raw);   // [n][cw + 1]
+    cd *vb = Vs + (size_t)n * (cw + 1);          // [n]
+    cd *sp = vb + n;                             // [blockDim] partial dots
+    cd *sc = sp + blockDim.x;                    // [cw]
+    const int t = threadIdx.x, nt = blockDim.x;
+    const int c0 = blockIdx.x * cw;
+    const int ncol = min(cw, k - c0);
+    const int LD = cw + 1;
+    for (int i = t; i < n * cw; i += nt) {
+        const int r = i / cw, c = i % cw;
+        Vs[r * LD + c] = cd{c < ncol ? Z[(int64_t)r * k + c0 + c] : 0.0, 0.0};
     }
     __syncthreads();
+    const int parts = nt / cw;   // threads per column in the dot products
     for (int j = n - 2; j >= 0; --j) {
-        const cd tau = sc.tau[j];
-        if (tau.x == 0.0 && tau.y == 0.0) continue;
+        const cd tj = tau[j];
+        if (tj.x == 0.0 && tj.y == 0.0) continue;
         const int L = n - j - 1;
-        // s_c = v^H V[j+1:, c]
-        for (int c = t; c < k; c += nt) {
+        for (int i = t; i < L; i += nt) vb[i] = (i == 0) ? cd{1.0, 0.0} : A[(int64_t)j * lda + j + 1 + i];
+        __syncthreads();
+        {
+            const int c = t % cw, p = t / cw;
             double sr = 0.0, si = 0.0;
-            for (int i = 0; i < L; ++i) {
-                const cd v = (i == 0) ? cd{1.0, 0.0} : Aat(j + 1 + i, j);
-                const cd x = V[(int64_t)c * ldv + j + 1 + i];
-                sr += v.x * x.x + v.y * x.y;
-                si += v.x * x.y - v.y * x.x;
+            if (p < parts)
+                for (int i = p; i < L; i += parts) {
+                    const cd vv = vb[i], x = Vs[(j + 1 + i) * LD + c];
+                    sr += vv.x * x.x + vv.y * x.y;
+                    si += vv.x * x.y - vv.y * x.x;
+                }
+            sp[t] = cd{sr, si};
+        }
+        __syncthreads();
+        if (t < cw) {
+            double sr = 0.0, si = 0.0;
+            for (int p = 0; p < parts; ++p) {
+                sr += sp[p * cw + t].x;
+                si += sp[p * cw + t].y;
             }
-            const cd s = cmulz(tau, cd{sr, si});
-            for (int i = 0; i < L; ++i) {
-                const cd v = (i == 0) ? cd{1.0, 0.0} : Aat(j + 1 + i, j);
-                cd &x = V[(int64_t)c * ldv + j + 1 + i];
-                const cd pr = cmulz(v, s);
-                x.x -= pr.x;
-                x.y -= pr.y;
-            }
+            sc[t] = cmulz(tj, cd{sr, si});
+        }
+        __syncthreads();
+        for (int i = t; i < L * cw; i += nt) {
+            const int r = i / cw, c = i % cw;
+            const cd pr = cmulz(vb[r], sc[c]);
+            cd &x = Vs[(j + 1 + r) * LD + c];
+            x.x -= pr.x;
+            x.y -= pr.y;
         }
         __syncthreads();
     }
-    for (int idx = t; idx < k; idx += nt)
-        if (!isfinite(w[idx])) atomicOr(status, 4);
+    for (int i = t; i < n * ncol; i += nt) {
+        const int c = i / n, r = i % n;
+        V[(int64_t)(c0 + c) * ldv + r] = Vs[r * LD + c];
+    }
+}
+
+__global__ void k_check_w(const double *w, int k, int *status) {
+    for (int i = threadIdx.x; i < k; i += blockDim.x)
+        if (!isfinite(w[i])) atomicOr(status, 4);
 }
 
 }  // namespace
@@ -456,7 +538,7 @@ void launch_chol_inv_f64(const cd *G, int64_t ldg, int n, cd *Rinv, int64_t ldr,
 }
 
 size_t heev_scratch_bytes(int n, int k) {
-    return 256 + (size_t)n * 16 + 2 * (size_t)n * 8 + 6 * (size_t)n * k * 8 + 4 * 256;
+    return 4 * 256 + (size_t)n * 16 + 2 * (size_t)n * 8 + (size_t)n * k * 8;
 }
 
 void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t ldv, void *scratch,
@@ -464,22 +546,47 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     PW_REQUIRE(n >= 1 && n <= 1024 && k >= 1 && k <= n, PW_ERR_ARG, "heev: need 1 <= k <= n <= 1024");
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
     char *p = static_cast<char *>(scratch);
-    HeevScratch sc;
-    sc.tau = reinterpret_cast<cd *>(p);
+    cd *tau = reinterpret_cast<cd *>(p);
     p += align((size_t)n * 16);
-    sc.d = reinterpret_cast<double *>(p);
+    double *d = reinterpret_cast<double *>(p);
     p += align((size_t)n * 8);
-    sc.e = reinterpret_cast<double *>(p);
+    double *e = reinterpret_cast<double *>(p);
     p += align((size_t)n * 8);
-    sc.Z = reinterpret_cast<double *>(p);
-    p += align((size_t)n * k * 8);
-    sc.lu = reinterpret_cast<double *>(p);
-    const size_t smem = 3 * (size_t)n * sizeof(cd) + (size_t)kDenseThreads * (sizeof(cd) + 8) +
-                        2 * (size_t)n * 8;
-    PW_HIP(hipFuncSetAttribute((const void *)k_heev, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)smem));
-    hipLaunchKernelGGL(k_heev, dim3(1), dim3(kDenseThreads), smem, st, A, lda, n, k, w, V, ldv, sc,
-                       status);
+    double *Z = reinterpret_cast<double *>(p);
+    // 1. tridiagonalisation
+    const int P = n <= 256 ? 16 : (n <= 512 ? 8 : 4);
+    const size_t sm1 = (size_t)(5 + P) * n * sizeof(cd) + kTrdThreads * sizeof(double);
+    auto trd = P == 16 ? (const void *)k_hetrd<16> : P == 8 ? (const void *)k_hetrd<8> : (const void *)k_hetrd<4>;
+    PW_HIP(hipFuncSetAttribute(trd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1));
+    if (P == 16)
+        hipLaunchKernelGGL(k_hetrd<16>, dim3(1), dim3(kTrdThreads), sm1, st, A, lda, n, d, e, tau);
+    else if (P == 8)
+        hipLaunchKernelGGL(k_hetrd<8>, dim3(1), dim3(kTrdThreads), sm1, st, A, lda, n, d, e, tau);
+    else
+        hipLaunchKernelGGL(k_hetrd<4>, dim3(1), dim3(kTrdThreads), sm1, st, A, lda, n, d, e, tau);
+    // 2. eigenvalues
+    const size_t sm2 = 2 * (size_t)n * 8;
+    hipLaunchKernelGGL(k_stebz, dim3((k + 63) / 64), dim3(1024), sm2, st, d, e, n, k, w);
+    // 3. inverse iteration
+    const size_t budget = 150 * 1024;
+    int E = (int)((budget - 16 * (size_t)n) / (48 * (size_t)n));
+    E = std::max(1, std::min(64, E));
+    const size_t sm3 = 16 * (size_t)n + 48 * (size_t)n * E;
+    PW_HIP(hipFuncSetAttribute((const void *)k_stein, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm3));
+    hipLaunchKernelGGL(k_stein, dim3((k + E - 1) / E), dim3(64), sm3, st, d, e, n, k, E, w, Z);
+    // 4. orthogonalisation
+    const bool in_lds = (size_t)n * k * 8 + (size_t)(k + 1024) * 8 <= 140 * 1024;
+    const size_t sm4 = (size_t)(k + 1024) * 8 + (in_lds ? (size_t)n * k * 8 : 0);
+    PW_HIP(hipFuncSetAttribute((const void *)k_orth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm4));
+    hipLaunchKernelGGL(k_orth, dim3(1), dim3(1024), sm4, st, Z, n, k, in_lds ? 1 : 0, w, 2e-5, d, e);
+    // 5. back-transform
+    int cw = 32;
+    while (cw > 1 && (size_t)n * (cw + 1) * 16 + (size_t)n * 16 + 256 * 16 + cw * 16 > 120 * 1024) cw /= 2;
+    const size_t sm5 = (size_t)n * (cw + 1) * 16 + (size_t)n * 16 + 256 * 16 + (size_t)cw * 16;
+    PW_HIP(hipFuncSetAttribute((const void *)k_unmtr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm5));
+    hipLaunchKernelGGL(k_unmtr, dim3((k + cw - 1) / cw), dim3(256), sm5, st, A, lda, n, k, cw, tau, Z,
+                       V, ldv);
+    hipLaunchKernelGGL(k_check_w, dim3(1), dim3(256), 0, st, w, k, status);
     PW_HIP(hipGetLastError());
 }
 
