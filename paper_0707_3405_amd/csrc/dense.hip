@@ -18,18 +18,17 @@ namespace {
 __device__ __forceinline__ cd cconj(cd a) { return {a.x, -a.y}; }
 __device__ __forceinline__ cd cmulz(cd a, cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
-// Block-wide sum of one double per thread (fixed order: deterministic).
+// Block-wide sum of one double per thread: wave shuffles, then the wave
+// partials added in wave order by every thread (deterministic, 2 barriers).
 __device__ double block_sum(double v, double *red) {
-    const int t = threadIdx.x;
-    red[t] = v;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, nw = blockDim.x >> 6;
+    if (lane == 0) red[wave] = v;
     __syncthreads();
-    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-        if (t < s) red[t] += red[t + s];
-        __syncthreads();
-    }
-    const double r = red[0];
+    double s = 0.0;
+    for (int q = 0; q < nw; ++q) s += red[q];
     __syncthreads();
-    return r;
+    return s;
 }
 
 // ---- Cholesky + inverse of the factor (n <= 64, in LDS) ---------------------
@@ -37,72 +36,78 @@ constexpr int kCholMax = 64;
 
 __global__ void __launch_bounds__(256) k_chol_inv(const cd *__restrict__ G, int64_t ldg, int n,
                                                   cd *__restrict__ Rinv, int64_t ldr, int *status) {
-    __shared__ cd Rs[kCholMax][kCholMax + 1];   // R (upper), row-major [row][col]
+    __shared__ cd Rs[kCholMax][kCholMax + 1];   // G, then R (upper), [row][col]
     __shared__ cd Xs[kCholMax][kCholMax + 1];   // R^-1
-    __shared__ double dmax;
-    __shared__ int fail;
+    __shared__ cd part[256];
+    __shared__ double red[4];
     const int t = threadIdx.x;
     for (int i = t; i < n * n; i += blockDim.x) {
         const int r = i % n, c = i / n;
         Rs[r][c] = G[(int64_t)c * ldg + r];
     }
-    if (t == 0) fail = 0;
     __syncthreads();
-    if (t == 0) {
-        double m = 0.0;
-        for (int i = 0; i < n; ++i) m = fmax(m, Rs[i][i].x);
-        dmax = m;
-    }
+    double dm = 0.0;
+    for (int i = t; i < n; i += blockDim.x) dm = fmax(dm, Rs[i][i].x);
+    for (int off = 32; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off));
+    if ((t & 63) == 0) red[t >> 6] = dm;
     __syncthreads();
+    const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
     // a tiny diagonal shift keeps a numerically semi-definite Gram factorable
     const double shift = 1e-15 * dmax * n;
+    bool fail = false;
+    // right-looking Cholesky; the trailing update uses the unscaled pivot row
+    // (G_ab -= conj(g_ja) g_jb / d), so each step needs one barrier
     for (int j = 0; j < n; ++j) {
-        if (t == 0) {
-            double d = Rs[j][j].x + shift;
-            if (!(d > 1e-300) || !isfinite(d)) {
-                fail = 1;
-                d = 1.0;
-            }
-            Rs[j][j] = cd{sqrt(d), 0.0};
+        double d = Rs[j][j].x + shift;
+        if (!(d > 1e-300) || !isfinite(d)) {
+            fail = true;
+            d = 1.0;
         }
-        __syncthreads();
-        const double inv = 1.0 / Rs[j][j].x;
-        for (int c = j + 1 + t; c < n; c += blockDim.x) Rs[j][c] = cd{Rs[j][c].x * inv, Rs[j][c].y * inv};
-        __syncthreads();
+        const double inv_d = 1.0 / d;
         const int m = n - j - 1;
         for (int i = t; i < m * m; i += blockDim.x) {
             const int a = j + 1 + i % m, b = j + 1 + i / m;
             if (b >= a) {
-                const cd u = cconj(Rs[j][a]), v = Rs[j][b];
-                const cd pr = cmulz(u, v);
-                Rs[a][b].x -= pr.x;
-                Rs[a][b].y -= pr.y;
+                const cd pr = cmulz(cconj(Rs[j][a]), Rs[j][b]);
+                Rs[a][b].x -= pr.x * inv_d;
+                Rs[a][b].y -= pr.y * inv_d;
             }
         }
         __syncthreads();
+        // row j of R: g_jb / sqrt(d); every thread has finished reading row j
+        const double isd = 1.0 / sqrt(d);
+        for (int c = j + 1 + t; c < n; c += blockDim.x) Rs[j][c] = cd{Rs[j][c].x * isd, Rs[j][c].y * isd};
+        if (t == 0) Rs[j][j] = cd{d * isd, 0.0};
     }
-    // R^-1 by rows from the bottom, columns in parallel:
-    // X_ic = (delta_ic - sum_{k=i+1..c} R_ik X_kc) / R_ii
+    __syncthreads();
+    // R^-1 by rows from the bottom; 4 threads per column share the sum
+    //   X_ic = (delta_ic - sum_{k=i+1..c} R_ik X_kc) / R_ii
+    const int c = t & 63, p = t >> 6;
     for (int i = n - 1; i >= 0; --i) {
-        for (int c = t; c < n; c += blockDim.x) {
+        double sr = 0.0, si = 0.0;
+        if (c < n && c > i)
+            for (int kk = i + 1 + p; kk <= c; kk += 4) {
+                const cd pr = cmulz(Rs[i][kk], Xs[kk][c]);
+                sr += pr.x;
+                si += pr.y;
+            }
+        part[t] = cd{sr, si};
+        __syncthreads();
+        if (p == 0 && c < n) {
             if (c < i) {
                 Xs[i][c] = cd{0.0, 0.0};
-                continue;
+            } else {
+                const double tr = (c == i ? 1.0 : 0.0) - (part[c].x + part[64 + c].x + part[128 + c].x + part[192 + c].x);
+                const double ti = -(part[c].y + part[64 + c].y + part[128 + c].y + part[192 + c].y);
+                const double inv = 1.0 / Rs[i][i].x;
+                Xs[i][c] = cd{tr * inv, ti * inv};
             }
-            double sr = (c == i) ? 1.0 : 0.0, si = 0.0;
-            for (int kk = i + 1; kk <= c; ++kk) {
-                const cd pr = cmulz(Rs[i][kk], Xs[kk][c]);
-                sr -= pr.x;
-                si -= pr.y;
-            }
-            const double inv = 1.0 / Rs[i][i].x;
-            Xs[i][c] = cd{sr * inv, si * inv};
         }
         __syncthreads();
     }
     for (int i = t; i < n * n; i += blockDim.x) {
-        const int r = i % n, c = i / n;
-        Rinv[(int64_t)c * ldr + r] = Xs[r][c];
+        const int r = i % n, cc = i / n;
+        Rinv[(int64_t)cc * ldr + r] = Xs[r][cc];
     }
     if (t == 0 && fail) atomicOr(status, 1);
 }
@@ -114,53 +119,136 @@ __global__ void __launch_bounds__(256) k_chol_inv(const cd *__restrict__ G, int6
 //   k_stein  (k/E groups)    eigenvectors of T by inverse iteration, LU in LDS
 //   k_orth   (1 workgroup)   Gram-Schmidt (twice) in eigenvalue order
 //   k_unmtr  (k/cw groups)   back-transform V = Q Z
-constexpr int kTrdThreads = 1024;
+constexpr int kTrdThreads = 512;
 
-// One fused pass per column j: the pending rank-2 update of step j-1 is
-// applied while y = A_trail v_j is accumulated, so the trailing lower
-// triangle is read and written once per step.  Row sums are kept per wave in
-// LDS and added in wave order (deterministic).
-template <int P>
+// One fused pass per column j over the full trailing square (both triangles
+// are kept; the rank-2 update leaves them exact conjugates): the pending
+// update of step j-1 is applied while y = A_trail v_j is accumulated, so the
+// trailing block is read and written once per step.  One lane owns one row,
+// a wave task covers 64 rows x CC columns with CC independent loads in
+// flight, and row sums stay in registers.  The pivot column is kept in LDS
+// between steps, and once the trailing square fits in LDS it moves there for
+// the remaining steps.  Row partials are kept per wave and added in wave
+// order (deterministic).
+struct GlobalSq {
+    cd *A;
+    int64_t lda;
+    __device__ cd &at(int i, int c) const { return A[(int64_t)c * lda + i]; }
+};
+struct LdsSq {   // rows/cols [base, n) in LDS, column-major with leading dim ld
+    cd *p;
+    int base, ld;
+    __device__ cd &at(int i, int c) const { return p[(c - base) * ld + (i - base)]; }
+};
+
+template <class Sq>
+__device__ __forceinline__ void hetrd_pass(const Sq &M, int j, int n, const cd *v, const cd *vp,
+                                           const cd *wp, cd *ypart, cd *colbuf) {
+    constexpr int CC = 16;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    const int r_first = j + 1, L = n - r_first;
+    const int nrb = (L + 63) / 64, ncc = (L + CC - 1) / CC;
+    for (int u = wave; u < nrb * ncc; u += nwaves) {
+        const int rb = u % nrb, cch = u / nrb;
+        const int i = r_first + rb * 64 + lane;
+        const bool rowok = i < n;
+        const int c0 = r_first + cch * CC;
+        const int nc = min(CC, n - c0);
+        cd a[CC];
+#pragma unroll
+        for (int q = 0; q < CC; ++q) a[q] = (rowok && q < nc) ? M.at(i, c0 + q) : cd{0.0, 0.0};
+        const cd vpi = rowok ? vp[i] : cd{0.0, 0.0};
+        const cd wpi = rowok ? wp[i] : cd{0.0, 0.0};
+        double yr = 0.0, yi = 0.0;
+#pragma unroll
+        for (int q = 0; q < CC; ++q) {
+            if (q < nc) {
+                const int c = c0 + q;
+                const cd u1 = cmulz(wpi, cconj(vp[c])), u2 = cmulz(vpi, cconj(wp[c]));
+                cd aa = a[q];
+                aa.x -= u1.x + u2.x;
+                aa.y -= u1.y + u2.y;
+                if (rowok) {
+                    M.at(i, c) = aa;
+                    if (c == r_first) colbuf[i] = aa;   // next pivot column
+                }
+                const cd vc = v[c];
+                yr += aa.x * vc.x - aa.y * vc.y;
+                yi += aa.x * vc.y + aa.y * vc.x;
+            }
+        }
+        if (rowok) {
+            cd &yp = ypart[wave * n + i];
+            yp.x += yr;
+            yp.y += yi;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(kTrdThreads)
     k_hetrd(cd *__restrict__ A, int64_t lda, int n, double *__restrict__ dd,
-            double *__restrict__ ee, cd *__restrict__ tau_out) {
+            double *__restrict__ ee, cd *__restrict__ tau_out, int lds_cap) {
     extern __shared__ unsigned char smem_raw[];
+    const int nwaves = blockDim.x >> 6;
     cd *vp = reinterpret_cast<cd *>(smem_raw);   // [n] previous v (absolute rows)
     cd *wp = vp + n;                              // [n] previous w
     cd *v = wp + n;                               // [n] current v
     cd *y = v + n;                                // [n] A v
-    cd *ycol = y + n;                             // [n] column (transposed) sums
-    cd *ywave = ycol + n;                         // [P][n] per-wave row sums
-    double *red = reinterpret_cast<double *>(ywave + (size_t)P * n);   // [blockDim]
+    cd *colbuf = y + n;                           // [n] current pivot column
+    cd *ypart = colbuf + n;                       // [nwaves][n] per-wave row sums
+    double *red = reinterpret_cast<double *>(ypart + (size_t)nwaves * n);   // [blockDim]
+    cd *sq = reinterpret_cast<cd *>(red + blockDim.x);                     // [lds_cap]
     __shared__ cd s_tau, s_scale;
     __shared__ double s_beta;
-    const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wave = t >> 6;
-    auto col = [&](int c) { return A + (int64_t)c * lda; };
+    const int t = threadIdx.x, nt = blockDim.x;
+    const GlobalSq G{A, lda};
+    // the trailing square of step j is [j+1, n); it moves to LDS at the first
+    // step where (n - 1 - j)^2 <= lds_cap
+    int jsw = n;
+    for (int j = 0; j < n; ++j) {
+        const long L = n - 1 - j;
+        if (L * L <= lds_cap) {
+            jsw = j;
+            break;
+        }
+    }
+    const LdsSq S{sq, jsw + 1, n - 1 - jsw};
 
-    for (int i = t; i < n; i += nt) vp[i] = wp[i] = cd{0.0, 0.0};
+    // exact Hermitian symmetrisation: A <- (A + A^H) / 2
+    for (int idx = t; idx < n * n; idx += nt) {
+        const int r = idx % n, c = idx / n;
+        if (r > c) {
+            const cd a = G.at(r, c), b = G.at(c, r);
+            const cd m = {0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+            G.at(r, c) = m;
+            G.at(c, r) = cconj(m);
+        } else if (r == c) {
+            G.at(r, c).y = 0.0;
+        }
+    }
+    __syncthreads();
+    for (int i = t; i < n; i += nt) {
+        vp[i] = wp[i] = cd{0.0, 0.0};
+        colbuf[i] = G.at(i, 0);
+    }
     __syncthreads();
     for (int j = 0; j < n; ++j) {
-        // pending update of the pivot column j (rows j..n-1)
-        {
-            const cd vj = vp[j], wj = wp[j];
-            cd *cj = col(j);
+        {   // pending update of the pivot column (rows j..n-1), in LDS
+            const cd vj = cconj(vp[j]), wj = cconj(wp[j]);
             for (int i = j + t; i < n; i += nt) {
-                const cd u1 = cmulz(wp[i], cconj(vj)), u2 = cmulz(vp[i], cconj(wj));
-                cj[i].x -= u1.x + u2.x;
-                cj[i].y -= u1.y + u2.y;
+                const cd u1 = cmulz(wp[i], vj), u2 = cmulz(vp[i], wj);
+                colbuf[i].x -= u1.x + u2.x;
+                colbuf[i].y -= u1.y + u2.y;
             }
         }
         __syncthreads();
-        if (t == 0) dd[j] = col(j)[j].x;
+        if (t == 0) dd[j] = colbuf[j].x;
         if (j == n - 1) break;
         double part = 0.0;
-        for (int i = j + 2 + t; i < n; i += nt) {
-            const cd x = col(j)[i];
-            part += x.x * x.x + x.y * x.y;
-        }
+        for (int i = j + 2 + t; i < n; i += nt) part += colbuf[i].x * colbuf[i].x + colbuf[i].y * colbuf[i].y;
         const double sigma = block_sum(part, red);
         if (t == 0) {
-            const cd alpha = col(j)[j + 1];
+            const cd alpha = colbuf[j + 1];
             if (sigma == 0.0 && alpha.y == 0.0) {
                 s_tau = cd{0.0, 0.0};
                 s_beta = alpha.x;
@@ -179,64 +267,40 @@ __global__ void __launch_bounds__(kTrdThreads)
         const cd tau = s_tau, scale = s_scale;
         const bool reflect = !(tau.x == 0.0 && tau.y == 0.0);
         for (int i = j + 1 + t; i < n; i += nt) {
-            if (!reflect) {
-                v[i] = cd{0.0, 0.0};
-            } else if (i == j + 1) {
-                v[i] = cd{1.0, 0.0};
-            } else {
-                const cd vv = cmulz(col(j)[i], scale);
-                v[i] = vv;
-                col(j)[i] = vv;
-            }
+            cd vv;
+            if (!reflect) vv = cd{0.0, 0.0};
+            else if (i == j + 1) vv = cd{1.0, 0.0};
+            else vv = cmulz(colbuf[i], scale);
+            v[i] = vv;
+            if (i > j + 1) G.at(i, j) = vv;   // reflector kept for the back-transform
         }
-        for (int i = t; i < P * n; i += nt) ywave[i] = cd{0.0, 0.0};
-        for (int i = t; i < n; i += nt) ycol[i] = cd{0.0, 0.0};
+        for (int i = t; i < nwaves * n; i += nt) ypart[i] = cd{0.0, 0.0};
         if (t == 0) {
             tau_out[j] = tau;
             ee[j] = s_beta;
-            col(j)[j + 1] = cd{s_beta, 0.0};
+            G.at(j + 1, j) = cd{s_beta, 0.0};
         }
-        __syncthreads();
-        if (wave < P) {
-            for (int c = j + 1 + wave; c < n; c += P) {
-                const cd vc = v[c], vpc = vp[c], wpc = wp[c];
-                cd *cc = col(c);
-                double cr = 0.0, ci = 0.0;
-                for (int i = c + lane; i < n; i += 64) {
-                    cd a = cc[i];
-                    const cd u1 = cmulz(wp[i], cconj(vpc)), u2 = cmulz(vp[i], cconj(wpc));
-                    a.x -= u1.x + u2.x;
-                    a.y -= u1.y + u2.y;
-                    cc[i] = a;
-                    const cd r = cmulz(a, vc);
-                    cd &yw = ywave[wave * n + i];
-                    yw.x += r.x;
-                    yw.y += r.y;
-                    if (i > c) {
-                        const cd vi = v[i];   // conj(a) v_i
-                        cr += a.x * vi.x + a.y * vi.y;
-                        ci += a.x * vi.y - a.y * vi.x;
-                    }
-                }
-                for (int off = 32; off > 0; off >>= 1) {
-                    cr += __shfl_xor(cr, off);
-                    ci += __shfl_xor(ci, off);
-                }
-                if (lane == 0) ycol[c] = cd{cr, ci};
+        if (j == jsw) {   // move the trailing square to LDS
+            const int L = n - 1 - j;
+            for (int idx = t; idx < L * L; idx += nt) {
+                const int r = j + 1 + idx % L, c = j + 1 + idx / L;
+                S.at(r, c) = G.at(r, c);
             }
         }
         __syncthreads();
-        for (int i = j + 1 + t; i < n; i += nt) {
-            double sr = ycol[i].x, si = ycol[i].y;
-            for (int q = 0; q < P; ++q) {
-                sr += ywave[q * n + i].x;
-                si += ywave[q * n + i].y;
-            }
-            y[i] = cd{sr, si};
-        }
+        if (j >= jsw) hetrd_pass(S, j, n, v, vp, wp, ypart, colbuf);
+        else hetrd_pass(G, j, n, v, vp, wp, ypart, colbuf);
         __syncthreads();
         double pv = 0.0;
-        for (int i = j + 1 + t; i < n; i += nt) pv += v[i].x * y[i].x + v[i].y * y[i].y;
+        for (int i = j + 1 + t; i < n; i += nt) {
+            double sr = 0.0, si = 0.0;
+            for (int q = 0; q < nwaves; ++q) {
+                sr += ypart[q * n + i].x;
+                si += ypart[q * n + i].y;
+            }
+            y[i] = cd{sr, si};
+            pv += v[i].x * sr + v[i].y * si;
+        }
         const double vhy = block_sum(pv, red);
         const double nu = 0.5 * (tau.x * tau.x + tau.y * tau.y) * vhy;
         for (int i = j + 1 + t; i < n; i += nt) {
@@ -245,6 +309,27 @@ __global__ void __launch_bounds__(kTrdThreads)
             vp[i] = v[i];
         }
         __syncthreads();
+    }
+}
+
+// Sturm counts (number of eigenvalues below x) at two shifts at once: the two
+// recurrences are independent, so their division chains overlap.
+__device__ void sturm_count2(const double *d, const double *e2, int n, double x1, double x2,
+                             double pivmin, int &c1, int &c2) {
+    c1 = c2 = 0;
+    double q1 = d[0] - x1, q2 = d[0] - x2;
+    if (fabs(q1) < pivmin) q1 = -pivmin;
+    if (fabs(q2) < pivmin) q2 = -pivmin;
+    c1 += q1 < 0;
+    c2 += q2 < 0;
+    for (int i = 1; i < n; ++i) {
+        const double di = d[i], ei = e2[i - 1];
+        q1 = di - x1 - ei / q1;
+        q2 = di - x2 - ei / q2;
+        if (fabs(q1) < pivmin) q1 = -pivmin;
+        if (fabs(q2) < pivmin) q2 = -pivmin;
+        c1 += q1 < 0;
+        c2 += q2 < 0;
     }
 }
 
@@ -281,7 +366,7 @@ __device__ TriBounds tri_bounds(const double *ds, const double *ee, int n) {
 
 // 16 lanes per eigenvalue: each round evaluates 16 interior points of the
 // bracket and keeps the sub-interval where the Sturm count crosses the index.
-__global__ void __launch_bounds__(1024) k_stebz(const double *__restrict__ dd,
+__global__ void __launch_bounds__(64) k_stebz(const double *__restrict__ dd,
                                                 const double *__restrict__ ee, int n, int k,
                                                 double *__restrict__ w) {
     extern __shared__ unsigned char smem_raw[];
@@ -296,20 +381,23 @@ __global__ void __launch_bounds__(1024) k_stebz(const double *__restrict__ dd,
     if (t == 0) tb = tri_bounds(dd, ee, n);
     __syncthreads();
     const int grp = t >> 4, s = t & 15;
-    const int idx = blockIdx.x * 64 + grp;
+    const int idx = blockIdx.x * (blockDim.x >> 4) + grp;
     if (idx >= k) return;
     double lo = tb.gl, hi = tb.gu;
     const int base = (t & 63) & ~15;
     for (int round = 0; round < 64; ++round) {
         const double width = hi - lo;
         if (width <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + tb.pivmin) break;
-        const double x = lo + width * (double)(s + 1) / 17.0;
-        const int c = sturm_count(ds, e2, n, x, tb.pivmin);
-        const unsigned long long mask = __ballot(c > idx);
-        const unsigned gm = (unsigned)((mask >> base) & 0xFFFFull);
-        const int first = gm ? __ffs(gm) - 1 : 16;
-        const double nlo = first == 0 ? lo : lo + width * (double)first / 17.0;
-        const double nhi = first == 16 ? hi : lo + width * (double)(first + 1) / 17.0;
+        // 32 interior points; lane s evaluates points s and s + 16
+        const double x1 = lo + width * (double)(s + 1) / 33.0;
+        const double x2 = lo + width * (double)(s + 17) / 33.0;
+        int c1, c2;
+        sturm_count2(ds, e2, n, x1, x2, tb.pivmin, c1, c2);
+        const unsigned g1 = (unsigned)((__ballot(c1 > idx) >> base) & 0xFFFFull);
+        const unsigned g2 = (unsigned)((__ballot(c2 > idx) >> base) & 0xFFFFull);
+        const int first = g1 ? __ffs(g1) - 1 : (g2 ? 16 + __ffs(g2) - 1 : 32);
+        const double nlo = first == 0 ? lo : lo + width * (double)first / 33.0;
+        const double nhi = first == 32 ? hi : lo + width * (double)(first + 1) / 33.0;
         lo = nlo;
         hi = nhi;
     }
@@ -369,6 +457,7 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
         }
     }
     if (fabs(at(DD, n - 1)) < eps_t) at(DD, n - 1) = eps_t;
+    for (int i = 0; i < n; ++i) at(DD, i) = 1.0 / at(DD, i);   // reciprocal pivots
     for (int i = 0; i < n; ++i) {
         uint64_t h = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(idx + 7) * 0xD1B54A32D192ED03ull;
         h ^= h >> 31;
@@ -391,7 +480,7 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
             double sv = at(ZZ, i);
             if (i + 1 < n) sv -= at(DU, i) * at(ZZ, i + 1);
             if (i + 2 < n) sv -= at(DU2, i) * at(ZZ, i + 2);
-            sv /= at(DD, i);
+            sv *= at(DD, i);
             at(ZZ, i) = sv;
             nrm = fmax(nrm, fabs(sv));
         }
@@ -416,13 +505,14 @@ __global__ void __launch_bounds__(1024) k_orth(double *__restrict__ Zg, int n, i
     double *red = coef + k;                                 // [blockDim]
     double *Zl = red + blockDim.x;                          // [n][k] if in_lds
     const int t = threadIdx.x, nt = blockDim.x, lane = t & 63, wave = t >> 6, nw = nt >> 6;
+    const int ldz = in_lds ? k + 1 : k;   // padded rows in LDS (no bank conflicts)
     double *Z = in_lds ? Zl : Zg;
     __shared__ double s_ctol;
     if (t == 0) s_ctol = ctol_rel * fmax(tri_bounds(dd, ee, n).tnorm, 1e-300);
     __syncthreads();
     const double ctol = s_ctol;
     if (in_lds) {
-        for (int i = t; i < n * k; i += nt) Zl[i] = Zg[i];
+        for (int i = t; i < n * k; i += nt) Zl[(i / k) * ldz + i % k] = Zg[i];
         __syncthreads();
     }
     int cstart = 0;
@@ -434,31 +524,31 @@ __global__ void __launch_bounds__(1024) k_orth(double *__restrict__ Zg, int n, i
                 // coef[i] = z_i . z_j, one wave per i, lanes over rows
                 for (int i = i0 + wave; i < j; i += nw) {
                     double sacc = 0.0;
-                    for (int r = lane; r < n; r += 64) sacc += Z[(int64_t)r * k + i] * Z[(int64_t)r * k + j];
+                    for (int r = lane; r < n; r += 64) sacc += Z[(int64_t)r * ldz + i] * Z[(int64_t)r * ldz + j];
                     for (int off = 32; off > 0; off >>= 1) sacc += __shfl_xor(sacc, off);
                     if (lane == 0) coef[i] = sacc;
                 }
                 __syncthreads();
                 for (int r = t; r < n; r += nt) {
-                    double sv = Z[(int64_t)r * k + j];
-                    for (int i = i0; i < j; ++i) sv -= coef[i] * Z[(int64_t)r * k + i];
-                    Z[(int64_t)r * k + j] = sv;
+                    double sv = Z[(int64_t)r * ldz + j];
+                    for (int i = i0; i < j; ++i) sv -= coef[i] * Z[(int64_t)r * ldz + i];
+                    Z[(int64_t)r * ldz + j] = sv;
                 }
                 __syncthreads();
             }
             double pn = 0.0;
             for (int r = t; r < n; r += nt) {
-                const double vv = Z[(int64_t)r * k + j];
+                const double vv = Z[(int64_t)r * ldz + j];
                 pn += vv * vv;
             }
             const double nn = block_sum(pn, red);
             const double inv = nn > 0 ? 1.0 / sqrt(nn) : 0.0;
-            for (int r = t; r < n; r += nt) Z[(int64_t)r * k + j] *= inv;
+            for (int r = t; r < n; r += nt) Z[(int64_t)r * ldz + j] *= inv;
             __syncthreads();
         }
     }
     if (in_lds)
-        for (int i = t; i < n * k; i += nt) Zg[i] = Zl[i];
+        for (int i = t; i < n * k; i += nt) Zg[i] = Zl[(i / k) * ldz + i % k];
 }
 
 // V[:, c] = H_0 ... H_{n-2} Z[:, c] for a chunk of cw columns held in LDS.
@@ -553,30 +643,27 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     double *e = reinterpret_cast<double *>(p);
     p += align((size_t)n * 8);
     double *Z = reinterpret_cast<double *>(p);
-    // 1. tridiagonalisation
-    const int P = n <= 256 ? 16 : (n <= 512 ? 8 : 4);
-    const size_t sm1 = (size_t)(5 + P) * n * sizeof(cd) + kTrdThreads * sizeof(double);
-    auto trd = P == 16 ? (const void *)k_hetrd<16> : P == 8 ? (const void *)k_hetrd<8> : (const void *)k_hetrd<4>;
-    PW_HIP(hipFuncSetAttribute(trd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1));
-    if (P == 16)
-        hipLaunchKernelGGL(k_hetrd<16>, dim3(1), dim3(kTrdThreads), sm1, st, A, lda, n, d, e, tau);
-    else if (P == 8)
-        hipLaunchKernelGGL(k_hetrd<8>, dim3(1), dim3(kTrdThreads), sm1, st, A, lda, n, d, e, tau);
-    else
-        hipLaunchKernelGGL(k_hetrd<4>, dim3(1), dim3(kTrdThreads), sm1, st, A, lda, n, d, e, tau);
+    // 1. tridiagonalisation (the trailing block of A is overwritten in both triangles)
+    const size_t base1 = (size_t)(5 + kTrdThreads / 64) * n * sizeof(cd) + kTrdThreads * sizeof(double);
+    const size_t cap_bytes = base1 < 156 * 1024 ? 156 * 1024 - base1 : 0;
+    const int lds_cap = (int)(cap_bytes / sizeof(cd));
+    const size_t sm1 = base1 + (size_t)lds_cap * sizeof(cd);
+    PW_HIP(hipFuncSetAttribute((const void *)k_hetrd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1));
+    hipLaunchKernelGGL(k_hetrd, dim3(1), dim3(kTrdThreads), sm1, st, A, lda, n, d, e, tau, lds_cap);
     // 2. eigenvalues
     const size_t sm2 = 2 * (size_t)n * 8;
-    hipLaunchKernelGGL(k_stebz, dim3((k + 63) / 64), dim3(1024), sm2, st, d, e, n, k, w);
+    // 4 eigenvalues (16 lanes each) per workgroup, spread over k/4 CUs
+    hipLaunchKernelGGL(k_stebz, dim3((k + 3) / 4), dim3(64), sm2, st, d, e, n, k, w);
     // 3. inverse iteration
     const size_t budget = 150 * 1024;
     int E = (int)((budget - 16 * (size_t)n) / (48 * (size_t)n));
-    E = std::max(1, std::min(64, E));
+    E = std::max(1, std::min(4, E));   // few eigenvalues per workgroup: spread over CUs
     const size_t sm3 = 16 * (size_t)n + 48 * (size_t)n * E;
     PW_HIP(hipFuncSetAttribute((const void *)k_stein, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm3));
     hipLaunchKernelGGL(k_stein, dim3((k + E - 1) / E), dim3(64), sm3, st, d, e, n, k, E, w, Z);
     // 4. orthogonalisation
-    const bool in_lds = (size_t)n * k * 8 + (size_t)(k + 1024) * 8 <= 140 * 1024;
-    const size_t sm4 = (size_t)(k + 1024) * 8 + (in_lds ? (size_t)n * k * 8 : 0);
+    const bool in_lds = (size_t)n * (k + 1) * 8 + (size_t)(k + 1024) * 8 <= 140 * 1024;
+    const size_t sm4 = (size_t)(k + 1024) * 8 + (in_lds ? (size_t)n * (k + 1) * 8 : 0);
     PW_HIP(hipFuncSetAttribute((const void *)k_orth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm4));
     hipLaunchKernelGGL(k_orth, dim3(1), dim3(1024), sm4, st, Z, n, k, in_lds ? 1 : 0, w, 2e-5, d, e);
     // 5. back-transform

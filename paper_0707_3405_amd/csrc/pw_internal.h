@@ -110,6 +110,12 @@ void launch_zero_f64(cd *X, int64_t ldx, int64_t rows, int cols, hipStream_t st)
 // P-coefficient block: rows [0, m) of Cfull set to zero (the X rows), others copied.
 void launch_pcoef_f64(const cd *Cfull, int64_t ldc, int n, int m, cd *Cp, int64_t ldp,
                       hipStream_t st);
+// Active-set variants: column jj of the output takes input column act[jj].
+void launch_precond_map_f64(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
+                            int64_t npw, const double *theta, const double *ekin_nrm, const int *act,
+                            int na, cd *W, int64_t ldw, hipStream_t st);
+void launch_pcoef_map_f64(const cd *Cfull, int64_t ldc, int n, int m, const int *act, int na, cd *Cp,
+                          int64_t ldp, hipStream_t st);
 void launch_check_finite_f64(const double *a, int64_t n, int *status, hipStream_t st);
 
 }  // namespace pw

@@ -155,6 +155,7 @@ struct Plan {
     double *res = nullptr;        // [M]
     double *w = nullptr;          // [max(3m, M)]
     double *rpart = nullptr;      // residual partials
+    int *act = nullptr;           // [m] active column map
     void *heev_scratch = nullptr;
     size_t bytes = 0;
 };
@@ -199,6 +200,7 @@ Plan make_plan(const pw_ctx_s &c, int M, int m, char *base) {
     p.res = a.take<double>(n3);
     p.w = a.take<double>(n3);
     p.rpart = a.take<double>(pw::resid_part_elems(c.npw, n3));
+    p.act = a.take<int>(m);
     p.heev_scratch = a.take<char>(pw::heev_scratch_bytes(n3, n3));
     p.bytes = align_up(a.used, 256);
     return p;
@@ -337,17 +339,18 @@ pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int
             Z = p.Z[cur];
             HZ = p.HZ[cur];
         }
-        bool havep = false, converged = false;
+        // Active set: only columns whose residual is still above tol receive a
+        // new direction W and a conjugate direction P, so H.W, the
+        // projections and the Rayleigh-Ritz size shrink as the block converges.
+        // Basis layout in Z / HZ: [X (mb) | P (np) | W (na)].
+        int np = 0, converged_it = -1;
+        std::vector<int> act;
         int it = 0;
         for (it = 0; it < max_iter; ++it) {
-            // residuals and preconditioned directions (W written to slot 2 if P
-            // may be used, else slot 1)
-            const int wslot = havep ? 2 : 1;
-            cd *W = Z + (int64_t)wslot * mb * ld;
             {
                 auto e = tm.begin();
                 pw::launch_band_dots_f64(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.rpart, p.theta, p.ekin, st);
-                pw::launch_resid_precond_f64(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.theta, p.ekin, W, ld,
+                pw::launch_resid_precond_f64(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.theta, p.ekin, nullptr, 0,
                                              p.rpart, p.res, st);
                 tm.end(PhaseTimer::kVec, e);
             }
@@ -355,40 +358,46 @@ pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int
             const int status = read_status(c);
             tm.collect();
             if (status & 4) throw Error{PW_ERR_NUMERIC, "non-finite value in the iteration"};
-            bool pfail = (status & 1) != 0;
-            if (pfail) {
+            if (status & 1) {
+                // a CholQR broke down (P or W): restart without P
                 PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), st));
-                if (havep) {
-                    // P could not be orthonormalised: drop it, move W to slot 1
-                    pw::launch_copy_cols_f64(W, ld, Z + (int64_t)mb * ld, ld, npw, mb, st);
-                    havep = false;
-                    W = Z + (int64_t)mb * ld;
-                    ++stats.p_restarts;
-                }
+                if (np > 0) ++stats.p_restarts;
+                np = 0;
             }
+            for (int j = 0; j < mb; ++j)
+                if (!std::isfinite(hres[j])) throw Error{PW_ERR_NUMERIC, "non-finite residual"};
             bool done = true;
             for (int j = 0; j < keep; ++j)
                 if (!(hres[j] <= tol)) done = false;
-            for (int j = 0; j < mb; ++j)
-                if (!std::isfinite(hres[j])) throw Error{PW_ERR_NUMERIC, "non-finite residual"};
             if (done) {
-                converged = true;
+                converged_it = it;
                 break;
             }
-            const int wcol = (havep ? 2 : 1) * mb;
+            act.clear();
+            for (int j = 0; j < mb; ++j)
+                if (hres[j] > tol) act.push_back(j);
+            const int na = (int)act.size();
+            PW_HIP(hipMemcpyAsync(p.act, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
+            const int wcol = mb + np;
+            cd *W = Z + (int64_t)wcol * ld;
+            {
+                auto e = tm.begin();
+                pw::launch_precond_map_f64(Z, ld, HZ, ld, c->sp.kin, npw, p.theta, p.ekin, p.act, na, W, ld, st);
+                tm.end(PhaseTimer::kVec, e);
+            }
             // constraint to previous blocks, then orthogonal to [X P] (twice) and orthonormal
-            project_out(c, p, tm, X, ldx, b0, W, ld, mb);
+            project_out(c, p, tm, X, ldx, b0, W, ld, na);
             for (int pass = 0; pass < 2; ++pass) {
-                project_out(c, p, tm, Z, ld, wcol, W, ld, mb);
-                cholqr(c, p, tm, W, ld, mb);
+                project_out(c, p, tm, Z, ld, wcol, W, ld, na);
+                cholqr(c, p, tm, W, ld, na);
             }
             {
                 auto e = tm.begin();
-                apply_H(c, p, m, W, ld, HZ + (int64_t)wcol * ld, ld, mb);
+                apply_H(c, p, m, W, ld, HZ + (int64_t)wcol * ld, ld, na);
                 tm.end(PhaseTimer::kApply, e);
-                stats.h_applies += mb;
+                stats.h_applies += na;
             }
-            const int nz = wcol + mb;
+            const int nz = wcol + na;
             // Rayleigh-Ritz on span{X, P, W} (orthonormal basis)
             {
                 auto e0 = tm.begin();
@@ -400,36 +409,38 @@ pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int
                                     st);
                 tm.end(PhaseTimer::kDense, e1);
             }
-            // P coefficients: C with the X rows removed, made orthogonal to C
-            // and orthonormal (all in coefficient space, the basis being orthonormal)
+            // P coefficients for the active columns: C with the X rows removed,
+            // made orthogonal to C and orthonormal (in coefficient space, the
+            // basis being orthonormal)
             cd *Cp = p.Cc + (int64_t)mb * 3 * m;
             {
                 auto e0 = tm.begin();
-                pw::launch_pcoef_f64(p.Cc, 3 * m, nz, mb, Cp, 3 * m, st);
+                pw::launch_pcoef_map_f64(p.Cc, 3 * m, nz, mb, p.act, na, Cp, 3 * m, st);
                 for (int pass = 0; pass < 2; ++pass) {
-                    pw::launch_gemm_tn_f64(p.Cc, 3 * m, Cp, 3 * m, nz, mb, mb, p.T1, mb, nullptr, 0.0,
+                    pw::launch_gemm_tn_f64(p.Cc, 3 * m, Cp, 3 * m, nz, mb, na, p.T1, mb, nullptr, 0.0,
                                            p.part, p.part_elems, st);
-                    pw::launch_gemm_nn_f64(p.Cc, 3 * m, p.T1, mb, nz, mb, mb, -1.0, 1.0, Cp, 3 * m, st);
-                    pw::launch_gemm_tn_f64(Cp, 3 * m, Cp, 3 * m, nz, mb, mb, p.Gs, mb, nullptr, 0.0,
+                    pw::launch_gemm_nn_f64(p.Cc, 3 * m, p.T1, mb, nz, mb, na, -1.0, 1.0, Cp, 3 * m, st);
+                    pw::launch_gemm_tn_f64(Cp, 3 * m, Cp, 3 * m, nz, na, na, p.Gs, na, nullptr, 0.0,
                                            p.part, p.part_elems, st);
-                    pw::launch_chol_inv_f64(p.Gs, mb, mb, p.Rinv, mb, c->d_status, st);
-                    pw::launch_gemm_nn_f64(Cp, 3 * m, p.Rinv, mb, nz, mb, mb, 1.0, 0.0, Cp, 3 * m, st);
+                    pw::launch_chol_inv_f64(p.Gs, na, na, p.Rinv, na, c->d_status, st);
+                    pw::launch_gemm_nn_f64(Cp, 3 * m, p.Rinv, na, nz, na, na, 1.0, 0.0, Cp, 3 * m, st);
                 }
                 tm.end(PhaseTimer::kDense, e0);
             }
             // [X P]_new = Z [C c_p], same for HZ
             {
                 auto e = tm.begin();
-                pw::launch_gemm_nn_f64(Z, ld, p.Cc, 3 * m, npw, nz, 2 * mb, 1.0, 0.0, p.Z[1 - cur], ld, st);
-                pw::launch_gemm_nn_f64(HZ, ld, p.Cc, 3 * m, npw, nz, 2 * mb, 1.0, 0.0, p.HZ[1 - cur], ld,
+                pw::launch_gemm_nn_f64(Z, ld, p.Cc, 3 * m, npw, nz, mb + na, 1.0, 0.0, p.Z[1 - cur], ld, st);
+                pw::launch_gemm_nn_f64(HZ, ld, p.Cc, 3 * m, npw, nz, mb + na, 1.0, 0.0, p.HZ[1 - cur], ld,
                                        st);
                 tm.end(PhaseTimer::kGemm, e);
             }
             cur = 1 - cur;
             Z = p.Z[cur];
             HZ = p.HZ[cur];
-            havep = true;
+            np = na;
         }
+        const bool converged = converged_it >= 0;
         stats.iterations += it;
         if (!converged) all_converged = false;
         // store the converged columns of the block

@@ -104,6 +104,24 @@ __global__ void __launch_bounds__(kThreads)
     if (threadIdx.x == 0) part[(int64_t)c * nb + b] = v[0];
 }
 
+// W[:, jj] = K(T / E_kin) (HX - theta X)[:, act[jj]] for the active columns.
+__global__ void __launch_bounds__(kThreads)
+    k_precond_map(const cd *__restrict__ X, int64_t ldx, const cd *__restrict__ HX, int64_t ldhx,
+                  const double *__restrict__ kin, int64_t npw, const double *__restrict__ theta,
+                  const double *__restrict__ ekin, const int *__restrict__ act, cd *__restrict__ W,
+                  int64_t ldw) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int jj = blockIdx.y;
+    if (r >= npw) return;
+    const int b = act[jj];
+    const cd a = X[(int64_t)b * ldx + r], hb = HX[(int64_t)b * ldhx + r];
+    const double th = theta[b];
+    const double xx = kin[r] / fmax(ekin[b], 1e-3);
+    const double num = 27.0 + xx * (18.0 + xx * (12.0 + xx * 8.0));
+    const double k = num / (num + 16.0 * xx * xx * xx * xx);
+    W[(int64_t)jj * ldw + r] = cd{k * (hb.x - th * a.x), k * (hb.y - th * a.y)};
+}
+
 __global__ void k_resid_final(const double *__restrict__ part, int nchunk, int nb,
                               const double *__restrict__ nrm2, double *__restrict__ res) {
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
@@ -184,6 +202,14 @@ __global__ void k_pcoef(const cd *__restrict__ Cf, int64_t ldc, int n, int m, cd
     Cp[(int64_t)j * ldp + i] = (i < m) ? cd{0.0, 0.0} : Cf[(int64_t)j * ldc + i];
 }
 
+__global__ void k_pcoef_map(const cd *__restrict__ Cf, int64_t ldc, int n, int m,
+                            const int *__restrict__ act, cd *__restrict__ Cp, int64_t ldp) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int jj = blockIdx.y;
+    if (i >= n) return;
+    Cp[(int64_t)jj * ldp + i] = (i < m) ? cd{0.0, 0.0} : Cf[(int64_t)act[jj] * ldc + i];
+}
+
 __global__ void k_check_finite(const double *a, int64_t n, int *status) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && !isfinite(a[i])) atomicOr(status, 4);
@@ -254,6 +280,23 @@ void launch_pcoef_f64(const cd *Cfull, int64_t ldc, int n, int m, cd *Cp, int64_
                       hipStream_t st) {
     hipLaunchKernelGGL(k_pcoef, dim3((n + 255) / 256, m), dim3(256), 0, st, Cfull, ldc, n, m, Cp,
                        ldp);
+    PW_HIP(hipGetLastError());
+}
+
+void launch_precond_map_f64(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
+                            int64_t npw, const double *theta, const double *ekin_nrm, const int *act,
+                            int na, cd *W, int64_t ldw, hipStream_t st) {
+    if (na <= 0) return;
+    hipLaunchKernelGGL(k_precond_map, dim3((unsigned)((npw + kThreads - 1) / kThreads), na),
+                       dim3(kThreads), 0, st, X, ldx, HX, ldhx, kin, npw, theta, ekin_nrm, act, W, ldw);
+    PW_HIP(hipGetLastError());
+}
+
+void launch_pcoef_map_f64(const cd *Cfull, int64_t ldc, int n, int m, const int *act, int na, cd *Cp,
+                          int64_t ldp, hipStream_t st) {
+    if (na <= 0) return;
+    hipLaunchKernelGGL(k_pcoef_map, dim3((n + 255) / 256, na), dim3(256), 0, st, Cfull, ldc, n, m, act,
+                       Cp, ldp);
     PW_HIP(hipGetLastError());
 }
 
