@@ -159,7 +159,7 @@ __device__ __forceinline__ void hetrd_pass(const Sq &M, int j, int n, const cd *
         for (int q = 0; q < CC; ++q) a[q] = (rowok && q < nc) ? M.at(i, c0 + q) : cd{0.0, 0.0};
         const cd vpi = rowok ? vp[i] : cd{0.0, 0.0};
         const cd wpi = rowok ? wp[i] : cd{0.0, 0.0};
-        double yr = 0.0, yi = 0.0;
+        double yr4[4] = {0.0, 0.0, 0.0, 0.0}, yi4[4] = {0.0, 0.0, 0.0, 0.0};   // 4 independent chains
 #pragma unroll
         for (int q = 0; q < CC; ++q) {
             if (q < nc) {
@@ -173,10 +173,12 @@ __device__ __forceinline__ void hetrd_pass(const Sq &M, int j, int n, const cd *
                     if (c == r_first) colbuf[i] = aa;   // next pivot column
                 }
                 const cd vc = v[c];
-                yr += aa.x * vc.x - aa.y * vc.y;
-                yi += aa.x * vc.y + aa.y * vc.x;
+                yr4[q & 3] += aa.x * vc.x - aa.y * vc.y;
+                yi4[q & 3] += aa.x * vc.y + aa.y * vc.x;
             }
         }
+        const double yr = (yr4[0] + yr4[1]) + (yr4[2] + yr4[3]);
+        const double yi = (yi4[0] + yi4[1]) + (yi4[2] + yi4[3]);
         if (rowok) {
             cd &yp = ypart[wave * n + i];
             yp.x += yr;
@@ -551,15 +553,105 @@ __global__ void __launch_bounds__(1024) k_orth(double *__restrict__ Zg, int n, i
         for (int i = t; i < n * k; i += nt) Zg[i] = Zl[(i / k) * ldz + i % k];
 }
 
+// CholQR, twice, of the columns of Z [n][k] (k <= 64, n <= 256, all in LDS):
+// G = Z^T Z, G = R^T R, Z <- Z R^-1.  Equivalent to Gram-Schmidt in column
+// (eigenvalue) order; one thread per row for the triangular multiply.
+constexpr int kOrthMaxK = 64;
+__global__ void __launch_bounds__(256) k_orth_chol(double *__restrict__ Zg, int n, int k,
+                                                   int *__restrict__ status) {
+    extern __shared__ unsigned char smem_raw[];
+    const int ldz = k + 1, ldg = k + 1;
+    double *Z = reinterpret_cast<double *>(smem_raw);   // [n][k+1]
+    double *G = Z + (size_t)n * ldz;                     // [k][k+1]: G, then R, then R^-1
+    double *rowt = G + (size_t)k * ldg;                  // [k]
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int i = t; i < n * k; i += nt) Z[(i / k) * ldz + i % k] = Zg[i];
+    __syncthreads();
+    bool fail = false;
+    for (int pass = 0; pass < 2; ++pass) {
+        // G = Z^T Z (upper triangle), four independent partial sums per dot
+        const int npair = k * (k + 1) / 2;
+        for (int pidx = t; pidx < npair; pidx += nt) {
+            int a = 0, rem = pidx;
+            while (rem >= k - a) {
+                rem -= k - a;
+                ++a;
+            }
+            const int b = a + rem;
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int r = 0;
+            for (; r + 3 < n; r += 4) {
+                s0 += Z[r * ldz + a] * Z[r * ldz + b];
+                s1 += Z[(r + 1) * ldz + a] * Z[(r + 1) * ldz + b];
+                s2 += Z[(r + 2) * ldz + a] * Z[(r + 2) * ldz + b];
+                s3 += Z[(r + 3) * ldz + a] * Z[(r + 3) * ldz + b];
+            }
+            for (; r < n; ++r) s0 += Z[r * ldz + a] * Z[r * ldz + b];
+            G[a * ldg + b] = (s0 + s1) + (s2 + s3);
+        }
+        __syncthreads();
+        // Cholesky G = R^T R (upper); the trailing update uses the unscaled pivot row
+        for (int j = 0; j < k; ++j) {
+            double d = G[j * ldg + j];
+            if (!(d > 1e-300)) {
+                fail = true;
+                d = 1.0;
+            }
+            const double inv_d = 1.0 / d;
+            const int m = k - j - 1;
+            for (int i = t; i < m * m; i += nt) {
+                const int a = j + 1 + i % m, b = j + 1 + i / m;
+                if (b >= a) G[a * ldg + b] -= G[j * ldg + a] * G[j * ldg + b] * inv_d;
+            }
+            __syncthreads();
+            const double isd = 1.0 / sqrt(d);
+            for (int c = j + 1 + t; c < k; c += nt) G[j * ldg + c] *= isd;
+            if (t == 0) G[j * ldg + j] = d * isd;
+        }
+        __syncthreads();
+        // R^-1 in place, rows from the bottom: X_ic = (delta_ic - sum_{q=i+1..c} R_iq X_qc) / R_ii
+        for (int i = k - 1; i >= 0; --i) {
+            for (int c = i + t; c < k; c += nt) rowt[c] = G[i * ldg + c];
+            __syncthreads();
+            for (int c = i + t; c < k; c += nt) {
+                double sacc = (c == i) ? 1.0 : 0.0;
+                for (int q = i + 1; q <= c; ++q) sacc -= rowt[q] * G[q * ldg + c];
+                G[i * ldg + c] = sacc / rowt[i];
+            }
+            __syncthreads();
+        }
+        // Z <- Z R^-1, one thread per row (row in registers)
+        for (int r = t; r < n; r += nt) {
+            double z[kOrthMaxK];
+#pragma unroll
+            for (int i = 0; i < kOrthMaxK; ++i) z[i] = i < k ? Z[r * ldz + i] : 0.0;
+            for (int j = 0; j < k; ++j) {
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+                for (int i = 0; i < kOrthMaxK; i += 2) {
+                    if (i <= j) s0 += z[i] * G[i * ldg + j];
+                    if (i + 1 <= j) s1 += z[i + 1] * G[(i + 1) * ldg + j];
+                }
+                Z[r * ldz + j] = s0 + s1;
+            }
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < n * k; i += nt) Zg[i] = Z[(i / k) * ldz + i % k];
+    if (t == 0 && fail) atomicOr(status, 2);
+}
+
 // V[:, c] = H_0 ... H_{n-2} Z[:, c] for a chunk of cw columns held in LDS.
+// Reflectors are staged into LDS kRefl at a time.
+constexpr int kRefl = 8;
 __global__ void __launch_bounds__(256) k_unmtr(const cd *__restrict__ A, int64_t lda, int n, int k,
                                                int cw, const cd *__restrict__ tau,
                                                const double *__restrict__ Z, cd *__restrict__ V,
                                                int64_t ldv) {
     extern __shared__ unsigned char smem_raw[];
     cd *Vs = reinterpret_cast<cd *>(smem_raw);   // [n][cw + 1]
-    cd *vb = Vs + (size_t)n * (cw + 1);          // [n]
-    cd *sp = vb + n;                             // [blockDim] partial dots
+    cd *vb = Vs + (size_t)n * (cw + 1);          // [kRefl][n] staged reflectors
+    cd *sp = vb + (size_t)kRefl * n;             // [blockDim] partial dots
     cd *sc = sp + blockDim.x;                    // [cw]
     const int t = threadIdx.x, nt = blockDim.x;
     const int c0 = blockIdx.x * cw;
@@ -569,44 +661,67 @@ __global__ void __launch_bounds__(256) k_unmtr(const cd *__restrict__ A, int64_t
         const int r = i / cw, c = i % cw;
         Vs[r * LD + c] = cd{c < ncol ? Z[(int64_t)r * k + c0 + c] : 0.0, 0.0};
     }
-    __syncthreads();
     const int parts = nt / cw;   // threads per column in the dot products
-    for (int j = n - 2; j >= 0; --j) {
-        const cd tj = tau[j];
-        if (tj.x == 0.0 && tj.y == 0.0) continue;
-        const int L = n - j - 1;
-        for (int i = t; i < L; i += nt) vb[i] = (i == 0) ? cd{1.0, 0.0} : A[(int64_t)j * lda + j + 1 + i];
+    for (int jhi = n - 2; jhi >= 0; jhi -= kRefl) {
+        const int jlo = max(0, jhi - kRefl + 1);
         __syncthreads();
-        {
-            const int c = t % cw, p = t / cw;
-            double sr = 0.0, si = 0.0;
-            if (p < parts)
-                for (int i = p; i < L; i += parts) {
-                    const cd vv = vb[i], x = Vs[(j + 1 + i) * LD + c];
-                    sr += vv.x * x.x + vv.y * x.y;
-                    si += vv.x * x.y - vv.y * x.x;
-                }
-            sp[t] = cd{sr, si};
-        }
-        __syncthreads();
-        if (t < cw) {
-            double sr = 0.0, si = 0.0;
-            for (int p = 0; p < parts; ++p) {
-                sr += sp[p * cw + t].x;
-                si += sp[p * cw + t].y;
+        // stage reflectors jhi..jlo: slot q holds reflector jhi - q, rows j+1..n-1
+        for (int idx = t; idx < kRefl * n; idx += nt) {
+            const int q = idx / n, i = idx % n;
+            const int j = jhi - q;
+            if (j >= jlo) {
+                const int L = n - j - 1;
+                vb[q * n + i] = (i >= L) ? cd{0.0, 0.0} : (i == 0) ? cd{1.0, 0.0} : A[(int64_t)j * lda + j + 1 + i];
             }
-            sc[t] = cmulz(tj, cd{sr, si});
         }
         __syncthreads();
-        for (int i = t; i < L * cw; i += nt) {
-            const int r = i / cw, c = i % cw;
-            const cd pr = cmulz(vb[r], sc[c]);
-            cd &x = Vs[(j + 1 + r) * LD + c];
-            x.x -= pr.x;
-            x.y -= pr.y;
+        for (int j = jhi; j >= jlo; --j) {
+            const cd tj = tau[j];
+            if (tj.x == 0.0 && tj.y == 0.0) continue;
+            const cd *vv = vb + (jhi - j) * n;
+            const int L = n - j - 1;
+            {
+                const int c = t % cw, p = t / cw;
+                double sr0 = 0.0, si0 = 0.0, sr1 = 0.0, si1 = 0.0;
+                if (p < parts) {
+                    int i = p;
+                    for (; i + parts < L; i += 2 * parts) {
+                        const cd a0 = vv[i], x0 = Vs[(j + 1 + i) * LD + c];
+                        const cd a1 = vv[i + parts], x1 = Vs[(j + 1 + i + parts) * LD + c];
+                        sr0 += a0.x * x0.x + a0.y * x0.y;
+                        si0 += a0.x * x0.y - a0.y * x0.x;
+                        sr1 += a1.x * x1.x + a1.y * x1.y;
+                        si1 += a1.x * x1.y - a1.y * x1.x;
+                    }
+                    for (; i < L; i += parts) {
+                        const cd a0 = vv[i], x0 = Vs[(j + 1 + i) * LD + c];
+                        sr0 += a0.x * x0.x + a0.y * x0.y;
+                        si0 += a0.x * x0.y - a0.y * x0.x;
+                    }
+                }
+                sp[t] = cd{sr0 + sr1, si0 + si1};
+            }
+            __syncthreads();
+            if (t < cw) {
+                double sr = 0.0, si = 0.0;
+                for (int p = 0; p < parts; ++p) {
+                    sr += sp[p * cw + t].x;
+                    si += sp[p * cw + t].y;
+                }
+                sc[t] = cmulz(tj, cd{sr, si});
+            }
+            __syncthreads();
+            for (int i = t; i < L * cw; i += nt) {
+                const int r = i / cw, c = i % cw;
+                const cd pr = cmulz(vv[r], sc[c]);
+                cd &x = Vs[(j + 1 + r) * LD + c];
+                x.x -= pr.x;
+                x.y -= pr.y;
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
+    __syncthreads();
     for (int i = t; i < n * ncol; i += nt) {
         const int c = i / n, r = i % n;
         V[(int64_t)(c0 + c) * ldv + r] = Vs[r * LD + c];
@@ -662,14 +777,23 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     PW_HIP(hipFuncSetAttribute((const void *)k_stein, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm3));
     hipLaunchKernelGGL(k_stein, dim3((k + E - 1) / E), dim3(64), sm3, st, d, e, n, k, E, w, Z);
     // 4. orthogonalisation
+    const size_t smc = ((size_t)n * (k + 1) + (size_t)k * (k + 1) + k) * 8;
+    if (k <= kOrthMaxK && n <= 256 && smc <= 150 * 1024) {
+        PW_HIP(hipFuncSetAttribute((const void *)k_orth_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smc));
+        hipLaunchKernelGGL(k_orth_chol, dim3(1), dim3(256), smc, st, Z, n, k, status);
+    } else {
     const bool in_lds = (size_t)n * (k + 1) * 8 + (size_t)(k + 1024) * 8 <= 140 * 1024;
     const size_t sm4 = (size_t)(k + 1024) * 8 + (in_lds ? (size_t)n * (k + 1) * 8 : 0);
     PW_HIP(hipFuncSetAttribute((const void *)k_orth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm4));
     hipLaunchKernelGGL(k_orth, dim3(1), dim3(1024), sm4, st, Z, n, k, in_lds ? 1 : 0, w, 2e-5, d, e);
+    }
     // 5. back-transform
     int cw = 32;
-    while (cw > 1 && (size_t)n * (cw + 1) * 16 + (size_t)n * 16 + 256 * 16 + cw * 16 > 120 * 1024) cw /= 2;
-    const size_t sm5 = (size_t)n * (cw + 1) * 16 + (size_t)n * 16 + 256 * 16 + (size_t)cw * 16;
+    auto sm5_of = [&](int w_) {
+        return (size_t)n * (w_ + 1) * 16 + (size_t)kRefl * n * 16 + 256 * 16 + (size_t)w_ * 16;
+    };
+    while (cw > 1 && sm5_of(cw) > 150 * 1024) cw /= 2;
+    const size_t sm5 = sm5_of(cw);
     PW_HIP(hipFuncSetAttribute((const void *)k_unmtr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm5));
     hipLaunchKernelGGL(k_unmtr, dim3((k + cw - 1) / cw), dim3(256), sm5, st, A, lda, n, k, cw, tau, Z,
                        V, ldv);
