@@ -9,6 +9,7 @@
 //    inverse iteration, classical Gram-Schmidt applied twice, back-transform.
 #include <algorithm>
 #include <cfloat>
+#include <type_traits>
 
 #include "pw_internal.h"
 
@@ -312,6 +313,234 @@ __global__ void __launch_bounds__(kTrdThreads)
         }
         __syncthreads();
     }
+}
+
+// ---- register-resident reduction for n <= 32 T (T <= 6) ----------------------
+// The same Householder sequence as k_hetrd (H_j = I - tau_j v_j v_j^H,
+// A <- H_j^H A H_j, w = tau y - (|tau|^2 / 2) Re(v^H y) v, A -= w v^H + v w^H),
+// but the whole matrix stays in registers: 1024 threads on a 32 x 32 grid,
+// thread (ti, tj) holds A(ti + 32a, tj + 32b) for tiles b <= a.  Off-diagonal
+// tiles are stored once and used for both triangles of y = A v; diagonal tiles
+// are stored in full.  Per column: the pivot column goes to LDS, one wave
+// forms the reflector, every thread accumulates its tiles' row and column
+// partials of y (row sums over tj by DPP, column sums per half-wave in LDS),
+// four threads per row add the partials into w, and every thread applies the
+// rank-2 update to its tiles.  Tiles whose rows or columns are all finished
+// are skipped.  All sums run in a fixed order (deterministic).
+constexpr int kRfMaxT = 6;
+
+template <int B, int E, class F>
+__device__ __forceinline__ void unroll_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        unroll_for<B + 1, E>(static_cast<F &&>(f));
+    }
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double x) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+// sum over the 16 lanes of a DPP row; every lane of the row gets the same value
+__device__ __forceinline__ double row16_sum(double x) {
+    x += dpp_f64<0xB1>(x);    // quad_perm [1,0,3,2]
+    x += dpp_f64<0x4E>(x);    // quad_perm [2,3,0,1]
+    x += dpp_f64<0x141>(x);   // row_half_mirror
+    x += dpp_f64<0x140>(x);   // row_mirror
+    return x;
+}
+__device__ __forceinline__ double quad_sum(double x) {
+    x += dpp_f64<0xB1>(x);
+    x += dpp_f64<0x4E>(x);
+    return x;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+    x = row16_sum(x);
+    x += __shfl_xor(x, 16);
+    x += __shfl_xor(x, 32);
+    return x;
+}
+
+template <int T>
+__global__ void __launch_bounds__(1024)
+    k_hetrd_rf(cd *__restrict__ A, int64_t lda, int n, double *__restrict__ dd,
+               double *__restrict__ ee, cd *__restrict__ tau_out) {
+    constexpr int NR = 32 * T;
+    constexpr int NE = T * (T + 1) / 2;
+    __shared__ cd xs[NR];        // pivot column
+    __shared__ cd vs[NR];        // reflector, zero outside rows j+1..n-1
+    __shared__ cd ws[NR];        // w, zero outside rows j+1..n-1
+    __shared__ cd pr[2][NR];     // row sums of y, one per DPP row of a half-wave
+    __shared__ cd pc[32][NR];    // column sums of y, one per half-wave
+    __shared__ double sv[16];    // per-wave partials of Re(v^H A v)
+    __shared__ cd s_tau;
+    const int t = threadIdx.x, tj = t & 31, ti = t >> 5, wave = t >> 6, lane = t & 63;
+
+    cd E[NE];
+    unroll_for<0, T>([&](auto a_) {
+        constexpr int a = a_;
+        unroll_for<0, a + 1>([&](auto b_) {
+            constexpr int b = b_;
+            const int i = ti + 32 * a, c = tj + 32 * b;
+            cd m = {0.0, 0.0};
+            if (i < n && c < n) {   // exact Hermitian part (A + A^H) / 2
+                const cd x = A[(int64_t)c * lda + i], y = A[(int64_t)i * lda + c];
+                m = cd{0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
+                if (i == c) m.y = 0.0;
+            }
+            E[a * (a + 1) / 2 + b] = m;
+        });
+    });
+    for (int i = t; i < NR; i += 1024) vs[i] = ws[i] = cd{0.0, 0.0};
+    // pivot column of step j: rows j..n-1 of column j, from its owners
+    auto gather = [&](int j) {
+        if (tj != (j & 31)) return;
+        const int jb = j >> 5;
+        unroll_for<0, T>([&](auto b_) {
+            constexpr int b = b_;
+            if (b != jb) return;
+            unroll_for<b, T>([&](auto a_) {
+                constexpr int a = a_;
+                const int i = ti + 32 * a;
+                if (i >= j && i < n) xs[i] = E[a * (a + 1) / 2 + b];
+            });
+        });
+    };
+    gather(0);
+    __syncthreads();
+    for (int j = 0; j + 1 < n; ++j) {
+        // ---- reflector from the pivot column (wave 0) ----
+        if (wave == 0) {
+            double sg = 0.0;
+            for (int r = j + 2 + lane; r < n; r += 64) sg += xs[r].x * xs[r].x + xs[r].y * xs[r].y;
+            const double sigma = wave_sum(sg);
+            const cd alpha = xs[j + 1];
+            cd tau, scale;
+            double beta;
+            if (sigma == 0.0 && alpha.y == 0.0) {
+                tau = cd{0.0, 0.0};
+                beta = alpha.x;
+                scale = cd{0.0, 0.0};
+            } else {
+                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
+                beta = alpha.x >= 0.0 ? -nrm : nrm;
+                tau = cd{(beta - alpha.x) / beta, -alpha.y / beta};
+                const double dr = alpha.x - beta, di = alpha.y;
+                const double den = dr * dr + di * di;
+                scale = cd{dr / den, -di / den};
+            }
+            const bool reflect = !(tau.x == 0.0 && tau.y == 0.0);
+            for (int r = j + 1 + lane; r < n; r += 64) {
+                cd vv;
+                if (!reflect) vv = cd{0.0, 0.0};
+                else if (r == j + 1) vv = cd{1.0, 0.0};
+                else vv = cmulz(xs[r], scale);
+                vs[r] = vv;
+                if (r > j + 1) A[(int64_t)j * lda + r] = vv;   // kept for the back-transform
+            }
+            if (lane == 0) {
+                dd[j] = xs[j].x;
+                ee[j] = beta;
+                tau_out[j] = tau;
+                A[(int64_t)j * lda + j + 1] = cd{beta, 0.0};
+                vs[j] = ws[j] = cd{0.0, 0.0};
+                s_tau = tau;
+            }
+        }
+        __syncthreads();
+        // ---- partials of y = A v: row sums, then column sums (few live registers) ----
+        {
+            double vpart = 0.0;
+            unroll_for<0, T>([&](auto a_) {
+                constexpr int a = a_;
+                if (32 * a + 31 <= j) return;   // rows all finished
+                double rr = 0.0, ri = 0.0;
+                unroll_for<0, a + 1>([&](auto b_) {
+                    constexpr int b = b_;
+                    if (32 * b + 31 <= j) return;   // columns all finished
+                    const cd e = E[a * (a + 1) / 2 + b];
+                    const cd vj = vs[tj + 32 * b];
+                    rr += e.x * vj.x - e.y * vj.y;
+                    ri += e.x * vj.y + e.y * vj.x;
+                });
+                const cd vi = vs[ti + 32 * a];
+                vpart += vi.x * rr + vi.y * ri;
+                rr = row16_sum(rr);
+                ri = row16_sum(ri);
+                if ((tj & 15) == 0) pr[tj >> 4][ti + 32 * a] = cd{rr, ri};
+            });
+            unroll_for<0, T - 1>([&](auto b_) {   // conj(e) v_i into y_j, off-diagonal tiles
+                constexpr int b = b_;
+                if (32 * b + 31 <= j) return;
+                double cr = 0.0, ci = 0.0;
+                unroll_for<b + 1, T>([&](auto a_) {
+                    constexpr int a = a_;
+                    const cd e = E[a * (a + 1) / 2 + b];
+                    const cd vi = vs[ti + 32 * a];
+                    cr += e.x * vi.x + e.y * vi.y;
+                    ci += e.x * vi.y - e.y * vi.x;
+                });
+                const cd vj = vs[tj + 32 * b];
+                vpart += vj.x * cr + vj.y * ci;
+                pc[ti][tj + 32 * b] = cd{cr, ci};
+            });
+            vpart = wave_sum(vpart);
+            if (lane == 0) sv[wave] = vpart;
+        }
+        __syncthreads();
+        // ---- w = tau y - nu v, four threads per row ----
+        if (t < 4 * NR) {
+            const int r = t >> 2, q = t & 3;
+            const bool live = r > j && r < n;
+            double sr = 0.0, si = 0.0;
+            if (live) {
+                if (r < 32 * (T - 1)) {   // the last row tile has no tile below the diagonal
+#pragma unroll
+                    for (int h = 0; h < 8; ++h) {
+                        sr += pc[8 * q + h][r].x;
+                        si += pc[8 * q + h][r].y;
+                    }
+                }
+                if (q == 0) {
+                    sr += pr[0][r].x + pr[1][r].x;
+                    si += pr[0][r].y + pr[1][r].y;
+                }
+            }
+            sr = quad_sum(sr);
+            si = quad_sum(si);
+            double vhy = 0.0;
+#pragma unroll
+            for (int w = 0; w < 16; ++w) vhy += sv[w];
+            const cd tau = s_tau;
+            const double nu = 0.5 * (tau.x * tau.x + tau.y * tau.y) * vhy;
+            if (live && q == 0) {
+                const cd ty = cmulz(tau, cd{sr, si});
+                const cd vr = vs[r];
+                ws[r] = cd{ty.x - nu * vr.x, ty.y - nu * vr.y};
+            }
+        }
+        __syncthreads();
+        // ---- A -= w v^H + v w^H on the live tiles ----
+        unroll_for<0, T>([&](auto a_) {
+            constexpr int a = a_;
+            if (32 * a + 31 <= j) return;
+            const cd vi = vs[ti + 32 * a], wi = ws[ti + 32 * a];
+            unroll_for<0, a + 1>([&](auto b_) {
+                constexpr int b = b_;
+                if (32 * b + 31 <= j) return;
+                const cd vj = cconj(vs[tj + 32 * b]), wj = cconj(ws[tj + 32 * b]);
+                const cd u1 = cmulz(wi, vj), u2 = cmulz(vi, wj);
+                cd &e = E[a * (a + 1) / 2 + b];
+                e.x -= u1.x + u2.x;
+                e.y -= u1.y + u2.y;
+            });
+        });
+        gather(j + 1);
+        __syncthreads();
+    }
+    if (t == 0) dd[n - 1] = xs[n - 1].x;
 }
 
 // Sturm counts (number of eigenvalues below x) at two shifts at once: the two
@@ -759,12 +988,24 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     p += align((size_t)n * 8);
     double *Z = reinterpret_cast<double *>(p);
     // 1. tridiagonalisation (the trailing block of A is overwritten in both triangles)
+    if (n <= 32 * kRfMaxT) {
+        const int T = (n + 31) / 32;
+        switch (T) {
+            case 1: hipLaunchKernelGGL(k_hetrd_rf<1>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            case 2: hipLaunchKernelGGL(k_hetrd_rf<2>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            case 3: hipLaunchKernelGGL(k_hetrd_rf<3>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            case 4: hipLaunchKernelGGL(k_hetrd_rf<4>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            case 5: hipLaunchKernelGGL(k_hetrd_rf<5>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            default: hipLaunchKernelGGL(k_hetrd_rf<6>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+        }
+    } else {
     const size_t base1 = (size_t)(5 + kTrdThreads / 64) * n * sizeof(cd) + kTrdThreads * sizeof(double);
     const size_t cap_bytes = base1 < 156 * 1024 ? 156 * 1024 - base1 : 0;
     const int lds_cap = (int)(cap_bytes / sizeof(cd));
     const size_t sm1 = base1 + (size_t)lds_cap * sizeof(cd);
     PW_HIP(hipFuncSetAttribute((const void *)k_hetrd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1));
     hipLaunchKernelGGL(k_hetrd, dim3(1), dim3(kTrdThreads), sm1, st, A, lda, n, d, e, tau, lds_cap);
+    }
     // 2. eigenvalues
     const size_t sm2 = 2 * (size_t)n * 8;
     // 4 eigenvalues (16 lanes each) per workgroup, spread over k/4 CUs
