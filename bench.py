@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--mixed-steps", type=int, default=2, help="timed solves in the mixed form")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -86,19 +87,19 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_0707_3405_amd import PlaneWaveProblem, Context
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_FP64, PW_PREC_MIXED
     from workloads import make_workload
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = make_workload(WORKLOAD)
     log(f"workload {WORKLOAD}: L={w.L} ecut={w.ecut} n={w.n} M={w.nbands} m={w.block}")
-    prob = PlaneWaveProblem.from_workload(w, device=0)
-    stream = prob.ctx.stream
+    # the workspace is sized for the mixed form, which also covers FP64
+    prob = PlaneWaveProblem.from_workload(w, device=0, prec=PW_PREC_MIXED)
     npw = prob.npw
     X = prob.empty_block(w.nbands)
 
-    def solve():
-        eig, st = prob.ctx.lobpcg_solve(w.nbands, w.block, w.tol, 300, X, use_guess=False)
+    def solve(prec=PW_PREC_FP64):
+        eig, st = prob.ctx.lobpcg_solve(w.nbands, w.block, w.tol, 300, X, use_guess=False, prec=prec)
         return eig
 
     for i in range(args.warmup):
@@ -122,22 +123,55 @@ def main():
     value = w.nbands / (elapsed / args.steps)
     res = prob.ctx.get_residuals(w.nbands)
     stats = prob.ctx.get_stats()
+    eig64 = eig.copy()
+
+    # ---- the same cell in the mixed form (complex64 iteration + FP64 refinement)
+    mixed = None
+    if args.mixed_steps > 0:
+        solve(PW_PREC_MIXED)
+        torch.cuda.synchronize()
+        mlat = []
+        for i in range(args.mixed_steps):
+            t0 = time.perf_counter()
+            eigm = solve(PW_PREC_MIXED)
+            torch.cuda.synchronize()
+            mlat.append(time.perf_counter() - t0)
+            log(f"mixed step {i + 1}/{args.mixed_steps}: {mlat[-1] * 1e3:.1f} ms")
+        mst = prob.ctx.get_stats()
+        mres = prob.ctx.get_residuals(w.nbands)
+        err = np.abs(eigm - eig64)
+        mixed = {"value": w.nbands / float(np.mean(mlat)), "unit": "eigenpairs/s",
+                 "ms_per_solve": 1e3 * float(np.mean(mlat)),
+                 "latency_p50_ms": float(np.percentile(np.array(mlat) * 1e3, 50)),
+                 "latency_p99_ms": float(np.percentile(np.array(mlat) * 1e3, 99)),
+                 "speedup_vs_fp64": (w.nbands / float(np.mean(mlat))) / value,
+                 "max_abs_eig_diff_vs_fp64_ha": float(err.max()),
+                 "mean_abs_eig_diff_vs_fp64_ha": float(err.mean()),
+                 "max_residual": float(mres.max()),
+                 "iterations": mst["iterations"], "complex64_iterations": mst["mixed_iterations"],
+                 "phase_ms": {k: mst[k] for k in ("ms_apply", "ms_gemm", "ms_dense", "ms_vec",
+                                                  "ms_final_rr")}}
 
     # ---- H.X FFT apply (local part, 64 bands), its own context without projectors
     mil = prob.ctx.get_miller()
     nst = len({(a, b) for a, b, _ in mil})
     nb = w.block
     loc = PlaneWaveProblem(w.cell, w.kfrac, w.ecut, w.n, w.vgrid, None, (), None, nbands=nb,
-                           block=nb, device=0)
+                           block=nb, device=0, prec=PW_PREC_MIXED)
     Xa = torch.randn((nb, npw), dtype=torch.complex128, device="cuda")
     Ya = torch.empty_like(Xa)
     t_fft = event_time_ms(torch, loc.ctx.stream, lambda: loc.ctx.apply_H(Xa, Ya), 20)
+    Xa32, Ya32 = Xa.to(torch.complex64), torch.empty((nb, npw), dtype=torch.complex64, device="cuda")
+    t_fft32 = event_time_ms(torch, loc.ctx.stream,
+                            lambda: loc.ctx.apply_H(Xa32, Ya32, prec=PW_PREC_MIXED), 20)
     bc = 16
     n3 = w.n ** 3
     nzp = 2 * int(np.abs(mil).max()) + 1          # kept z-planes of the plane-first model
     b_alg_survey = nb * (2 * npw * bc + 4 * nzp * w.n ** 2 * bc) + n3 * 8
     b_alg_design = nb * (3 * npw * bc + 4 * nst * w.n * bc) + n3 * 8
     fft_gbs = b_alg_design / (t_fft * 1e-3) / 1e9
+    b_alg_design32 = nb * (3 * npw * 8 + 4 * nst * w.n * 8) + n3 * 4
+    fft_gbs32 = b_alg_design32 / (t_fft32 * 1e-3) / 1e9
 
     # ---- Gram GEMM at the Rayleigh-Ritz shape: [X P W]^H [HX HP HW], 192 x 192, K = npw
     ncol = 3 * w.block
@@ -201,6 +235,8 @@ def main():
         "hx_fft_gbs": fft_gbs,
         "hx_fft_ms_per_64_bands": t_fft,
         "hx_fft_gbs_survey_byte_model": b_alg_survey / (t_fft * 1e-3) / 1e9,
+        "hx_fft_gbs_complex64": fft_gbs32,
+        "hx_fft_ms_per_64_bands_complex64": t_fft32,
         "gram_tflops": gram_tflops,
         "gram_ms": t_gram,
         "latency_p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
@@ -211,6 +247,7 @@ def main():
         "max_residual": float(res.max()),
         "roofline": roof,
         "roofline_all": roofs,
+        "mixed": mixed,
     }
     if not args.no_cpu:
         cores = len(os.sched_getaffinity(0))

@@ -52,9 +52,17 @@ typedef enum {
     PW_ERR_NUMERIC = 6         /* NaN/Inf or a breakdown the solver could not recover from */
 } pw_status;
 
+/* Precision of the iteration.  PW_PREC_MIXED runs the block iteration on
+ * complex64 blocks: the FFT apply, V(r) multiply, projector and Gram GEMMs in
+ * FP32 (FP32 matrix cores, FP32 sums within a K chunk, chunk sums in FP64),
+ * while the Gram results, Cholesky factors, Rayleigh-Ritz eigenproblems and
+ * every reduction stay FP64.  Each block is iterated to a residual of
+ * max(tol, 1e-5), then the FP64 iteration refines all bands from those
+ * vectors to tol and runs the final Rayleigh-Ritz, so the returned
+ * eigenpairs meet the same residual test as PW_PREC_FP64. */
 typedef enum {
     PW_PREC_FP64 = 0,          /* every step in complex128 / float64 */
-    PW_PREC_MIXED = 1          /* reserved: FFT apply in complex64, FP64 small dense steps */
+    PW_PREC_MIXED = 1          /* complex64 iteration, FP64 small dense steps and refinement */
 } pw_precision;
 
 /* Per-solve counters and phase times (milliseconds, measured with HIP events
@@ -70,6 +78,8 @@ typedef struct {
     double ms_dense;           /* small dense FP64 steps (Cholesky, eigensolver) */
     double ms_vec;             /* residual / preconditioner / copies */
     double ms_final_rr;        /* final Rayleigh-Ritz over all bands */
+    int32_t mixed_iterations;  /* PW_PREC_MIXED: iterations of the complex64 stage (included in
+                                  iterations); 0 for PW_PREC_FP64 */
 } pw_stats;
 
 /* Create a context bound to HIP device `device` and stream `hip_stream`
@@ -113,8 +123,9 @@ pw_status pw_set_projectors(pw_ctx ctx, int32_t natom, const double *pos,
                             int32_t nproj_per_atom, const int32_t *lm, const double *D);
 
 /* Device workspace the caller allocates: bytes needed by pw_lobpcg_solve for
- * (nbands, block) and by pw_apply_H (which works in chunks of `block`
- * columns). */
+ * (nbands, block) at precision prec, and by pw_apply_H (which works in chunks
+ * of `block` columns).  A workspace sized for PW_PREC_MIXED also serves
+ * PW_PREC_FP64. */
 pw_status pw_workspace_size(pw_ctx ctx, int32_t nbands, int32_t block, pw_precision prec,
                             size_t *bytes);
 /* Hand the workspace to the context (device pointer, 256-byte aligned).  The
@@ -122,8 +133,10 @@ pw_status pw_workspace_size(pw_ctx ctx, int32_t nbands, int32_t block, pw_precis
 pw_status pw_set_workspace(pw_ctx ctx, void *dptr, size_t bytes);
 
 /* Y = H X on the context stream (rows a2-a7 of the hot path).  X, Y: device,
- * complex128, column-major [npw x nb], ldx, ldy >= npw; X and Y must not
- * overlap.  Needs basis, potential and workspace.  Asynchronous. */
+ * column-major [npw x nb], ldx, ldy >= npw, complex128 for PW_PREC_FP64 and
+ * complex64 for PW_PREC_MIXED (FFT, V(r) multiply and projector GEMMs then
+ * run in FP32); X and Y must not overlap.  Needs basis, potential and a
+ * workspace sized for prec.  Asynchronous. */
 pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ldy,
                      int32_t nb, pw_precision prec);
 
@@ -131,8 +144,10 @@ pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ld
  * of `block` bands, each block kept orthogonal to the previous ones, then a
  * final Rayleigh-Ritz over all bands.  Convergence per block: every residual
  * ||H x - theta x||_2 (||x||_2 = 1) <= tol.  X: device complex128
- * [npw x nbands], ldx >= npw; on entry a starting guess if use_guess != 0,
- * on exit the orthonormal eigenvectors.  eig: host double[nbands], ascending.
+ * [npw x nbands], ldx >= npw, for both precisions; on entry a starting guess
+ * if use_guess != 0, on exit the orthonormal eigenvectors.  prec: see
+ * pw_precision (the workspace must be sized for it).  eig: host
+ * double[nbands], ascending.
  * Returns PW_ERR_NOT_CONVERGED (with the best pairs written) if a block hits
  * max_iter or a final residual exceeds tol.  Synchronises the stream. */
 pw_status pw_lobpcg_solve(pw_ctx ctx, int32_t nbands, int32_t block, double tol,
@@ -159,6 +174,15 @@ pw_status pw_gram(pw_ctx ctx, const void *A, int64_t lda, const void *B, int64_t
 pw_status pw_block_update(pw_ctx ctx, const void *A, int64_t lda, const void *C, int64_t ldc,
                           int64_t K, int32_t p, int32_t q, double alpha, double beta,
                           void *Y, int64_t ldy);
+/* The same two products on complex64 blocks (the PW_PREC_MIXED iteration):
+ * A, B, Y complex64; C complex128 (pw_gram_mixed: FP32 products and sums
+ * within each K chunk, chunk partials summed in FP64; pw_block_update_mixed:
+ * C rounded to complex64 as it is read, FP32 products and sums). */
+pw_status pw_gram_mixed(pw_ctx ctx, const void *A, int64_t lda, const void *B, int64_t ldb,
+                        int64_t K, int32_t p, int32_t q, void *C, int64_t ldc);
+pw_status pw_block_update_mixed(pw_ctx ctx, const void *A, int64_t lda, const void *C,
+                                int64_t ldc, int64_t K, int32_t p, int32_t q, double alpha,
+                                double beta, void *Y, int64_t ldy);
 /* Lowest k eigenpairs of a Hermitian n x n matrix A (lda >= n) -- the small
  * dense Rayleigh-Ritz eigenproblem of Algorithm 1 step 4 and of the final
  * Rayleigh-Ritz (sec. 3.2, sec. 4.2).  Householder tridiagonalisation,

@@ -26,7 +26,7 @@ EXPORTS = ("pw_create", "pw_destroy", "pw_last_error", "pw_init_basis", "pw_fft_
            "pw_get_miller", "pw_get_kinetic", "pw_set_local_potential", "pw_set_projectors",
            "pw_workspace_size", "pw_set_workspace", "pw_apply_H", "pw_lobpcg_solve",
            "pw_get_residuals", "pw_get_stats", "pw_gram", "pw_block_update", "pw_small_eigh",
-           "pw_residuals")
+           "pw_residuals", "pw_gram_mixed", "pw_block_update_mixed")
 
 
 class PWError(RuntimeError):
@@ -41,7 +41,8 @@ class PWStats(ctypes.Structure):
                 ("h_applies", ctypes.c_int32), ("p_restarts", ctypes.c_int32),
                 ("ms_total", ctypes.c_double), ("ms_apply", ctypes.c_double),
                 ("ms_gemm", ctypes.c_double), ("ms_dense", ctypes.c_double),
-                ("ms_vec", ctypes.c_double), ("ms_final_rr", ctypes.c_double)]
+                ("ms_vec", ctypes.c_double), ("ms_final_rr", ctypes.c_double),
+                ("mixed_iterations", ctypes.c_int32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -82,6 +83,8 @@ def load_library():
         "pw_get_stats": (ctypes.c_int, [P, ctypes.POINTER(PWStats)]),
         "pw_gram": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, P, I64]),
         "pw_block_update": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, D, D, P, I64]),
+        "pw_gram_mixed": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, P, I64]),
+        "pw_block_update_mixed": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, D, D, P, I64]),
         "pw_small_eigh": (ctypes.c_int, [P, P, I64, I32, I32, P, P, I64]),
         "pw_residuals": (ctypes.c_int, [P, P, I64, P, I64, I32, P, P, P, I64]),
     }
@@ -243,18 +246,23 @@ class Context:
 
     # ---- building blocks ---------------------------------------------------------
     def gram(self, A, B, C, K=None, p=None, q=None):
+        """C = A^H B; A, B complex128 (pw_gram) or complex64 (pw_gram_mixed), C complex128."""
         K = A.shape[1] if K is None else K
         p = A.shape[0] if p is None else p
         q = B.shape[0] if q is None else q
-        self._check(self.lib.pw_gram(self.h, _ptr(A), _ld(A), _ptr(B), _ld(B), K, p, q, _ptr(C), _ld(C)))
+        fn = self.lib.pw_gram_mixed if A.dtype == self._torch.complex64 else self.lib.pw_gram
+        self._check(fn(self.h, _ptr(A), _ld(A), _ptr(B), _ld(B), K, p, q, _ptr(C), _ld(C)))
         return C
 
     def block_update(self, A, Cm, Y, alpha=1.0, beta=0.0, K=None, p=None, q=None):
+        """Y = alpha A C + beta Y; A, Y complex128 or complex64, C complex128."""
         K = A.shape[1] if K is None else K
         p = A.shape[0] if p is None else p
         q = Cm.shape[0] if q is None else q
-        self._check(self.lib.pw_block_update(self.h, _ptr(A), _ld(A), _ptr(Cm), _ld(Cm), K, p, q,
-                                             float(alpha), float(beta), _ptr(Y), _ld(Y)))
+        fn = (self.lib.pw_block_update_mixed if A.dtype == self._torch.complex64
+              else self.lib.pw_block_update)
+        self._check(fn(self.h, _ptr(A), _ld(A), _ptr(Cm), _ld(Cm), K, p, q,
+                       float(alpha), float(beta), _ptr(Y), _ld(Y)))
         return Y
 
     def small_eigh(self, A, n, k, w, V):

@@ -696,7 +696,7 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
         h ^= h >> 29;
         at(ZZ, i) = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
     }
-    for (int iter = 0; iter < 3; ++iter) {
+    for (int iter = 0; iter < 2; ++iter) {
         for (int i = 0; i + 1 < n; ++i) {
             if (at(PIV, i) != 0.0) {
                 const double tmp = at(ZZ, i);
@@ -957,6 +957,192 @@ __global__ void __launch_bounds__(256) k_unmtr(const cd *__restrict__ A, int64_t
     }
 }
 
+// CholQR, twice, of the columns of Z [n][k] (k <= 64, all in LDS): G = Z^T Z
+// with 4 x 4 register blocks per thread, G = R^T R by right-looking Cholesky
+// with the unscaled pivot row (one barrier per column), then Z <- Z R^-1 as a
+// triangular solve with one thread per row and the row in registers.
+// Equivalent to Gram-Schmidt in column (eigenvalue) order.
+constexpr int kOc2Ld = 68;   // LDS row stride of Z (doubles)
+constexpr int kOc2Lg = 65;   // LDS row stride of G
+__host__ __device__ constexpr size_t orth_chol2_lds(int n) {
+    return ((size_t)n * kOc2Ld + 64 * kOc2Lg + 128) * sizeof(double);
+}
+__global__ void __launch_bounds__(256) k_orth_chol2(double *__restrict__ Zg, int n, int k,
+                                                    int *__restrict__ status) {
+    extern __shared__ double smd[];
+    double *Z = smd;                        // [n][kOc2Ld], columns >= k zero
+    double *G = Z + (size_t)n * kOc2Ld;     // [64][kOc2Lg]: G, then R (upper)
+    double *dpiv = G + 64 * kOc2Lg;         // [64] pivots used
+    double *rinv = dpiv + 64;               // [64] 1 / R_jj
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int i = t; i < n * kOc2Ld; i += nt) {
+        const int r = i / kOc2Ld, c = i % kOc2Ld;
+        Z[i] = c < k ? Zg[(size_t)r * k + c] : 0.0;
+    }
+    // rows and columns >= k of G / R and rinv stay zero: the solve below then
+    // runs over all 64 columns without guards
+    for (int i = t; i < 64 * kOc2Lg + 128; i += nt) G[i] = 0.0;
+    __syncthreads();
+    bool fail = false;
+    for (int pass = 0; pass < 2; ++pass) {
+        {   // G = Z^T Z, thread t owns rows a0..a0+3 and columns b0..b0+3
+            const int a0 = 4 * (t >> 4), b0 = 4 * (t & 15);
+            if (a0 < k && b0 < k) {
+                double acc[4][4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
+                for (int r = 0; r < n; ++r) {
+                    const double *zr = Z + (size_t)r * kOc2Ld;
+                    double za[4], zb[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        za[i] = zr[a0 + i];
+                        zb[i] = zr[b0 + i];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+#pragma unroll
+                        for (int jj = 0; jj < 4; ++jj) acc[i][jj] += za[i] * zb[jj];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int jj = 0; jj < 4; ++jj) G[(a0 + i) * kOc2Lg + b0 + jj] = acc[i][jj];
+            }
+        }
+        __syncthreads();
+        for (int j = 0; j < k; ++j) {   // Cholesky, upper triangle, unscaled pivot row
+            double d = G[j * kOc2Lg + j];
+            if (!(d > 1e-300)) {
+                fail = true;
+                d = 1.0;
+            }
+            const double inv_d = 1.0 / d;
+            // thread (t / 16, t % 16) updates rows a = j+1+t/16 (step 16), columns b >= a
+            for (int a = j + 1 + (t >> 4); a < k; a += 16) {
+                const double ga = G[j * kOc2Lg + a] * inv_d;
+                for (int b = a + (t & 15); b < k; b += 16) G[a * kOc2Lg + b] -= ga * G[j * kOc2Lg + b];
+            }
+            if (t == 0) dpiv[j] = d;
+            __syncthreads();
+        }
+        for (int j = t >> 4; j < k; j += 16) {   // R_jc = G_jc / sqrt(d_j)
+            const double sd = sqrt(dpiv[j]), isd = 1.0 / sd;
+            for (int c = j + 1 + (t & 15); c < k; c += 16) G[j * kOc2Lg + c] *= isd;
+            if ((t & 15) == 0) {
+                G[j * kOc2Lg + j] = sd;
+                rinv[j] = isd;
+            }
+        }
+        __syncthreads();
+        if (t < n) {   // row t of Z R^-1 (forward substitution); n <= blockDim
+            const int r = t;
+            double z[64];
+            double *zr = Z + (size_t)r * kOc2Ld;
+#pragma unroll
+            for (int c = 0; c < 64; ++c) z[c] = zr[c];
+            // z (128 VGPRs) plus at most 8 values of R in flight: an empty asm
+            // with a memory clobber after every 8 loads bounds the live range
+#pragma unroll
+            for (int c = 0; c < 64; ++c) {
+                const double xc = z[c] * rinv[c];
+                z[c] = xc;
+#pragma unroll
+                for (int c2 = c + 1; c2 < 64; ++c2) {
+                    z[c2] -= xc * G[c * kOc2Lg + c2];
+                    if ((c2 & 7) == 7) asm volatile("" ::: "memory");
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 64; ++c) zr[c] = z[c];   // columns >= k stay zero
+        }
+        __syncthreads();
+    }
+    for (int i = t; i < n * k; i += nt) Zg[i] = Z[(i / k) * kOc2Ld + i % k];
+    if (t == 0 && fail) atomicOr(status, 2);
+}
+
+// V[:, c] = H_0 ... H_{n-2} Z[:, c] for n <= 64 RPL: one wave per kUwCols
+// columns, RPL rows per lane, column sums by DPP and shuffles, no barriers.
+// Reflectors are applied in groups of kUwRing with a ring of kUwRing
+// reflectors loaded ahead, so the loads of one group overlap the work of the
+// previous one.
+constexpr int kUwCols = 4;
+constexpr int kUwRing = 8;
+template <int RPL>
+__global__ void __launch_bounds__(64) k_unmtr_w(const cd *__restrict__ A, int64_t lda, int n, int k,
+                                                const cd *__restrict__ tau,
+                                                const double *__restrict__ Z, cd *__restrict__ V,
+                                                int64_t ldv) {
+    const int l = threadIdx.x;
+    const int c0 = blockIdx.x * kUwCols;
+    cd x[RPL][kUwCols];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q)
+#pragma unroll
+        for (int c = 0; c < kUwCols; ++c) {
+            const int r = l + 64 * q;
+            x[q][c] = cd{(r < n && c0 + c < k) ? Z[(int64_t)r * k + c0 + c] : 0.0, 0.0};
+        }
+    cd ring[kUwRing][RPL];
+    cd rtau[kUwRing];
+    // reflector j (0 <= j <= n-2): rows j+1..n-1, v_{j+1} = 1; j < 0 is a no-op
+    auto load = [&](int slot_j, cd (&v)[RPL], cd &tj) {
+        const int j = slot_j;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int r = l + 64 * q;
+            v[q] = (j >= 0 && r == j + 1) ? cd{1.0, 0.0}
+                                          : ((j >= 0 && r > j + 1 && r < n) ? A[(int64_t)j * lda + r]
+                                                                            : cd{0.0, 0.0});
+        }
+        tj = j >= 0 ? tau[j] : cd{0.0, 0.0};
+    };
+    const int jtop = n - 2;
+#pragma unroll
+    for (int s = 0; s < kUwRing; ++s) load(jtop - s, ring[s], rtau[s]);
+    for (int jg = jtop; jg >= 0; jg -= kUwRing) {
+#pragma unroll
+        for (int s = 0; s < kUwRing; ++s) {
+            const cd tj = rtau[s];
+            cd v[RPL];
+#pragma unroll
+            for (int q = 0; q < RPL; ++q) v[q] = ring[s][q];
+            load(jg - s - kUwRing, ring[s], rtau[s]);   // refill the slot for the next group
+            if (tj.x == 0.0 && tj.y == 0.0) continue;
+#pragma unroll
+            for (int c = 0; c < kUwCols; ++c) {
+                double dr = 0.0, di = 0.0;   // v^H x_c
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    dr += v[q].x * x[q][c].x + v[q].y * x[q][c].y;
+                    di += v[q].x * x[q][c].y - v[q].y * x[q][c].x;
+                }
+                dr = wave_sum(dr);
+                di = wave_sum(di);
+                const cd sc = cmulz(tj, cd{dr, di});
+#pragma unroll
+                for (int q = 0; q < RPL; ++q) {
+                    const cd u = cmulz(v[q], sc);
+                    x[q][c].x -= u.x;
+                    x[q][c].y -= u.y;
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < kUwCols; ++c) {
+        if (c0 + c >= k) break;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            const int r = l + 64 * q;
+            if (r < n) V[(int64_t)(c0 + c) * ldv + r] = x[q][c];
+        }
+    }
+}
+
 __global__ void k_check_w(const double *w, int k, int *status) {
     for (int i = threadIdx.x; i < k; i += blockDim.x)
         if (!isfinite(w[i])) atomicOr(status, 4);
@@ -1019,7 +1205,11 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     hipLaunchKernelGGL(k_stein, dim3((k + E - 1) / E), dim3(64), sm3, st, d, e, n, k, E, w, Z);
     // 4. orthogonalisation
     const size_t smc = ((size_t)n * (k + 1) + (size_t)k * (k + 1) + k) * 8;
-    if (k <= kOrthMaxK && n <= 256 && smc <= 150 * 1024) {
+    if (k <= 64 && orth_chol2_lds(n) <= 150 * 1024) {
+        const size_t sm = orth_chol2_lds(n);
+        PW_HIP(hipFuncSetAttribute((const void *)k_orth_chol2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
+        hipLaunchKernelGGL(k_orth_chol2, dim3(1), dim3(256), sm, st, Z, n, k, status);
+    } else if (k <= kOrthMaxK && n <= 256 && smc <= 150 * 1024) {
         PW_HIP(hipFuncSetAttribute((const void *)k_orth_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smc));
         hipLaunchKernelGGL(k_orth_chol, dim3(1), dim3(256), smc, st, Z, n, k, status);
     } else {
@@ -1029,6 +1219,18 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     hipLaunchKernelGGL(k_orth, dim3(1), dim3(1024), sm4, st, Z, n, k, in_lds ? 1 : 0, w, 2e-5, d, e);
     }
     // 5. back-transform
+    if (n <= 256) {
+        const dim3 g((k + kUwCols - 1) / kUwCols);
+        switch ((n + 63) / 64) {
+            case 1: hipLaunchKernelGGL(k_unmtr_w<1>, g, dim3(64), 0, st, A, lda, n, k, tau, Z, V, ldv); break;
+            case 2: hipLaunchKernelGGL(k_unmtr_w<2>, g, dim3(64), 0, st, A, lda, n, k, tau, Z, V, ldv); break;
+            case 3: hipLaunchKernelGGL(k_unmtr_w<3>, g, dim3(64), 0, st, A, lda, n, k, tau, Z, V, ldv); break;
+            default: hipLaunchKernelGGL(k_unmtr_w<4>, g, dim3(64), 0, st, A, lda, n, k, tau, Z, V, ldv); break;
+        }
+        hipLaunchKernelGGL(k_check_w, dim3(1), dim3(256), 0, st, w, k, status);
+        PW_HIP(hipGetLastError());
+        return;
+    }
     int cw = 32;
     auto sm5_of = [&](int w_) {
         return (size_t)n * (w_ + 1) * 16 + (size_t)kRefl * n * 16 + 256 * 16 + (size_t)w_ * 16;

@@ -317,19 +317,29 @@ void launch_permute_potential(const double *v, int n, double scale, double *v_zy
     PW_HIP(hipGetLastError());
 }
 
-void launch_fft_apply_f64(const SphereDev &sp, const double *v_zyx, const cd *X, int64_t ldx,
-                          cd *Y, int64_t ldy, int nb, cd *S, hipStream_t st) {
+template <class T>
+void fft_apply_impl(const SphereDev &sp, const T *v_zyx, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
+                    int64_t ldy, int nb, cpx<T> *S, hipStream_t st) {
     if (nb <= 0) return;
     switch (sp.n) {
-#define PW_CASE(NN)                                                          \
-    case NN:                                                                 \
-        run_apply<NN, double>(sp, v_zyx, X, ldx, Y, ldy, nb, S, st);         \
+#define PW_CASE(NN)                                                  \
+    case NN:                                                         \
+        run_apply<NN, T>(sp, v_zyx, X, ldx, Y, ldy, nb, S, st);      \
         return;
         PW_FFT_SIZES(PW_CASE)
 #undef PW_CASE
         default:
             throw Error{PW_ERR_ARG, "unsupported FFT size"};
     }
+}
+
+void launch_fft_apply(const SphereDev &sp, const double *v_zyx, const cd *X, int64_t ldx, cd *Y,
+                      int64_t ldy, int nb, cd *S, hipStream_t st) {
+    fft_apply_impl(sp, v_zyx, X, ldx, Y, ldy, nb, S, st);
+}
+void launch_fft_apply(const SphereDev &sp, const float *v_zyx, const cf *X, int64_t ldx, cf *Y,
+                      int64_t ldy, int nb, cf *S, hipStream_t st) {
+    fft_apply_impl(sp, v_zyx, X, ldx, Y, ldy, nb, S, st);
 }
 
 }  // namespace pw

@@ -19,26 +19,53 @@
 // elements of one column (64 contiguous bytes), and lanes 16 apart read the
 // neighbouring 64 bytes.
 //
-// MFMA operand layout (16x16x4 f64, wave64): A operand lane l holds
-// A[i = l%16][k = l/16]; B operand lane l holds B[k = l/16][j = l%16]; result
-// register r of lane l holds D[i = l/16 + 4r][j = l%16] (rows interleaved by 4,
-// as measured on gfx950).
+// MFMA operand layout (16x16x4, wave64): A operand lane l holds
+// A[i = l%16][k = l/16]; B operand lane l holds B[k = l/16][j = l%16].  Result
+// register r of lane l holds D[i][j = l%16] with i = l/16 + 4r for the f64
+// form and i = 4(l/16) + r for the f32 form (both measured on gfx950).
+//
+// The same kernels serve complex128 blocks (v_mfma_f64_16x16x4f64) and the
+// complex64 blocks of the mixed-precision form (v_mfma_f32_16x16x4f32, FP32
+// products and accumulation within a K chunk; the chunk partials are summed
+// in double).  Small coefficient matrices are always complex128 and are
+// rounded to the block type as they are loaded.
 #include "pw_internal.h"
 
 namespace pw {
 namespace {
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ f64x4 mfma(double a, double b, f64x4 c) {
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
+template <class T>
+struct Mfma;
+template <>
+struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(double a, double b, v4 c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int r) { return g + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ __forceinline__ v4 op(float a, float b, v4 c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
+};
 
 constexpr int kTile = 64;      // workgroup tile (complex elements) per dimension
 constexpr int kThreads = 256;  // 4 waves in a 2 x 2 arrangement, 32 x 32 each
 
-__device__ __forceinline__ cd ldg_or_zero(const cd *p, bool ok) {
-    return ok ? *p : cd{0.0, 0.0};
+template <class T>
+__device__ __forceinline__ cpx<T> ldg_or_zero(const cpx<T> *p, bool ok) {
+    return ok ? *p : cpx<T>{T(0), T(0)};
+}
+// coefficient element rounded to the block type
+template <class T>
+__device__ __forceinline__ cpx<T> ldc_or_zero(const cd *p, bool ok) {
+    if (!ok) return cpx<T>{T(0), T(0)};
+    const cd v = *p;
+    return cpx<T>{T(v.x), T(v.y)};
 }
 
 // Map a hardware workgroup id to a logical id so that each XCD (ids are
@@ -49,10 +76,13 @@ __device__ __forceinline__ int xcd_logical(int lin, int total) {
     return xcd * q + min(xcd, r) + local;
 }
 
+template <class T>
 __global__ void __launch_bounds__(kThreads)
-    k_gemm_tn(const cd *__restrict__ A, int64_t lda, const cd *__restrict__ B, int64_t ldb,
+    k_gemm_tn(const cpx<T> *__restrict__ A, int64_t lda, const cpx<T> *__restrict__ B, int64_t ldb,
               int64_t K, int p, int q, int64_t kchunk, int tiles_m, int tiles_n, int nsplit,
-              cd *__restrict__ part) {
+              cpx<T> *__restrict__ part) {
+    using M = Mfma<T>;
+    using v4 = typename M::v4;
     const int total = tiles_m * tiles_n * nsplit;
     const int lid = xcd_logical(blockIdx.x, total);
     // split is the slow index so that the tiles sharing one K chunk run close
@@ -67,14 +97,14 @@ __global__ void __launch_bounds__(kThreads)
     const int64_t kbeg = (int64_t)split * kchunk;
     const int64_t kend = min(K, kbeg + kchunk);
 
-    f64x4 accr[2][2], acci[2][2];
+    v4 accr[2][2], acci[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = f64x4{0, 0, 0, 0};
+        for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = v4{0, 0, 0, 0};
 
-    const cd *Ac[2];
-    const cd *Bc[2];
+    const cpx<T> *Ac[2];
+    const cpx<T> *Bc[2];
     bool aok[2], bok[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
@@ -85,7 +115,7 @@ __global__ void __launch_bounds__(kThreads)
         Bc[t] = B + (int64_t)(bok[t] ? cj : 0) * ldb;
     }
     for (int64_t kb = kbeg; kb < kend; kb += 16) {
-        cd a[2][4], b[2][4];
+        cpx<T> a[2][4], b[2][4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int64_t k = kb + 4 * g + s;
@@ -103,35 +133,36 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
                 for (int nj = 0; nj < 2; ++nj) {
                     // conj(a) * b
-                    accr[mi][nj] = mfma(a[mi][s].x, b[nj][s].x, accr[mi][nj]);
-                    accr[mi][nj] = mfma(a[mi][s].y, b[nj][s].y, accr[mi][nj]);
-                    acci[mi][nj] = mfma(a[mi][s].x, b[nj][s].y, acci[mi][nj]);
-                    acci[mi][nj] = mfma(-a[mi][s].y, b[nj][s].x, acci[mi][nj]);
+                    accr[mi][nj] = M::op(a[mi][s].x, b[nj][s].x, accr[mi][nj]);
+                    accr[mi][nj] = M::op(a[mi][s].y, b[nj][s].y, accr[mi][nj]);
+                    acci[mi][nj] = M::op(a[mi][s].x, b[nj][s].y, acci[mi][nj]);
+                    acci[mi][nj] = M::op(-a[mi][s].y, b[nj][s].x, acci[mi][nj]);
                 }
     }
-    cd *P = part + (size_t)split * p * q;
+    cpx<T> *P = part + (size_t)split * p * q;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int nj = 0; nj < 2; ++nj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = i0 + 16 * mi + g + 4 * r;
+                const int i = i0 + 16 * mi + M::row(g, r);
                 const int j = j0 + 16 * nj + li;
-                if (i < p && j < q) P[(size_t)j * p + i] = cd{accr[mi][nj][r], acci[mi][nj][r]};
+                if (i < p && j < q) P[(size_t)j * p + i] = cpx<T>{accr[mi][nj][r], acci[mi][nj][r]};
             }
 }
 
-__global__ void k_reduce_parts(const cd *__restrict__ part, int nsplit, int p, int q, cd *C,
+template <class T>
+__global__ void k_reduce_parts(const cpx<T> *__restrict__ part, int nsplit, int p, int q, cd *C,
                                int64_t ldc, const double *__restrict__ scale_row, double beta) {
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= (int64_t)p * q) return;
     const int i = (int)(idx % p), j = (int)(idx / p);
     double sr = 0.0, si = 0.0;
     for (int s = 0; s < nsplit; ++s) {
-        const cd v = part[(size_t)s * p * q + idx];
-        sr += v.x;
-        si += v.y;
+        const cpx<T> v = part[(size_t)s * p * q + idx];
+        sr += (double)v.x;
+        si += (double)v.y;
     }
     if (scale_row) {
         sr *= scale_row[i];
@@ -145,10 +176,13 @@ __global__ void k_reduce_parts(const cd *__restrict__ part, int nsplit, int p, i
     *c = cd{sr, si};
 }
 
+template <class T>
 __global__ void __launch_bounds__(kThreads)
-    k_gemm_nn(const cd *__restrict__ A, int64_t lda, const cd *__restrict__ Cm, int64_t ldc,
-              int64_t K, int p, int q, double alpha, double beta, cd *Y, int64_t ldy,
+    k_gemm_nn(const cpx<T> *__restrict__ A, int64_t lda, const cd *__restrict__ Cm, int64_t ldc,
+              int64_t K, int p, int q, double alpha, double beta, cpx<T> *Y, int64_t ldy,
               int tiles_m) {
+    using M = Mfma<T>;
+    using v4 = typename M::v4;
     const int lid = xcd_logical(blockIdx.x, gridDim.x);
     const int tm = lid % tiles_m, tn = lid / tiles_m;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -156,11 +190,11 @@ __global__ void __launch_bounds__(kThreads)
     const int64_t r0 = (int64_t)tm * kTile + (wave & 1) * 32;
     const int c0 = tn * kTile + (wave >> 1) * 32;
 
-    f64x4 accr[2][2], acci[2][2];
+    v4 accr[2][2], acci[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = f64x4{0, 0, 0, 0};
+        for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = v4{0, 0, 0, 0};
 
     bool rok[2], cok[2];
 #pragma unroll
@@ -169,7 +203,7 @@ __global__ void __launch_bounds__(kThreads)
         cok[t] = c0 + 16 * t + li < q;
     }
     for (int kb = 0; kb < p; kb += 16) {
-        cd a[2][4], b[2][4];
+        cpx<T> a[2][4], b[2][4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             const int kk = kb + 4 * g + s;
@@ -178,8 +212,8 @@ __global__ void __launch_bounds__(kThreads)
             for (int t = 0; t < 2; ++t) {
                 a[t][s] = ldg_or_zero(A + (int64_t)(kin ? kk : 0) * lda + (rok[t] ? r0 + 16 * t + li : 0),
                                       kin && rok[t]);
-                b[t][s] = ldg_or_zero(Cm + (int64_t)(cok[t] ? c0 + 16 * t + li : 0) * ldc + (kin ? kk : 0),
-                                      kin && cok[t]);
+                b[t][s] = ldc_or_zero<T>(Cm + (int64_t)(cok[t] ? c0 + 16 * t + li : 0) * ldc + (kin ? kk : 0),
+                                         kin && cok[t]);
             }
         }
 #pragma unroll
@@ -189,10 +223,10 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
                 for (int nj = 0; nj < 2; ++nj) {
                     // a * c
-                    accr[mi][nj] = mfma(a[mi][s].x, b[nj][s].x, accr[mi][nj]);
-                    accr[mi][nj] = mfma(-a[mi][s].y, b[nj][s].y, accr[mi][nj]);
-                    acci[mi][nj] = mfma(a[mi][s].x, b[nj][s].y, acci[mi][nj]);
-                    acci[mi][nj] = mfma(a[mi][s].y, b[nj][s].x, acci[mi][nj]);
+                    accr[mi][nj] = M::op(a[mi][s].x, b[nj][s].x, accr[mi][nj]);
+                    accr[mi][nj] = M::op(-a[mi][s].y, b[nj][s].y, accr[mi][nj]);
+                    acci[mi][nj] = M::op(a[mi][s].x, b[nj][s].y, acci[mi][nj]);
+                    acci[mi][nj] = M::op(a[mi][s].y, b[nj][s].x, acci[mi][nj]);
                 }
     }
     // every wave of the workgroup has read its rows of A before any writes:
@@ -204,23 +238,26 @@ __global__ void __launch_bounds__(kThreads)
         for (int nj = 0; nj < 2; ++nj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = r0 + 16 * mi + g + 4 * r;
+                const int64_t i = r0 + 16 * mi + M::row(g, r);
                 const int j = c0 + 16 * nj + li;
                 if (i < K && j < q) {
-                    cd *y = Y + (int64_t)j * ldy + i;
-                    double yr = alpha * accr[mi][nj][r], yi = alpha * acci[mi][nj][r];
+                    cpx<T> *y = Y + (int64_t)j * ldy + i;
+                    T yr = T(alpha) * accr[mi][nj][r], yi = T(alpha) * acci[mi][nj][r];
                     if (beta != 0.0) {
-                        const cd o = *y;
-                        yr += beta * o.x;
-                        yi += beta * o.y;
+                        const cpx<T> o = *y;
+                        yr += T(beta) * o.x;
+                        yi += T(beta) * o.y;
                     }
-                    *y = cd{yr, yi};
+                    *y = cpx<T>{yr, yi};
                 }
             }
 }
 
+#ifndef PW_SPLIT_WGS
+#define PW_SPLIT_WGS 768   // target workgroup count of a split-K launch
+#endif
 int choose_split(int64_t K, int tiles) {
-    int64_t ns = (768 + tiles - 1) / tiles;
+    int64_t ns = (PW_SPLIT_WGS + tiles - 1) / tiles;
     const int64_t kmax = (K + 255) / 256;
     if (ns > kmax) ns = kmax;
     if (ns < 1) ns = 1;
@@ -236,9 +273,10 @@ size_t gemm_tn_part_elems(int64_t K, int p, int q, int *nsplit_out) {
     return (size_t)ns * p * q;
 }
 
-void launch_gemm_tn_f64(const cd *A, int64_t lda, const cd *B, int64_t ldb, int64_t K, int p,
-                        int q, cd *C, int64_t ldc, const double *scale_row, double beta,
-                        cd *part, size_t part_elems, hipStream_t st) {
+template <class T>
+void gemm_tn_impl(const cpx<T> *A, int64_t lda, const cpx<T> *B, int64_t ldb, int64_t K, int p, int q,
+                  cd *C, int64_t ldc, const double *scale_row, double beta, cd *part, size_t part_elems,
+                  hipStream_t st) {
     if (p <= 0 || q <= 0) return;
     const int tiles_m = (p + kTile - 1) / kTile, tiles_n = (q + kTile - 1) / kTile;
     int ns = choose_split(K, tiles_m * tiles_n);
@@ -249,23 +287,45 @@ void launch_gemm_tn_f64(const cd *A, int64_t lda, const cd *B, int64_t ldb, int6
     ns = (int)((K + kchunk - 1) / kchunk);
     if (ns < 1) ns = 1;
     const int total = tiles_m * tiles_n * ns;
-    hipLaunchKernelGGL(k_gemm_tn, dim3(total), dim3(kThreads), 0, st, A, lda, B, ldb, K, p, q,
-                       kchunk, tiles_m, tiles_n, ns, part);
+    // partials in the block type (the buffer is sized for complex128)
+    cpx<T> *pt = reinterpret_cast<cpx<T> *>(part);
+    hipLaunchKernelGGL(k_gemm_tn<T>, dim3(total), dim3(kThreads), 0, st, A, lda, B, ldb, K, p, q,
+                       kchunk, tiles_m, tiles_n, ns, pt);
     const int64_t n = (int64_t)p * q;
-    hipLaunchKernelGGL(k_reduce_parts, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, part,
+    hipLaunchKernelGGL(k_reduce_parts<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pt,
                        ns, p, q, C, ldc, scale_row, beta);
     PW_HIP(hipGetLastError());
 }
 
-void launch_gemm_nn_f64(const cd *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p,
-                        int q, double alpha, double beta, cd *Y, int64_t ldy, hipStream_t st) {
+template <class T>
+void gemm_nn_impl(const cpx<T> *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
+                  double alpha, double beta, cpx<T> *Y, int64_t ldy, hipStream_t st) {
     if (K <= 0 || q <= 0) return;
     const int tiles_m = (int)((K + kTile - 1) / kTile), tiles_n = (q + kTile - 1) / kTile;
     PW_REQUIRE(!((const void *)A == (const void *)Y) || q <= kTile, PW_ERR_ARG,
                "in-place block update needs q <= 64");
-    hipLaunchKernelGGL(k_gemm_nn, dim3(tiles_m * tiles_n), dim3(kThreads), 0, st, A, lda, C, ldc,
+    hipLaunchKernelGGL(k_gemm_nn<T>, dim3(tiles_m * tiles_n), dim3(kThreads), 0, st, A, lda, C, ldc,
                        K, p, q, alpha, beta, Y, ldy, tiles_m);
     PW_HIP(hipGetLastError());
+}
+
+void launch_gemm_tn(const cd *A, int64_t lda, const cd *B, int64_t ldb, int64_t K, int p, int q,
+                    cd *C, int64_t ldc, const double *scale_row, double beta, cd *part,
+                    size_t part_elems, hipStream_t st) {
+    gemm_tn_impl(A, lda, B, ldb, K, p, q, C, ldc, scale_row, beta, part, part_elems, st);
+}
+void launch_gemm_tn(const cf *A, int64_t lda, const cf *B, int64_t ldb, int64_t K, int p, int q,
+                    cd *C, int64_t ldc, const double *scale_row, double beta, cd *part,
+                    size_t part_elems, hipStream_t st) {
+    gemm_tn_impl(A, lda, B, ldb, K, p, q, C, ldc, scale_row, beta, part, part_elems, st);
+}
+void launch_gemm_nn(const cd *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
+                    double alpha, double beta, cd *Y, int64_t ldy, hipStream_t st) {
+    gemm_nn_impl(A, lda, C, ldc, K, p, q, alpha, beta, Y, ldy, st);
+}
+void launch_gemm_nn(const cf *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
+                    double alpha, double beta, cf *Y, int64_t ldy, hipStream_t st) {
+    gemm_nn_impl(A, lda, C, ldc, K, p, q, alpha, beta, Y, ldy, st);
 }
 
 }  // namespace pw

@@ -63,20 +63,29 @@ struct SphereDev {
 
 // FFT apply (rows a2-a6): Y = T X + (V psi)(G) for nb columns.  S is the stick
 // buffer [nb][n][ldst] complex.  v_zyx is V / n^3 in [z][y][x] order.
-void launch_fft_apply_f64(const SphereDev &sp, const double *v_zyx, const cd *X, int64_t ldx,
-                          cd *Y, int64_t ldy, int nb, cd *S, hipStream_t st);
+void launch_fft_apply(const SphereDev &sp, const double *v_zyx, const cd *X, int64_t ldx,
+                      cd *Y, int64_t ldy, int nb, cd *S, hipStream_t st);
+// complex64 form: v_zyx as float
+void launch_fft_apply(const SphereDev &sp, const float *v_zyx, const cf *X, int64_t ldx,
+                      cf *Y, int64_t ldy, int nb, cf *S, hipStream_t st);
 bool fft_size_supported(int n);
 std::vector<int> fft_supported_sizes();
 
-// Complex FP64 GEMMs on MFMA.
+// Complex GEMMs on MFMA over complex128 (cd) or complex64 (cf) blocks;
+// small outputs and coefficient matrices are always complex128.
 //   tn: part[s] = A^H B over K-chunk s; reduce: C = scale_row * sum_s part[s] (+ beta C)
 size_t gemm_tn_part_elems(int64_t K, int p, int q, int *nsplit_out);
-void launch_gemm_tn_f64(const cd *A, int64_t lda, const cd *B, int64_t ldb, int64_t K, int p,
-                        int q, cd *C, int64_t ldc, const double *scale_row, double beta,
-                        cd *part, size_t part_elems, hipStream_t st);
+void launch_gemm_tn(const cd *A, int64_t lda, const cd *B, int64_t ldb, int64_t K, int p, int q,
+                    cd *C, int64_t ldc, const double *scale_row, double beta, cd *part,
+                    size_t part_elems, hipStream_t st);
+void launch_gemm_tn(const cf *A, int64_t lda, const cf *B, int64_t ldb, int64_t K, int p, int q,
+                    cd *C, int64_t ldc, const double *scale_row, double beta, cd *part,
+                    size_t part_elems, hipStream_t st);
 //   nn: Y = alpha A C + beta Y
-void launch_gemm_nn_f64(const cd *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p,
-                        int q, double alpha, double beta, cd *Y, int64_t ldy, hipStream_t st);
+void launch_gemm_nn(const cd *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
+                    double alpha, double beta, cd *Y, int64_t ldy, hipStream_t st);
+void launch_gemm_nn(const cf *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
+                    double alpha, double beta, cf *Y, int64_t ldy, hipStream_t st);
 
 // Small dense FP64 (single workgroup).
 size_t heev_scratch_bytes(int n, int k);
@@ -89,33 +98,47 @@ void launch_chol_inv_f64(const cd *G, int64_t ldg, int n, cd *Rinv, int64_t ldr,
 
 // Vector kernels.
 size_t resid_part_elems(int64_t npw, int nb);
+// Blocks are complex128 (cd) or complex64 (cf); every reduction is in double.
 // theta[nb]; ekin_nrm[2 nb] = (E_kin per band, |x|^2 per band)
-void launch_band_dots_f64(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
-                          int64_t npw, int nb, double *part, double *theta, double *ekin_nrm,
-                          hipStream_t st);
-void launch_resid_precond_f64(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx,
-                              const double *kin, int64_t npw, int nb, const double *theta,
-                              const double *ekin_nrm, cd *W, int64_t ldw, double *part, double *res,
-                              hipStream_t st);
+void launch_band_dots(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
+                      int64_t npw, int nb, double *part, double *theta, double *ekin_nrm, hipStream_t st);
+void launch_band_dots(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, const double *kin,
+                      int64_t npw, int nb, double *part, double *theta, double *ekin_nrm, hipStream_t st);
+void launch_resid_precond(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
+                          int64_t npw, int nb, const double *theta, const double *ekin_nrm, cd *W,
+                          int64_t ldw, double *part, double *res, hipStream_t st);
+void launch_resid_precond(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, const double *kin,
+                          int64_t npw, int nb, const double *theta, const double *ekin_nrm, cf *W,
+                          int64_t ldw, double *part, double *res, hipStream_t st);
 void launch_build_projectors_f64(const double *qvec, int64_t npw, int natom, const double *pos,
                                  int nlm, const int *lm, double pref, cd *B, int64_t ldb,
                                  hipStream_t st);
 void launch_permute_potential(const double *v, int n, double scale, double *v_zyx,
                               int *bad, hipStream_t st);
-void launch_copy_cols_f64(const cd *A, int64_t lda, cd *B, int64_t ldb, int64_t rows, int cols,
-                          hipStream_t st);
-void launch_random_block_f64(cd *X, int64_t ldx, int64_t rows, int cols, uint64_t seed,
-                             const double *kin, hipStream_t st);
-void launch_zero_f64(cd *X, int64_t ldx, int64_t rows, int cols, hipStream_t st);
+// column copy, with conversion when the storage types differ
+void launch_copy_cols(const cd *A, int64_t lda, cd *B, int64_t ldb, int64_t rows, int cols, hipStream_t st);
+void launch_copy_cols(const cf *A, int64_t lda, cf *B, int64_t ldb, int64_t rows, int cols, hipStream_t st);
+void launch_copy_cols(const cd *A, int64_t lda, cf *B, int64_t ldb, int64_t rows, int cols, hipStream_t st);
+void launch_copy_cols(const cf *A, int64_t lda, cd *B, int64_t ldb, int64_t rows, int cols, hipStream_t st);
+void launch_random_block(cd *X, int64_t ldx, int64_t rows, int cols, uint64_t seed, const double *kin,
+                         hipStream_t st);
+void launch_random_block(cf *X, int64_t ldx, int64_t rows, int cols, uint64_t seed, const double *kin,
+                         hipStream_t st);
+void launch_zero(cd *X, int64_t ldx, int64_t rows, int cols, hipStream_t st);
+void launch_zero(cf *X, int64_t ldx, int64_t rows, int cols, hipStream_t st);
 // P-coefficient block: rows [0, m) of Cfull set to zero (the X rows), others copied.
 void launch_pcoef_f64(const cd *Cfull, int64_t ldc, int n, int m, cd *Cp, int64_t ldp,
                       hipStream_t st);
 // Active-set variants: column jj of the output takes input column act[jj].
-void launch_precond_map_f64(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
-                            int64_t npw, const double *theta, const double *ekin_nrm, const int *act,
-                            int na, cd *W, int64_t ldw, hipStream_t st);
+void launch_precond_map(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
+                        int64_t npw, const double *theta, const double *ekin_nrm, const int *act, int na,
+                        cd *W, int64_t ldw, hipStream_t st);
+void launch_precond_map(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, const double *kin,
+                        int64_t npw, const double *theta, const double *ekin_nrm, const int *act, int na,
+                        cf *W, int64_t ldw, hipStream_t st);
 void launch_pcoef_map_f64(const cd *Cfull, int64_t ldc, int n, int m, const int *act, int na, cd *Cp,
                           int64_t ldp, hipStream_t st);
 void launch_check_finite_f64(const double *a, int64_t n, int *status, hipStream_t st);
+void launch_convert_f64_f32(const double *a, float *b, int64_t n, hipStream_t st);
 
 }  // namespace pw

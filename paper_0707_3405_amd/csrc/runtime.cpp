@@ -7,6 +7,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <type_traits>
 
 #include "pw_internal.h"
 
@@ -90,19 +91,22 @@ struct pw_ctx_s {
     std::vector<void *> dev_allocs;   // context-owned device memory
     double *d_qvec = nullptr;
 
-    // potential
+    // potential (V / N^3 in [z][y][x]); float copy for the mixed form
     bool has_v = false;
     double *d_v = nullptr;
+    float *d_v32 = nullptr;
 
     // projectors
     int natom = 0, nlm = 0;
     cd *d_B = nullptr;
+    pw::cf *d_B32 = nullptr;   // complex64 copy for the mixed form
     double *d_D = nullptr;
 
     // workspace
     char *ws = nullptr;
     size_t ws_bytes = 0;
     int plan_nbands = 0, plan_block = 0;
+    pw_precision plan_prec = PW_PREC_FP64;
 
     int *d_status = nullptr;
     int nst_host = 0, ncx_host = 0;
@@ -133,13 +137,22 @@ struct pw_ctx_s {
 
 namespace {
 
+// Mixed form: the complex64 LOBPCG runs each block to this residual (or its
+// iteration cap), then the FP64 iteration refines from its vectors.
+constexpr double kMixedTol = 1e-5;
+constexpr int kMixedMaxIter = 200;
+
 // ---- workspace plan ----------------------------------------------------------
+// S is the block storage type: cd (complex128) or cf (complex64).  Small
+// matrices (Grams, coefficients, overlaps) are complex128 in both forms.
+template <class S>
 struct Plan {
-    cd *S = nullptr;              // stick buffer [block][n][ldst]
-    cd *Z[2] = {nullptr, nullptr};    // [ldp x 3m] basis blocks [X | P | W]
-    cd *HZ[2] = {nullptr, nullptr};   // [ldp x 3m]
-    cd *HXall = nullptr;          // [ldp x M]
-    cd *T = nullptr;              // [ldp x M] rotation temp
+    S *Sb = nullptr;              // stick buffer [block][n][ldst]
+    S *Z[2] = {nullptr, nullptr};     // [ldp x 3m] basis blocks [X | P | W]
+    S *HZ[2] = {nullptr, nullptr};    // [ldp x 3m]
+    S *HXall = nullptr;           // [ldp x M]
+    S *T = nullptr;               // [ldp x M] rotation temp
+    S *Xs = nullptr;              // [ldp x M] internal copy of X (complex64 form only)
     cd *Pj = nullptr;             // projector overlaps [nproj x block]
     cd *part = nullptr;           // GEMM split-K partials
     size_t part_elems = 0;
@@ -160,20 +173,22 @@ struct Plan {
     size_t bytes = 0;
 };
 
-Plan make_plan(const pw_ctx_s &c, int M, int m, char *base) {
-    Plan p;
+template <class S>
+Plan<S> make_plan(const pw_ctx_s &c, int M, int m, char *base) {
+    Plan<S> p;
     Arena a;
     a.base = base;
     const int64_t ld = c.ldp;
     const int nproj = c.nproj();
     const int n3 = std::max(3 * m, M);
-    p.S = a.take<cd>((size_t)m * c.n * c.sp.ldst);
+    p.Sb = a.take<S>((size_t)m * c.n * c.sp.ldst);
     for (int i = 0; i < 2; ++i) {
-        p.Z[i] = a.take<cd>((size_t)ld * 3 * m);
-        p.HZ[i] = a.take<cd>((size_t)ld * 3 * m);
+        p.Z[i] = a.take<S>((size_t)ld * 3 * m);
+        p.HZ[i] = a.take<S>((size_t)ld * 3 * m);
     }
-    p.HXall = a.take<cd>((size_t)ld * M);
-    p.T = a.take<cd>((size_t)ld * M);
+    p.HXall = a.take<S>((size_t)ld * M);
+    p.T = a.take<S>((size_t)ld * M);
+    if (!std::is_same<S, cd>::value) p.Xs = a.take<S>((size_t)ld * M);
     p.Pj = a.take<cd>((size_t)std::max(nproj, 1) * m);
     size_t pe = 0;
     auto upd = [&](int64_t K, int pp, int qq) {
@@ -206,6 +221,12 @@ Plan make_plan(const pw_ctx_s &c, int M, int m, char *base) {
     return p;
 }
 
+size_t plan_bytes(const pw_ctx_s &c, int M, int m, pw_precision prec) {
+    size_t b = make_plan<cd>(c, M, m, nullptr).bytes;
+    if (prec == PW_PREC_MIXED) b = std::max(b, make_plan<pw::cf>(c, M, m, nullptr).bytes);
+    return b;
+}
+
 void require_basis(const pw_ctx_s *c) {
     PW_REQUIRE(c->has_basis, PW_ERR_STATE, "pw_init_basis has not been called");
 }
@@ -213,39 +234,56 @@ void require_device(const pw_ctx_s *c) {
     PW_REQUIRE(c->device >= 0, PW_ERR_STATE, "host-only context (device < 0) cannot run kernels");
 }
 
-Plan ready_plan(pw_ctx_s *c, int M, int m) {
+template <class S>
+Plan<S> ready_plan(pw_ctx_s *c, int M, int m) {
     require_basis(c);
     require_device(c);
     PW_REQUIRE(c->has_v, PW_ERR_STATE, "pw_set_local_potential has not been called");
     PW_REQUIRE(c->ws != nullptr, PW_ERR_STATE, "pw_set_workspace has not been called");
-    Plan dry = make_plan(*c, M, m, nullptr);
+    Plan<S> dry = make_plan<S>(*c, M, m, nullptr);
     PW_REQUIRE(dry.bytes <= c->ws_bytes, PW_ERR_NOMEM,
-               "workspace too small for this (nbands, block); query pw_workspace_size");
-    return make_plan(*c, M, m, c->ws);
+               "workspace too small for this (nbands, block, precision); query pw_workspace_size");
+    return make_plan<S>(*c, M, m, c->ws);
 }
 
-// ---- H.X ------------------------------------------------------------------------
-void apply_H(pw_ctx_s *c, const Plan &p, int chunk, const cd *X, int64_t ldx, cd *Y, int64_t ldy,
-             int nb) {
-    for (int b0 = 0; b0 < nb; b0 += chunk) {
-        const int nc = std::min(chunk, nb - b0);
-        const cd *Xc = X + (int64_t)b0 * ldx;
-        cd *Yc = Y + (int64_t)b0 * ldy;
-        pw::launch_fft_apply_f64(c->sp, c->d_v, Xc, ldx, Yc, ldy, nc, p.S, c->stream);
-        const int np = c->nproj();
-        if (np > 0) {
-            // P = diag(D) B^H X ; Y += B P
-            pw::launch_gemm_tn_f64(c->d_B, c->ldp, Xc, ldx, c->npw, np, nc, p.Pj, np, c->d_D, 0.0,
-                                   p.part, p.part_elems, c->stream);
-            pw::launch_gemm_nn_f64(c->d_B, c->ldp, p.Pj, np, c->npw, np, nc, 1.0, 1.0, Yc, ldy,
-                                   c->stream);
-        }
+// complex64 copies of the potential and projector table, made on first use
+void ensure_mixed_tables(pw_ctx_s *c) {
+    const size_t n3 = (size_t)c->n * c->n * c->n;
+    if (!c->d_v32) {
+        c->d_v32 = c->dev_alloc<float>(n3);
+        pw::launch_convert_f64_f32(c->d_v, c->d_v32, (int64_t)n3, c->stream);
+    }
+    const int np = c->nproj();
+    if (np > 0 && !c->d_B32) {
+        c->d_B32 = c->dev_alloc<pw::cf>((size_t)c->ldp * np);
+        pw::launch_copy_cols(c->d_B, c->ldp, c->d_B32, c->ldp, c->ldp, np, c->stream);
     }
 }
 
-struct Sync {
-    int status = 0;
-};
+const double *potential_of(const pw_ctx_s *c, const cd *) { return c->d_v; }
+const float *potential_of(const pw_ctx_s *c, const pw::cf *) { return c->d_v32; }
+const cd *projectors_of(const pw_ctx_s *c, const cd *) { return c->d_B; }
+const pw::cf *projectors_of(const pw_ctx_s *c, const pw::cf *) { return c->d_B32; }
+
+// ---- H.X ------------------------------------------------------------------------
+template <class S>
+void apply_H(pw_ctx_s *c, const Plan<S> &p, int chunk, const S *X, int64_t ldx, S *Y, int64_t ldy,
+             int nb) {
+    const S *B = projectors_of(c, X);
+    for (int b0 = 0; b0 < nb; b0 += chunk) {
+        const int nc = std::min(chunk, nb - b0);
+        const S *Xc = X + (int64_t)b0 * ldx;
+        S *Yc = Y + (int64_t)b0 * ldy;
+        pw::launch_fft_apply(c->sp, potential_of(c, X), Xc, ldx, Yc, ldy, nc, p.Sb, c->stream);
+        const int np = c->nproj();
+        if (np > 0) {
+            // P = diag(D) B^H X ; Y += B P
+            pw::launch_gemm_tn(B, c->ldp, Xc, ldx, c->npw, np, nc, p.Pj, np, c->d_D, 0.0, p.part,
+                               p.part_elems, c->stream);
+            pw::launch_gemm_nn(B, c->ldp, p.Pj, np, c->npw, np, nc, 1.0, 1.0, Yc, ldy, c->stream);
+        }
+    }
+}
 
 int read_status(pw_ctx_s *c) {
     int s = 0;
@@ -255,38 +293,42 @@ int read_status(pw_ctx_s *c) {
 }
 
 // CholQR of V [npw x nb] in place: G = V^H V, V <- V R^-1.
-void cholqr(pw_ctx_s *c, const Plan &p, PhaseTimer &tm, cd *V, int64_t ldv, int nb) {
+template <class S>
+void cholqr(pw_ctx_s *c, const Plan<S> &p, PhaseTimer &tm, S *V, int64_t ldv, int nb) {
     auto e0 = tm.begin();
-    pw::launch_gemm_tn_f64(V, ldv, V, ldv, c->npw, nb, nb, p.Gs, nb, nullptr, 0.0, p.part,
-                           p.part_elems, c->stream);
+    pw::launch_gemm_tn(V, ldv, V, ldv, c->npw, nb, nb, p.Gs, nb, nullptr, 0.0, p.part, p.part_elems,
+                       c->stream);
     tm.end(PhaseTimer::kGemm, e0);
     auto e1 = tm.begin();
     pw::launch_chol_inv_f64(p.Gs, nb, nb, p.Rinv, nb, c->d_status, c->stream);
     tm.end(PhaseTimer::kDense, e1);
     auto e2 = tm.begin();
-    pw::launch_gemm_nn_f64(V, ldv, p.Rinv, nb, c->npw, nb, nb, 1.0, 0.0, V, ldv, c->stream);
+    pw::launch_gemm_nn(V, ldv, p.Rinv, nb, c->npw, nb, nb, 1.0, 0.0, V, ldv, c->stream);
     tm.end(PhaseTimer::kGemm, e2);
 }
 
 // V <- V - Q (Q^H V), Q [npw x nq]
-void project_out(pw_ctx_s *c, const Plan &p, PhaseTimer &tm, const cd *Q, int64_t ldq, int nq,
-                 cd *V, int64_t ldv, int nb) {
+template <class S>
+void project_out(pw_ctx_s *c, const Plan<S> &p, PhaseTimer &tm, const S *Q, int64_t ldq, int nq,
+                 S *V, int64_t ldv, int nb) {
     if (nq <= 0) return;
     auto e0 = tm.begin();
-    pw::launch_gemm_tn_f64(Q, ldq, V, ldv, c->npw, nq, nb, p.Ov, nq, nullptr, 0.0, p.part,
-                           p.part_elems, c->stream);
-    pw::launch_gemm_nn_f64(Q, ldq, p.Ov, nq, c->npw, nq, nb, -1.0, 1.0, V, ldv, c->stream);
+    pw::launch_gemm_tn(Q, ldq, V, ldv, c->npw, nq, nb, p.Ov, nq, nullptr, 0.0, p.part, p.part_elems,
+                       c->stream);
+    pw::launch_gemm_nn(Q, ldq, p.Ov, nq, c->npw, nq, nb, -1.0, 1.0, V, ldv, c->stream);
     tm.end(PhaseTimer::kGemm, e0);
 }
 
-pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int64_t ldx,
-                 int use_guess, double *eig) {
-    Plan p = ready_plan(c, M, m);
+// Block LOBPCG over M bands in blocks of m.  X (storage S) receives the
+// converged vectors; with final_rr the Rayleigh-Ritz over all M bands and the
+// residual check follow.  Timing and counters accumulate into stats.
+template <class S>
+pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int max_iter, S *X,
+                 int64_t ldx, int use_guess, double *eig, bool final_rr, pw_stats &stats) {
     hipStream_t st = c->stream;
     const int64_t ld = c->ldp, npw = c->npw;
     PhaseTimer tm;
     tm.st = st;
-    pw_stats stats{};
     hipEvent_t t_begin, t_end;
     PW_HIP(hipEventCreate(&t_begin));
     PW_HIP(hipEventCreate(&t_end));
@@ -304,16 +346,16 @@ pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int
         const int mb = (int)std::min<int64_t>(std::min(m, keep + guard), npw - b0);
         ++stats.blocks;
         int cur = 0;
-        cd *Z = p.Z[cur], *HZ = p.HZ[cur];
+        S *Z = p.Z[cur], *HZ = p.HZ[cur];
         // start block: X in slot 0 (caller guess for the stored columns)
         const int nguess = use_guess ? std::min(mb, M - b0) : 0;
-        if (nguess > 0) pw::launch_copy_cols_f64(X + (int64_t)b0 * ldx, ldx, Z, ld, npw, nguess, st);
+        if (nguess > 0) pw::launch_copy_cols(X + (int64_t)b0 * ldx, ldx, Z, ld, npw, nguess, st);
         if (nguess < mb)
-            pw::launch_random_block_f64(Z + (int64_t)nguess * ld, ld, npw, mb - nguess,
-                                        0x5EED0000ull + (uint64_t)b0, c->sp.kin, st);
+            pw::launch_random_block(Z + (int64_t)nguess * ld, ld, npw, mb - nguess,
+                                    0x5EED0000ull + (uint64_t)b0, c->sp.kin, st);
         // orthogonal to previous blocks, orthonormal (twice)
         for (int pass = 0; pass < 2; ++pass) {
-            project_out(c, p, tm, X, ldx, b0, Z, ld, mb);
+            project_out(c, p, tm, (const S *)X, ldx, b0, Z, ld, mb);
             cholqr(c, p, tm, Z, ld, mb);
         }
         {
@@ -325,15 +367,15 @@ pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int
         // initial Rayleigh-Ritz on span(X)
         {
             auto e0 = tm.begin();
-            pw::launch_gemm_tn_f64(Z, ld, HZ, ld, npw, mb, mb, p.Agram, mb, nullptr, 0.0, p.part,
-                                   p.part_elems, st);
+            pw::launch_gemm_tn(Z, ld, HZ, ld, npw, mb, mb, p.Agram, mb, nullptr, 0.0, p.part,
+                               p.part_elems, st);
             tm.end(PhaseTimer::kGemm, e0);
             auto e1 = tm.begin();
             pw::launch_heev_f64(p.Agram, mb, mb, mb, p.w, p.Cc, 3 * m, p.heev_scratch, c->d_status, st);
             tm.end(PhaseTimer::kDense, e1);
             auto e2 = tm.begin();
-            pw::launch_gemm_nn_f64(Z, ld, p.Cc, 3 * m, npw, mb, mb, 1.0, 0.0, p.Z[1 - cur], ld, st);
-            pw::launch_gemm_nn_f64(HZ, ld, p.Cc, 3 * m, npw, mb, mb, 1.0, 0.0, p.HZ[1 - cur], ld, st);
+            pw::launch_gemm_nn(Z, ld, p.Cc, 3 * m, npw, mb, mb, 1.0, 0.0, p.Z[1 - cur], ld, st);
+            pw::launch_gemm_nn(HZ, ld, p.Cc, 3 * m, npw, mb, mb, 1.0, 0.0, p.HZ[1 - cur], ld, st);
             tm.end(PhaseTimer::kGemm, e2);
             cur = 1 - cur;
             Z = p.Z[cur];
@@ -349,9 +391,9 @@ pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int
         for (it = 0; it < max_iter; ++it) {
             {
                 auto e = tm.begin();
-                pw::launch_band_dots_f64(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.rpart, p.theta, p.ekin, st);
-                pw::launch_resid_precond_f64(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.theta, p.ekin, nullptr, 0,
-                                             p.rpart, p.res, st);
+                pw::launch_band_dots(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.rpart, p.theta, p.ekin, st);
+                pw::launch_resid_precond(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.theta, p.ekin, (S *)nullptr,
+                                         0, p.rpart, p.res, st);
                 tm.end(PhaseTimer::kVec, e);
             }
             PW_HIP(hipMemcpyAsync(hres.data(), p.res, sizeof(double) * mb, hipMemcpyDeviceToHost, st));
@@ -379,16 +421,16 @@ pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int
             const int na = (int)act.size();
             PW_HIP(hipMemcpyAsync(p.act, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
             const int wcol = mb + np;
-            cd *W = Z + (int64_t)wcol * ld;
+            S *W = Z + (int64_t)wcol * ld;
             {
                 auto e = tm.begin();
-                pw::launch_precond_map_f64(Z, ld, HZ, ld, c->sp.kin, npw, p.theta, p.ekin, p.act, na, W, ld, st);
+                pw::launch_precond_map(Z, ld, HZ, ld, c->sp.kin, npw, p.theta, p.ekin, p.act, na, W, ld, st);
                 tm.end(PhaseTimer::kVec, e);
             }
             // constraint to previous blocks, then orthogonal to [X P] (twice) and orthonormal
-            project_out(c, p, tm, X, ldx, b0, W, ld, na);
+            project_out(c, p, tm, (const S *)X, ldx, b0, W, ld, na);
             for (int pass = 0; pass < 2; ++pass) {
-                project_out(c, p, tm, Z, ld, wcol, W, ld, na);
+                project_out(c, p, tm, (const S *)Z, ld, wcol, W, ld, na);
                 cholqr(c, p, tm, W, ld, na);
             }
             {
@@ -401,8 +443,8 @@ pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int
             // Rayleigh-Ritz on span{X, P, W} (orthonormal basis)
             {
                 auto e0 = tm.begin();
-                pw::launch_gemm_tn_f64(Z, ld, HZ, ld, npw, nz, nz, p.Agram, nz, nullptr, 0.0, p.part,
-                                       p.part_elems, st);
+                pw::launch_gemm_tn(Z, ld, HZ, ld, npw, nz, nz, p.Agram, nz, nullptr, 0.0, p.part,
+                                   p.part_elems, st);
                 tm.end(PhaseTimer::kGemm, e0);
                 auto e1 = tm.begin();
                 pw::launch_heev_f64(p.Agram, nz, nz, mb, p.w, p.Cc, 3 * m, p.heev_scratch, c->d_status,
@@ -417,22 +459,22 @@ pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int
                 auto e0 = tm.begin();
                 pw::launch_pcoef_map_f64(p.Cc, 3 * m, nz, mb, p.act, na, Cp, 3 * m, st);
                 for (int pass = 0; pass < 2; ++pass) {
-                    pw::launch_gemm_tn_f64(p.Cc, 3 * m, Cp, 3 * m, nz, mb, na, p.T1, mb, nullptr, 0.0,
-                                           p.part, p.part_elems, st);
-                    pw::launch_gemm_nn_f64(p.Cc, 3 * m, p.T1, mb, nz, mb, na, -1.0, 1.0, Cp, 3 * m, st);
-                    pw::launch_gemm_tn_f64(Cp, 3 * m, Cp, 3 * m, nz, na, na, p.Gs, na, nullptr, 0.0,
-                                           p.part, p.part_elems, st);
+                    pw::launch_gemm_tn(p.Cc, 3 * m, Cp, 3 * m, nz, mb, na, p.T1, mb, nullptr, 0.0,
+                                       p.part, p.part_elems, st);
+                    pw::launch_gemm_nn(p.Cc, 3 * m, p.T1, mb, nz, mb, na, -1.0, 1.0, Cp, 3 * m, st);
+                    pw::launch_gemm_tn(Cp, 3 * m, Cp, 3 * m, nz, na, na, p.Gs, na, nullptr, 0.0,
+                                       p.part, p.part_elems, st);
                     pw::launch_chol_inv_f64(p.Gs, na, na, p.Rinv, na, c->d_status, st);
-                    pw::launch_gemm_nn_f64(Cp, 3 * m, p.Rinv, na, nz, na, na, 1.0, 0.0, Cp, 3 * m, st);
+                    pw::launch_gemm_nn(Cp, 3 * m, p.Rinv, na, nz, na, na, 1.0, 0.0, Cp, 3 * m, st);
                 }
                 tm.end(PhaseTimer::kDense, e0);
             }
             // [X P]_new = Z [C c_p], same for HZ
             {
                 auto e = tm.begin();
-                pw::launch_gemm_nn_f64(Z, ld, p.Cc, 3 * m, npw, nz, mb + na, 1.0, 0.0, p.Z[1 - cur], ld, st);
-                pw::launch_gemm_nn_f64(HZ, ld, p.Cc, 3 * m, npw, nz, mb + na, 1.0, 0.0, p.HZ[1 - cur], ld,
-                                       st);
+                pw::launch_gemm_nn(Z, ld, p.Cc, 3 * m, npw, nz, mb + na, 1.0, 0.0, p.Z[1 - cur], ld, st);
+                pw::launch_gemm_nn(HZ, ld, p.Cc, 3 * m, npw, nz, mb + na, 1.0, 0.0, p.HZ[1 - cur], ld,
+                                   st);
                 tm.end(PhaseTimer::kGemm, e);
             }
             cur = 1 - cur;
@@ -444,42 +486,45 @@ pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int
         stats.iterations += it;
         if (!converged) all_converged = false;
         // store the converged columns of the block
-        pw::launch_copy_cols_f64(Z, ld, X + (int64_t)b0 * ldx, ldx, npw, keep, st);
-        pw::launch_copy_cols_f64(HZ, ld, p.HXall + (int64_t)b0 * ld, ld, npw, keep, st);
+        pw::launch_copy_cols(Z, ld, X + (int64_t)b0 * ldx, ldx, npw, keep, st);
+        pw::launch_copy_cols(HZ, ld, p.HXall + (int64_t)b0 * ld, ld, npw, keep, st);
         b0 += keep;
     }
 
-    // final Rayleigh-Ritz over all M bands
-    auto ef = tm.begin();
-    pw::launch_gemm_tn_f64(X, ldx, p.HXall, ld, npw, M, M, p.Agram, M, nullptr, 0.0, p.part,
+    if (final_rr) {   // Rayleigh-Ritz over all M bands
+        auto ef = tm.begin();
+        pw::launch_gemm_tn(X, ldx, p.HXall, ld, npw, M, M, p.Agram, M, nullptr, 0.0, p.part,
                            p.part_elems, st);
-    pw::launch_heev_f64(p.Agram, M, M, M, p.w, p.U, M, p.heev_scratch, c->d_status, st);
-    pw::launch_gemm_nn_f64(X, ldx, p.U, M, npw, M, M, 1.0, 0.0, p.T, ld, st);
-    pw::launch_copy_cols_f64(p.T, ld, X, ldx, npw, M, st);
-    pw::launch_gemm_nn_f64(p.HXall, ld, p.U, M, npw, M, M, 1.0, 0.0, p.T, ld, st);
-    pw::launch_copy_cols_f64(p.T, ld, p.HXall, ld, npw, M, st);
-    pw::launch_band_dots_f64(X, ldx, p.HXall, ld, c->sp.kin, npw, M, p.rpart, p.theta, p.ekin, st);
-    pw::launch_resid_precond_f64(X, ldx, p.HXall, ld, c->sp.kin, npw, M, p.theta, p.ekin, nullptr, 0,
+        pw::launch_heev_f64(p.Agram, M, M, M, p.w, p.U, M, p.heev_scratch, c->d_status, st);
+        pw::launch_gemm_nn(X, ldx, p.U, M, npw, M, M, 1.0, 0.0, p.T, ld, st);
+        pw::launch_copy_cols(p.T, ld, X, ldx, npw, M, st);
+        pw::launch_gemm_nn(p.HXall, ld, p.U, M, npw, M, M, 1.0, 0.0, p.T, ld, st);
+        pw::launch_copy_cols(p.T, ld, p.HXall, ld, npw, M, st);
+        pw::launch_band_dots(X, ldx, p.HXall, ld, c->sp.kin, npw, M, p.rpart, p.theta, p.ekin, st);
+        pw::launch_resid_precond(X, ldx, p.HXall, ld, c->sp.kin, npw, M, p.theta, p.ekin, (S *)nullptr, 0,
                                  p.rpart, p.res, st);
-    tm.end(PhaseTimer::kFinal, ef);
+        tm.end(PhaseTimer::kFinal, ef);
+    }
     PW_HIP(hipEventRecord(t_end, st));
-    c->res.assign(M, 0.0);
-    PW_HIP(hipMemcpyAsync(eig, p.theta, sizeof(double) * M, hipMemcpyDeviceToHost, st));
-    PW_HIP(hipMemcpyAsync(c->res.data(), p.res, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+    if (final_rr) {
+        c->res.assign(M, 0.0);
+        PW_HIP(hipMemcpyAsync(eig, p.theta, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+        PW_HIP(hipMemcpyAsync(c->res.data(), p.res, sizeof(double) * M, hipMemcpyDeviceToHost, st));
+    }
     const int status = read_status(c);
     tm.collect();
     float total = 0.f;
     PW_HIP(hipEventElapsedTime(&total, t_begin, t_end));
     (void)hipEventDestroy(t_begin);
     (void)hipEventDestroy(t_end);
-    stats.ms_total = total;
-    stats.ms_apply = tm.ms[PhaseTimer::kApply];
-    stats.ms_gemm = tm.ms[PhaseTimer::kGemm];
-    stats.ms_dense = tm.ms[PhaseTimer::kDense];
-    stats.ms_vec = tm.ms[PhaseTimer::kVec];
-    stats.ms_final_rr = tm.ms[PhaseTimer::kFinal];
-    c->stats = stats;
+    stats.ms_total += total;
+    stats.ms_apply += tm.ms[PhaseTimer::kApply];
+    stats.ms_gemm += tm.ms[PhaseTimer::kGemm];
+    stats.ms_dense += tm.ms[PhaseTimer::kDense];
+    stats.ms_vec += tm.ms[PhaseTimer::kVec];
+    stats.ms_final_rr += tm.ms[PhaseTimer::kFinal];
     if (status & 4) throw Error{PW_ERR_NUMERIC, "non-finite value in the final Rayleigh-Ritz"};
+    if (!final_rr) return all_converged ? PW_OK : PW_ERR_NOT_CONVERGED;
     for (int j = 0; j < M; ++j) {
         if (!std::isfinite(eig[j])) throw Error{PW_ERR_NUMERIC, "non-finite eigenvalue"};
     }
@@ -492,6 +537,31 @@ pw_status lobpcg(pw_ctx_s *c, int M, int m, double tol, int max_iter, cd *X, int
         return PW_ERR_NOT_CONVERGED;
     }
     return PW_OK;
+}
+
+// FP64 solve, or the mixed form: complex64 LOBPCG to kMixedTol, then the FP64
+// iteration (with its final Rayleigh-Ritz) from those vectors.
+pw_status solve(pw_ctx_s *c, int M, int m, double tol, int max_iter, pw_precision prec, cd *X,
+                int64_t ldx, int use_guess, double *eig) {
+    pw_stats stats{};
+    pw_status rc;
+    if (prec == PW_PREC_MIXED) {
+        ensure_mixed_tables(c);
+        Plan<pw::cf> p32 = ready_plan<pw::cf>(c, M, m);
+        if (use_guess) pw::launch_copy_cols(X, ldx, p32.Xs, c->ldp, c->npw, M, c->stream);
+        // an unconverged block here is not an error: the FP64 stage continues from it
+        (void)lobpcg(c, p32, M, m, std::max(tol, kMixedTol), std::min(max_iter, kMixedMaxIter), p32.Xs,
+                     c->ldp, use_guess, eig, false, stats);
+        pw::launch_copy_cols(p32.Xs, c->ldp, X, ldx, c->npw, M, c->stream);
+        stats.mixed_iterations = stats.iterations;
+        Plan<cd> p64 = ready_plan<cd>(c, M, m);
+        rc = lobpcg(c, p64, M, m, tol, max_iter, X, ldx, 1, eig, true, stats);
+    } else {
+        Plan<cd> p64 = ready_plan<cd>(c, M, m);
+        rc = lobpcg(c, p64, M, m, tol, max_iter, X, ldx, use_guess, eig, true, stats);
+    }
+    c->stats = stats;
+    return rc;
 }
 
 // ---- basis setup -------------------------------------------------------------------
@@ -508,8 +578,10 @@ void init_basis(pw_ctx_s *c, const double cell[9], const double kfrac[3], double
     c->has_basis = c->has_v = false;
     c->natom = c->nlm = 0;
     c->d_B = nullptr;
+    c->d_B32 = nullptr;
     c->d_D = nullptr;
     c->d_v = nullptr;
+    c->d_v32 = nullptr;
     c->d_qvec = nullptr;
     c->ws = nullptr;
     c->ws_bytes = 0;
@@ -649,6 +721,8 @@ void set_potential(pw_ctx_s *c, const double *v, int on_device) {
         src = tmp;
     }
     if (!c->d_v) c->d_v = c->dev_alloc<double>(tot);
+    c->dev_free(c->d_v32);   // the float copy is rebuilt on the next mixed-form call
+    c->d_v32 = nullptr;
     PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
     pw::launch_permute_potential(src, N, 1.0 / (double(N) * N * N), c->d_v, c->d_status, c->stream);
     const int s = read_status(c);
@@ -664,8 +738,10 @@ void set_projectors(pw_ctx_s *c, int natom, const double *pos, int nlm, const in
     require_device(c);
     PW_REQUIRE(natom >= 0 && nlm >= 0, PW_ERR_ARG, "negative projector count");
     c->dev_free(c->d_B);
+    c->dev_free(c->d_B32);
     c->dev_free(c->d_D);
     c->d_B = nullptr;
+    c->d_B32 = nullptr;
     c->d_D = nullptr;
     c->natom = c->nlm = 0;
     if (natom == 0 || nlm == 0) return;
@@ -688,7 +764,7 @@ void set_projectors(pw_ctx_s *c, int natom, const double *pos, int nlm, const in
     const double omega = std::fabs(a[0] * (a[4] * a[8] - a[5] * a[7]) - a[1] * (a[3] * a[8] - a[5] * a[6]) +
                                    a[2] * (a[3] * a[7] - a[4] * a[6]));
     const double pref = std::sqrt(32.0 * std::pow(M_PI, 2.5)) / std::sqrt(omega);
-    pw::launch_zero_f64(c->d_B, c->ldp, c->ldp, np, c->stream);
+    pw::launch_zero(c->d_B, c->ldp, c->ldp, np, c->stream);
     pw::launch_build_projectors_f64(c->d_qvec, c->npw, natom, d_pos, nlm, lm ? d_lm : nullptr, pref,
                                     c->d_B, c->ldp, c->stream);
     PW_HIP(hipStreamSynchronize(c->stream));
@@ -714,6 +790,47 @@ pw_status guard(pw_ctx c, F &&f) {
         c->err = "unexpected exception";
         return PW_ERR_DEVICE;
     }
+}
+
+}  // namespace
+
+namespace {
+template <class S>
+pw_status gram_impl(pw_ctx c, const void *A, int64_t lda, const void *B, int64_t ldb, int64_t K,
+                    int32_t p, int32_t q, void *C, int64_t ldc) {
+    return guard(c, [&] {
+        require_device(c);
+        PW_REQUIRE(A && B && C, PW_ERR_ARG, "null argument");
+        PW_REQUIRE(K >= 0 && p >= 0 && q >= 0 && lda >= K && ldb >= K && ldc >= p, PW_ERR_ARG,
+                   "bad GEMM shape");
+        PW_REQUIRE(c->ws != nullptr, PW_ERR_STATE, "pw_set_workspace has not been called");
+        if (p == 0 || q == 0) return PW_OK;
+        const size_t need = pw::gemm_tn_part_elems(K, p, q, nullptr) * sizeof(cd);
+        PW_REQUIRE(need <= c->ws_bytes, PW_ERR_NOMEM, "workspace too small for this Gram");
+        if (K == 0) {
+            pw::launch_zero(static_cast<cd *>(C), ldc, p, q, c->stream);
+            return PW_OK;
+        }
+        pw::launch_gemm_tn(static_cast<const S *>(A), lda, static_cast<const S *>(B), ldb, K, p, q,
+                           static_cast<cd *>(C), ldc, nullptr, 0.0, reinterpret_cast<cd *>(c->ws),
+                           c->ws_bytes / sizeof(cd), c->stream);
+        return PW_OK;
+    });
+}
+
+template <class S>
+pw_status block_update_impl(pw_ctx c, const void *A, int64_t lda, const void *C, int64_t ldc,
+                            int64_t K, int32_t p, int32_t q, double alpha, double beta, void *Y,
+                            int64_t ldy) {
+    return guard(c, [&] {
+        require_device(c);
+        PW_REQUIRE(A && C && Y, PW_ERR_ARG, "null argument");
+        PW_REQUIRE(K >= 0 && p >= 0 && q >= 0 && lda >= K && ldy >= K && ldc >= p, PW_ERR_ARG,
+                   "bad GEMM shape");
+        pw::launch_gemm_nn(static_cast<const S *>(A), lda, static_cast<const cd *>(C), ldc, K, p, q,
+                           alpha, beta, static_cast<S *>(Y), ldy, c->stream);
+        return PW_OK;
+    });
 }
 
 }  // namespace
@@ -804,13 +921,14 @@ pw_status pw_workspace_size(pw_ctx c, int32_t nbands, int32_t block, pw_precisio
     return guard(c, [&] {
         require_basis(c);
         PW_REQUIRE(bytes, PW_ERR_ARG, "null output");
-        PW_REQUIRE(prec == PW_PREC_FP64, PW_ERR_ARG, "only PW_PREC_FP64 is implemented");
+        PW_REQUIRE(prec == PW_PREC_FP64 || prec == PW_PREC_MIXED, PW_ERR_ARG, "unknown precision");
         PW_REQUIRE(nbands >= 1 && block >= 1 && block <= 64, PW_ERR_ARG, "need nbands >= 1 and 1 <= block <= 64");
         PW_REQUIRE(nbands <= 1024 && nbands <= c->npw, PW_ERR_ARG, "nbands must be <= min(npw, 1024)");
         const int m = std::min(block, nbands);
         c->plan_nbands = nbands;
         c->plan_block = m;
-        *bytes = make_plan(*c, nbands, m, nullptr).bytes;
+        c->plan_prec = prec;
+        *bytes = plan_bytes(*c, nbands, m, prec);
         return PW_OK;
     });
 }
@@ -821,7 +939,7 @@ pw_status pw_set_workspace(pw_ctx c, void *dptr, size_t bytes) {
         PW_REQUIRE(dptr, PW_ERR_ARG, "null workspace");
         PW_REQUIRE(((uintptr_t)dptr & 255) == 0, PW_ERR_ARG, "workspace must be 256-byte aligned");
         if (c->plan_nbands > 0) {
-            const size_t need = make_plan(*c, c->plan_nbands, c->plan_block, nullptr).bytes;
+            const size_t need = plan_bytes(*c, c->plan_nbands, c->plan_block, c->plan_prec);
             PW_REQUIRE(bytes >= need, PW_ERR_NOMEM, "workspace smaller than pw_workspace_size");
         }
         c->ws = static_cast<char *>(dptr);
@@ -833,15 +951,21 @@ pw_status pw_set_workspace(pw_ctx c, void *dptr, size_t bytes) {
 pw_status pw_apply_H(pw_ctx c, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nb,
                      pw_precision prec) {
     return guard(c, [&] {
-        PW_REQUIRE(prec == PW_PREC_FP64, PW_ERR_ARG, "only PW_PREC_FP64 is implemented");
+        PW_REQUIRE(prec == PW_PREC_FP64 || prec == PW_PREC_MIXED, PW_ERR_ARG, "unknown precision");
         require_basis(c);
         PW_REQUIRE(X && Y, PW_ERR_ARG, "null block");
         PW_REQUIRE(nb >= 0, PW_ERR_ARG, "negative column count");
         PW_REQUIRE(ldx >= c->npw && ldy >= c->npw, PW_ERR_ARG, "leading dimension < npw");
         if (nb == 0) return PW_OK;
         const int chunk = c->plan_block > 0 ? c->plan_block : 1;
-        Plan p = ready_plan(c, std::max(c->plan_nbands, 1), chunk);
-        apply_H(c, p, chunk, static_cast<const cd *>(X), ldx, static_cast<cd *>(Y), ldy, nb);
+        if (prec == PW_PREC_MIXED) {
+            Plan<pw::cf> p = ready_plan<pw::cf>(c, std::max(c->plan_nbands, 1), chunk);
+            ensure_mixed_tables(c);
+            apply_H(c, p, chunk, static_cast<const pw::cf *>(X), ldx, static_cast<pw::cf *>(Y), ldy, nb);
+        } else {
+            Plan<cd> p = ready_plan<cd>(c, std::max(c->plan_nbands, 1), chunk);
+            apply_H(c, p, chunk, static_cast<const cd *>(X), ldx, static_cast<cd *>(Y), ldy, nb);
+        }
         return PW_OK;
     });
 }
@@ -849,7 +973,7 @@ pw_status pw_apply_H(pw_ctx c, const void *X, int64_t ldx, void *Y, int64_t ldy,
 pw_status pw_lobpcg_solve(pw_ctx c, int32_t nbands, int32_t block, double tol, int32_t max_iter,
                           pw_precision prec, void *X, int64_t ldx, int32_t use_guess, double *eig) {
     return guard(c, [&] {
-        PW_REQUIRE(prec == PW_PREC_FP64, PW_ERR_ARG, "only PW_PREC_FP64 is implemented");
+        PW_REQUIRE(prec == PW_PREC_FP64 || prec == PW_PREC_MIXED, PW_ERR_ARG, "unknown precision");
         require_basis(c);
         PW_REQUIRE(X && eig, PW_ERR_ARG, "null argument");
         PW_REQUIRE(nbands >= 1 && block >= 1 && block <= 64, PW_ERR_ARG, "need nbands >= 1, 1 <= block <= 64");
@@ -862,7 +986,7 @@ pw_status pw_lobpcg_solve(pw_ctx c, int32_t nbands, int32_t block, double tol, i
                    "call pw_workspace_size with this (nbands, block) before the solve");
         require_device(c);
         PW_HIP(hipSetDevice(c->device));
-        return lobpcg(c, nbands, m, tol, max_iter, static_cast<cd *>(X), ldx, use_guess, eig);
+        return solve(c, nbands, m, tol, max_iter, prec, static_cast<cd *>(X), ldx, use_guess, eig);
     });
 }
 
@@ -885,38 +1009,21 @@ pw_status pw_get_stats(pw_ctx c, pw_stats *stats) {
 
 pw_status pw_gram(pw_ctx c, const void *A, int64_t lda, const void *B, int64_t ldb, int64_t K,
                   int32_t p, int32_t q, void *C, int64_t ldc) {
-    return guard(c, [&] {
-        require_device(c);
-        PW_REQUIRE(A && B && C, PW_ERR_ARG, "null argument");
-        PW_REQUIRE(K >= 0 && p >= 0 && q >= 0 && lda >= K && ldb >= K && ldc >= p, PW_ERR_ARG,
-                   "bad GEMM shape");
-        PW_REQUIRE(c->ws != nullptr, PW_ERR_STATE, "pw_set_workspace has not been called");
-        if (p == 0 || q == 0) return PW_OK;
-        const size_t need = pw::gemm_tn_part_elems(K, p, q, nullptr) * sizeof(cd);
-        PW_REQUIRE(need <= c->ws_bytes, PW_ERR_NOMEM, "workspace too small for this Gram");
-        if (K == 0) {
-            pw::launch_zero_f64(static_cast<cd *>(C), ldc, p, q, c->stream);
-            return PW_OK;
-        }
-        pw::launch_gemm_tn_f64(static_cast<const cd *>(A), lda, static_cast<const cd *>(B), ldb, K, p,
-                               q, static_cast<cd *>(C), ldc, nullptr, 0.0,
-                               reinterpret_cast<cd *>(c->ws), c->ws_bytes / sizeof(cd), c->stream);
-        return PW_OK;
-    });
+    return gram_impl<cd>(c, A, lda, B, ldb, K, p, q, C, ldc);
 }
-
+pw_status pw_gram_mixed(pw_ctx c, const void *A, int64_t lda, const void *B, int64_t ldb, int64_t K,
+                        int32_t p, int32_t q, void *C, int64_t ldc) {
+    return gram_impl<pw::cf>(c, A, lda, B, ldb, K, p, q, C, ldc);
+}
 pw_status pw_block_update(pw_ctx c, const void *A, int64_t lda, const void *C, int64_t ldc,
                           int64_t K, int32_t p, int32_t q, double alpha, double beta, void *Y,
                           int64_t ldy) {
-    return guard(c, [&] {
-        require_device(c);
-        PW_REQUIRE(A && C && Y, PW_ERR_ARG, "null argument");
-        PW_REQUIRE(K >= 0 && p >= 0 && q >= 0 && lda >= K && ldy >= K && ldc >= p, PW_ERR_ARG,
-                   "bad GEMM shape");
-        pw::launch_gemm_nn_f64(static_cast<const cd *>(A), lda, static_cast<const cd *>(C), ldc, K, p,
-                               q, alpha, beta, static_cast<cd *>(Y), ldy, c->stream);
-        return PW_OK;
-    });
+    return block_update_impl<cd>(c, A, lda, C, ldc, K, p, q, alpha, beta, Y, ldy);
+}
+pw_status pw_block_update_mixed(pw_ctx c, const void *A, int64_t lda, const void *C, int64_t ldc,
+                                int64_t K, int32_t p, int32_t q, double alpha, double beta, void *Y,
+                                int64_t ldy) {
+    return block_update_impl<pw::cf>(c, A, lda, C, ldc, K, p, q, alpha, beta, Y, ldy);
 }
 
 pw_status pw_small_eigh(pw_ctx c, void *A, int64_t lda, int32_t n, int32_t k, void *w, void *V,
@@ -951,10 +1058,10 @@ pw_status pw_residuals(pw_ctx c, const void *X, int64_t ldx, const void *HX, int
         PW_REQUIRE(need <= c->ws_bytes, PW_ERR_NOMEM, "workspace too small");
         double *part = reinterpret_cast<double *>(c->ws);
         double *ekin = part + align_up(pw::resid_part_elems(c->npw, nb), 32);
-        pw::launch_band_dots_f64(static_cast<const cd *>(X), ldx, static_cast<const cd *>(HX), ldhx,
+        pw::launch_band_dots(static_cast<const cd *>(X), ldx, static_cast<const cd *>(HX), ldhx,
                                  c->sp.kin, c->npw, nb, part, static_cast<double *>(theta), ekin,
                                  c->stream);
-        pw::launch_resid_precond_f64(static_cast<const cd *>(X), ldx, static_cast<const cd *>(HX), ldhx,
+        pw::launch_resid_precond(static_cast<const cd *>(X), ldx, static_cast<const cd *>(HX), ldhx,
                                      c->sp.kin, c->npw, nb, static_cast<const double *>(theta), ekin,
                                      static_cast<cd *>(W), ldw, part, static_cast<double *>(res),
                                      c->stream);

@@ -14,6 +14,15 @@ namespace {
 constexpr int kChunk = 2048;   // rows per reduction workgroup
 constexpr int kThreads = 256;
 
+// Blocks are stored as complex128 (cd) or complex64 (cf); arithmetic and every
+// reduction run in double.
+__device__ __forceinline__ cd widen(cd v) { return v; }
+__device__ __forceinline__ cd widen(cf v) { return cd{(double)v.x, (double)v.y}; }
+template <class S>
+__device__ __forceinline__ S narrow(double x, double y) {
+    return S{(decltype(S::x))x, (decltype(S::y))y};
+}
+
 template <int NV>
 __device__ void wg_reduce(double (&v)[NV], double *red) {
     const int t = threadIdx.x;
@@ -31,17 +40,18 @@ __device__ void wg_reduce(double (&v)[NV], double *red) {
 }
 
 // Rayleigh quotient pieces per (chunk, band): Re(x^H Hx), sum T|x|^2, |x|^2.
+template <class S>
 __global__ void __launch_bounds__(kThreads)
-    k_band_dots(const cd *__restrict__ X, int64_t ldx, const cd *__restrict__ HX, int64_t ldhx,
+    k_band_dots(const S *__restrict__ X, int64_t ldx, const S *__restrict__ HX, int64_t ldhx,
                 const double *__restrict__ kin, int64_t npw, int nb, double *__restrict__ part) {
     __shared__ double red[3 * kThreads];
     const int c = blockIdx.x, b = blockIdx.y;
     const int64_t r0 = (int64_t)c * kChunk, r1 = min(npw, r0 + kChunk);
-    const cd *x = X + (int64_t)b * ldx;
-    const cd *h = HX + (int64_t)b * ldhx;
+    const S *x = X + (int64_t)b * ldx;
+    const S *h = HX + (int64_t)b * ldhx;
     double v[3] = {0.0, 0.0, 0.0};
     for (int64_t r = r0 + threadIdx.x; r < r1; r += kThreads) {
-        const cd a = x[r], hb = h[r];
+        const cd a = widen(x[r]), hb = widen(h[r]);
         const double n2 = a.x * a.x + a.y * a.y;
         v[0] += a.x * hb.x + a.y * hb.y;
         v[1] += kin[r] * n2;
@@ -75,29 +85,30 @@ __global__ void k_band_dots_final(const double *__restrict__ part, int nchunk, i
 }
 
 // R = HX - theta X; W = K(T / E_kin) R (if W); partial |R|^2 per (chunk, band).
+template <class S>
 __global__ void __launch_bounds__(kThreads)
-    k_resid(const cd *__restrict__ X, int64_t ldx, const cd *__restrict__ HX, int64_t ldhx,
+    k_resid(const S *__restrict__ X, int64_t ldx, const S *__restrict__ HX, int64_t ldhx,
             const double *__restrict__ kin, int64_t npw, int nb, const double *__restrict__ theta,
-            const double *__restrict__ ekin, cd *__restrict__ W, int64_t ldw,
+            const double *__restrict__ ekin, S *__restrict__ W, int64_t ldw,
             double *__restrict__ part) {
     __shared__ double red[kThreads];
     const int c = blockIdx.x, b = blockIdx.y;
     const int64_t r0 = (int64_t)c * kChunk, r1 = min(npw, r0 + kChunk);
-    const cd *x = X + (int64_t)b * ldx;
-    const cd *h = HX + (int64_t)b * ldhx;
+    const S *x = X + (int64_t)b * ldx;
+    const S *h = HX + (int64_t)b * ldhx;
     const double th = theta[b];
     const double ek = fmax(ekin[b], 1e-3);
     const double iek = 1.0 / ek;
     double v[1] = {0.0};
     for (int64_t r = r0 + threadIdx.x; r < r1; r += kThreads) {
-        const cd a = x[r], hb = h[r];
+        const cd a = widen(x[r]), hb = widen(h[r]);
         const cd rr = {hb.x - th * a.x, hb.y - th * a.y};
         v[0] += rr.x * rr.x + rr.y * rr.y;
         if (W) {
             const double xx = kin[r] * iek;
             const double num = 27.0 + xx * (18.0 + xx * (12.0 + xx * 8.0));
             const double k = num / (num + 16.0 * xx * xx * xx * xx);
-            W[(int64_t)b * ldw + r] = cd{k * rr.x, k * rr.y};
+            W[(int64_t)b * ldw + r] = narrow<S>(k * rr.x, k * rr.y);
         }
     }
     wg_reduce<1>(v, red);
@@ -105,21 +116,22 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 // W[:, jj] = K(T / E_kin) (HX - theta X)[:, act[jj]] for the active columns.
+template <class S>
 __global__ void __launch_bounds__(kThreads)
-    k_precond_map(const cd *__restrict__ X, int64_t ldx, const cd *__restrict__ HX, int64_t ldhx,
+    k_precond_map(const S *__restrict__ X, int64_t ldx, const S *__restrict__ HX, int64_t ldhx,
                   const double *__restrict__ kin, int64_t npw, const double *__restrict__ theta,
-                  const double *__restrict__ ekin, const int *__restrict__ act, cd *__restrict__ W,
+                  const double *__restrict__ ekin, const int *__restrict__ act, S *__restrict__ W,
                   int64_t ldw) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int jj = blockIdx.y;
     if (r >= npw) return;
     const int b = act[jj];
-    const cd a = X[(int64_t)b * ldx + r], hb = HX[(int64_t)b * ldhx + r];
+    const cd a = widen(X[(int64_t)b * ldx + r]), hb = widen(HX[(int64_t)b * ldhx + r]);
     const double th = theta[b];
     const double xx = kin[r] / fmax(ekin[b], 1e-3);
     const double num = 27.0 + xx * (18.0 + xx * (12.0 + xx * 8.0));
     const double k = num / (num + 16.0 * xx * xx * xx * xx);
-    W[(int64_t)jj * ldw + r] = cd{k * (hb.x - th * a.x), k * (hb.y - th * a.y)};
+    W[(int64_t)jj * ldw + r] = narrow<S>(k * (hb.x - th * a.x), k * (hb.y - th * a.y));
 }
 
 __global__ void k_resid_final(const double *__restrict__ part, int nchunk, int nb,
@@ -160,22 +172,29 @@ __global__ void k_build_projectors(const double *__restrict__ qvec, int64_t npw,
     B[(int64_t)col * ldb + g] = cd{rad * c, -rad * s};
 }
 
-__global__ void k_copy_cols(const cd *__restrict__ A, int64_t lda, cd *__restrict__ B, int64_t ldb,
+// copy with conversion between storage precisions (round to nearest)
+template <class SA, class SB>
+__global__ void k_copy_cols(const SA *__restrict__ A, int64_t lda, SB *__restrict__ B, int64_t ldb,
                             int64_t rows) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
-    if (r < rows) B[(int64_t)c * ldb + r] = A[(int64_t)c * lda + r];
+    if (r < rows) {
+        const cd v = widen(A[(int64_t)c * lda + r]);
+        B[(int64_t)c * ldb + r] = narrow<SB>(v.x, v.y);
+    }
 }
 
-__global__ void k_zero(cd *X, int64_t ldx, int64_t rows) {
+template <class S>
+__global__ void k_zero(S *X, int64_t ldx, int64_t rows) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
-    if (r < rows) X[(int64_t)c * ldx + r] = cd{0.0, 0.0};
+    if (r < rows) X[(int64_t)c * ldx + r] = narrow<S>(0.0, 0.0);
 }
 
 // Counter-based starting block: uniform(-1,1)^2 from a splitmix64 hash of
 // (seed, row, column), damped by 1/(1 + T_g) towards low kinetic energy.
-__global__ void k_random_block(cd *X, int64_t ldx, int64_t rows, uint64_t seed,
+template <class S>
+__global__ void k_random_block(S *X, int64_t ldx, int64_t rows, uint64_t seed,
                                const double *__restrict__ kin) {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
@@ -191,7 +210,7 @@ __global__ void k_random_block(cd *X, int64_t ldx, int64_t rows, uint64_t seed,
     const double u1 = (double)(h1 >> 11) * (2.0 / 9007199254740992.0) - 1.0;
     const double u2 = (double)(h2 >> 11) * (2.0 / 9007199254740992.0) - 1.0;
     const double d = 1.0 / (1.0 + kin[r]);
-    X[(int64_t)c * ldx + r] = cd{u1 * d, u2 * d};
+    X[(int64_t)c * ldx + r] = narrow<S>(u1 * d, u2 * d);
 }
 
 __global__ void k_pcoef(const cd *__restrict__ Cf, int64_t ldc, int n, int m, cd *__restrict__ Cp,
@@ -210,6 +229,11 @@ __global__ void k_pcoef_map(const cd *__restrict__ Cf, int64_t ldc, int n, int m
     Cp[(int64_t)jj * ldp + i] = (i < m) ? cd{0.0, 0.0} : Cf[(int64_t)act[jj] * ldc + i];
 }
 
+__global__ void k_convert_f64_f32(const double *__restrict__ a, float *__restrict__ b, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) b[i] = (float)a[i];
+}
+
 __global__ void k_check_finite(const double *a, int64_t n, int *status) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n && !isfinite(a[i])) atomicOr(status, 4);
@@ -222,26 +246,44 @@ size_t resid_part_elems(int64_t npw, int nb) {
     return (size_t)nchunk * nb * 3;
 }
 
-void launch_band_dots_f64(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
-                          int64_t npw, int nb, double *part, double *theta, double *ekin,
-                          hipStream_t st) {
+template <class S>
+void band_dots_impl(const S *X, int64_t ldx, const S *HX, int64_t ldhx, const double *kin,
+                    int64_t npw, int nb, double *part, double *theta, double *ekin, hipStream_t st) {
     const int nchunk = (int)((npw + kChunk - 1) / kChunk);
-    hipLaunchKernelGGL(k_band_dots, dim3(nchunk, nb), dim3(kThreads), 0, st, X, ldx, HX, ldhx, kin,
+    hipLaunchKernelGGL(k_band_dots<S>, dim3(nchunk, nb), dim3(kThreads), 0, st, X, ldx, HX, ldhx, kin,
                        npw, nb, part);
     hipLaunchKernelGGL(k_band_dots_final, dim3(1), dim3(256), 0, st, part, nchunk, nb, theta, ekin);
     PW_HIP(hipGetLastError());
 }
+void launch_band_dots(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
+                      int64_t npw, int nb, double *part, double *theta, double *ekin, hipStream_t st) {
+    band_dots_impl(X, ldx, HX, ldhx, kin, npw, nb, part, theta, ekin, st);
+}
+void launch_band_dots(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, const double *kin,
+                      int64_t npw, int nb, double *part, double *theta, double *ekin, hipStream_t st) {
+    band_dots_impl(X, ldx, HX, ldhx, kin, npw, nb, part, theta, ekin, st);
+}
 
-void launch_resid_precond_f64(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx,
-                              const double *kin, int64_t npw, int nb, const double *theta,
-                              const double *ekin, cd *W, int64_t ldw, double *part, double *res,
-                              hipStream_t st) {
+template <class S>
+void resid_impl(const S *X, int64_t ldx, const S *HX, int64_t ldhx, const double *kin, int64_t npw,
+                int nb, const double *theta, const double *ekin, S *W, int64_t ldw, double *part,
+                double *res, hipStream_t st) {
     const int nchunk = (int)((npw + kChunk - 1) / kChunk);
-    hipLaunchKernelGGL(k_resid, dim3(nchunk, nb), dim3(kThreads), 0, st, X, ldx, HX, ldhx, kin, npw,
+    hipLaunchKernelGGL(k_resid<S>, dim3(nchunk, nb), dim3(kThreads), 0, st, X, ldx, HX, ldhx, kin, npw,
                        nb, theta, ekin, W, ldw, part);
     // ekin array carries |x|^2 in its second half (see k_band_dots_final)
     hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, st, part, nchunk, nb, ekin + nb, res);
     PW_HIP(hipGetLastError());
+}
+void launch_resid_precond(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
+                          int64_t npw, int nb, const double *theta, const double *ekin, cd *W,
+                          int64_t ldw, double *part, double *res, hipStream_t st) {
+    resid_impl(X, ldx, HX, ldhx, kin, npw, nb, theta, ekin, W, ldw, part, res, st);
+}
+void launch_resid_precond(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, const double *kin,
+                          int64_t npw, int nb, const double *theta, const double *ekin, cf *W,
+                          int64_t ldw, double *part, double *res, hipStream_t st) {
+    resid_impl(X, ldx, HX, ldhx, kin, npw, nb, theta, ekin, W, ldw, part, res, st);
 }
 
 void launch_build_projectors_f64(const double *qvec, int64_t npw, int natom, const double *pos,
@@ -253,27 +295,51 @@ void launch_build_projectors_f64(const double *qvec, int64_t npw, int natom, con
     PW_HIP(hipGetLastError());
 }
 
-void launch_copy_cols_f64(const cd *A, int64_t lda, cd *B, int64_t ldb, int64_t rows, int cols,
-                          hipStream_t st) {
+template <class SA, class SB>
+void copy_impl(const SA *A, int64_t lda, SB *B, int64_t ldb, int64_t rows, int cols, hipStream_t st) {
     if (rows <= 0 || cols <= 0) return;
-    hipLaunchKernelGGL(k_copy_cols, dim3((unsigned)((rows + 255) / 256), cols), dim3(256), 0, st, A,
-                       lda, B, ldb, rows);
+    hipLaunchKernelGGL((k_copy_cols<SA, SB>), dim3((unsigned)((rows + 255) / 256), cols), dim3(256), 0,
+                       st, A, lda, B, ldb, rows);
     PW_HIP(hipGetLastError());
 }
+void launch_copy_cols(const cd *A, int64_t lda, cd *B, int64_t ldb, int64_t rows, int cols, hipStream_t st) {
+    copy_impl(A, lda, B, ldb, rows, cols, st);
+}
+void launch_copy_cols(const cf *A, int64_t lda, cf *B, int64_t ldb, int64_t rows, int cols, hipStream_t st) {
+    copy_impl(A, lda, B, ldb, rows, cols, st);
+}
+void launch_copy_cols(const cd *A, int64_t lda, cf *B, int64_t ldb, int64_t rows, int cols, hipStream_t st) {
+    copy_impl(A, lda, B, ldb, rows, cols, st);
+}
+void launch_copy_cols(const cf *A, int64_t lda, cd *B, int64_t ldb, int64_t rows, int cols, hipStream_t st) {
+    copy_impl(A, lda, B, ldb, rows, cols, st);
+}
 
-void launch_zero_f64(cd *X, int64_t ldx, int64_t rows, int cols, hipStream_t st) {
+template <class S>
+void zero_impl(S *X, int64_t ldx, int64_t rows, int cols, hipStream_t st) {
     if (rows <= 0 || cols <= 0) return;
-    hipLaunchKernelGGL(k_zero, dim3((unsigned)((rows + 255) / 256), cols), dim3(256), 0, st, X, ldx,
+    hipLaunchKernelGGL(k_zero<S>, dim3((unsigned)((rows + 255) / 256), cols), dim3(256), 0, st, X, ldx,
                        rows);
     PW_HIP(hipGetLastError());
 }
+void launch_zero(cd *X, int64_t ldx, int64_t rows, int cols, hipStream_t st) { zero_impl(X, ldx, rows, cols, st); }
+void launch_zero(cf *X, int64_t ldx, int64_t rows, int cols, hipStream_t st) { zero_impl(X, ldx, rows, cols, st); }
 
-void launch_random_block_f64(cd *X, int64_t ldx, int64_t rows, int cols, uint64_t seed,
-                             const double *kin, hipStream_t st) {
+template <class S>
+void random_impl(S *X, int64_t ldx, int64_t rows, int cols, uint64_t seed, const double *kin,
+                 hipStream_t st) {
     if (rows <= 0 || cols <= 0) return;
-    hipLaunchKernelGGL(k_random_block, dim3((unsigned)((rows + 255) / 256), cols), dim3(256), 0, st,
+    hipLaunchKernelGGL(k_random_block<S>, dim3((unsigned)((rows + 255) / 256), cols), dim3(256), 0, st,
                        X, ldx, rows, seed, kin);
     PW_HIP(hipGetLastError());
+}
+void launch_random_block(cd *X, int64_t ldx, int64_t rows, int cols, uint64_t seed, const double *kin,
+                         hipStream_t st) {
+    random_impl(X, ldx, rows, cols, seed, kin, st);
+}
+void launch_random_block(cf *X, int64_t ldx, int64_t rows, int cols, uint64_t seed, const double *kin,
+                         hipStream_t st) {
+    random_impl(X, ldx, rows, cols, seed, kin, st);
 }
 
 void launch_pcoef_f64(const cd *Cfull, int64_t ldc, int n, int m, cd *Cp, int64_t ldp,
@@ -283,13 +349,24 @@ void launch_pcoef_f64(const cd *Cfull, int64_t ldc, int n, int m, cd *Cp, int64_
     PW_HIP(hipGetLastError());
 }
 
-void launch_precond_map_f64(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
-                            int64_t npw, const double *theta, const double *ekin_nrm, const int *act,
-                            int na, cd *W, int64_t ldw, hipStream_t st) {
+template <class S>
+void precond_map_impl(const S *X, int64_t ldx, const S *HX, int64_t ldhx, const double *kin,
+                      int64_t npw, const double *theta, const double *ekin_nrm, const int *act, int na,
+                      S *W, int64_t ldw, hipStream_t st) {
     if (na <= 0) return;
-    hipLaunchKernelGGL(k_precond_map, dim3((unsigned)((npw + kThreads - 1) / kThreads), na),
+    hipLaunchKernelGGL(k_precond_map<S>, dim3((unsigned)((npw + kThreads - 1) / kThreads), na),
                        dim3(kThreads), 0, st, X, ldx, HX, ldhx, kin, npw, theta, ekin_nrm, act, W, ldw);
     PW_HIP(hipGetLastError());
+}
+void launch_precond_map(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
+                        int64_t npw, const double *theta, const double *ekin_nrm, const int *act, int na,
+                        cd *W, int64_t ldw, hipStream_t st) {
+    precond_map_impl(X, ldx, HX, ldhx, kin, npw, theta, ekin_nrm, act, na, W, ldw, st);
+}
+void launch_precond_map(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, const double *kin,
+                        int64_t npw, const double *theta, const double *ekin_nrm, const int *act, int na,
+                        cf *W, int64_t ldw, hipStream_t st) {
+    precond_map_impl(X, ldx, HX, ldhx, kin, npw, theta, ekin_nrm, act, na, W, ldw, st);
 }
 
 void launch_pcoef_map_f64(const cd *Cfull, int64_t ldc, int n, int m, const int *act, int na, cd *Cp,
@@ -297,6 +374,12 @@ void launch_pcoef_map_f64(const cd *Cfull, int64_t ldc, int n, int m, const int 
     if (na <= 0) return;
     hipLaunchKernelGGL(k_pcoef_map, dim3((n + 255) / 256, na), dim3(256), 0, st, Cfull, ldc, n, m, act,
                        Cp, ldp);
+    PW_HIP(hipGetLastError());
+}
+
+void launch_convert_f64_f32(const double *a, float *b, int64_t n, hipStream_t st) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(k_convert_f64_f32, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, b, n);
     PW_HIP(hipGetLastError());
 }
 

@@ -24,14 +24,16 @@ class PlaneWaveProblem:
         if pos is not None and len(lm):
             self.ctx.set_projectors(pos, lm, D)
         self.nbands, self.block = nbands, min(block, nbands)
+        self.prec = prec
         self.ws = self.ctx.alloc_workspace(nbands, self.block, prec)
         self.device = device
 
     @classmethod
-    def from_workload(cls, w, device=0, stream=None, nbands=None, block=None):
+    def from_workload(cls, w, device=0, stream=None, nbands=None, block=None, prec=PW_PREC_FP64):
         return cls(w.cell, w.kfrac, w.ecut, w.n, w.vgrid, w.pos if w.lm else None, w.lm, w.D,
                    nbands=w.nbands if nbands is None else nbands,
-                   block=w.block if block is None else block, device=device, stream=stream)
+                   block=w.block if block is None else block, device=device, stream=stream,
+                   prec=prec)
 
     def empty_block(self, nb):
         return self.torch.zeros((nb, self.npw), dtype=self.torch.complex128,
@@ -42,7 +44,7 @@ class PlaneWaveProblem:
         self.ctx.apply_H(X, Y)
         return Y
 
-    def solve(self, tol, max_iter=300, X=None, allow_not_converged=False):
+    def solve(self, tol, max_iter=300, X=None, allow_not_converged=False, prec=None):
         if X is None:
             X = self.empty_block(self.nbands)
             use_guess = False
@@ -50,5 +52,6 @@ class PlaneWaveProblem:
             use_guess = True
         eig, status = self.ctx.lobpcg_solve(self.nbands, self.block, tol, max_iter, X,
                                             use_guess=use_guess,
+                                            prec=self.prec if prec is None else prec,
                                             allow_not_converged=allow_not_converged)
         return eig, X, status

@@ -79,9 +79,14 @@ def test_block_update_in_place(torch_cuda):
     assert np.abs(X.cpu().numpy().T - ref).max() <= 1e-12
 
 
-@pytest.mark.parametrize("n,k,kind", [(1, 1, "rand"), (2, 2, "rand"), (5, 3, "rand"), (48, 16, "rand"),
+# sizes straddle the kernel variants: register-resident reduction (n <= 192),
+# LDS CholQR2 of the eigenvectors (k <= 64, n <= 219), one-wave back-transform
+# (n <= 256) and the general forms above those sizes
+@pytest.mark.parametrize("n,k,kind", [(1, 1, "rand"), (2, 2, "rand"), (5, 3, "rand"), (33, 7, "rand"),
+                                      (48, 16, "rand"), (64, 64, "rand"), (100, 1, "rand"),
                                       (130, 40, "rand"), (192, 64, "rand"), (192, 64, "degenerate"),
-                                      (128, 64, "graded"), (512, 512, "rand")])
+                                      (128, 64, "graded"), (193, 64, "rand"), (230, 70, "rand"),
+                                      (300, 32, "degenerate"), (512, 512, "rand")])
 def test_small_eigh(torch_cuda, n, k, kind):
     torch = torch_cuda
     prob = _ctx(torch)
