@@ -6,12 +6,16 @@ jittered fcc sites in a 20 bohr cube, Ecut 20 Ha (34181 plane waves), k =
 (1/4,1/4,1/4), 96^3 grid, 432 KB projectors, 512 bands in blocks of 64,
 residual tolerance 1e-6, FP64.
 
-Prints ONE JSON line (rank 0).  Besides the headline value it reports the H.X
-FFT throughput, the roofline of the dominant kernel (timed with HIP events on
-the stream it runs on), solve-latency percentiles, and the CPU oracle timed on
+Prints ONE JSON line (rank 0).  Besides the headline value (FP64) it reports
+the same solve in the mixed-precision form (complex64 iteration + FP64
+refinement) with its per-eigenvalue difference from the FP64 result, the H.X
+FFT throughput in both precisions, the roofline of the dominant phase and of
+the other two (each timed with HIP events on the stream it runs on at its
+canonical launch shape), solve-latency percentiles, and the CPU oracle timed on
 a bounded sample of the same workload.
 
-    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu]
+    python bench.py [--gpus 1] [--steps 3] [--warmup 1] [--no-cpu] [--mixed-steps 2]
+    python bench.py --roofline-only      # the roofline launches alone (profiling)
 """
 from __future__ import annotations
 
@@ -27,6 +31,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a plain-copy
+# calibration; profiles/hbm_bytes_fcc108_l20.txt) for the kernels as they were profiled;
+# set an entry to None when its kernels change.
+TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 2.82e8, "dense": None}
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
 WORKLOAD = "fcc108_l20"
 
@@ -80,6 +88,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=6)
     ap.add_argument("--mixed-steps", type=int, default=2, help="timed solves in the mixed form")
+    ap.add_argument("--roofline-only", action="store_true",
+                    help="only the per-kernel roofline timings (for profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1",
@@ -102,55 +112,56 @@ def main():
         eig, st = prob.ctx.lobpcg_solve(w.nbands, w.block, w.tol, 300, X, use_guess=False, prec=prec)
         return eig
 
-    for i in range(args.warmup):
-        solve()
-        log(f"warmup {i + 1}/{args.warmup} done")
-    torch.cuda.synchronize()
-    lat = []
-    iters = []
-    t_start = time.perf_counter()
-    for i in range(args.steps):
-        t0 = time.perf_counter()
-        eig = solve()
+    if not args.roofline_only:
+        for i in range(args.warmup):
+            solve()
+            log(f"warmup {i + 1}/{args.warmup} done")
         torch.cuda.synchronize()
-        lat.append(time.perf_counter() - t0)
-        st = prob.ctx.get_stats()
-        iters.append(st["iterations"])
-        log(f"step {i + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms, {st['iterations']} iterations")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    ms_per_step = 1e3 * elapsed / args.steps
-    value = w.nbands / (elapsed / args.steps)
-    res = prob.ctx.get_residuals(w.nbands)
-    stats = prob.ctx.get_stats()
-    eig64 = eig.copy()
-
-    # ---- the same cell in the mixed form (complex64 iteration + FP64 refinement)
-    mixed = None
-    if args.mixed_steps > 0:
-        solve(PW_PREC_MIXED)
-        torch.cuda.synchronize()
-        mlat = []
-        for i in range(args.mixed_steps):
+        lat = []
+        iters = []
+        t_start = time.perf_counter()
+        for i in range(args.steps):
             t0 = time.perf_counter()
-            eigm = solve(PW_PREC_MIXED)
+            eig = solve()
             torch.cuda.synchronize()
-            mlat.append(time.perf_counter() - t0)
-            log(f"mixed step {i + 1}/{args.mixed_steps}: {mlat[-1] * 1e3:.1f} ms")
-        mst = prob.ctx.get_stats()
-        mres = prob.ctx.get_residuals(w.nbands)
-        err = np.abs(eigm - eig64)
-        mixed = {"value": w.nbands / float(np.mean(mlat)), "unit": "eigenpairs/s",
-                 "ms_per_solve": 1e3 * float(np.mean(mlat)),
-                 "latency_p50_ms": float(np.percentile(np.array(mlat) * 1e3, 50)),
-                 "latency_p99_ms": float(np.percentile(np.array(mlat) * 1e3, 99)),
-                 "speedup_vs_fp64": (w.nbands / float(np.mean(mlat))) / value,
-                 "max_abs_eig_diff_vs_fp64_ha": float(err.max()),
-                 "mean_abs_eig_diff_vs_fp64_ha": float(err.mean()),
-                 "max_residual": float(mres.max()),
-                 "iterations": mst["iterations"], "complex64_iterations": mst["mixed_iterations"],
-                 "phase_ms": {k: mst[k] for k in ("ms_apply", "ms_gemm", "ms_dense", "ms_vec",
-                                                  "ms_final_rr")}}
+            lat.append(time.perf_counter() - t0)
+            st = prob.ctx.get_stats()
+            iters.append(st["iterations"])
+            log(f"step {i + 1}/{args.steps}: {lat[-1] * 1e3:.1f} ms, {st['iterations']} iterations")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t_start
+        ms_per_step = 1e3 * elapsed / args.steps
+        value = w.nbands / (elapsed / args.steps)
+        res = prob.ctx.get_residuals(w.nbands)
+        stats = prob.ctx.get_stats()
+        eig64 = eig.copy()
+
+        # ---- the same cell in the mixed form (complex64 iteration + FP64 refinement)
+        mixed = None
+        if args.mixed_steps > 0:
+            solve(PW_PREC_MIXED)
+            torch.cuda.synchronize()
+            mlat = []
+            for i in range(args.mixed_steps):
+                t0 = time.perf_counter()
+                eigm = solve(PW_PREC_MIXED)
+                torch.cuda.synchronize()
+                mlat.append(time.perf_counter() - t0)
+                log(f"mixed step {i + 1}/{args.mixed_steps}: {mlat[-1] * 1e3:.1f} ms")
+            mst = prob.ctx.get_stats()
+            mres = prob.ctx.get_residuals(w.nbands)
+            err = np.abs(eigm - eig64)
+            mixed = {"value": w.nbands / float(np.mean(mlat)), "unit": "eigenpairs/s",
+                     "ms_per_solve": 1e3 * float(np.mean(mlat)),
+                     "latency_p50_ms": float(np.percentile(np.array(mlat) * 1e3, 50)),
+                     "latency_p99_ms": float(np.percentile(np.array(mlat) * 1e3, 99)),
+                     "speedup_vs_fp64": (w.nbands / float(np.mean(mlat))) / value,
+                     "max_abs_eig_diff_vs_fp64_ha": float(err.max()),
+                     "mean_abs_eig_diff_vs_fp64_ha": float(err.mean()),
+                     "max_residual": float(mres.max()),
+                     "iterations": mst["iterations"], "complex64_iterations": mst["mixed_iterations"],
+                     "phase_ms": {k: mst[k] for k in ("ms_apply", "ms_gemm", "ms_dense", "ms_vec",
+                                                      "ms_final_rr")}}
 
     # ---- H.X FFT apply (local part, 64 bands), its own context without projectors
     mil = prob.ctx.get_miller()
@@ -199,19 +210,28 @@ def main():
     eig_tflops = eig_flops / (t_eig * 1e-3) / 1e12
 
     roofs = {
-        "dense": dict(bound="alu", kernel="pw_small_eigh 192x192 lowest 64 (k_hetrd, k_stebz, k_stein, "
-                      "k_orth_chol, k_unmtr)", achieved=eig_tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                      frac=eig_tflops / FP64_PEAK_TFLOPS, traffic=None,
+        "dense": dict(bound="alu", kernel="pw_small_eigh 192x192 lowest 64 (k_hetrd_rf<6>, k_stebz, "
+                      "k_stein, k_orth_chol2, k_unmtr_w<3>, k_check_w)", achieved=eig_tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
+                      frac=eig_tflops / FP64_PEAK_TFLOPS, traffic=TRAFFIC_MEASURED["dense"],
                       algorithmic=f"{eig_flops:.3e} FLOP per call (16/3 n^3 + 8 n^2 k)", launch_ms=t_eig),
-        "gemm": dict(bound="mfma", kernel="k_gemm_tn (+k_reduce_parts), Rayleigh-Ritz Gram 192x192, K=34181",
+        "gemm": dict(bound="mfma", kernel="k_gemm_tn_lds (+k_reduce_parts), Rayleigh-Ritz Gram 192x192, "
+                     "K=34181",
                      achieved=gram_tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
-                     frac=gram_tflops / FP64_PEAK_TFLOPS, traffic=None,
+                     frac=gram_tflops / FP64_PEAK_TFLOPS, traffic=TRAFFIC_MEASURED["gemm"],
                      algorithmic=f"{gram_flops:.3e} FLOP per launch (8 p q K)", launch_ms=t_gram),
         "apply": dict(bound="hbm", kernel="k_zinv + k_plane + k_zfwd (local H.X, 64 bands)",
                       achieved=fft_gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=fft_gbs / HBM_PEAK_GBS,
-                      traffic=None, algorithmic=f"{b_alg_design:.3e} B per 64-band apply",
+                      traffic=TRAFFIC_MEASURED["apply"], algorithmic=f"{b_alg_design:.3e} B per 64-band apply",
                       launch_ms=t_fft),
     }
+    if args.roofline_only:
+        # plain device copy of known size: reference for HBM byte counters
+        src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        t_copy = event_time_ms(torch, torch.cuda.current_stream(), lambda: dst.copy_(src), 5)
+        print(json.dumps({"roofline_all": roofs, "copy_256MiB_ms": t_copy,
+                          "copy_256MiB_gbs": 2 * (1 << 28) / (t_copy * 1e-3) / 1e9}), flush=True)
+        return
     phases = {k: stats[k] for k in ("ms_apply", "ms_gemm", "ms_dense", "ms_vec", "ms_final_rr")}
     dominant = max(("dense", "gemm", "apply"), key=lambda k: phases["ms_" + k])
     roof = roofs[dominant]

@@ -76,70 +76,116 @@ __device__ __forceinline__ int xcd_logical(int lin, int total) {
     return xcd * q + min(xcd, r) + local;
 }
 
+// TN: the k-blocks are staged through LDS: each k-block of A and B
+// (16 rows x 64 columns each) is read from HBM once per workgroup with loads
+// that cover 4 columns x 256 contiguous bytes per wave instruction, written
+// to LDS (column stride padded to 17 elements), and the MFMA operands are read
+// from there.  The next block's global loads are in flight during the current
+// block's MFMAs (two LDS buffers, one barrier per block).
 template <class T>
 __global__ void __launch_bounds__(kThreads)
-    k_gemm_tn(const cpx<T> *__restrict__ A, int64_t lda, const cpx<T> *__restrict__ B, int64_t ldb,
-              int64_t K, int p, int q, int64_t kchunk, int tiles_m, int tiles_n, int nsplit,
-              cpx<T> *__restrict__ part) {
+    k_gemm_tn_lds(const cpx<T> *__restrict__ A, int64_t lda, const cpx<T> *__restrict__ B,
+                  int64_t ldb, int64_t K, int p, int q, int64_t kchunk, int tiles_m, int tiles_n,
+                  int nsplit, cpx<T> *__restrict__ part) {
     using M = Mfma<T>;
     using v4 = typename M::v4;
+    constexpr int KB = 16, LDC = KB + 1;
+    __shared__ cpx<T> sA[2][kTile * LDC], sB[2][kTile * LDC];
     const int total = tiles_m * tiles_n * nsplit;
     const int lid = xcd_logical(blockIdx.x, total);
-    // split is the slow index so that the tiles sharing one K chunk run close
-    // together on one XCD and share its L2.
     const int split = lid / (tiles_m * tiles_n);
     const int tile = lid % (tiles_m * tiles_n);
     const int tm = tile % tiles_m, tn = tile / tiles_m;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = lane & 15, g = lane >> 4;
-    const int i0 = tm * kTile + (wave & 1) * 32;
-    const int j0 = tn * kTile + (wave >> 1) * 32;
     const int64_t kbeg = (int64_t)split * kchunk;
     const int64_t kend = min(K, kbeg + kchunk);
 
-    v4 accr[2][2], acci[2][2];
+    // global -> LDS assignment: instruction u covers columns 16 wave + 4u + g, rows li
+    const cpx<T> *Ag[4];
+    const cpx<T> *Bg[4];
+    bool aok[4], bok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int c = 16 * wave + 4 * u + g;
+        const int ca = tm * kTile + c, cb = tn * kTile + c;
+        aok[u] = ca < p;
+        bok[u] = cb < q;
+        Ag[u] = A + (int64_t)(aok[u] ? ca : 0) * lda;
+        Bg[u] = B + (int64_t)(bok[u] ? cb : 0) * ldb;
+    }
+    cpx<T> ra[4], rb[4];
+    auto gload = [&](int64_t kb) {
+        const int64_t k = kb + li;
+        const bool kin = k < kend;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ra[u] = ldg_or_zero(Ag[u] + k, kin && aok[u]);
+            rb[u] = ldg_or_zero(Bg[u] + k, kin && bok[u]);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = 16 * wave + 4 * u + g;
+            sA[buf][c * LDC + li] = ra[u];
+            sB[buf][c * LDC + li] = rb[u];
+        }
+    };
+
+    // 3-multiplication complex product per 16x16 sub-tile: with
+    // t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar - ai)(br + bi),
+    // conj(a) b = (t1 + t2) + i (t3 - t1 + t2)
+    v4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = v4{0, 0, 0, 0};
-
-    const cpx<T> *Ac[2];
-    const cpx<T> *Bc[2];
-    bool aok[2], bok[2];
+        for (int b = 0; b < 2; ++b) t1[a][b] = t2[a][b] = t3[a][b] = v4{0, 0, 0, 0};
+    const int ia = (wave & 1) * 32, jb = (wave >> 1) * 32;
+    // sub-tiles wholly outside p x q are skipped (uniform per wave)
+    bool live[2][2];
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int ci = i0 + 16 * t + li, cj = j0 + 16 * t + li;
-        aok[t] = ci < p;
-        bok[t] = cj < q;
-        Ac[t] = A + (int64_t)(aok[t] ? ci : 0) * lda;
-        Bc[t] = B + (int64_t)(bok[t] ? cj : 0) * ldb;
-    }
-    for (int64_t kb = kbeg; kb < kend; kb += 16) {
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj)
+            live[mi][nj] = tm * kTile + ia + 16 * mi < p && tn * kTile + jb + 16 * nj < q;
+    auto mma = [&](int buf) {
         cpx<T> a[2][4], b[2][4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int64_t k = kb + 4 * g + s;
-            const bool kin = k < kend;
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                a[t][s] = ldg_or_zero(Ac[t] + k, kin && aok[t]);
-                b[t][s] = ldg_or_zero(Bc[t] + k, kin && bok[t]);
+            for (int s = 0; s < 4; ++s) {
+                a[t][s] = sA[buf][(ia + 16 * t + li) * LDC + 4 * g + s];
+                b[t][s] = sB[buf][(jb + 16 * t + li) * LDC + 4 * g + s];
             }
-        }
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
             for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
                 for (int nj = 0; nj < 2; ++nj) {
-                    // conj(a) * b
-                    accr[mi][nj] = M::op(a[mi][s].x, b[nj][s].x, accr[mi][nj]);
-                    accr[mi][nj] = M::op(a[mi][s].y, b[nj][s].y, accr[mi][nj]);
-                    acci[mi][nj] = M::op(a[mi][s].x, b[nj][s].y, acci[mi][nj]);
-                    acci[mi][nj] = M::op(-a[mi][s].y, b[nj][s].x, acci[mi][nj]);
+                    if (!live[mi][nj]) continue;
+                    t1[mi][nj] = M::op(a[mi][s].x, b[nj][s].x, t1[mi][nj]);
+                    t2[mi][nj] = M::op(a[mi][s].y, b[nj][s].y, t2[mi][nj]);
+                    t3[mi][nj] = M::op(a[mi][s].x - a[mi][s].y, b[nj][s].x + b[nj][s].y, t3[mi][nj]);
                 }
+    };
+    if (kbeg < kend) {
+        gload(kbeg);
+        lstore(0);
+        __syncthreads();
+        int buf = 0;
+        for (int64_t kb = kbeg; kb < kend; kb += KB) {
+            const bool more = kb + KB < kend;
+            if (more) gload(kb + KB);
+            mma(buf);
+            if (more) lstore(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
     }
     cpx<T> *P = part + (size_t)split * p * q;
+    const int i0 = tm * kTile + ia, j0 = tn * kTile + jb;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
@@ -148,7 +194,9 @@ __global__ void __launch_bounds__(kThreads)
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + 16 * mi + M::row(g, r);
                 const int j = j0 + 16 * nj + li;
-                if (i < p && j < q) P[(size_t)j * p + i] = cpx<T>{accr[mi][nj][r], acci[mi][nj][r]};
+                if (i < p && j < q)
+                    P[(size_t)j * p + i] = cpx<T>{t1[mi][nj][r] + t2[mi][nj][r],
+                                                  t3[mi][nj][r] - t1[mi][nj][r] + t2[mi][nj][r]};
             }
 }
 
@@ -190,11 +238,13 @@ __global__ void __launch_bounds__(kThreads)
     const int64_t r0 = (int64_t)tm * kTile + (wave & 1) * 32;
     const int c0 = tn * kTile + (wave >> 1) * 32;
 
-    v4 accr[2][2], acci[2][2];
+    // 3-multiplication complex product: with t1 = sum ar cr, t2 = sum ai ci,
+    // t3 = sum (ar + ai)(cr + ci), a c = (t1 - t2) + i (t3 - t1 - t2)
+    v4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
     for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) accr[a][b] = acci[a][b] = v4{0, 0, 0, 0};
+        for (int b = 0; b < 2; ++b) t1[a][b] = t2[a][b] = t3[a][b] = v4{0, 0, 0, 0};
 
     bool rok[2], cok[2];
 #pragma unroll
@@ -202,6 +252,11 @@ __global__ void __launch_bounds__(kThreads)
         rok[t] = r0 + 16 * t + li < K;
         cok[t] = c0 + 16 * t + li < q;
     }
+    bool live[2][2];   // sub-tiles wholly outside K x q are skipped (uniform per wave)
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) live[mi][nj] = r0 + 16 * mi < K && c0 + 16 * nj < q;
     for (int kb = 0; kb < p; kb += 16) {
         cpx<T> a[2][4], b[2][4];
 #pragma unroll
@@ -222,11 +277,10 @@ __global__ void __launch_bounds__(kThreads)
             for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
                 for (int nj = 0; nj < 2; ++nj) {
-                    // a * c
-                    accr[mi][nj] = M::op(a[mi][s].x, b[nj][s].x, accr[mi][nj]);
-                    accr[mi][nj] = M::op(-a[mi][s].y, b[nj][s].y, accr[mi][nj]);
-                    acci[mi][nj] = M::op(a[mi][s].x, b[nj][s].y, acci[mi][nj]);
-                    acci[mi][nj] = M::op(a[mi][s].y, b[nj][s].x, acci[mi][nj]);
+                    if (!live[mi][nj]) continue;
+                    t1[mi][nj] = M::op(a[mi][s].x, b[nj][s].x, t1[mi][nj]);
+                    t2[mi][nj] = M::op(a[mi][s].y, b[nj][s].y, t2[mi][nj]);
+                    t3[mi][nj] = M::op(a[mi][s].x + a[mi][s].y, b[nj][s].x + b[nj][s].y, t3[mi][nj]);
                 }
     }
     // every wave of the workgroup has read its rows of A before any writes:
@@ -242,7 +296,8 @@ __global__ void __launch_bounds__(kThreads)
                 const int j = c0 + 16 * nj + li;
                 if (i < K && j < q) {
                     cpx<T> *y = Y + (int64_t)j * ldy + i;
-                    T yr = T(alpha) * accr[mi][nj][r], yi = T(alpha) * acci[mi][nj][r];
+                    T yr = T(alpha) * (t1[mi][nj][r] - t2[mi][nj][r]);
+                    T yi = T(alpha) * (t3[mi][nj][r] - t1[mi][nj][r] - t2[mi][nj][r]);
                     if (beta != 0.0) {
                         const cpx<T> o = *y;
                         yr += T(beta) * o.x;
@@ -258,7 +313,7 @@ __global__ void __launch_bounds__(kThreads)
 #endif
 int choose_split(int64_t K, int tiles) {
     int64_t ns = (PW_SPLIT_WGS + tiles - 1) / tiles;
-    const int64_t kmax = (K + 255) / 256;
+    const int64_t kmax = (K + 255) / 256;   // chunks of at least 16 k-blocks
     if (ns > kmax) ns = kmax;
     if (ns < 1) ns = 1;
     return (int)ns;
@@ -289,7 +344,7 @@ void gemm_tn_impl(const cpx<T> *A, int64_t lda, const cpx<T> *B, int64_t ldb, in
     const int total = tiles_m * tiles_n * ns;
     // partials in the block type (the buffer is sized for complex128)
     cpx<T> *pt = reinterpret_cast<cpx<T> *>(part);
-    hipLaunchKernelGGL(k_gemm_tn<T>, dim3(total), dim3(kThreads), 0, st, A, lda, B, ldb, K, p, q,
+    hipLaunchKernelGGL(k_gemm_tn_lds<T>, dim3(total), dim3(kThreads), 0, st, A, lda, B, ldb, K, p, q,
                        kchunk, tiles_m, tiles_n, ns, pt);
     const int64_t n = (int64_t)p * q;
     hipLaunchKernelGGL(k_reduce_parts<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pt,
