@@ -153,6 +153,21 @@ pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ld
 pw_status pw_lobpcg_solve(pw_ctx ctx, int32_t nbands, int32_t block, double tol,
                           int32_t max_iter, pw_precision prec, void *X, int64_t ldx,
                           int32_t use_guess, double *eig);
+/* Independent solves of n contexts run concurrently -- the k-points of one
+ * cell, or any independent cells (sec. 5.2: k-points need no communication
+ * inside the eigensolve).  Each context must be ready for pw_lobpcg_solve
+ * (basis, potential, projectors, a workspace sized for (nbands, block, prec))
+ * and bound to its own stream; contexts may have different plane-wave counts.
+ * The library drives context i from its own host thread, so the kernels of
+ * different contexts overlap on the device.  X[i], ldx[i], eig[i] are as in
+ * pw_lobpcg_solve for context i; status[i] receives its result.  Returns
+ * PW_OK if every solve succeeded, else the first error that is not
+ * PW_ERR_NOT_CONVERGED, else PW_ERR_NOT_CONVERGED.  A context may appear
+ * once.  Synchronises every context's stream. */
+pw_status pw_lobpcg_solve_batch(pw_ctx *ctxs, int32_t n, int32_t nbands, int32_t block,
+                                double tol, int32_t max_iter, pw_precision prec,
+                                void *const *X, const int64_t *ldx, int32_t use_guess,
+                                double *const *eig, pw_status *status);
 /* Residual norms ||H x_j - theta_j x_j||_2 of the last solve, host double[nbands]. */
 pw_status pw_get_residuals(pw_ctx ctx, double *res);
 /* Counters and phase times of the last solve. */

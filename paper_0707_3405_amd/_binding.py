@@ -26,7 +26,7 @@ EXPORTS = ("pw_create", "pw_destroy", "pw_last_error", "pw_init_basis", "pw_fft_
            "pw_get_miller", "pw_get_kinetic", "pw_set_local_potential", "pw_set_projectors",
            "pw_workspace_size", "pw_set_workspace", "pw_apply_H", "pw_lobpcg_solve",
            "pw_get_residuals", "pw_get_stats", "pw_gram", "pw_block_update", "pw_small_eigh",
-           "pw_residuals", "pw_gram_mixed", "pw_block_update_mixed")
+           "pw_residuals", "pw_gram_mixed", "pw_block_update_mixed", "pw_lobpcg_solve_batch")
 
 
 class PWError(RuntimeError):
@@ -84,6 +84,7 @@ def load_library():
         "pw_gram": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, P, I64]),
         "pw_block_update": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, D, D, P, I64]),
         "pw_gram_mixed": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, P, I64]),
+        "pw_lobpcg_solve_batch": (ctypes.c_int, [P, I32, I32, I32, D, I32, ctypes.c_int, P, P, I32, P, P]),
         "pw_block_update_mixed": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, D, D, P, I64]),
         "pw_small_eigh": (ctypes.c_int, [P, P, I64, I32, I32, P, P, I64]),
         "pw_residuals": (ctypes.c_int, [P, P, I64, P, I64, I32, P, P, P, I64]),

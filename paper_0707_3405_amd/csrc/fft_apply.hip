@@ -29,6 +29,13 @@ namespace {
 using namespace fft;
 
 constexpr int kThreads = 256;
+#ifndef PW_PLANE_THREADS
+#define PW_PLANE_THREADS 512   // workgroup size of the plane pass
+#endif
+#ifndef PW_PLANE_RB
+#define PW_PLANE_RB 32         // largest row chunk of the plane pass
+#endif
+constexpr int kPlaneThreads = PW_PLANE_THREADS;
 
 template <class T>
 __device__ __forceinline__ void load_twiddles(cpx<T> *tw_s, const double *tw_g, int n) {
@@ -89,7 +96,7 @@ __device__ __forceinline__ int xcd_logical(int lin, int total) {
 }
 
 template <int N, class T>
-__global__ void __launch_bounds__(kThreads) k_plane(SphereDev sp, const T *__restrict__ vperm,
+__global__ void __launch_bounds__(kPlaneThreads) k_plane(SphereDev sp, const T *__restrict__ vperm,
                                                     cpx<T> *__restrict__ S, int nb, int rb) {
     constexpr int LD = N + 1;
     constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
@@ -263,10 +270,11 @@ void run_apply(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx
     // pass 2 LDS: twiddles + kept columns + row chunk; largest row chunk that
     // keeps the workgroup under 150 KB.
     const size_t base2 = (size_t)N * e + (size_t)sp.ncx * (N + 1) * e;
-    int rb = 32;
-    while (rb > 1 && base2 + (size_t)rb * (N + 1) * e > 150 * 1024) rb /= 2;
+    int rb = PW_PLANE_RB;
+    auto sm2_of = [&](int r) { return base2 + (size_t)r * (N + 1) * e; };
+    while (rb > 1 && sm2_of(rb) > 150 * 1024) rb /= 2;
     if (rb > N) rb = N;
-    const size_t sm2 = base2 + (size_t)rb * (N + 1) * e;
+    const size_t sm2 = sm2_of(rb);
     PW_REQUIRE(sm2 <= 160 * 1024, PW_ERR_ARG, "FFT plane does not fit in LDS");
     PW_HIP(hipFuncSetAttribute((const void *)k_zinv<N, T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm13));
@@ -275,7 +283,7 @@ void run_apply(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx
     PW_HIP(hipFuncSetAttribute((const void *)k_zfwd<N, T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm13));
     hipLaunchKernelGGL((k_zinv<N, T>), g13, dim3(kThreads), sm13, st, sp, X, ldx, S, spb);
-    hipLaunchKernelGGL((k_plane<N, T>), dim3(N * nb), dim3(kThreads), sm2, st, sp, vperm, S, nb,
+    hipLaunchKernelGGL((k_plane<N, T>), dim3(N * nb), dim3(kPlaneThreads), sm2, st, sp, vperm, S, nb,
                        rb);
     hipLaunchKernelGGL((k_zfwd<N, T>), g13, dim3(kThreads), sm13, st, sp, S, X, ldx, Y, ldy, spb);
     PW_HIP(hipGetLastError());

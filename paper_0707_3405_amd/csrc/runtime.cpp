@@ -7,6 +7,7 @@
 #include <cstring>
 #include <memory>
 #include <new>
+#include <thread>
 #include <type_traits>
 
 #include "pw_internal.h"
@@ -988,6 +989,31 @@ pw_status pw_lobpcg_solve(pw_ctx c, int32_t nbands, int32_t block, double tol, i
         PW_HIP(hipSetDevice(c->device));
         return solve(c, nbands, m, tol, max_iter, prec, static_cast<cd *>(X), ldx, use_guess, eig);
     });
+}
+
+pw_status pw_lobpcg_solve_batch(pw_ctx *ctxs, int32_t n, int32_t nbands, int32_t block, double tol,
+                                int32_t max_iter, pw_precision prec, void *const *X,
+                                const int64_t *ldx, int32_t use_guess, double *const *eig,
+                                pw_status *status) {
+    if (!ctxs || !X || !ldx || !eig || !status || n < 1) return PW_ERR_ARG;
+    for (int i = 0; i < n; ++i) {
+        if (!ctxs[i]) return PW_ERR_ARG;
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == ctxs[i]) return PW_ERR_ARG;   // one solve per context at a time
+    }
+    // one host thread per context; each context runs on its own stream
+    std::vector<std::thread> th;
+    th.reserve(n);
+    for (int i = 0; i < n; ++i)
+        th.emplace_back([=] {
+            status[i] = pw_lobpcg_solve(ctxs[i], nbands, block, tol, max_iter, prec, X[i], ldx[i],
+                                        use_guess, eig[i]);
+        });
+    for (auto &t : th) t.join();
+    pw_status worst = PW_OK;
+    for (int i = 0; i < n; ++i)
+        if (status[i] != PW_OK && (worst == PW_OK || worst == PW_ERR_NOT_CONVERGED)) worst = status[i];
+    return worst;
 }
 
 pw_status pw_get_residuals(pw_ctx c, double *res) {

@@ -55,3 +55,34 @@ class PlaneWaveProblem:
                                             prec=self.prec if prec is None else prec,
                                             allow_not_converged=allow_not_converged)
         return eig, X, status
+
+
+def solve_batch(problems, tol, max_iter=300, Xs=None, prec=None, allow_not_converged=False):
+    """Concurrent solves of several problems (e.g. the k-points of one cell) through
+    pw_lobpcg_solve_batch: one host thread and one stream per problem.
+
+    Every problem must share nbands and block.  Returns (eigs, Xs, statuses)."""
+    import ctypes
+    from ._binding import PWError, PW_OK, PW_ERR_NOT_CONVERGED, _ptr, _ld
+    n = len(problems)
+    nb, blk = problems[0].nbands, problems[0].block
+    if any(p.nbands != nb or p.block != blk for p in problems):
+        raise ValueError("solve_batch needs one (nbands, block) for every problem")
+    prec = problems[0].prec if prec is None else prec
+    use_guess = Xs is not None
+    if Xs is None:
+        Xs = [p.empty_block(nb) for p in problems]
+    eigs = [np.zeros(nb, np.float64) for _ in problems]
+    ctxs = (ctypes.c_void_p * n)(*[p.ctx.h for p in problems])
+    xp = (ctypes.c_void_p * n)(*[_ptr(x).value for x in Xs])
+    ld = (ctypes.c_int64 * n)(*[_ld(x) for x in Xs])
+    ep = (ctypes.c_void_p * n)(*[e.ctypes.data for e in eigs])
+    st = (ctypes.c_int * n)()
+    lib = problems[0].ctx.lib
+    rc = lib.pw_lobpcg_solve_batch(ctxs, n, nb, blk, float(tol), max_iter, prec, xp, ld,
+                                   int(use_guess), ep, st)
+    statuses = list(st)
+    if rc != PW_OK and not (allow_not_converged and rc == PW_ERR_NOT_CONVERGED):
+        bad = next(i for i, s in enumerate(statuses) if s != PW_OK)
+        raise PWError(rc, f"problem {bad}: " + lib.pw_last_error(problems[bad].ctx.h).decode())
+    return eigs, Xs, statuses

@@ -6,6 +6,9 @@ Calls only `oracle/` (and the seeded input generators in `workloads/`):
   mid_nl      dense H diagonalised by the oracle's C Jacobi.
   fcc32_l12   oracle.matfree.solve (block LOBPCG + final Rayleigh-Ritz), tol 1e-9.
   fcc108_l20  oracle.matfree.solve, tol 1e-8 (34181 plane waves: no dense H).
+  kpts_l16_k1, kpts_l16_k9
+              oracle.matfree.solve, tol 1e-8, at k-points 1 and 9 of the
+              ten-k-point batch cell (workloads.make_kpoint_workloads).
 
 Each file lists index, eigenvalue (Ha) and, for the matrix-free runs, the
 residual norm and the residual certificate (oracle.matfree.certificate).
@@ -25,7 +28,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import pw, matfree                      # noqa: E402
 from oracle.jacobi import eigh_jacobi              # noqa: E402
-from workloads import make_workload                # noqa: E402
+from workloads import make_workload, make_kpoint_workloads   # noqa: E402
 
 
 def dense_case(name):
@@ -43,8 +46,8 @@ def dense_case(name):
     print("wrote", path)
 
 
-def matfree_case(name, tol):
-    w = make_workload(name)
+def matfree_case(name, tol, w=None):
+    w = make_workload(name) if w is None else w
     mil = pw.sphere(w.cell, w.kfrac, w.ecut)
     H = matfree.MatFreeH(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D)
     t0 = time.time()
@@ -68,6 +71,8 @@ CASES = {
     "mid_nl": lambda: dense_case("mid_nl"),
     "fcc32_l12": lambda: matfree_case("fcc32_l12", 1e-9),
     "fcc108_l20": lambda: matfree_case("fcc108_l20", 1e-8),
+    "kpts_l16_k1": lambda: matfree_case("kpts_l16_k1", 1e-8, make_kpoint_workloads()[1]),
+    "kpts_l16_k9": lambda: matfree_case("kpts_l16_k9", 1e-8, make_kpoint_workloads()[9]),
 }
 
 if __name__ == "__main__":

@@ -102,6 +102,23 @@ def make_workload(name: str) -> Workload:
     return w
 
 
+KPTS_4X4X4_IRREDUCIBLE = ((0, 0, 0), (0, 0, .25), (0, 0, .5), (0, .25, .25), (0, .25, .5),
+                          (0, .5, .5), (.25, .25, .25), (.25, .25, .5), (.25, .5, .5), (.5, .5, .5))
+
+
+def make_kpoint_workloads(name: str = "kpts_l16", kpts=KPTS_4X4X4_IRREDUCIBLE) -> list:
+    """One workload per k-point, all sharing the cell, wells, projectors and V(r)."""
+    base = make_workload(name)
+    out = []
+    for k in kpts:
+        w = Workload(name=f"{name}@{k}", seed=base.seed, L=base.L, ecut=base.ecut, n=base.n,
+                     kfrac=tuple(float(x) for x in k), pos=base.pos, nbands=base.nbands,
+                     block=base.block, tol=base.tol, lm=base.lm, D=base.D)
+        w.vgrid = base.vgrid
+        out.append(w)
+    return out
+
+
 def start_block(seed: int, npw: int, ncol: int) -> np.ndarray:
     """Complex standard-normal block [npw, ncol] from its own PCG64 stream."""
     rng = np.random.default_rng(10_000 + seed)
@@ -121,6 +138,10 @@ WORKLOADS = {
                     proj=True, M=12, m=4, tol=1e-8),
     "mid_nl": dict(seed=11, L=12.0, ecut=8.0, n=36, k=(0.25, 0.0, 0.5),
                    natom=6, proj=True, M=48, m=16, tol=1e-7),
+    # ten k-points of one cell (the irreducible Gamma-centred 4x4x4 set under
+    # cubic symmetry), solved as a batch; `k` is replaced per k-point
+    "kpts_l16": dict(seed=3, L=16.0, ecut=15.0, n=72, k=(0, 0, 0), natom=64,
+                     proj=True, M=256, m=32, tol=1e-6),
     "fcc32_l12": dict(seed=5, L=12.0, ecut=12.0, n=48, k=(0.25, 0.25, 0.25),
                       fcc=2, proj=True, M=128, m=32, tol=1e-6),
 }
