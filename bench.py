@@ -86,8 +86,10 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-iters", type=int, default=6)
+    ap.add_argument("--cpu-iters", type=int, default=15)
     ap.add_argument("--mixed-steps", type=int, default=2, help="timed solves in the mixed form")
+    ap.add_argument("--batch-steps", type=int, default=1,
+                    help="timed batches of the ten-k-point cell (0: skip)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the per-kernel roofline timings (for profiling runs)")
     args = ap.parse_args()
@@ -97,8 +99,8 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_FP64, PW_PREC_MIXED
-    from workloads import make_workload
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_FP64, PW_PREC_MIXED, solve_batch
+    from workloads import make_workload, make_kpoint_workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     w = make_workload(WORKLOAD)
@@ -224,6 +226,36 @@ def main():
                       traffic=TRAFFIC_MEASURED["apply"], algorithmic=f"{b_alg_design:.3e} B per 64-band apply",
                       launch_ms=t_fft),
     }
+    # ---- batched k-points: the ten irreducible k-points of the 4x4x4 grid of the
+    # L = 16 bohr cell (256 bands each, blocks of 32), solved concurrently
+    batched = None
+    if args.batch_steps > 0 and not args.roofline_only:
+        wk = make_kpoint_workloads()
+        probs = [PlaneWaveProblem.from_workload(x, device=0, stream=torch.cuda.Stream(),
+                                                prec=PW_PREC_MIXED) for x in wk]
+        batched = {"workload": "kpts_l16: 10 k-points, L=16, Ecut=15, 72^3, 64 wells, 256 proj.",
+                   "nbands_total": sum(x.nbands for x in wk),
+                   "npw": [p.npw for p in probs]}
+        res_eigs = {}
+        for name, prec in (("fp64", PW_PREC_FP64), ("mixed", PW_PREC_MIXED)):
+            solve_batch(probs[:2], wk[0].tol, prec=prec)       # first-call set-up
+            torch.cuda.synchronize()
+            ts = []
+            for i in range(args.batch_steps):
+                t0 = time.perf_counter()
+                eigs, _, _ = solve_batch(probs, wk[0].tol, prec=prec)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            res_eigs[name] = np.concatenate(eigs)
+            batched[name] = {"value": batched["nbands_total"] / float(np.mean(ts)),
+                             "unit": "eigenpairs/s", "ms_per_batch": 1e3 * float(np.mean(ts)),
+                             "max_residual": float(max(p.ctx.get_residuals(p.nbands).max()
+                                                       for p in probs))}
+            log(f"batched k-points {name}: {1e3 * np.mean(ts):.0f} ms")
+        batched["max_abs_eig_diff_mixed_vs_fp64_ha"] = float(np.abs(res_eigs["mixed"] -
+                                                                    res_eigs["fp64"]).max())
+        del probs
+
     if args.roofline_only:
         # plain device copy of known size: reference for HBM byte counters
         src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
@@ -268,6 +300,7 @@ def main():
         "roofline": roof,
         "roofline_all": roofs,
         "mixed": mixed,
+        "batched_kpoints": batched,
     }
     if not args.no_cpu:
         cores = len(os.sched_getaffinity(0))
