@@ -125,7 +125,8 @@ pw_status pw_set_projectors(pw_ctx ctx, int32_t natom, const double *pos,
 /* Device workspace the caller allocates: bytes needed by pw_lobpcg_solve for
  * (nbands, block) at precision prec, and by pw_apply_H (which works in chunks
  * of `block` columns).  A workspace sized for PW_PREC_MIXED also serves
- * PW_PREC_FP64. */
+ * PW_PREC_FP64.  Also answers on a host-only context (device < 0), so a
+ * caller can size device memory before touching the GPU. */
 pw_status pw_workspace_size(pw_ctx ctx, int32_t nbands, int32_t block, pw_precision prec,
                             size_t *bytes);
 /* Hand the workspace to the context (device pointer, 256-byte aligned).  The

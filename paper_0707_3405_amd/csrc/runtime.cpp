@@ -665,6 +665,16 @@ void init_basis(pw_ctx_s *c, const double cell[9], const double kfrac[3], double
     c->npw = npw;
     c->nst_host = nst;
     c->ncx_host = xmax - xmin + 1;
+    // sizes (also on a host-only context, so pw_workspace_size can plan there)
+    c->ldp = (int64_t)align_up((size_t)npw, 32);
+    pw::SphereDev &sp = c->sp;
+    sp = pw::SphereDev{};
+    sp.npw = npw;
+    sp.n = N;
+    sp.nst = nst;
+    sp.ldst = (int32_t)align_up((size_t)nst, 16);
+    sp.ncx = xmax - xmin + 1;
+    sp.xmin = xmin;
     if (c->device < 0) {   // host-only context: tables stay on the host
         c->has_basis = true;
         *npw_out = npw;
@@ -672,14 +682,6 @@ void init_basis(pw_ctx_s *c, const double cell[9], const double kfrac[3], double
     }
     c->d_status = c->dev_alloc<int>(1);
     PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
-    c->ldp = (int64_t)align_up((size_t)npw, 32);
-    pw::SphereDev &sp = c->sp;
-    sp.npw = npw;
-    sp.n = N;
-    sp.nst = nst;
-    sp.ldst = (int32_t)align_up((size_t)nst, 16);
-    sp.ncx = xmax - xmin + 1;
-    sp.xmin = xmin;
     auto up_i = [&](const std::vector<int32_t> &v) {
         int32_t *d = c->dev_alloc<int32_t>(v.size());
         PW_HIP(hipMemcpy(d, v.data(), v.size() * sizeof(int32_t), hipMemcpyHostToDevice));

@@ -119,6 +119,35 @@ def make_kpoint_workloads(name: str = "kpts_l16", kpts=KPTS_4X4X4_IRREDUCIBLE) -
     return out
 
 
+# grid sizes a served request may use (products of 2, 3, 5 with both factors of
+# a two-factor split <= 16)
+SERVE_FFT_SIZES = (16, 20, 24, 32, 36, 40, 48, 60, 64, 72, 80, 96, 108, 120, 128)
+
+
+def make_request(i: int, base_seed: int = 1000, L_range=(8.0, 24.0), ecut_range=(5.0, 25.0)):
+    """Request i of a served stream: a cubic cell with L ~ U(L_range), Ecut ~ U(ecut_range),
+    round(0.0135 L^3) Gaussian wells at uniform positions with 4 projectors each,
+    k ~ U[0,1)^3, nbands = 32 round(5.5 natom / 32) clamped to [32, 1024], block
+    min(64, nbands), tol 1e-6, and a precision flag (mixed with probability 1/2).
+    The grid is the smallest listed size >= 2 ceil(L sqrt(2 Ecut) / 2 pi + 1) + 1.
+    Returns (Workload, mixed)."""
+    rng = np.random.default_rng(base_seed + i)
+    L = float(rng.uniform(*L_range))
+    ecut = float(rng.uniform(*ecut_range))
+    natom = max(1, int(round(0.0135 * L ** 3)))
+    kfrac = tuple(float(x) for x in rng.uniform(0.0, 1.0, 3))
+    mixed = bool(rng.uniform() < 0.5)
+    pos = rng.uniform(0.0, L, (natom, 3))
+    D = rng.uniform(0.5, 1.5, natom * len(LM4))
+    nbands = int(min(1024, max(32, 32 * round(5.5 * natom / 32))))
+    nmax = int(np.ceil(L * np.sqrt(2.0 * ecut) / (2 * np.pi) + 1.0))
+    n = next(s for s in SERVE_FFT_SIZES if s >= 2 * nmax + 1)
+    w = Workload(name=f"request{i}", seed=base_seed + i, L=L, ecut=ecut, n=n, kfrac=kfrac,
+                 pos=pos, nbands=nbands, block=min(64, nbands), tol=1e-6, lm=LM4, D=D)
+    w.vgrid = well_potential(L, n, pos)
+    return w, mixed
+
+
 def start_block(seed: int, npw: int, ncol: int) -> np.ndarray:
     """Complex standard-normal block [npw, ncol] from its own PCG64 stream."""
     rng = np.random.default_rng(10_000 + seed)
