@@ -90,6 +90,8 @@ def main():
     ap.add_argument("--mixed-steps", type=int, default=2, help="timed solves in the mixed form")
     ap.add_argument("--batch-steps", type=int, default=1,
                     help="timed batches of the ten-k-point cell (0: skip)")
+    ap.add_argument("--serve-requests", type=int, default=16,
+                    help="requests in the served-stream sample (0: skip)")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the per-kernel roofline timings (for profiling runs)")
     args = ap.parse_args()
@@ -256,6 +258,23 @@ def main():
                                                                     res_eigs["fp64"]).max())
         del probs
 
+    # ---- served stream sample: Poisson arrivals (4/s) of cells with L in [8, 16] bohr,
+    # Ecut in [5, 15] Ha, bands ~ atoms, random k, FP64 or mixed
+    served = None
+    if args.serve_requests > 0 and not args.roofline_only:
+        from paper_0707_3405_amd.serve import Server, poisson_arrivals
+        from workloads import make_request
+        arr = poisson_arrivals(args.serve_requests, 4.0)
+        reqs = []
+        for i in range(args.serve_requests):
+            wr, mixed_r = make_request(i, L_range=(8.0, 16.0), ecut_range=(5.0, 15.0))
+            reqs.append((float(arr[i]), wr, PW_PREC_MIXED if mixed_r else PW_PREC_FP64))
+        _, served = Server(max_active=8).run(reqs)
+        served["sample"] = ("Poisson arrivals at 4/s; L ~ U[8,16] bohr, Ecut ~ U[5,15] Ha, "
+                            "round(0.0135 L^3) wells with 4 projectors, bands 32 round(5.5 atoms/32), "
+                            "k ~ U[0,1)^3, FP64 or mixed with p = 1/2")
+        log(f"served stream: {served['solves_per_s']:.2f} solves/s, p99 {served['latency_p99_s']:.3f} s")
+
     if args.roofline_only:
         # plain device copy of known size: reference for HBM byte counters
         src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
@@ -301,6 +320,7 @@ def main():
         "roofline_all": roofs,
         "mixed": mixed,
         "batched_kpoints": batched,
+        "served": served,
     }
     if not args.no_cpu:
         cores = len(os.sched_getaffinity(0))
