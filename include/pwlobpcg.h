@@ -144,7 +144,10 @@ pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ld
 /* Lowest `nbands` eigenpairs by block LOBPCG (sec. 3.2, Algorithm 1) in blocks
  * of `block` bands, each block kept orthogonal to the previous ones, then a
  * final Rayleigh-Ritz over all bands.  Convergence per block: every residual
- * ||H x - theta x||_2 (||x||_2 = 1) <= tol.  X: device complex128
+ * ||H x - theta x||_2 (||x||_2 = 1) <= tol.  tol = 0 selects the fixed-sweep
+ * mode of the paper's iteration count (sec. 3.2): every block runs exactly
+ * max_iter iterations with all columns active, the final Rayleigh-Ritz
+ * follows and the call returns PW_OK (FP64 only).  X: device complex128
  * [npw x nbands], ldx >= npw, for both precisions; on entry a starting guess
  * if use_guess != 0, on exit the orthonormal eigenvectors.  prec: see
  * pw_precision (the workspace must be sized for it).  eig: host
@@ -169,6 +172,17 @@ pw_status pw_lobpcg_solve_batch(pw_ctx *ctxs, int32_t n, int32_t nbands, int32_t
                                 double tol, int32_t max_iter, pw_precision prec,
                                 void *const *X, const int64_t *ldx, int32_t use_guess,
                                 double *const *eig, pw_status *status);
+/* Electron density of nb bands (sec. 4.1: the density is built from the bands
+ * with the same FFTs as H.X): rho(r_j) = sum_n occ[n] |psi_n(r_j)|^2 with
+ * psi_n(r) = Omega^-1/2 sum_G X[G, n] e^{i(k+G).r} on the grid points
+ * r_j = cell^T (j / N).  X: device complex128 [npw x nb], ldx >= npw, library
+ * sphere order; occ: host double[nb]; rho: device double [N][N][N], C order
+ * [j0][j1][j2] (the layout of pw_set_local_potential).  Needs basis and a
+ * workspace of at least block * N * (sticks rounded up to 16) * 16 + N^3 * 8 +
+ * nb * 8 bytes (any workspace sized by pw_workspace_size for the same block
+ * is enough for nb <= nbands).  Deterministic; synchronises the stream. */
+pw_status pw_density(pw_ctx ctx, const void *X, int64_t ldx, int32_t nb, const double *occ,
+                     void *rho);
 /* Residual norms ||H x_j - theta_j x_j||_2 of the last solve, host double[nbands]. */
 pw_status pw_get_residuals(pw_ctx ctx, double *res);
 /* Counters and phase times of the last solve. */

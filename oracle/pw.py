@@ -143,3 +143,21 @@ def dense_hamiltonian(cell, kfrac, miller, vgrid, pos=None, lm=(), D=None):
         H = H + (B * np.asarray(D, float)[None, :]) @ B.conj().T
         H = 0.5 * (H + H.conj().T)
     return H
+
+
+def density(cell, kfrac, miller, n, C, occ):
+    """Electron density on the n^3 grid from the band coefficients (sec. 4.1: the
+    density is formed from the bands with the FFT): rho(r_j) = sum_b occ_b
+    |psi_b(r_j)|^2, psi_b(r) = Omega^-1/2 sum_G C[G, b] e^{i(k+G).r},
+    r_j = cell^T j / n, C order [j0][j1][j2].  The phase e^{ik.r} has unit
+    modulus and drops out.  numpy's inverse FFT evaluates the sum over G."""
+    cell = np.asarray(cell, dtype=float)
+    omega = abs(np.linalg.det(cell))
+    idx = np.mod(np.asarray(miller), n)
+    rho = np.zeros((n, n, n))
+    for b in range(C.shape[1]):
+        g = np.zeros((n, n, n), dtype=complex)
+        g[idx[:, 0], idx[:, 1], idx[:, 2]] = C[:, b]
+        psi = np.fft.ifftn(g) * n ** 3          # sum_G C e^{+2 pi i n.j / n}
+        rho += occ[b] * (psi.real ** 2 + psi.imag ** 2)
+    return rho / omega

@@ -26,7 +26,8 @@ EXPORTS = ("pw_create", "pw_destroy", "pw_last_error", "pw_init_basis", "pw_fft_
            "pw_get_miller", "pw_get_kinetic", "pw_set_local_potential", "pw_set_projectors",
            "pw_workspace_size", "pw_set_workspace", "pw_apply_H", "pw_lobpcg_solve",
            "pw_get_residuals", "pw_get_stats", "pw_gram", "pw_block_update", "pw_small_eigh",
-           "pw_residuals", "pw_gram_mixed", "pw_block_update_mixed", "pw_lobpcg_solve_batch")
+           "pw_residuals", "pw_gram_mixed", "pw_block_update_mixed", "pw_lobpcg_solve_batch",
+           "pw_density")
 
 
 class PWError(RuntimeError):
@@ -85,6 +86,7 @@ def load_library():
         "pw_block_update": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, D, D, P, I64]),
         "pw_gram_mixed": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, P, I64]),
         "pw_lobpcg_solve_batch": (ctypes.c_int, [P, I32, I32, I32, D, I32, ctypes.c_int, P, P, I32, P, P]),
+        "pw_density": (ctypes.c_int, [P, P, I64, I32, P, P]),
         "pw_block_update_mixed": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, D, D, P, I64]),
         "pw_small_eigh": (ctypes.c_int, [P, P, I64, I32, I32, P, P, I64]),
         "pw_residuals": (ctypes.c_int, [P, P, I64, P, I64, I32, P, P, P, I64]),
@@ -234,6 +236,13 @@ class Context:
                                                   _ptr(X), _ld(X), int(bool(use_guess)),
                                                   eig.ctypes.data), allow=allow)
         return eig, st
+
+    def density(self, X, occ, rho, nb=None):
+        """rho (device float64 [N, N, N]) = sum_n occ[n] |psi_n(r)|^2 of the columns of X."""
+        nb = X.shape[0] if nb is None else nb
+        occ = np.ascontiguousarray(np.asarray(occ, np.float64))
+        self._check(self.lib.pw_density(self.h, _ptr(X), _ld(X), nb, occ.ctypes.data, _ptr(rho)))
+        return rho
 
     def get_residuals(self, nbands):
         out = np.zeros(nbands, np.float64)

@@ -193,6 +193,87 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane(SphereDev sp, const T *
     for (int s = threadIdx.x; s < sp.nst; s += blockDim.x) Sp[s] = A[sp.st_xc[s] * LD + sp.st_y[s]];
 }
 
+// ---- density: per z-plane inverse xy transforms, occ |psi|^2 accumulated -----
+// rho_zyx[z][y][x] += sum_b occ[b] |psi_b(x, y, z)|^2 over the nb bands of the
+// stick buffer (psi without the 1/sqrt(Omega) factor).  One workgroup owns one
+// plane and adds the bands in order, so no two threads write one element and
+// the sum is deterministic.
+template <int N, class T>
+__global__ void __launch_bounds__(kPlaneThreads)
+    k_plane_rho(SphereDev sp, const cpx<T> *__restrict__ S, int nb, const double *__restrict__ occ,
+                double *__restrict__ rho_zyx, int rb) {
+    constexpr int LD = N + 1;
+    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+    extern __shared__ unsigned char smem_raw[];
+    cpx<T> *tw = reinterpret_cast<cpx<T> *>(smem_raw);
+    cpx<T> *A = tw + N;                 // [ncx][LD], y along the row
+    cpx<T> *R = A + sp.ncx * LD;        // [rb][LD], x along the row
+    const int z = blockIdx.x;
+    const int ncx = sp.ncx;
+    const int xmin_g = ((sp.xmin % N) + N) % N;
+    double *rz = rho_zyx + (int64_t)z * N * N;
+    load_twiddles(tw, sp.twid, N);
+    for (int band = 0; band < nb; ++band) {
+        const double f = occ[band];
+        const cpx<T> *Sp = S + ((int64_t)band * N + z) * sp.ldst;
+        __syncthreads();
+        for (int i = threadIdx.x; i < ncx * LD; i += blockDim.x) A[i] = cpx<T>{T(0), T(0)};
+        __syncthreads();
+        for (int s = threadIdx.x; s < sp.nst; s += blockDim.x) A[sp.st_xc[s] * LD + sp.st_y[s]] = Sp[s];
+        __syncthreads();
+        for (int it = threadIdx.x; it < ncx * R2; it += blockDim.x) {
+            const int c = it % ncx, n2 = it / ncx;
+            dit_a<N, +1>(A + c * LD, n2, tw);
+        }
+        __syncthreads();
+        for (int it = threadIdx.x; it < ncx * R1; it += blockDim.x) {
+            const int c = it % ncx, k1 = it / ncx;
+            cpx<T> out[R2];
+            dit_b<N, +1>(A + c * LD, k1, out);
+#pragma unroll
+            for (int k2 = 0; k2 < R2; ++k2) A[c * LD + k1 * R2 + k2] = out[k2];
+        }
+        __syncthreads();
+        for (int y0 = 0; y0 < N; y0 += rb) {
+            const int nr = min(rb, N - y0);
+            for (int i = threadIdx.x; i < nr * N; i += blockDim.x) {
+                const int r = i / N, x = i - r * N;
+                int xc = x - xmin_g;
+                xc += (xc < 0) ? N : 0;
+                R[r * LD + x] = (xc < ncx) ? A[xc * LD + digit_rev<N>(y0 + r)] : cpx<T>{T(0), T(0)};
+            }
+            __syncthreads();
+            for (int it = threadIdx.x; it < nr * R2; it += blockDim.x) {
+                const int r = it % nr, n2 = it / nr;
+                dit_a<N, +1>(R + r * LD, n2, tw);
+            }
+            __syncthreads();
+            for (int it = threadIdx.x; it < nr * R1; it += blockDim.x) {
+                const int r = it % nr, k1 = it / nr;
+                cpx<T> out[R2];
+                dit_b<N, +1>(R + r * LD, k1, out);
+                double *row = rz + (int64_t)(y0 + r) * N;
+#pragma unroll
+                for (int k2 = 0; k2 < R2; ++k2) {
+                    const int x = freq_at<N>(k1 * R2 + k2);
+                    const double a = (double)out[k2].x, b = (double)out[k2].y;
+                    row[x] += f * (a * a + b * b);
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// rho[x][y][z] = rho_zyx[z][y][x] * scale
+__global__ void k_rho_permute(const double *__restrict__ rho_zyx, int n, double scale,
+                              double *__restrict__ rho) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)n * n * n) return;
+    const int z = (int)(i % n), y = (int)((i / n) % n), x = (int)(i / ((int64_t)n * n));
+    rho[i] = rho_zyx[((int64_t)z * n + y) * n + x] * scale;
+}
+
 // ---- pass 3: forward z-FFT per stick, gather, kinetic -----------------------
 template <int N, class T>
 __global__ void __launch_bounds__(kThreads) k_zfwd(SphereDev sp, const cpx<T> *__restrict__ S,
@@ -322,6 +403,51 @@ void launch_permute_potential(const double *v, int n, double scale, double *v_zy
         default:
             throw Error{PW_ERR_ARG, "unsupported FFT size"};
     }
+    PW_HIP(hipGetLastError());
+}
+
+template <int N>
+void run_density(const SphereDev &sp, const cd *X, int64_t ldx, int nb, const double *occ,
+                 double *rho_zyx, cd *S, hipStream_t st) {
+    const int spb = kSticksPerBlock;
+    const size_t e = sizeof(cd);
+    const size_t sm1 = (size_t)N * e + (size_t)spb * (N + 1) * e;
+    const size_t base2 = (size_t)N * e + (size_t)sp.ncx * (N + 1) * e;
+    int rb = PW_PLANE_RB;
+    while (rb > 1 && base2 + (size_t)rb * (N + 1) * e > 150 * 1024) rb /= 2;
+    if (rb > N) rb = N;
+    const size_t sm2 = base2 + (size_t)rb * (N + 1) * e;
+    PW_REQUIRE(sm2 <= 160 * 1024, PW_ERR_ARG, "FFT plane does not fit in LDS");
+    PW_HIP(hipFuncSetAttribute((const void *)k_zinv<N, double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1));
+    PW_HIP(hipFuncSetAttribute((const void *)k_plane_rho<N, double>,
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2));
+    hipLaunchKernelGGL((k_zinv<N, double>), dim3((sp.nst + spb - 1) / spb, nb), dim3(kThreads), sm1, st,
+                       sp, X, ldx, S, spb);
+    hipLaunchKernelGGL((k_plane_rho<N, double>), dim3(N), dim3(kPlaneThreads), sm2, st, sp, S, nb, occ,
+                       rho_zyx, rb);
+    PW_HIP(hipGetLastError());
+}
+
+void launch_density_accumulate(const SphereDev &sp, const cd *X, int64_t ldx, int nb,
+                               const double *occ, double *rho_zyx, cd *S, hipStream_t st) {
+    if (nb <= 0) return;
+    switch (sp.n) {
+#define PW_CASE(NN)                                                         \
+    case NN:                                                                \
+        run_density<NN>(sp, X, ldx, nb, occ, rho_zyx, S, st);               \
+        return;
+        PW_FFT_SIZES(PW_CASE)
+#undef PW_CASE
+        default:
+            throw Error{PW_ERR_ARG, "unsupported FFT size"};
+    }
+}
+
+void launch_density_finish(const double *rho_zyx, int n, double scale, double *rho, hipStream_t st) {
+    const int64_t tot = (int64_t)n * n * n;
+    hipLaunchKernelGGL(k_rho_permute, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, rho_zyx, n,
+                       scale, rho);
     PW_HIP(hipGetLastError());
 }
 

@@ -68,6 +68,12 @@ void launch_fft_apply(const SphereDev &sp, const double *v_zyx, const cd *X, int
 // complex64 form: v_zyx as float
 void launch_fft_apply(const SphereDev &sp, const float *v_zyx, const cf *X, int64_t ldx,
                       cf *Y, int64_t ldy, int nb, cf *S, hipStream_t st);
+// Density: rho_zyx[z][y][x] += sum_b occ[b] |psi_b|^2 for nb columns of X (psi
+// = inverse transform of the sphere coefficients, no 1/sqrt(Omega)); then
+// rho[x][y][z] = scale * rho_zyx[z][y][x].
+void launch_density_accumulate(const SphereDev &sp, const cd *X, int64_t ldx, int nb,
+                               const double *occ, double *rho_zyx, cd *S, hipStream_t st);
+void launch_density_finish(const double *rho_zyx, int n, double scale, double *rho, hipStream_t st);
 bool fft_size_supported(int n);
 std::vector<int> fft_supported_sizes();
 

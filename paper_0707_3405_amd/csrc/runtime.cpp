@@ -529,6 +529,7 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
     for (int j = 0; j < M; ++j) {
         if (!std::isfinite(eig[j])) throw Error{PW_ERR_NUMERIC, "non-finite eigenvalue"};
     }
+    if (tol == 0.0) return PW_OK;   // fixed-sweep mode: max_iter iterations per block, no test
     bool res_ok = true;
     for (int j = 0; j < M; ++j)
         if (!(c->res[j] <= tol)) res_ok = false;
@@ -983,7 +984,8 @@ pw_status pw_lobpcg_solve(pw_ctx c, int32_t nbands, int32_t block, double tol, i
         PW_REQUIRE(nbands <= 1024 && nbands <= c->npw, PW_ERR_ARG, "nbands must be <= min(npw, 1024)");
         PW_REQUIRE(3 * std::min(block, nbands) <= c->npw, PW_ERR_ARG, "3 * block must not exceed npw");
         PW_REQUIRE(ldx >= c->npw, PW_ERR_ARG, "ldx < npw");
-        PW_REQUIRE(tol > 0 && max_iter >= 1, PW_ERR_ARG, "need tol > 0 and max_iter >= 1");
+        PW_REQUIRE(tol >= 0 && max_iter >= 1, PW_ERR_ARG, "need tol >= 0 and max_iter >= 1");
+        PW_REQUIRE(tol > 0 || prec == PW_PREC_FP64, PW_ERR_ARG, "the fixed-sweep mode (tol = 0) is FP64 only");
         const int m = std::min(block, nbands);
         PW_REQUIRE(c->plan_nbands >= nbands && c->plan_block == m, PW_ERR_STATE,
                    "call pw_workspace_size with this (nbands, block) before the solve");
@@ -1016,6 +1018,40 @@ pw_status pw_lobpcg_solve_batch(pw_ctx *ctxs, int32_t n, int32_t nbands, int32_t
     for (int i = 0; i < n; ++i)
         if (status[i] != PW_OK && (worst == PW_OK || worst == PW_ERR_NOT_CONVERGED)) worst = status[i];
     return worst;
+}
+
+pw_status pw_density(pw_ctx c, const void *X, int64_t ldx, int32_t nb, const double *occ,
+                     void *rho) {
+    return guard(c, [&] {
+        require_device(c);
+        require_basis(c);
+        PW_REQUIRE(X && occ && rho, PW_ERR_ARG, "null argument");
+        PW_REQUIRE(nb >= 1 && ldx >= c->npw, PW_ERR_ARG, "need nb >= 1 and ldx >= npw");
+        PW_REQUIRE(c->ws != nullptr, PW_ERR_STATE, "pw_set_workspace has not been called");
+        for (int i = 0; i < nb; ++i) PW_REQUIRE(std::isfinite(occ[i]), PW_ERR_ARG, "non-finite occupation");
+        const int chunk = c->plan_block > 0 ? c->plan_block : 1;
+        const int64_t n3 = (int64_t)c->n * c->n * c->n;
+        Arena a;
+        a.base = c->ws;
+        cd *S = a.take<cd>((size_t)chunk * c->n * c->sp.ldst);
+        double *rz = a.take<double>((size_t)n3);
+        double *docc = a.take<double>((size_t)nb);
+        PW_REQUIRE(align_up(a.used, 256) <= c->ws_bytes, PW_ERR_NOMEM, "workspace too small for the density");
+        hipStream_t st = c->stream;
+        pw::launch_zero(reinterpret_cast<cd *>(rz), n3 / 2, n3 / 2, 1, st);   // N is even
+        PW_HIP(hipMemcpyAsync(docc, occ, sizeof(double) * nb, hipMemcpyHostToDevice, st));
+        const cd *Xc = static_cast<const cd *>(X);
+        for (int b0 = 0; b0 < nb; b0 += chunk) {
+            const int nc = std::min(chunk, nb - b0);
+            pw::launch_density_accumulate(c->sp, Xc + (int64_t)b0 * ldx, ldx, nc, docc + b0, rz, S, st);
+        }
+        const double *m = c->cell;
+        const double omega = std::fabs(m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+                                       m[2] * (m[3] * m[7] - m[4] * m[6]));
+        pw::launch_density_finish(rz, c->n, 1.0 / omega, static_cast<double *>(rho), st);
+        PW_HIP(hipStreamSynchronize(st));   // occ is read from host memory above
+        return PW_OK;
+    });
 }
 
 pw_status pw_get_residuals(pw_ctx c, double *res) {

@@ -132,3 +132,27 @@ def test_error_paths(torch_cuda):
     with pytest.raises(PWError) as e:
         ctx.init_basis(w.cell, w.kfrac, w.ecut, (25, 25, 25))
     assert e.value.status == PW_ERR_ARG
+
+
+def test_fixed_sweep_mode(torch_cuda, oracle_problem):
+    """tol = 0: every block runs exactly max_iter iterations (the paper's nline).
+    Ritz values are upper bounds of the exact eigenvalues (Rayleigh-Ritz on a
+    subspace) and reach them once enough sweeps are made."""
+    torch = torch_cuda
+    from paper_0707_3405_amd import PlaneWaveProblem
+    from workloads import make_workload
+    w = make_workload("mid_nl")
+    _, mil, H, mf = oracle_problem("mid_nl", dense=False)
+    ref = load_golden("mid_nl")[0][:w.nbands]
+    prob = PlaneWaveProblem.from_workload(w, device=0)
+    prev = None
+    for nline in (2, 4, 120):
+        eig, X, status = prob.solve(0.0, max_iter=nline)
+        torch.cuda.synchronize()
+        st = prob.ctx.get_stats()
+        assert st["iterations"] == st["blocks"] * nline
+        assert np.all(eig >= ref - 1e-10), (eig - ref).min()
+        if prev is not None:
+            assert eig.sum() <= prev.sum() + 1e-10
+        prev = eig
+    assert np.abs(eig - ref).max() <= 1e-8, np.abs(eig - ref).max()

@@ -310,3 +310,28 @@ def test_final_rayleigh_ritz_is_variational():
     r = matfree.solve(mf, w.nbands, w.block, tol=1e-4, seed=1)
     ref = np.linalg.eigvalsh(H)[:w.nbands]
     assert np.all(r["eig"] >= ref - 1e-13)
+
+
+def test_density_pins():
+    """oracle.pw.density: Parseval (the grid sum equals sum occ ||c||^2 N^3 / Omega),
+    a single plane wave gives the uniform occ / Omega, and grid points evaluated by
+    direct summation over the sphere (no FFT) agree."""
+    from workloads import make_workload
+    w = make_workload("tiny_nl")
+    mil = pw.sphere(w.cell, w.kfrac, w.ecut)
+    rng = np.random.default_rng(3)
+    C = rng.standard_normal((mil.shape[0], 3)) + 1j * rng.standard_normal((mil.shape[0], 3))
+    occ = np.array([2.0, 1.0, 0.5])
+    rho = pw.density(w.cell, w.kfrac, mil, w.n, C, occ)
+    omega = abs(np.linalg.det(w.cell))
+    total = rho.sum() * omega / w.n ** 3
+    expect = sum(occ[b] * np.vdot(C[:, b], C[:, b]).real for b in range(3))
+    assert abs(total - expect) <= 1e-12 * expect
+    one = np.zeros((mil.shape[0], 1), complex)
+    one[5, 0] = 1.0
+    r1 = pw.density(w.cell, w.kfrac, mil, w.n, one, [1.5])
+    assert np.allclose(r1, 1.5 / omega, rtol=0, atol=1e-14 / omega)
+    for j in [(0, 0, 0), (1, 2, 3), (w.n - 1, 7, 11), (4, w.n // 2, 9)]:
+        ph = np.exp(2j * np.pi * (mil @ np.array(j)) / w.n)
+        direct = sum(occ[b] * abs(np.sum(C[:, b] * ph)) ** 2 for b in range(3)) / omega
+        assert abs(rho[j] - direct) <= 1e-12 * direct

@@ -129,7 +129,8 @@ def make_request(i: int, base_seed: int = 1000, L_range=(8.0, 24.0), ecut_range=
     round(0.0135 L^3) Gaussian wells at uniform positions with 4 projectors each,
     k ~ U[0,1)^3, nbands = 32 round(5.5 natom / 32) clamped to [32, 1024], block
     min(64, nbands), tol 1e-6, and a precision flag (mixed with probability 1/2).
-    The grid is the smallest listed size >= 2 ceil(L sqrt(2 Ecut) / 2 pi + 1) + 1.
+    The grid is the smallest listed size >= 4 nmax + 1 with nmax = ceil(L sqrt(2 Ecut) / 2 pi + 1)
+    (products of two bands are then resolved without wrap-around).
     Returns (Workload, mixed)."""
     rng = np.random.default_rng(base_seed + i)
     L = float(rng.uniform(*L_range))
@@ -141,7 +142,7 @@ def make_request(i: int, base_seed: int = 1000, L_range=(8.0, 24.0), ecut_range=
     D = rng.uniform(0.5, 1.5, natom * len(LM4))
     nbands = int(min(1024, max(32, 32 * round(5.5 * natom / 32))))
     nmax = int(np.ceil(L * np.sqrt(2.0 * ecut) / (2 * np.pi) + 1.0))
-    n = next(s for s in SERVE_FFT_SIZES if s >= 2 * nmax + 1)
+    n = next(s for s in SERVE_FFT_SIZES if s >= 4 * nmax + 1)
     w = Workload(name=f"request{i}", seed=base_seed + i, L=L, ecut=ecut, n=n, kfrac=kfrac,
                  pos=pos, nbands=nbands, block=min(64, nbands), tol=1e-6, lm=LM4, D=D)
     w.vgrid = well_potential(L, n, pos)
