@@ -224,20 +224,56 @@ __global__ void k_reduce_parts(const cpx<T> *__restrict__ part, int nsplit, int 
     *c = cd{sr, si};
 }
 
+// NN: the k-blocks are staged through LDS: per 16-wide k-block the workgroup
+// reads 16 columns x 64 rows of A (one wave instruction = one 1 KB column
+// segment) and 16 x 64 of C, both once, into padded LDS tiles; the next
+// block's global loads are in flight during the current block's MFMAs.
 template <class T>
 __global__ void __launch_bounds__(kThreads)
-    k_gemm_nn(const cpx<T> *__restrict__ A, int64_t lda, const cd *__restrict__ Cm, int64_t ldc,
-              int64_t K, int p, int q, double alpha, double beta, cpx<T> *Y, int64_t ldy,
-              int tiles_m) {
+    k_gemm_nn_lds(const cpx<T> *__restrict__ A, int64_t lda, const cd *__restrict__ Cm, int64_t ldc,
+                  int64_t K, int p, int q, double alpha, double beta, cpx<T> *Y, int64_t ldy,
+                  int tiles_m) {
     using M = Mfma<T>;
     using v4 = typename M::v4;
+    constexpr int KB = 16, LDA = kTile + 1, LDCC = KB + 1;
+    __shared__ cpx<T> sA[2][KB * LDA], sC[2][kTile * LDCC];
     const int lid = xcd_logical(blockIdx.x, gridDim.x);
     const int tm = lid % tiles_m, tn = lid / tiles_m;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = lane & 15, g = lane >> 4;
-    const int64_t r0 = (int64_t)tm * kTile + (wave & 1) * 32;
-    const int c0 = tn * kTile + (wave >> 1) * 32;
+    const int64_t rbase = (int64_t)tm * kTile;
+    const int cbase = tn * kTile;
+    const int ia = (wave & 1) * 32, jb = (wave >> 1) * 32;
 
+    // global -> LDS: A instruction u covers column kb + 4 wave + u, rows lane;
+    // C instruction u covers columns 16 wave + 4u + g, k rows li
+    const bool arow = rbase + lane < K;
+    const cpx<T> *Arow = A + (arow ? rbase + lane : 0);
+    const cd *Cc[4];
+    bool cok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int col = cbase + 16 * wave + 4 * u + g;
+        cok[u] = col < q;
+        Cc[u] = Cm + (int64_t)(cok[u] ? col : 0) * ldc;
+    }
+    cpx<T> ra[4], rc[4];
+    auto gload = [&](int kb) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = kb + 4 * wave + u;
+            ra[u] = ldg_or_zero(Arow + (int64_t)(kk < p ? kk : 0) * lda, arow && kk < p);
+            const int kc = kb + li;
+            rc[u] = ldc_or_zero<T>(Cc[u] + (kc < p ? kc : 0), cok[u] && kc < p);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sA[buf][(4 * wave + u) * LDA + lane] = ra[u];
+            sC[buf][(16 * wave + 4 * u + g) * LDCC + li] = rc[u];
+        }
+    };
     // 3-multiplication complex product: with t1 = sum ar cr, t2 = sum ai ci,
     // t3 = sum (ar + ai)(cr + ci), a c = (t1 - t2) + i (t3 - t1 - t2)
     v4 t1[2][2], t2[2][2], t3[2][2];
@@ -245,32 +281,21 @@ __global__ void __launch_bounds__(kThreads)
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) t1[a][b] = t2[a][b] = t3[a][b] = v4{0, 0, 0, 0};
-
-    bool rok[2], cok[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        rok[t] = r0 + 16 * t + li < K;
-        cok[t] = c0 + 16 * t + li < q;
-    }
     bool live[2][2];   // sub-tiles wholly outside K x q are skipped (uniform per wave)
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int nj = 0; nj < 2; ++nj) live[mi][nj] = r0 + 16 * mi < K && c0 + 16 * nj < q;
-    for (int kb = 0; kb < p; kb += 16) {
+        for (int nj = 0; nj < 2; ++nj)
+            live[mi][nj] = rbase + ia + 16 * mi < K && cbase + jb + 16 * nj < q;
+    auto mma = [&](int buf) {
         cpx<T> a[2][4], b[2][4];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const int kk = kb + 4 * g + s;
-            const bool kin = kk < p;
+        for (int t = 0; t < 2; ++t)
 #pragma unroll
-            for (int t = 0; t < 2; ++t) {
-                a[t][s] = ldg_or_zero(A + (int64_t)(kin ? kk : 0) * lda + (rok[t] ? r0 + 16 * t + li : 0),
-                                      kin && rok[t]);
-                b[t][s] = ldc_or_zero<T>(Cm + (int64_t)(cok[t] ? c0 + 16 * t + li : 0) * ldc + (kin ? kk : 0),
-                                         kin && cok[t]);
+            for (int s = 0; s < 4; ++s) {
+                a[t][s] = sA[buf][(4 * g + s) * LDA + ia + 16 * t + li];
+                b[t][s] = sC[buf][(jb + 16 * t + li) * LDCC + 4 * g + s];
             }
-        }
 #pragma unroll
         for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -282,18 +307,31 @@ __global__ void __launch_bounds__(kThreads)
                     t2[mi][nj] = M::op(a[mi][s].y, b[nj][s].y, t2[mi][nj]);
                     t3[mi][nj] = M::op(a[mi][s].x + a[mi][s].y, b[nj][s].x + b[nj][s].y, t3[mi][nj]);
                 }
+    };
+    if (p > 0) {
+        gload(0);
+        lstore(0);
+        __syncthreads();
+        int buf = 0;
+        for (int kb = 0; kb < p; kb += KB) {
+            const bool more = kb + KB < p;
+            if (more) gload(kb + KB);
+            mma(buf);
+            if (more) lstore(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
     }
-    // every wave of the workgroup has read its rows of A before any writes:
-    // this makes the in-place form Y == A safe when one workgroup spans all q.
-    __syncthreads();
+    // all reads of A (global -> LDS) finished before the final barrier above:
+    // the in-place form Y == A is safe when one workgroup spans all q
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int nj = 0; nj < 2; ++nj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = r0 + 16 * mi + M::row(g, r);
-                const int j = c0 + 16 * nj + li;
+                const int64_t i = rbase + ia + 16 * mi + M::row(g, r);
+                const int j = cbase + jb + 16 * nj + li;
                 if (i < K && j < q) {
                     cpx<T> *y = Y + (int64_t)j * ldy + i;
                     T yr = T(alpha) * (t1[mi][nj][r] - t2[mi][nj][r]);
@@ -359,7 +397,7 @@ void gemm_nn_impl(const cpx<T> *A, int64_t lda, const cd *C, int64_t ldc, int64_
     const int tiles_m = (int)((K + kTile - 1) / kTile), tiles_n = (q + kTile - 1) / kTile;
     PW_REQUIRE(!((const void *)A == (const void *)Y) || q <= kTile, PW_ERR_ARG,
                "in-place block update needs q <= 64");
-    hipLaunchKernelGGL(k_gemm_nn<T>, dim3(tiles_m * tiles_n), dim3(kThreads), 0, st, A, lda, C, ldc,
+    hipLaunchKernelGGL(k_gemm_nn_lds<T>, dim3(tiles_m * tiles_n), dim3(kThreads), 0, st, A, lda, C, ldc,
                        K, p, q, alpha, beta, Y, ldy, tiles_m);
     PW_HIP(hipGetLastError());
 }
