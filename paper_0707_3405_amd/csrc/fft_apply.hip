@@ -147,18 +147,18 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane(SphereDev sp, const T *
             dit_a<N, +1>(R + r * LD, n2, tw);
         }
         __syncthreads();
+        // second inverse stage, V multiply and first forward stage act on the
+        // same R2 values of item k1: fused in registers
         for (int it = threadIdx.x; it < nr * R1; it += blockDim.x) {
             const int r = it % nr, k1 = it / nr;
             cpx<T> out[R2];
             dit_b<N, +1>(R + r * LD, k1, out);
             const T *vrow = Vz + (int64_t)(y0 + r) * N + k1 * R2;
 #pragma unroll
-            for (int k2 = 0; k2 < R2; ++k2) R[r * LD + k1 * R2 + k2] = cscale(out[k2], vrow[k2]);
-        }
-        __syncthreads();
-        for (int it = threadIdx.x; it < nr * R1; it += blockDim.x) {
-            const int r = it % nr, k1 = it / nr;
-            dif_b<N, -1>(R + r * LD, k1);
+            for (int k2 = 0; k2 < R2; ++k2) out[k2] = cscale(out[k2], vrow[k2]);
+            Dft<R2, -1, T>::run(out);
+#pragma unroll
+            for (int n2 = 0; n2 < R2; ++n2) R[r * LD + k1 * R2 + n2] = out[n2];
         }
         __syncthreads();
         for (int it = threadIdx.x; it < nr * R2; it += blockDim.x) {
