@@ -101,7 +101,8 @@ def main():
         sys.exit(2)
 
     import torch
-    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_FP64, PW_PREC_MIXED, solve_batch
+    from paper_0707_3405_amd import (PlaneWaveProblem, PW_PREC_FP64, PW_PREC_MIXED,
+                                     PW_PREC_MIXED_BF16, solve_batch)
     from workloads import make_workload, make_kpoint_workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -140,32 +141,49 @@ def main():
         stats = prob.ctx.get_stats()
         eig64 = eig.copy()
 
-        # ---- the same cell in the mixed form (complex64 iteration + FP64 refinement)
-        mixed = None
-        if args.mixed_steps > 0:
-            solve(PW_PREC_MIXED)
+        # ---- the same cell in the mixed forms (complex64 iteration + FP64 refinement;
+        # the BF16 form also runs the projector products on split-bf16 matrix cores)
+        def run_mixed(prec, label):
+            solve(prec)
             torch.cuda.synchronize()
             mlat = []
             for i in range(args.mixed_steps):
                 t0 = time.perf_counter()
-                eigm = solve(PW_PREC_MIXED)
+                eigm = solve(prec)
                 torch.cuda.synchronize()
                 mlat.append(time.perf_counter() - t0)
-                log(f"mixed step {i + 1}/{args.mixed_steps}: {mlat[-1] * 1e3:.1f} ms")
+                log(f"{label} step {i + 1}/{args.mixed_steps}: {mlat[-1] * 1e3:.1f} ms")
             mst = prob.ctx.get_stats()
             mres = prob.ctx.get_residuals(w.nbands)
             err = np.abs(eigm - eig64)
-            mixed = {"value": w.nbands / float(np.mean(mlat)), "unit": "eigenpairs/s",
-                     "ms_per_solve": 1e3 * float(np.mean(mlat)),
-                     "latency_p50_ms": float(np.percentile(np.array(mlat) * 1e3, 50)),
-                     "latency_p99_ms": float(np.percentile(np.array(mlat) * 1e3, 99)),
-                     "speedup_vs_fp64": (w.nbands / float(np.mean(mlat))) / value,
-                     "max_abs_eig_diff_vs_fp64_ha": float(err.max()),
-                     "mean_abs_eig_diff_vs_fp64_ha": float(err.mean()),
-                     "max_residual": float(mres.max()),
-                     "iterations": mst["iterations"], "complex64_iterations": mst["mixed_iterations"],
-                     "phase_ms": {k: mst[k] for k in ("ms_apply", "ms_gemm", "ms_dense", "ms_vec",
-                                                      "ms_final_rr")}}
+            return {"value": w.nbands / float(np.mean(mlat)), "unit": "eigenpairs/s",
+                    "ms_per_solve": 1e3 * float(np.mean(mlat)),
+                    "latency_p50_ms": float(np.percentile(np.array(mlat) * 1e3, 50)),
+                    "latency_p99_ms": float(np.percentile(np.array(mlat) * 1e3, 99)),
+                    "speedup_vs_fp64": (w.nbands / float(np.mean(mlat))) / value,
+                    "max_abs_eig_diff_vs_fp64_ha": float(err.max()),
+                    "mean_abs_eig_diff_vs_fp64_ha": float(err.mean()),
+                    "max_residual": float(mres.max()),
+                    "iterations": mst["iterations"], "complex64_iterations": mst["mixed_iterations"],
+                    "phase_ms": {k: mst[k] for k in ("ms_apply", "ms_gemm", "ms_dense", "ms_vec",
+                                                     "ms_final_rr")}}
+
+        mixed = mixed_bf16 = None
+        if args.mixed_steps > 0:
+            mixed = run_mixed(PW_PREC_MIXED, "mixed")
+            mixed_bf16 = run_mixed(PW_PREC_MIXED_BF16, "mixed-bf16")
+
+        # ---- full H.X (local + 432 projectors) per 64 bands in the three forms
+        Xh = torch.randn((w.block, npw), dtype=torch.complex128, device="cuda")
+        Yh = torch.empty_like(Xh)
+        Xh32 = Xh.to(torch.complex64)
+        Yh32 = torch.empty_like(Xh32)
+        hx_full = {
+            "fp64": event_time_ms(torch, prob.ctx.stream, lambda: prob.ctx.apply_H(Xh, Yh), 10),
+            "complex64": event_time_ms(torch, prob.ctx.stream,
+                                       lambda: prob.ctx.apply_H(Xh32, Yh32, prec=PW_PREC_MIXED), 10),
+            "complex64_bf16_projectors": event_time_ms(
+                torch, prob.ctx.stream, lambda: prob.ctx.apply_H(Xh32, Yh32, prec=PW_PREC_MIXED_BF16), 10)}
 
     # ---- H.X FFT apply (local part, 64 bands), its own context without projectors
     mil = prob.ctx.get_miller()
@@ -319,6 +337,8 @@ def main():
         "roofline": roof,
         "roofline_all": roofs,
         "mixed": mixed,
+        "mixed_bf16": mixed_bf16,
+        "hx_full_ms_per_64_bands": hx_full,
         "batched_kpoints": batched,
         "served": served,
     }

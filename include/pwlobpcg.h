@@ -59,10 +59,17 @@ typedef enum {
  * every reduction stay FP64.  Each block is iterated to a residual of
  * max(tol, 1e-5), then the FP64 iteration refines all bands from those
  * vectors to tol and runs the final Rayleigh-Ritz, so the returned
- * eigenpairs meet the same residual test as PW_PREC_FP64. */
+ * eigenpairs meet the same residual test as PW_PREC_FP64.
+ * PW_PREC_MIXED_BF16 is the same iteration with the nonlocal projector
+ * products on BF16 matrix cores (sec. 4.1's projector "zgemm"s, the largest
+ * GEMMs of H X). */
 typedef enum {
     PW_PREC_FP64 = 0,          /* every step in complex128 / float64 */
-    PW_PREC_MIXED = 1          /* complex64 iteration, FP64 small dense steps and refinement */
+    PW_PREC_MIXED = 1,         /* complex64 iteration, FP64 small dense steps and refinement */
+    PW_PREC_MIXED_BF16 = 2     /* PW_PREC_MIXED with the projector products (B^H X and
+                                  B (D B^H X)) on BF16 matrix cores: complex64 operands
+                                  split into hi + lo bf16 pairs, three products per real
+                                  product, FP32 accumulation */
 } pw_precision;
 
 /* Per-solve counters and phase times (milliseconds, measured with HIP events
@@ -78,7 +85,7 @@ typedef struct {
     double ms_dense;           /* small dense FP64 steps (Cholesky, eigensolver) */
     double ms_vec;             /* residual / preconditioner / copies */
     double ms_final_rr;        /* final Rayleigh-Ritz over all bands */
-    int32_t mixed_iterations;  /* PW_PREC_MIXED: iterations of the complex64 stage (included in
+    int32_t mixed_iterations;  /* mixed forms: iterations of the complex64 stage (included in
                                   iterations); 0 for PW_PREC_FP64 */
 } pw_stats;
 
@@ -124,7 +131,7 @@ pw_status pw_set_projectors(pw_ctx ctx, int32_t natom, const double *pos,
 
 /* Device workspace the caller allocates: bytes needed by pw_lobpcg_solve for
  * (nbands, block) at precision prec, and by pw_apply_H (which works in chunks
- * of `block` columns).  A workspace sized for PW_PREC_MIXED also serves
+ * of `block` columns).  A workspace sized for either mixed form also serves
  * PW_PREC_FP64.  Also answers on a host-only context (device < 0), so a
  * caller can size device memory before touching the GPU. */
 pw_status pw_workspace_size(pw_ctx ctx, int32_t nbands, int32_t block, pw_precision prec,
@@ -135,7 +142,7 @@ pw_status pw_set_workspace(pw_ctx ctx, void *dptr, size_t bytes);
 
 /* Y = H X on the context stream (rows a2-a7 of the hot path).  X, Y: device,
  * column-major [npw x nb], ldx, ldy >= npw, complex128 for PW_PREC_FP64 and
- * complex64 for PW_PREC_MIXED (FFT, V(r) multiply and projector GEMMs then
+ * complex64 for the mixed forms (FFT, V(r) multiply and projector GEMMs then
  * run in FP32); X and Y must not overlap.  Needs basis, potential and a
  * workspace sized for prec.  Asynchronous. */
 pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ldy,

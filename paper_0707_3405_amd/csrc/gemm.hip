@@ -29,6 +29,13 @@
 // products and accumulation within a K chunk; the chunk partials are summed
 // in double).  Small coefficient matrices are always complex128 and are
 // rounded to the block type as they are loaded.
+//
+// A third form serves the projector products of the BF16 mixed iteration:
+// complex64 operands are split into bf16 pairs (x = hi + lo, hi = bf16(x),
+// lo = bf16(x - hi)) and each real product is hi*hi + hi*lo + lo*hi on
+// v_mfma_f32_16x16x16_bf16 with FP32 accumulation (the split-bfloat16
+// scheme of Henry, Tang and Heinecke, ARITH 2019); the dropped lo*lo term and
+// the rounding of lo leave a relative error near 2^-16 per product.
 #include "pw_internal.h"
 
 namespace pw {
@@ -68,6 +75,26 @@ __device__ __forceinline__ cpx<T> ldc_or_zero(const cd *p, bool ok) {
     return cpx<T>{T(v.x), T(v.y)};
 }
 
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+struct Bf16Pair {
+    s16x4 hi, lo;
+};
+// four FP32 values (consecutive k of one MFMA operand) as a hi/lo bf16 pair
+__device__ __forceinline__ Bf16Pair split_bf16(float v0, float v1, float v2, float v3) {
+    const f32x4 v = {v0, v1, v2, v3};
+    const bf16x4 h = __builtin_convertvector(v, bf16x4);
+    const bf16x4 l = __builtin_convertvector(v - __builtin_convertvector(h, f32x4), bf16x4);
+    return {__builtin_bit_cast(s16x4, h), __builtin_bit_cast(s16x4, l)};
+}
+// c += a b over 16 k with the three split products, small terms first
+__device__ __forceinline__ f32x4 mma_split(const Bf16Pair &a, const Bf16Pair &b, f32x4 c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.lo, b.hi, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.lo, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a.hi, b.hi, c, 0, 0, 0);
+}
+
 // Map a hardware workgroup id to a logical id so that each XCD (ids are
 // dealt round-robin over 8 XCDs) receives a contiguous range.
 __device__ __forceinline__ int xcd_logical(int lin, int total) {
@@ -76,13 +103,45 @@ __device__ __forceinline__ int xcd_logical(int lin, int total) {
     return xcd * q + min(xcd, r) + local;
 }
 
+// One k-block of the 3-multiplication complex product in split-bf16 form.
+// SIGN = -1 forms t3 from (ar - ai)(br + bi) (TN, conj(a) b), SIGN = +1 from
+// (ar + ai)(br + bi) (NN, a b); a, b hold k = 4g + s, s = 0..3.
+template <int SIGN>
+__device__ __forceinline__ void mma_bf16(const cpx<float> (&a)[2][4], const cpx<float> (&b)[2][4],
+                                         const bool (&live)[2][2], f32x4 (&t1)[2][2],
+                                         f32x4 (&t2)[2][2], f32x4 (&t3)[2][2]) {
+    Bf16Pair ar[2], ai[2], as[2], br[2], bi[2], bs[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        ar[t] = split_bf16(a[t][0].x, a[t][1].x, a[t][2].x, a[t][3].x);
+        ai[t] = split_bf16(a[t][0].y, a[t][1].y, a[t][2].y, a[t][3].y);
+        as[t] = split_bf16(a[t][0].x + SIGN * a[t][0].y, a[t][1].x + SIGN * a[t][1].y,
+                           a[t][2].x + SIGN * a[t][2].y, a[t][3].x + SIGN * a[t][3].y);
+        br[t] = split_bf16(b[t][0].x, b[t][1].x, b[t][2].x, b[t][3].x);
+        bi[t] = split_bf16(b[t][0].y, b[t][1].y, b[t][2].y, b[t][3].y);
+        bs[t] = split_bf16(b[t][0].x + b[t][0].y, b[t][1].x + b[t][1].y, b[t][2].x + b[t][2].y,
+                           b[t][3].x + b[t][3].y);
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) {
+            if (!live[mi][nj]) continue;
+            t1[mi][nj] = mma_split(ar[mi], br[nj], t1[mi][nj]);
+            t2[mi][nj] = mma_split(ai[mi], bi[nj], t2[mi][nj]);
+            t3[mi][nj] = mma_split(as[mi], bs[nj], t3[mi][nj]);
+        }
+}
+
 // TN: the k-blocks are staged through LDS: each k-block of A and B
 // (16 rows x 64 columns each) is read from HBM once per workgroup with loads
 // that cover 4 columns x 256 contiguous bytes per wave instruction, written
 // to LDS (column stride padded to 17 elements), and the MFMA operands are read
 // from there.  The next block's global loads are in flight during the current
-// block's MFMAs (two LDS buffers, one barrier per block).
-template <class T>
+// block's MFMAs (two LDS buffers, one barrier per block).  BF selects the
+// split-bf16 products (complex64 only): one 16x16x16 MFMA per product covers a
+// whole k-block, lane group g holding k = 4g .. 4g + 3 in both operands.
+template <class T, bool BF>
 __global__ void __launch_bounds__(kThreads)
     k_gemm_tn_lds(const cpx<T> *__restrict__ A, int64_t lda, const cpx<T> *__restrict__ B,
                   int64_t ldb, int64_t K, int p, int q, int64_t kchunk, int tiles_m, int tiles_n,
@@ -158,17 +217,21 @@ __global__ void __launch_bounds__(kThreads)
                 a[t][s] = sA[buf][(ia + 16 * t + li) * LDC + 4 * g + s];
                 b[t][s] = sB[buf][(jb + 16 * t + li) * LDC + 4 * g + s];
             }
+        if constexpr (BF) {
+            mma_bf16<-1>(a, b, live, t1, t2, t3);
+        } else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
+                for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-                for (int nj = 0; nj < 2; ++nj) {
-                    if (!live[mi][nj]) continue;
-                    t1[mi][nj] = M::op(a[mi][s].x, b[nj][s].x, t1[mi][nj]);
-                    t2[mi][nj] = M::op(a[mi][s].y, b[nj][s].y, t2[mi][nj]);
-                    t3[mi][nj] = M::op(a[mi][s].x - a[mi][s].y, b[nj][s].x + b[nj][s].y, t3[mi][nj]);
-                }
+                    for (int nj = 0; nj < 2; ++nj) {
+                        if (!live[mi][nj]) continue;
+                        t1[mi][nj] = M::op(a[mi][s].x, b[nj][s].x, t1[mi][nj]);
+                        t2[mi][nj] = M::op(a[mi][s].y, b[nj][s].y, t2[mi][nj]);
+                        t3[mi][nj] = M::op(a[mi][s].x - a[mi][s].y, b[nj][s].x + b[nj][s].y, t3[mi][nj]);
+                    }
+        }
     };
     if (kbeg < kend) {
         gload(kbeg);
@@ -227,8 +290,9 @@ __global__ void k_reduce_parts(const cpx<T> *__restrict__ part, int nsplit, int 
 // NN: the k-blocks are staged through LDS: per 16-wide k-block the workgroup
 // reads 16 columns x 64 rows of A (one wave instruction = one 1 KB column
 // segment) and 16 x 64 of C, both once, into padded LDS tiles; the next
-// block's global loads are in flight during the current block's MFMAs.
-template <class T>
+// block's global loads are in flight during the current block's MFMAs.  BF
+// as for TN.
+template <class T, bool BF>
 __global__ void __launch_bounds__(kThreads)
     k_gemm_nn_lds(const cpx<T> *__restrict__ A, int64_t lda, const cd *__restrict__ Cm, int64_t ldc,
                   int64_t K, int p, int q, double alpha, double beta, cpx<T> *Y, int64_t ldy,
@@ -296,17 +360,21 @@ __global__ void __launch_bounds__(kThreads)
                 a[t][s] = sA[buf][(4 * g + s) * LDA + ia + 16 * t + li];
                 b[t][s] = sC[buf][(jb + 16 * t + li) * LDCC + 4 * g + s];
             }
+        if constexpr (BF) {
+            mma_bf16<+1>(a, b, live, t1, t2, t3);
+        } else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
+            for (int s = 0; s < 4; ++s)
 #pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
+                for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-                for (int nj = 0; nj < 2; ++nj) {
-                    if (!live[mi][nj]) continue;
-                    t1[mi][nj] = M::op(a[mi][s].x, b[nj][s].x, t1[mi][nj]);
-                    t2[mi][nj] = M::op(a[mi][s].y, b[nj][s].y, t2[mi][nj]);
-                    t3[mi][nj] = M::op(a[mi][s].x + a[mi][s].y, b[nj][s].x + b[nj][s].y, t3[mi][nj]);
-                }
+                    for (int nj = 0; nj < 2; ++nj) {
+                        if (!live[mi][nj]) continue;
+                        t1[mi][nj] = M::op(a[mi][s].x, b[nj][s].x, t1[mi][nj]);
+                        t2[mi][nj] = M::op(a[mi][s].y, b[nj][s].y, t2[mi][nj]);
+                        t3[mi][nj] = M::op(a[mi][s].x + a[mi][s].y, b[nj][s].x + b[nj][s].y, t3[mi][nj]);
+                    }
+        }
     };
     if (p > 0) {
         gload(0);
@@ -366,7 +434,7 @@ size_t gemm_tn_part_elems(int64_t K, int p, int q, int *nsplit_out) {
     return (size_t)ns * p * q;
 }
 
-template <class T>
+template <class T, bool BF = false>
 void gemm_tn_impl(const cpx<T> *A, int64_t lda, const cpx<T> *B, int64_t ldb, int64_t K, int p, int q,
                   cd *C, int64_t ldc, const double *scale_row, double beta, cd *part, size_t part_elems,
                   hipStream_t st) {
@@ -382,7 +450,7 @@ void gemm_tn_impl(const cpx<T> *A, int64_t lda, const cpx<T> *B, int64_t ldb, in
     const int total = tiles_m * tiles_n * ns;
     // partials in the block type (the buffer is sized for complex128)
     cpx<T> *pt = reinterpret_cast<cpx<T> *>(part);
-    hipLaunchKernelGGL(k_gemm_tn_lds<T>, dim3(total), dim3(kThreads), 0, st, A, lda, B, ldb, K, p, q,
+    hipLaunchKernelGGL((k_gemm_tn_lds<T, BF>), dim3(total), dim3(kThreads), 0, st, A, lda, B, ldb, K, p, q,
                        kchunk, tiles_m, tiles_n, ns, pt);
     const int64_t n = (int64_t)p * q;
     hipLaunchKernelGGL(k_reduce_parts<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pt,
@@ -390,14 +458,14 @@ void gemm_tn_impl(const cpx<T> *A, int64_t lda, const cpx<T> *B, int64_t ldb, in
     PW_HIP(hipGetLastError());
 }
 
-template <class T>
+template <class T, bool BF = false>
 void gemm_nn_impl(const cpx<T> *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
                   double alpha, double beta, cpx<T> *Y, int64_t ldy, hipStream_t st) {
     if (K <= 0 || q <= 0) return;
     const int tiles_m = (int)((K + kTile - 1) / kTile), tiles_n = (q + kTile - 1) / kTile;
     PW_REQUIRE(!((const void *)A == (const void *)Y) || q <= kTile, PW_ERR_ARG,
                "in-place block update needs q <= 64");
-    hipLaunchKernelGGL(k_gemm_nn_lds<T>, dim3(tiles_m * tiles_n), dim3(kThreads), 0, st, A, lda, C, ldc,
+    hipLaunchKernelGGL((k_gemm_nn_lds<T, BF>), dim3(tiles_m * tiles_n), dim3(kThreads), 0, st, A, lda, C, ldc,
                        K, p, q, alpha, beta, Y, ldy, tiles_m);
     PW_HIP(hipGetLastError());
 }
@@ -419,6 +487,15 @@ void launch_gemm_nn(const cd *A, int64_t lda, const cd *C, int64_t ldc, int64_t 
 void launch_gemm_nn(const cf *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
                     double alpha, double beta, cf *Y, int64_t ldy, hipStream_t st) {
     gemm_nn_impl(A, lda, C, ldc, K, p, q, alpha, beta, Y, ldy, st);
+}
+void launch_gemm_tn_bf16(const cf *A, int64_t lda, const cf *B, int64_t ldb, int64_t K, int p, int q,
+                         cd *C, int64_t ldc, const double *scale_row, double beta, cd *part,
+                         size_t part_elems, hipStream_t st) {
+    gemm_tn_impl<float, true>(A, lda, B, ldb, K, p, q, C, ldc, scale_row, beta, part, part_elems, st);
+}
+void launch_gemm_nn_bf16(const cf *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
+                         double alpha, double beta, cf *Y, int64_t ldy, hipStream_t st) {
+    gemm_nn_impl<float, true>(A, lda, C, ldc, K, p, q, alpha, beta, Y, ldy, st);
 }
 
 }  // namespace pw

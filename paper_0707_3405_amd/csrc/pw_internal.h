@@ -92,6 +92,12 @@ void launch_gemm_nn(const cd *A, int64_t lda, const cd *C, int64_t ldc, int64_t 
                     double alpha, double beta, cd *Y, int64_t ldy, hipStream_t st);
 void launch_gemm_nn(const cf *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
                     double alpha, double beta, cf *Y, int64_t ldy, hipStream_t st);
+//   the same two products on complex64 blocks with split-bf16 MFMA products
+void launch_gemm_tn_bf16(const cf *A, int64_t lda, const cf *B, int64_t ldb, int64_t K, int p, int q,
+                         cd *C, int64_t ldc, const double *scale_row, double beta, cd *part,
+                         size_t part_elems, hipStream_t st);
+void launch_gemm_nn_bf16(const cf *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
+                         double alpha, double beta, cf *Y, int64_t ldy, hipStream_t st);
 
 // Small dense FP64 (single workgroup).
 size_t heev_scratch_bytes(int n, int k);

@@ -101,6 +101,7 @@ struct pw_ctx_s {
     int natom = 0, nlm = 0;
     cd *d_B = nullptr;
     pw::cf *d_B32 = nullptr;   // complex64 copy for the mixed form
+    bool proj_bf16 = false;    // complex64 projector products on split-bf16 MFMA
     double *d_D = nullptr;
 
     // workspace
@@ -139,9 +140,12 @@ struct pw_ctx_s {
 namespace {
 
 // Mixed form: the complex64 LOBPCG runs each block to this residual (or its
-// iteration cap), then the FP64 iteration refines from its vectors.
+// iteration cap, or its precision floor: no halving of the largest residual
+// in kMixedFloorIters iterations), then the FP64 iteration refines from its
+// vectors.
 constexpr double kMixedTol = 1e-5;
 constexpr int kMixedMaxIter = 200;
+constexpr int kMixedFloorIters = 10;
 
 // ---- workspace plan ----------------------------------------------------------
 // S is the block storage type: cd (complex128) or cf (complex64).  Small
@@ -224,8 +228,13 @@ Plan<S> make_plan(const pw_ctx_s &c, int M, int m, char *base) {
 
 size_t plan_bytes(const pw_ctx_s &c, int M, int m, pw_precision prec) {
     size_t b = make_plan<cd>(c, M, m, nullptr).bytes;
-    if (prec == PW_PREC_MIXED) b = std::max(b, make_plan<pw::cf>(c, M, m, nullptr).bytes);
+    if (prec != PW_PREC_FP64) b = std::max(b, make_plan<pw::cf>(c, M, m, nullptr).bytes);
     return b;
+}
+
+void require_precision(pw_precision prec) {
+    PW_REQUIRE(prec == PW_PREC_FP64 || prec == PW_PREC_MIXED || prec == PW_PREC_MIXED_BF16, PW_ERR_ARG,
+               "unknown precision");
 }
 
 void require_basis(const pw_ctx_s *c) {
@@ -279,6 +288,15 @@ void apply_H(pw_ctx_s *c, const Plan<S> &p, int chunk, const S *X, int64_t ldx, 
         const int np = c->nproj();
         if (np > 0) {
             // P = diag(D) B^H X ; Y += B P
+            if constexpr (std::is_same<S, pw::cf>::value) {
+                if (c->proj_bf16) {
+                    pw::launch_gemm_tn_bf16(B, c->ldp, Xc, ldx, c->npw, np, nc, p.Pj, np, c->d_D, 0.0,
+                                            p.part, p.part_elems, c->stream);
+                    pw::launch_gemm_nn_bf16(B, c->ldp, p.Pj, np, c->npw, np, nc, 1.0, 1.0, Yc, ldy,
+                                            c->stream);
+                    continue;
+                }
+            }
             pw::launch_gemm_tn(B, c->ldp, Xc, ldx, c->npw, np, nc, p.Pj, np, c->d_D, 0.0, p.part,
                                p.part_elems, c->stream);
             pw::launch_gemm_nn(B, c->ldp, p.Pj, np, c->npw, np, nc, 1.0, 1.0, Yc, ldy, c->stream);
@@ -325,7 +343,8 @@ void project_out(pw_ctx_s *c, const Plan<S> &p, PhaseTimer &tm, const S *Q, int6
 // residual check follow.  Timing and counters accumulate into stats.
 template <class S>
 pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int max_iter, S *X,
-                 int64_t ldx, int use_guess, double *eig, bool final_rr, pw_stats &stats) {
+                 int64_t ldx, int use_guess, double *eig, bool final_rr, pw_stats &stats,
+                 int floor_iters = 0) {
     hipStream_t st = c->stream;
     const int64_t ld = c->ldp, npw = c->npw;
     PhaseTimer tm;
@@ -388,6 +407,10 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
         // Basis layout in Z / HZ: [X (mb) | P (np) | W (na)].
         int np = 0, converged_it = -1;
         std::vector<int> act;
+        // floor detection (floor_iters > 0): the block ends early once its
+        // largest residual has not halved for floor_iters iterations
+        double best = HUGE_VAL;
+        int since_best = 0;
         int it = 0;
         for (it = 0; it < max_iter; ++it) {
             {
@@ -415,6 +438,16 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
             if (done) {
                 converged_it = it;
                 break;
+            }
+            if (floor_iters > 0) {
+                double rmax = 0.0;
+                for (int j = 0; j < keep; ++j) rmax = std::max(rmax, hres[j]);
+                if (rmax < 0.5 * best) {
+                    best = rmax;
+                    since_best = 0;
+                } else if (++since_best >= floor_iters) {
+                    break;
+                }
             }
             act.clear();
             for (int j = 0; j < mb; ++j)
@@ -547,13 +580,14 @@ pw_status solve(pw_ctx_s *c, int M, int m, double tol, int max_iter, pw_precisio
                 int64_t ldx, int use_guess, double *eig) {
     pw_stats stats{};
     pw_status rc;
-    if (prec == PW_PREC_MIXED) {
+    if (prec != PW_PREC_FP64) {
         ensure_mixed_tables(c);
+        c->proj_bf16 = prec == PW_PREC_MIXED_BF16;
         Plan<pw::cf> p32 = ready_plan<pw::cf>(c, M, m);
         if (use_guess) pw::launch_copy_cols(X, ldx, p32.Xs, c->ldp, c->npw, M, c->stream);
         // an unconverged block here is not an error: the FP64 stage continues from it
         (void)lobpcg(c, p32, M, m, std::max(tol, kMixedTol), std::min(max_iter, kMixedMaxIter), p32.Xs,
-                     c->ldp, use_guess, eig, false, stats);
+                     c->ldp, use_guess, eig, false, stats, kMixedFloorIters);
         pw::launch_copy_cols(p32.Xs, c->ldp, X, ldx, c->npw, M, c->stream);
         stats.mixed_iterations = stats.iterations;
         Plan<cd> p64 = ready_plan<cd>(c, M, m);
@@ -925,7 +959,7 @@ pw_status pw_workspace_size(pw_ctx c, int32_t nbands, int32_t block, pw_precisio
     return guard(c, [&] {
         require_basis(c);
         PW_REQUIRE(bytes, PW_ERR_ARG, "null output");
-        PW_REQUIRE(prec == PW_PREC_FP64 || prec == PW_PREC_MIXED, PW_ERR_ARG, "unknown precision");
+        require_precision(prec);
         PW_REQUIRE(nbands >= 1 && block >= 1 && block <= 64, PW_ERR_ARG, "need nbands >= 1 and 1 <= block <= 64");
         PW_REQUIRE(nbands <= 1024 && nbands <= c->npw, PW_ERR_ARG, "nbands must be <= min(npw, 1024)");
         const int m = std::min(block, nbands);
@@ -955,16 +989,17 @@ pw_status pw_set_workspace(pw_ctx c, void *dptr, size_t bytes) {
 pw_status pw_apply_H(pw_ctx c, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nb,
                      pw_precision prec) {
     return guard(c, [&] {
-        PW_REQUIRE(prec == PW_PREC_FP64 || prec == PW_PREC_MIXED, PW_ERR_ARG, "unknown precision");
+        require_precision(prec);
         require_basis(c);
         PW_REQUIRE(X && Y, PW_ERR_ARG, "null block");
         PW_REQUIRE(nb >= 0, PW_ERR_ARG, "negative column count");
         PW_REQUIRE(ldx >= c->npw && ldy >= c->npw, PW_ERR_ARG, "leading dimension < npw");
         if (nb == 0) return PW_OK;
         const int chunk = c->plan_block > 0 ? c->plan_block : 1;
-        if (prec == PW_PREC_MIXED) {
+        if (prec != PW_PREC_FP64) {
             Plan<pw::cf> p = ready_plan<pw::cf>(c, std::max(c->plan_nbands, 1), chunk);
             ensure_mixed_tables(c);
+            c->proj_bf16 = prec == PW_PREC_MIXED_BF16;
             apply_H(c, p, chunk, static_cast<const pw::cf *>(X), ldx, static_cast<pw::cf *>(Y), ldy, nb);
         } else {
             Plan<cd> p = ready_plan<cd>(c, std::max(c->plan_nbands, 1), chunk);
@@ -977,7 +1012,7 @@ pw_status pw_apply_H(pw_ctx c, const void *X, int64_t ldx, void *Y, int64_t ldy,
 pw_status pw_lobpcg_solve(pw_ctx c, int32_t nbands, int32_t block, double tol, int32_t max_iter,
                           pw_precision prec, void *X, int64_t ldx, int32_t use_guess, double *eig) {
     return guard(c, [&] {
-        PW_REQUIRE(prec == PW_PREC_FP64 || prec == PW_PREC_MIXED, PW_ERR_ARG, "unknown precision");
+        require_precision(prec);
         require_basis(c);
         PW_REQUIRE(X && eig, PW_ERR_ARG, "null argument");
         PW_REQUIRE(nbands >= 1 && block >= 1 && block <= 64, PW_ERR_ARG, "need nbands >= 1, 1 <= block <= 64");

@@ -35,8 +35,8 @@ def footprint(w, prec):
     hc.close()
     ldp = (npw + 31) // 32 * 32
     n3 = w.n ** 3
-    proj = ldp * w.nproj * (16 + (8 if prec == PW_PREC_MIXED else 0))
-    pot = n3 * 8 * 2 + (n3 * 4 if prec == PW_PREC_MIXED else 0)   # V, its staging copy, float copy
+    proj = ldp * w.nproj * (16 + (8 if prec != PW_PREC_FP64 else 0))
+    pot = n3 * 8 * 2 + (n3 * 4 if prec != PW_PREC_FP64 else 0)   # V, its staging copy, float copy
     tables = npw * (8 + 4 + 24) + 4096 * 8
     vectors = npw * w.nbands * 16                                    # the caller's X
     return npw, int(1.02 * (ws + proj + pot + tables + vectors)) + (8 << 20)

@@ -116,3 +116,77 @@ def test_solve_mixed_vs_oracle(torch_cuda, name):
     assert err.max() <= 1e-6, err.max()
     assert res.max() <= w.tol
     assert st["mixed_iterations"] > 0
+
+
+# ---- PW_PREC_MIXED_BF16: projector products on split-bf16 matrix cores ----
+# Per real product the split a*b ~ ah*bh + ah*bl + al*bh drops al*bl and the
+# rounding of the lo parts: at most 3 * 2^-18 |a||b|.  Through B^H X and then
+# B (D .) the column error is bounded by 2 u sum_i |D_i| ||beta_i||^2 ||x||
+# (Cauchy-Schwarz on each product), on top of the FP32 bar of the local part.
+U_SPLIT = 3.0 * 2.0 ** -18
+
+
+def _bf16_apply(torch, w, X, nbands, block):
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_MIXED, PW_PREC_MIXED_BF16
+    prob = PlaneWaveProblem.from_workload(w, device=0, nbands=nbands, block=block, prec=PW_PREC_MIXED)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda")
+    Yb, Yf = torch.empty_like(Xd), torch.empty_like(Xd)
+    prob.ctx.apply_H(Xd, Yb, prec=PW_PREC_MIXED_BF16)
+    prob.ctx.apply_H(Xd, Yf, prec=PW_PREC_MIXED)
+    torch.cuda.synchronize()
+    return Yb.cpu().numpy().T, Yf.cpu().numpy().T
+
+
+@pytest.mark.parametrize("name,nb", [("mid_nl", 37), ("fcc32_l12", 16)])
+def test_apply_bf16_matches_dense(torch_cuda, oracle_problem, name, nb):
+    torch = torch_cuda
+    from workloads import start_block
+    w, mil, H, mf = oracle_problem(name, dense=True)
+    assert mf.B is not None
+    X = start_block(5, mil.shape[0], nb).astype(np.complex64)
+    Yb, Yf = _bf16_apply(torch, w, X, max(nb, 16), 16)
+    ref = H @ X.astype(np.complex128)
+    xn = np.linalg.norm(X, axis=0)
+    hn = np.abs(np.linalg.eigvalsh(H)).max()
+    snl = float(np.sum(np.abs(mf.D) * np.sum(np.abs(mf.B) ** 2, axis=0)))
+    err = np.linalg.norm(Yb - ref, axis=0)
+    bound = 1e-6 * hn * xn + 2 * U_SPLIT * snl * xn
+    print(f"{name}: bf16 apply err/bound max {np.max(err / bound):.3e}")
+    assert np.all(err <= bound), np.max(err / bound)
+    # a different product path from the FP32 one (not bitwise the same result)
+    assert not np.array_equal(Yb, Yf)
+
+
+def test_apply_bf16_paper_scale(torch_cuda, oracle_problem):
+    torch = torch_cuda
+    from workloads import start_block
+    w, mil, _, mf = oracle_problem("fcc108_l20", dense=False)
+    X = start_block(13, mil.shape[0], 64).astype(np.complex64)
+    Yb, _ = _bf16_apply(torch, w, X, w.nbands, w.block)
+    ref = mf.apply(X.astype(np.complex128))
+    xn = np.linalg.norm(X, axis=0)
+    hn = w.ecut + np.abs(w.vgrid).max() + np.abs(w.D).sum()
+    snl = float(np.sum(np.abs(mf.D) * np.sum(np.abs(mf.B) ** 2, axis=0)))
+    err = np.linalg.norm(Yb - ref, axis=0)
+    bound = 1e-6 * hn * xn + 2 * U_SPLIT * snl * xn
+    print(f"fcc108_l20: bf16 apply err/bound max {np.max(err / bound):.3e}")
+    assert np.all(err <= bound), np.max(err / bound)
+
+
+@pytest.mark.parametrize("name", ["mid_nl", "fcc32_l12", "fcc108_l20"])
+def test_solve_bf16_vs_oracle(torch_cuda, name):
+    torch = torch_cuda
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_MIXED_BF16
+    from workloads import make_workload
+    w = make_workload(name)
+    prob = PlaneWaveProblem.from_workload(w, device=0, prec=PW_PREC_MIXED_BF16)
+    eig, X, status = prob.solve(w.tol, max_iter=300)
+    torch.cuda.synchronize()
+    res, st = prob.ctx.get_residuals(prob.nbands), prob.ctx.get_stats()
+    ref = load_golden(name)[0][:w.nbands]
+    err = np.abs(eig - ref)
+    print(f"{name} bf16: max |eig - oracle| = {err.max():.3e} (mean {err.mean():.3e}), "
+          f"max residual {res.max():.3e}, stats {st}")
+    assert err.max() <= 1e-6, err.max()
+    assert res.max() <= w.tol
+    assert st["mixed_iterations"] > 0
