@@ -9,16 +9,18 @@ Contents (each function cites the passage of Bottin, Leroux, Knyazev, Zerah,
 Comput. Mater. Sci. 2007, that it follows):
 
   pw.py       plane-wave sphere, kinetic diagonal, DFT of the local potential,
-              Kleinman-Bylander projectors, and the dense Galerkin Hamiltonian
+              Kleinman-Bylander projectors, the dense Galerkin Hamiltonian
               (sec. 2.1: the expansion of the wave-function over plane waves
-              and the projected eigenproblem).
+              and the projected eigenproblem), the overlap operator O of the
+              generalized form and its Cholesky reduction to one Hermitian
+              matrix, and the electron density.
   jacobi.c    cyclic complex-Hermitian Jacobi diagonalisation (plain C, FP64,
               single-threaded, no BLAS) -- the oracle's eigensolver.
   jacobi.py   ctypes loader for jacobi.c (built by __graft_entry__.build()).
   matfree.py  matrix-free H.X through numpy FFTs, the block LOBPCG of
-              sec. 3.2 (Algorithm 1) run block by block with the constraint to
-              previous blocks, the final Rayleigh-Ritz over all bands, and
-              residual certificates.  Paper-scale reference and CPU baseline.
+              sec. 3.2 (Algorithm 1, with O = I or the overlap operator) run
+              block by block with the constraint to previous blocks, the final
+              Rayleigh-Ritz over all bands, and residual certificates.  Paper-scale reference and CPU baseline.
 
 Parity pins: every function here is checked in tests/test_oracle_*.py against
 closed forms, lattice counts, library special cases or brute force, never

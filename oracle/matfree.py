@@ -8,11 +8,14 @@ TEST INFRASTRUCTURE ONLY (oracle).  Plain numpy/scipy, FP64/complex128.
   transform back, add the kinetic diagonal, add the non-local projector term in
   reciprocal space.  Full (unpruned) library FFTs; equal to the dense matrix of
   oracle.pw.dense_hamiltonian in exact arithmetic.
+* `MatFreeH.apply_O` -- the overlap operator O = I + sum_p q_p |beta_p><beta_p|
+  of the generalized form (sec. 2.1; see oracle.pw.overlap_dense), identity
+  when no q is given.
 * `lobpcg_block` -- Algorithm 1 (sec. 3.2): Rayleigh quotients, residuals
-  R = H Psi - Psi Upsilon, preconditioned W = K(R), Rayleigh-Ritz on
-  span{Psi, W, P}, Psi <- Psi Delta + W Lambda + P Gamma, P <- W Lambda + P Gamma,
-  with the current block kept orthogonal to the previously computed bands
-  (identity overlap).
+  R = H Psi - O Psi Upsilon, preconditioned W = K(R), Rayleigh-Ritz on
+  span{Psi, W, P} with the Gram pair (Z^H H Z, Z^H O Z),
+  Psi <- Psi Delta + W Lambda + P Gamma, P <- W Lambda + P Gamma, with the
+  current block kept O-orthogonal to the previously computed bands.
 * `solve` -- the multiband-by-multiband sweep over M/m blocks followed by the
   final Rayleigh-Ritz over all M bands (end of sec. 3.2; sec. 2.1 step 4).
 * `certificate` -- residual-based eigenvalue error bounds for Hermitian H.
@@ -36,7 +39,7 @@ class MatFreeH:
     """H = T + V_loc + sum_p D_p |beta_p><beta_p| on one sphere (sec. 2.1, 2.2)."""
 
     def __init__(self, cell, kfrac, miller, vgrid, pos=None, lm=(), D=None,
-                 workers: int = -1):
+                 workers: int = -1, q=None):
         self.miller = np.asarray(miller, np.int64)
         self.vgrid = np.asarray(vgrid, float)
         self.shape = self.vgrid.shape
@@ -50,6 +53,8 @@ class MatFreeH:
         else:
             self.B = None
             self.D = None
+        # overlap coefficients per projector (None: O = I)
+        self.q = None if q is None or self.B is None else np.asarray(q, float)
         self.napply = 0
 
     def apply_local(self, X, chunk: int = 8):
@@ -77,6 +82,14 @@ class MatFreeH:
         return Y
 
 
+    def apply_O(self, X):
+        """O X = X + B (q . (B^H X)); X itself (no copy) when O = I."""
+        X = np.asarray(X, np.complex128)
+        if self.q is None:
+            return X
+        return X + self.B @ (self.q[:, None] * (self.B.conj().T @ X))
+
+
 def tpa_precondition(T, X, R, ekin_floor: float = 1e-3):
     """W = K(R), K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4), x = T_g/E_kin,n.
 
@@ -89,16 +102,17 @@ def tpa_precondition(T, X, R, ekin_floor: float = 1e-3):
     return (num / (num + 16 * x ** 4)) * R
 
 
-def rayleigh_ritz(Z, HZ, nwant: int, drop_rel: float = 1e-14):
+def rayleigh_ritz(Z, HZ, nwant: int, drop_rel: float = 1e-14, OZ=None):
     """Rayleigh-Ritz on span(Z): lowest `nwant` Ritz pairs as coefficients C.
 
-    The Gram pair A = Z^H H Z, B = Z^H Z is reduced through an orthonormal
-    basis of span(Z) taken from the eigenvectors of B (directions with
-    eigenvalue below drop_rel * max are outside the numerically spanned space),
-    then A is diagonalised.  Returns (theta[nwant], C[ncol, nwant]).
+    The Gram pair A = Z^H H Z, B = Z^H O Z (O Z given as OZ; Z^H Z without
+    it) is reduced through a B-orthonormal basis of span(Z) taken from the
+    eigenvectors of B (directions with eigenvalue below drop_rel * max are
+    outside the numerically spanned space), then A is diagonalised.  Returns
+    (theta[nwant], C[ncol, nwant]) with C^H B C = I.
     """
     A = Z.conj().T @ HZ
-    B = Z.conj().T @ Z
+    B = Z.conj().T @ (Z if OZ is None else OZ)
     A = 0.5 * (A + A.conj().T)
     B = 0.5 * (B + B.conj().T)
     bv, bu = scipy.linalg.eigh(B)
@@ -110,33 +124,37 @@ def rayleigh_ritz(Z, HZ, nwant: int, drop_rel: float = 1e-14):
     return theta[:nwant], S @ U[:, :nwant]
 
 
-def _orth_against(V, Y):
+def _orth_against(V, Y, OY=None):
+    """V - Y (Y^H O V): the O-orthogonal complement of span(Y), O Y given as OY."""
     if Y is None or Y.shape[1] == 0:
         return V
-    return V - Y @ (Y.conj().T @ V)
+    return V - Y @ ((Y if OY is None else OY).conj().T @ V)
 
 
-def lobpcg_block(H: MatFreeH, Psi0, Y=None, tol=1e-8, maxit=300, history=None, nconv=None):
-    """Algorithm 1 of sec. 3.2 for one block, O-orthogonal (here: orthogonal) to Y.
+def lobpcg_block(H: MatFreeH, Psi0, Y=None, tol=1e-8, maxit=300, history=None, nconv=None,
+                 OY=None, out=None):
+    """Algorithm 1 of sec. 3.2 for one block, O-orthogonal to Y (O Y given as OY).
 
     Iterates all m columns of Psi0; stops when the lowest `nconv` (default m)
-    residuals are <= tol.  Returns (eps[m], Psi[npw, m], HPsi, res[m], iterations).
+    residuals are <= tol.  Returns (eps[m], Psi[npw, m], HPsi, res[m], iterations);
+    with `out` (a dict) also out["OPsi"] = O Psi.
     """
     m = Psi0.shape[1]
     nconv = m if nconv is None else nconv
-    Psi = _orth_against(np.asarray(Psi0, np.complex128), Y)
+    Psi = _orth_against(np.asarray(Psi0, np.complex128), Y, OY)
     HPsi = H.apply(Psi)
-    eps, C = rayleigh_ritz(Psi, HPsi, m)
-    Psi, HPsi = Psi @ C, HPsi @ C
-    P = HP = None
+    OPsi = H.apply_O(Psi)
+    eps, C = rayleigh_ritz(Psi, HPsi, m, OZ=OPsi)
+    Psi, HPsi, OPsi = Psi @ C, HPsi @ C, OPsi @ C
+    P = HP = OP = None
     it = 0
     res = None
     for it in range(1, maxit + 1):
-        # step 1: Upsilon = diag of Rayleigh quotients (Eq. 1 with O = I)
-        nrm2 = np.einsum("gn,gn->n", Psi.conj(), Psi).real
+        # step 1: Upsilon = diag of Rayleigh quotients x^H H x / x^H O x
+        nrm2 = np.einsum("gn,gn->n", Psi.conj(), OPsi).real
         eps = np.einsum("gn,gn->n", Psi.conj(), HPsi).real / nrm2
-        # step 2: residuals
-        R = HPsi - Psi * eps[None, :]
+        # step 2: residuals R = H Psi - O Psi Upsilon
+        R = HPsi - OPsi * eps[None, :]
         res = np.linalg.norm(R, axis=0) / np.sqrt(nrm2)
         if history is not None:
             history.append(eps.copy())
@@ -144,28 +162,32 @@ def lobpcg_block(H: MatFreeH, Psi0, Y=None, tol=1e-8, maxit=300, history=None, n
             it -= 1
             break
         # step 3: preconditioned residuals, constrained to the earlier blocks
-        W = _orth_against(tpa_precondition(H.T, Psi, R), Y)
+        W = _orth_against(tpa_precondition(H.T, Psi, R), Y, OY)
         W = W / np.linalg.norm(W, axis=0)[None, :]      # scaling is irrelevant
         HW = H.apply(W)
+        OW = H.apply_O(W)
         # step 4: Rayleigh-Ritz in span{Psi, W, P}
         if P is None:
-            Z, HZ = np.hstack([Psi, W]), np.hstack([HPsi, HW])
+            Z, HZ, OZ = np.hstack([Psi, W]), np.hstack([HPsi, HW]), np.hstack([OPsi, OW])
         else:
             s = np.linalg.norm(P, axis=0)
             s[s == 0] = 1.0
-            P, HP = P / s[None, :], HP / s[None, :]
-            Z, HZ = np.hstack([Psi, W, P]), np.hstack([HPsi, HW, HP])
-        eps, C = rayleigh_ritz(Z, HZ, m)
+            P, HP, OP = P / s[None, :], HP / s[None, :], OP / s[None, :]
+            Z, HZ, OZ = (np.hstack([Psi, W, P]), np.hstack([HPsi, HW, HP]),
+                         np.hstack([OPsi, OW, OP]))
+        eps, C = rayleigh_ritz(Z, HZ, m, OZ=OZ)
         Delta = C[:m]
         # Psi_new = Psi Delta + W Lambda + P Gamma ; P_new = W Lambda + P Gamma (step 5)
-        Pn = Z[:, m:] @ C[m:]
-        HPn = HZ[:, m:] @ C[m:]
+        Pn, HPn, OPn = Z[:, m:] @ C[m:], HZ[:, m:] @ C[m:], OZ[:, m:] @ C[m:]
         Psi = Psi @ Delta + Pn
         HPsi = HPsi @ Delta + HPn
-        P, HP = Pn, HPn
-    # normalise columns before returning
-    nrm = np.sqrt(np.einsum("gn,gn->n", Psi.conj(), Psi).real)
-    Psi, HPsi = Psi / nrm[None, :], HPsi / nrm[None, :]
+        OPsi = OPsi @ Delta + OPn
+        P, HP, OP = Pn, HPn, OPn
+    # O-normalise columns before returning
+    nrm = np.sqrt(np.einsum("gn,gn->n", Psi.conj(), OPsi).real)
+    Psi, HPsi, OPsi = Psi / nrm[None, :], HPsi / nrm[None, :], OPsi / nrm[None, :]
+    if out is not None:
+        out["OPsi"] = OPsi
     return eps, Psi, HPsi, res, it
 
 
@@ -193,17 +215,21 @@ def solve(H: MatFreeH, nbands: int, block: int, tol=1e-8, maxit=300, seed=0,
         def start(b, npw, m):
             return start_block(seed * 1000 + b, npw, m)
     npw = H.npw
-    Xs, HXs, iters = [], [], []
+    Xs, HXs, OXs, iters = [], [], [], []
     t0 = time.perf_counter()
     b, ib = 0, 0
     while b < nbands:
         keep = min(block - g, nbands - b)
         width = min(block, keep + g, npw - b)
         Y = np.hstack(Xs) if Xs else None
+        OY = np.hstack(OXs) if OXs else None
+        extra = {}
         eps, Psi, HPsi, res, it = lobpcg_block(H, start(ib, npw, width), Y,
-                                               tol=tol, maxit=maxit, nconv=keep)
+                                               tol=tol, maxit=maxit, nconv=keep, OY=OY,
+                                               out=extra)
         Xs.append(Psi[:, :keep])
         HXs.append(HPsi[:, :keep])
+        OXs.append(extra["OPsi"][:, :keep])
         iters.append(it)
         if log:
             log(f"block {ib}: {it} iterations, max res {res[:keep].max():.2e}, "
@@ -212,15 +238,16 @@ def solve(H: MatFreeH, nbands: int, block: int, tol=1e-8, maxit=300, seed=0,
         ib += 1
     X = np.hstack(Xs)
     HX = np.hstack(HXs)
+    OX = np.hstack(OXs)
     if final_rr:
-        eps, C = rayleigh_ritz(X, HX, nbands)
-        X, HX = X @ C, HX @ C
-    nrm = np.sqrt(np.einsum("gn,gn->n", X.conj(), X).real)
-    eps = np.einsum("gn,gn->n", X.conj(), HX).real / nrm ** 2
+        eps, C = rayleigh_ritz(X, HX, nbands, OZ=OX)
+        X, HX, OX = X @ C, HX @ C, OX @ C
+    nrm2 = np.einsum("gn,gn->n", X.conj(), OX).real
+    eps = np.einsum("gn,gn->n", X.conj(), HX).real / nrm2
     order = np.argsort(eps)
-    X, HX, eps = X[:, order], HX[:, order], eps[order]
-    R = HX - X * eps[None, :]
-    res = np.linalg.norm(R, axis=0) / np.linalg.norm(X, axis=0)
+    X, HX, OX, eps, nrm2 = X[:, order], HX[:, order], OX[:, order], eps[order], nrm2[order]
+    R = HX - OX * eps[None, :]
+    res = np.linalg.norm(R, axis=0) / np.sqrt(nrm2)
     return dict(eig=eps, X=X, HX=HX, res=res, iters=iters,
                 seconds=time.perf_counter() - t0)
 

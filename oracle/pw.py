@@ -22,6 +22,7 @@ Everything is float64 / complex128 and written for clarity, not speed.
 from __future__ import annotations
 
 import numpy as np
+import scipy.linalg
 
 C_KB = np.sqrt(32.0 * np.pi ** 2.5)   # projector normalisation constant
 
@@ -143,6 +144,33 @@ def dense_hamiltonian(cell, kfrac, miller, vgrid, pos=None, lm=(), D=None):
         H = H + (B * np.asarray(D, float)[None, :]) @ B.conj().T
         H = 0.5 * (H + H.conj().T)
     return H
+
+
+def overlap_dense(B, q):
+    """Overlap operator O = I + sum_p q_p beta_p beta_p^H, complex128.
+
+    Sec. 2.1 puts an overlap operator O on the right-hand side of the
+    Kohn-Sham equations (H psi = eps O psi) for ultrasoft / PAW projectors and
+    gives no formula; the Vanderbilt form I + sum_ij |beta_i> q_ij <beta_j| is
+    used with q diagonal in the projector index, over the same projector
+    table B as the non-local potential.  q >= 0 makes O >= I (positive
+    definite)."""
+    B = np.asarray(B, complex)
+    O = np.eye(B.shape[0], dtype=complex)
+    if B.shape[1]:
+        O = O + (B * np.asarray(q, float)[None, :]) @ B.conj().T
+        O = 0.5 * (O + O.conj().T)
+    return O
+
+
+def generalized_to_standard(H, O):
+    """The pencil (H, O) as one Hermitian matrix with the same eigenvalues:
+    O = L L^H (Cholesky), A = L^-1 H L^-H; an eigenvector y of A gives the
+    pencil's eigenvector x = L^-H y (x^H O x = y^H y).  Returns (A, L)."""
+    L = scipy.linalg.cholesky(O, lower=True)
+    Y = scipy.linalg.solve_triangular(L, H, lower=True)
+    A = scipy.linalg.solve_triangular(L, Y.conj().T, lower=True).conj().T
+    return 0.5 * (A + A.conj().T), L
 
 
 def density(cell, kfrac, miller, n, C, occ):

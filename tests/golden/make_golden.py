@@ -9,6 +9,13 @@ Calls only `oracle/` (and the seeded input generators in `workloads/`):
   kpts_l16_k1, kpts_l16_k9
               oracle.matfree.solve, tol 1e-8, at k-points 1 and 9 of the
               ten-k-point batch cell (workloads.make_kpoint_workloads).
+  mid_nl_ovl  generalized form H c = eps O c on the mid_nl cell with the overlap
+              coefficients of workloads.overlap_coefficients: dense H and O
+              (oracle.pw), Cholesky reduction, the oracle's C Jacobi.
+  fcc32_l12_ovl
+              the same overlap on fcc32_l12: oracle.matfree.solve in the
+              O-metric, tol 1e-9 (its error bound holds because O >= I makes
+              the residual 2-norm an upper bound of its O^-1-norm).
 
 Each file lists index, eigenvalue (Ha) and, for the matrix-free runs, the
 residual norm and the residual certificate (oracle.matfree.certificate).
@@ -28,7 +35,7 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import pw, matfree                      # noqa: E402
 from oracle.jacobi import eigh_jacobi              # noqa: E402
-from workloads import make_workload, make_kpoint_workloads   # noqa: E402
+from workloads import make_workload, make_kpoint_workloads, overlap_coefficients   # noqa: E402
 
 
 def dense_case(name):
@@ -46,10 +53,31 @@ def dense_case(name):
     print("wrote", path)
 
 
-def matfree_case(name, tol, w=None):
+def dense_pencil_case(base):
+    w = make_workload(base)
+    mil = pw.sphere(w.cell, w.kfrac, w.ecut)
+    H = pw.dense_hamiltonian(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D)
+    O = pw.overlap_dense(pw.projectors(w.cell, w.kfrac, mil, w.pos, w.lm), overlap_coefficients(w))
+    A, _ = pw.generalized_to_standard(H, O)
+    ev, _, sweeps = eigh_jacobi(A)
+    path = os.path.join(HERE, f"{base}_ovl_eig.txt")
+    with open(path, "w") as f:
+        f.write(f"# {base}_ovl: npw={len(mil)}, pencil (H, O) with O = I + B diag(q) B^H, "
+                f"Cholesky reduction diagonalised by cyclic Jacobi ({sweeps} sweeps), "
+                f"all {len(ev)} eigenvalues in Ha\n")
+        f.write("# written by tests/golden/make_golden.py (oracle only)\n")
+        for i, e in enumerate(np.sort(ev)):
+            f.write(f"{i} {e:.17e}\n")
+    print("wrote", path)
+
+
+def matfree_case(name, tol, w=None, overlap=False):
     w = make_workload(name) if w is None else w
     mil = pw.sphere(w.cell, w.kfrac, w.ecut)
-    H = matfree.MatFreeH(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D)
+    q = overlap_coefficients(w) if overlap else None
+    H = matfree.MatFreeH(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D, q=q)
+    if overlap:
+        name = name + "_ovl"
     t0 = time.time()
     r = matfree.solve(H, w.nbands, w.block, tol=tol, seed=w.seed,
                       log=lambda s: print(name, s, flush=True))
@@ -73,6 +101,8 @@ CASES = {
     "fcc108_l20": lambda: matfree_case("fcc108_l20", 1e-8),
     "kpts_l16_k1": lambda: matfree_case("kpts_l16_k1", 1e-8, make_kpoint_workloads()[1]),
     "kpts_l16_k9": lambda: matfree_case("kpts_l16_k9", 1e-8, make_kpoint_workloads()[9]),
+    "mid_nl_ovl": lambda: dense_pencil_case("mid_nl"),
+    "fcc32_l12_ovl": lambda: matfree_case("fcc32_l12", 1e-9, overlap=True),
 }
 
 if __name__ == "__main__":

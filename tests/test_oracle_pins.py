@@ -335,3 +335,116 @@ def test_density_pins():
         ph = np.exp(2j * np.pi * (mil @ np.array(j)) / w.n)
         direct = sum(occ[b] * abs(np.sum(C[:, b] * ph)) ** 2 for b in range(3)) / omega
         assert abs(rho[j] - direct) <= 1e-12 * direct
+
+
+# ---- generalized form (overlap operator O != I) --------------------------------------
+
+def _overlap_case(name):
+    from workloads import overlap_coefficients
+    w = make_workload(name)
+    mil = pw.sphere(w.cell, w.kfrac, w.ecut)
+    q = overlap_coefficients(w)
+    B = pw.projectors(w.cell, w.kfrac, mil, w.pos, w.lm)
+    return w, mil, q, B
+
+
+def test_overlap_operator_properties():
+    """O = I + B diag(q) B^H: the matrix-free apply equals the dense matrix; O >= I
+    for q >= 0 with exactly nproj eigenvalues above 1, and those equal the
+    eigenvalues of 1 + diag(q)^1/2 B^H B diag(q)^1/2 (same nonzero spectrum of
+    M M^H and M^H M); trace(O - I) = sum_p q_p |beta_p|^2."""
+    w, mil, q, B = _overlap_case("tiny_nl")
+    O = pw.overlap_dense(B, q)
+    mf = matfree.MatFreeH(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D, q=q)
+    X = start_block(4, mil.shape[0], 5)
+    assert np.abs(mf.apply_O(X) - O @ X).max() <= 1e-13
+    ev = np.linalg.eigvalsh(O)
+    assert ev.min() >= 1 - 1e-13
+    above = np.sort(ev[ev > 1 + 1e-10])
+    assert above.size == w.nproj
+    sq = np.sqrt(q)
+    small = np.linalg.eigvalsh(np.eye(w.nproj) + sq[:, None] * (B.conj().T @ B) * sq[None, :])
+    assert np.abs(above - np.sort(small)).max() <= 1e-12
+    assert abs(np.trace(O).real - mil.shape[0] - np.sum(q * np.linalg.norm(B, axis=0) ** 2)) <= 1e-11
+
+
+def test_overlap_pencil_secular_equation():
+    """H = T (V = 0, no non-local term), O = I + q |b><b| with one s projector: the
+    pencil T c = lam O c has, per distinct kinetic value t of multiplicity d,
+    d - 1 eigenvalues equal to t, and one root of 1 = lam q sum_t w_t / (t - lam)
+    (w_t = sum of |b_g|^2 over that value) between consecutive values t and
+    below the smallest.  Against the oracle's dense route (Cholesky reduction +
+    Jacobi)."""
+    from scipy.optimize import brentq
+    w = make_workload("tiny_nl")
+    mil = pw.sphere(w.cell, w.kfrac, w.ecut)
+    T = pw.kinetic(w.cell, w.kfrac, mil)
+    b = pw.projectors(w.cell, w.kfrac, mil, w.pos[:1], ((0, 0),))
+    qv = 0.7
+    O = pw.overlap_dense(b, [qv])
+    A, _ = pw.generalized_to_standard(np.diag(T).astype(complex), O)
+    got = np.sort(eigh_jacobi(A)[0])
+    # group equal kinetic values (equal up to rounding)
+    order = np.argsort(T)
+    ts, ws, mult = [], [], []
+    for i in order:
+        if ts and abs(T[i] - ts[-1]) <= 1e-9 * max(1.0, ts[-1]):
+            ws[-1] += abs(b[i, 0]) ** 2
+            mult[-1] += 1
+        else:
+            ts.append(T[i])
+            ws.append(abs(b[i, 0]) ** 2)
+            mult.append(1)
+    ts, ws = np.array(ts), np.array(ws)
+    assert ts[0] > 0 and np.all(ws > 0)
+    f = lambda lam: lam * qv * np.sum(ws / (ts - lam)) - 1.0
+    roots = [brentq(f, 1e-14, ts[0] * (1 - 1e-14), xtol=1e-15, rtol=1e-15, maxiter=500)]
+    for i in range(len(ts) - 1):
+        gap = ts[i + 1] - ts[i]
+        roots.append(brentq(f, ts[i] + 1e-12 * gap, ts[i + 1] - 1e-12 * gap,
+                            xtol=1e-15, rtol=1e-15, maxiter=500))
+    ref = np.sort(np.concatenate([roots, np.repeat(ts, np.array(mult) - 1)]))
+    assert ref.size == got.size
+    assert np.abs(got[:60] - ref[:60]).max() <= 1e-10
+    assert np.all(got[:60] < np.sort(T)[:60] + 1e-12)   # O >= I lowers a positive spectrum
+
+
+def test_generalized_reduction_matches_lapack_pencil():
+    """Cholesky reduction + the oracle's Jacobi against LAPACK's Hermitian-definite
+    pencil solver (zhegvd) on the full Hamiltonian and overlap."""
+    w, mil, q, B = _overlap_case("tiny_nl")
+    H = pw.dense_hamiltonian(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D)
+    O = pw.overlap_dense(B, q)
+    A, L = pw.generalized_to_standard(H, O)
+    ev, V, _ = eigh_jacobi(A)
+    ref = scipy.linalg.eigh(H, O, eigvals_only=True, driver="gvd")
+    assert np.abs(np.sort(ev) - ref).max() <= 1e-12
+    # eigenvectors map back to O-orthonormal pencil eigenvectors
+    X = scipy.linalg.solve_triangular(L.conj().T, V, lower=False)
+    assert np.abs(X.conj().T @ O @ X - np.eye(X.shape[1])).max() <= 1e-11
+    assert np.abs(H @ X - O @ X * ev[None, :]).max() <= 1e-10
+
+
+@pytest.mark.parametrize("name", ["tiny_nl", "mid_nl"])
+def test_oracle_generalized_lobpcg_matches_dense(name):
+    """The matrix-free block LOBPCG in the O-metric against the dense pencil."""
+    w, mil, q, B = _overlap_case(name)
+    H = pw.dense_hamiltonian(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D)
+    O = pw.overlap_dense(B, q)
+    ref = scipy.linalg.eigh(H, O, eigvals_only=True, driver="gvd")[:w.nbands]
+    mf = matfree.MatFreeH(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D, q=q)
+    r = matfree.solve(mf, w.nbands, w.block, tol=1e-9, seed=w.seed)
+    assert np.abs(r["eig"] - ref).max() <= 1e-10, np.abs(r["eig"] - ref).max()
+    assert r["res"].max() <= 1e-9
+    # the overlap moves the spectrum: the standard problem is far away
+    assert np.abs(np.linalg.eigvalsh(H)[:w.nbands] - ref).max() > 1e-3
+
+
+def test_oracle_generalized_with_zero_overlap_is_standard():
+    w = make_workload("tiny_nl")
+    mil = pw.sphere(w.cell, w.kfrac, w.ecut)
+    a = matfree.solve(matfree.MatFreeH(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D),
+                      w.nbands, w.block, tol=1e-9, seed=1)
+    b = matfree.solve(matfree.MatFreeH(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D,
+                                       q=np.zeros(w.nproj)), w.nbands, w.block, tol=1e-9, seed=1)
+    assert np.abs(a["eig"] - b["eig"]).max() <= 1e-12

@@ -6,7 +6,9 @@ of the eigensolver's arithmetic (no sphere, no Hamiltonian, no FFT), so the
 oracle and the HIP path can both consume it without sharing method code.
 """
 from .gen import (Workload, make_workload, well_potential, WORKLOADS,
-                  start_block, make_kpoint_workloads, KPTS_4X4X4_IRREDUCIBLE, make_request)
+                  start_block, make_kpoint_workloads, KPTS_4X4X4_IRREDUCIBLE, make_request,
+                  overlap_coefficients)
 
 __all__ = ["Workload", "make_workload", "well_potential", "WORKLOADS",
-           "start_block", "make_kpoint_workloads", "KPTS_4X4X4_IRREDUCIBLE", "make_request"]
+           "start_block", "make_kpoint_workloads", "KPTS_4X4X4_IRREDUCIBLE", "make_request",
+           "overlap_coefficients"]

@@ -149,6 +149,14 @@ def make_request(i: int, base_seed: int = 1000, L_range=(8.0, 24.0), ecut_range=
     return w, mixed
 
 
+def overlap_coefficients(w: Workload, lo: float = 0.2, hi: float = 0.8) -> np.ndarray:
+    """Overlap coefficients q_p ~ U(lo, hi) per projector of w (the generalized
+    form's O = I + sum_p q_p |beta_p><beta_p|), from their own PCG64 stream.
+    q >= 0 keeps O positive definite."""
+    rng = np.random.default_rng(20_000 + w.seed)
+    return rng.uniform(lo, hi, w.nproj)
+
+
 def start_block(seed: int, npw: int, ncol: int) -> np.ndarray:
     """Complex standard-normal block [npw, ncol] from its own PCG64 stream."""
     rng = np.random.default_rng(10_000 + seed)
