@@ -129,6 +129,18 @@ pw_status pw_set_local_potential(pw_ctx ctx, const double *v, int on_device);
 pw_status pw_set_projectors(pw_ctx ctx, int32_t natom, const double *pos,
                             int32_t nproj_per_atom, const int32_t *lm, const double *D);
 
+/* Overlap operator of the generalized form H psi = eps O psi (sec. 2.1: the
+ * right-hand side of the Kohn-Sham equations for ultrasoft / PAW
+ * projectors; Algorithm 1 with R = H Psi - O Psi Upsilon):
+ *   O = I + sum_p q[p] |beta_p><beta_p|
+ * over the projectors of pw_set_projectors, in the same order as D.  q: host
+ * double[nproj], finite and >= 0 (O >= I, positive definite), else
+ * PW_ERR_ARG; q = NULL restores O = I.  Needs projectors (PW_ERR_STATE
+ * otherwise); pw_set_projectors clears the overlap.  With an overlap set,
+ * pw_lobpcg_solve solves the generalized problem and the workspace grows by
+ * O Z and O X blocks: call pw_workspace_size after this call. */
+pw_status pw_set_overlap(pw_ctx ctx, const double *q);
+
 /* Device workspace the caller allocates: bytes needed by pw_lobpcg_solve for
  * (nbands, block) at precision prec, and by pw_apply_H (which works in chunks
  * of `block` columns).  A workspace sized for either mixed form also serves
@@ -148,10 +160,19 @@ pw_status pw_set_workspace(pw_ctx ctx, void *dptr, size_t bytes);
 pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ldy,
                      int32_t nb, pw_precision prec);
 
+/* Y = O X (the overlap of pw_set_overlap; PW_ERR_STATE if none is set), with
+ * the same blocks, precisions, requirements and stream behaviour as
+ * pw_apply_H: a copy of X plus the projector products B diag(q) B^H X. */
+pw_status pw_apply_O(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ldy,
+                     int32_t nb, pw_precision prec);
+
 /* Lowest `nbands` eigenpairs by block LOBPCG (sec. 3.2, Algorithm 1) in blocks
  * of `block` bands, each block kept orthogonal to the previous ones, then a
  * final Rayleigh-Ritz over all bands.  Convergence per block: every residual
- * ||H x - theta x||_2 (||x||_2 = 1) <= tol.  tol = 0 selects the fixed-sweep
+ * ||H x - theta x||_2 (||x||_2 = 1) <= tol.  With an overlap set
+ * (pw_set_overlap) the pencil (H, O) is solved instead: every orthogonality
+ * is in the O inner product, theta = x^H H x / x^H O x and the residual is
+ * ||H x - theta O x||_2 / (x^H O x)^1/2; X is returned O-orthonormal.  tol = 0 selects the fixed-sweep
  * mode of the paper's iteration count (sec. 3.2): every block runs exactly
  * max_iter iterations with all columns active, the final Rayleigh-Ritz
  * follows and the call returns PW_OK (FP64 only).  X: device complex128

@@ -27,7 +27,7 @@ EXPORTS = ("pw_create", "pw_destroy", "pw_last_error", "pw_init_basis", "pw_fft_
            "pw_workspace_size", "pw_set_workspace", "pw_apply_H", "pw_lobpcg_solve",
            "pw_get_residuals", "pw_get_stats", "pw_gram", "pw_block_update", "pw_small_eigh",
            "pw_residuals", "pw_gram_mixed", "pw_block_update_mixed", "pw_lobpcg_solve_batch",
-           "pw_density")
+           "pw_density", "pw_set_overlap", "pw_apply_O")
 
 
 class PWError(RuntimeError):
@@ -79,6 +79,8 @@ def load_library():
         "pw_workspace_size": (ctypes.c_int, [P, I32, I32, ctypes.c_int, ctypes.POINTER(SZ)]),
         "pw_set_workspace": (ctypes.c_int, [P, P, SZ]),
         "pw_apply_H": (ctypes.c_int, [P, P, I64, P, I64, I32, ctypes.c_int]),
+        "pw_apply_O": (ctypes.c_int, [P, P, I64, P, I64, I32, ctypes.c_int]),
+        "pw_set_overlap": (ctypes.c_int, [P, P]),
         "pw_lobpcg_solve": (ctypes.c_int, [P, I32, I32, D, I32, ctypes.c_int, P, I64, I32, P]),
         "pw_get_residuals": (ctypes.c_int, [P, P]),
         "pw_get_stats": (ctypes.c_int, [P, ctypes.POINTER(PWStats)]),
@@ -204,6 +206,14 @@ class Context:
         self._check(self.lib.pw_set_projectors(self.h, pos.shape[0], pos.ctypes.data, lm.shape[0],
                                                lm.ctypes.data, D.ctypes.data))
 
+    def set_overlap(self, q):
+        """O = I + sum_p q_p |beta_p><beta_p| (None: O = I); size the workspace afterwards."""
+        if q is None:
+            self._check(self.lib.pw_set_overlap(self.h, None))
+            return
+        q = np.ascontiguousarray(np.asarray(q, np.float64))
+        self._check(self.lib.pw_set_overlap(self.h, q.ctypes.data))
+
     def workspace_size(self, nbands, block, prec=PW_PREC_FP64):
         out = ctypes.c_size_t(0)
         self._check(self.lib.pw_workspace_size(self.h, nbands, block, prec, ctypes.byref(out)))
@@ -226,6 +236,11 @@ class Context:
     def apply_H(self, X, Y, nb=None, prec=PW_PREC_FP64):
         nb = X.shape[0] if nb is None else nb
         self._check(self.lib.pw_apply_H(self.h, _ptr(X), _ld(X), _ptr(Y), _ld(Y), nb, prec))
+        return Y
+
+    def apply_O(self, X, Y, nb=None, prec=PW_PREC_FP64):
+        nb = X.shape[0] if nb is None else nb
+        self._check(self.lib.pw_apply_O(self.h, _ptr(X), _ld(X), _ptr(Y), _ld(Y), nb, prec))
         return Y
 
     def lobpcg_solve(self, nbands, block, tol, max_iter, X, use_guess=False, prec=PW_PREC_FP64,

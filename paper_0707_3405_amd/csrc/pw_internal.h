@@ -111,11 +111,14 @@ void launch_chol_inv_f64(const cd *G, int64_t ldg, int n, cd *Rinv, int64_t ldr,
 // Vector kernels.
 size_t resid_part_elems(int64_t npw, int nb);
 // Blocks are complex128 (cd) or complex64 (cf); every reduction is in double.
-// theta[nb]; ekin_nrm[2 nb] = (E_kin per band, |x|^2 per band)
+// theta[nb]; ekin_nrm[2 nb] = (E_kin per band, |x|^2 per band); with OX (the
+// generalized form) the norm is Re(x^H O x) and theta = x^H H x / x^H O x
 void launch_band_dots(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
-                      int64_t npw, int nb, double *part, double *theta, double *ekin_nrm, hipStream_t st);
+                      int64_t npw, int nb, double *part, double *theta, double *ekin_nrm, hipStream_t st,
+                      const cd *OX = nullptr, int64_t ldox = 0);
 void launch_band_dots(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, const double *kin,
-                      int64_t npw, int nb, double *part, double *theta, double *ekin_nrm, hipStream_t st);
+                      int64_t npw, int nb, double *part, double *theta, double *ekin_nrm, hipStream_t st,
+                      const cf *OX = nullptr, int64_t ldox = 0);
 void launch_resid_precond(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
                           int64_t npw, int nb, const double *theta, const double *ekin_nrm, cd *W,
                           int64_t ldw, double *part, double *res, hipStream_t st);

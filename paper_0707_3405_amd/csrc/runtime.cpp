@@ -103,6 +103,7 @@ struct pw_ctx_s {
     pw::cf *d_B32 = nullptr;   // complex64 copy for the mixed form
     bool proj_bf16 = false;    // complex64 projector products on split-bf16 MFMA
     double *d_D = nullptr;
+    double *d_Q = nullptr;     // overlap coefficients (generalized form); null: O = I
 
     // workspace
     char *ws = nullptr;
@@ -156,6 +157,8 @@ struct Plan {
     S *Z[2] = {nullptr, nullptr};     // [ldp x 3m] basis blocks [X | P | W]
     S *HZ[2] = {nullptr, nullptr};    // [ldp x 3m]
     S *HXall = nullptr;           // [ldp x M]
+    S *OZ[2] = {nullptr, nullptr};    // [ldp x 3m] O Z (generalized form only)
+    S *OXall = nullptr;           // [ldp x M] O X (generalized form only)
     S *T = nullptr;               // [ldp x M] rotation temp
     S *Xs = nullptr;              // [ldp x M] internal copy of X (complex64 form only)
     cd *Pj = nullptr;             // projector overlaps [nproj x block]
@@ -192,6 +195,10 @@ Plan<S> make_plan(const pw_ctx_s &c, int M, int m, char *base) {
         p.HZ[i] = a.take<S>((size_t)ld * 3 * m);
     }
     p.HXall = a.take<S>((size_t)ld * M);
+    if (c.d_Q) {
+        for (int i = 0; i < 2; ++i) p.OZ[i] = a.take<S>((size_t)ld * 3 * m);
+        p.OXall = a.take<S>((size_t)ld * M);
+    }
     p.T = a.take<S>((size_t)ld * M);
     if (!std::is_same<S, cd>::value) p.Xs = a.take<S>((size_t)ld * M);
     p.Pj = a.take<cd>((size_t)std::max(nproj, 1) * m);
@@ -275,32 +282,46 @@ const float *potential_of(const pw_ctx_s *c, const pw::cf *) { return c->d_v32; 
 const cd *projectors_of(const pw_ctx_s *c, const cd *) { return c->d_B; }
 const pw::cf *projectors_of(const pw_ctx_s *c, const pw::cf *) { return c->d_B32; }
 
-// ---- H.X ------------------------------------------------------------------------
+// ---- H.X and O.X -----------------------------------------------------------------
+// Y += B diag(s) B^H X over nc <= block columns (projector table B [npw x nproj])
+template <class S>
+void proj_add(pw_ctx_s *c, const Plan<S> &p, const double *s, const S *X, int64_t ldx, S *Y,
+              int64_t ldy, int nc) {
+    const S *B = projectors_of(c, X);
+    const int np = c->nproj();
+    if constexpr (std::is_same<S, pw::cf>::value) {
+        if (c->proj_bf16) {
+            pw::launch_gemm_tn_bf16(B, c->ldp, X, ldx, c->npw, np, nc, p.Pj, np, s, 0.0, p.part,
+                                    p.part_elems, c->stream);
+            pw::launch_gemm_nn_bf16(B, c->ldp, p.Pj, np, c->npw, np, nc, 1.0, 1.0, Y, ldy, c->stream);
+            return;
+        }
+    }
+    pw::launch_gemm_tn(B, c->ldp, X, ldx, c->npw, np, nc, p.Pj, np, s, 0.0, p.part, p.part_elems,
+                       c->stream);
+    pw::launch_gemm_nn(B, c->ldp, p.Pj, np, c->npw, np, nc, 1.0, 1.0, Y, ldy, c->stream);
+}
+
 template <class S>
 void apply_H(pw_ctx_s *c, const Plan<S> &p, int chunk, const S *X, int64_t ldx, S *Y, int64_t ldy,
              int nb) {
-    const S *B = projectors_of(c, X);
     for (int b0 = 0; b0 < nb; b0 += chunk) {
         const int nc = std::min(chunk, nb - b0);
         const S *Xc = X + (int64_t)b0 * ldx;
         S *Yc = Y + (int64_t)b0 * ldy;
         pw::launch_fft_apply(c->sp, potential_of(c, X), Xc, ldx, Yc, ldy, nc, p.Sb, c->stream);
-        const int np = c->nproj();
-        if (np > 0) {
-            // P = diag(D) B^H X ; Y += B P
-            if constexpr (std::is_same<S, pw::cf>::value) {
-                if (c->proj_bf16) {
-                    pw::launch_gemm_tn_bf16(B, c->ldp, Xc, ldx, c->npw, np, nc, p.Pj, np, c->d_D, 0.0,
-                                            p.part, p.part_elems, c->stream);
-                    pw::launch_gemm_nn_bf16(B, c->ldp, p.Pj, np, c->npw, np, nc, 1.0, 1.0, Yc, ldy,
-                                            c->stream);
-                    continue;
-                }
-            }
-            pw::launch_gemm_tn(B, c->ldp, Xc, ldx, c->npw, np, nc, p.Pj, np, c->d_D, 0.0, p.part,
-                               p.part_elems, c->stream);
-            pw::launch_gemm_nn(B, c->ldp, p.Pj, np, c->npw, np, nc, 1.0, 1.0, Yc, ldy, c->stream);
-        }
+        if (c->nproj() > 0) proj_add(c, p, c->d_D, Xc, ldx, Yc, ldy, nc);   // + B diag(D) B^H X
+    }
+}
+
+// Y = O X = X + B diag(q) B^H X (generalized form; the overlap is set)
+template <class S>
+void apply_O(pw_ctx_s *c, const Plan<S> &p, int chunk, const S *X, int64_t ldx, S *Y, int64_t ldy,
+             int nb) {
+    pw::launch_copy_cols(X, ldx, Y, ldy, c->npw, nb, c->stream);
+    for (int b0 = 0; b0 < nb; b0 += chunk) {
+        const int nc = std::min(chunk, nb - b0);
+        proj_add(c, p, c->d_Q, X + (int64_t)b0 * ldx, ldx, Y + (int64_t)b0 * ldy, ldy, nc);
     }
 }
 
@@ -311,30 +332,40 @@ int read_status(pw_ctx_s *c) {
     return s;
 }
 
-// CholQR of V [npw x nb] in place: G = V^H V, V <- V R^-1.
+// CholQR of V [npw x nb] in place: G = V^H V, V <- V R^-1.  In the
+// generalized form (OV given, OV = O V) the factor is of G = V^H O V and OV
+// is carried along: OV <- OV R^-1.
 template <class S>
-void cholqr(pw_ctx_s *c, const Plan<S> &p, PhaseTimer &tm, S *V, int64_t ldv, int nb) {
+void cholqr(pw_ctx_s *c, const Plan<S> &p, PhaseTimer &tm, S *V, int64_t ldv, int nb, S *OV = nullptr) {
     auto e0 = tm.begin();
-    pw::launch_gemm_tn(V, ldv, V, ldv, c->npw, nb, nb, p.Gs, nb, nullptr, 0.0, p.part, p.part_elems,
-                       c->stream);
+    pw::launch_gemm_tn(V, ldv, OV ? OV : V, ldv, c->npw, nb, nb, p.Gs, nb, nullptr, 0.0, p.part,
+                       p.part_elems, c->stream);
     tm.end(PhaseTimer::kGemm, e0);
     auto e1 = tm.begin();
     pw::launch_chol_inv_f64(p.Gs, nb, nb, p.Rinv, nb, c->d_status, c->stream);
     tm.end(PhaseTimer::kDense, e1);
     auto e2 = tm.begin();
     pw::launch_gemm_nn(V, ldv, p.Rinv, nb, c->npw, nb, nb, 1.0, 0.0, V, ldv, c->stream);
+    if (OV) pw::launch_gemm_nn(OV, ldv, p.Rinv, nb, c->npw, nb, nb, 1.0, 0.0, OV, ldv, c->stream);
     tm.end(PhaseTimer::kGemm, e2);
 }
 
-// V <- V - Q (Q^H V), Q [npw x nq]
+// V <- V - Q (Q^H V), Q [npw x nq].  Generalized form: OQ = O Q given, the
+// coefficients are (OQ)^H V (O-orthogonal complement), and OV <- OV - OQ (..)
+// when OV is given.
 template <class S>
 void project_out(pw_ctx_s *c, const Plan<S> &p, PhaseTimer &tm, const S *Q, int64_t ldq, int nq,
-                 S *V, int64_t ldv, int nb) {
+                 S *V, int64_t ldv, int nb, const S *OQ = nullptr, int64_t ldoq = 0, S *OV = nullptr) {
     if (nq <= 0) return;
     auto e0 = tm.begin();
-    pw::launch_gemm_tn(Q, ldq, V, ldv, c->npw, nq, nb, p.Ov, nq, nullptr, 0.0, p.part, p.part_elems,
-                       c->stream);
+    if (OQ)
+        pw::launch_gemm_tn(OQ, ldoq, V, ldv, c->npw, nq, nb, p.Ov, nq, nullptr, 0.0, p.part,
+                           p.part_elems, c->stream);
+    else
+        pw::launch_gemm_tn(Q, ldq, V, ldv, c->npw, nq, nb, p.Ov, nq, nullptr, 0.0, p.part,
+                           p.part_elems, c->stream);
     pw::launch_gemm_nn(Q, ldq, p.Ov, nq, c->npw, nq, nb, -1.0, 1.0, V, ldv, c->stream);
+    if (OQ && OV) pw::launch_gemm_nn(OQ, ldoq, p.Ov, nq, c->npw, nq, nb, -1.0, 1.0, OV, ldv, c->stream);
     tm.end(PhaseTimer::kGemm, e0);
 }
 
@@ -367,6 +398,11 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
         ++stats.blocks;
         int cur = 0;
         S *Z = p.Z[cur], *HZ = p.HZ[cur];
+        // generalized form: O Z is carried beside Z and H Z, and every
+        // orthogonality is in the O inner product
+        const bool gen = c->d_Q != nullptr;
+        S *OZ = gen ? p.OZ[cur] : nullptr;
+        S *OXprev = gen ? p.OXall : nullptr;
         // start block: X in slot 0 (caller guess for the stored columns)
         const int nguess = use_guess ? std::min(mb, M - b0) : 0;
         if (nguess > 0) pw::launch_copy_cols(X + (int64_t)b0 * ldx, ldx, Z, ld, npw, nguess, st);
@@ -374,9 +410,14 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
             pw::launch_random_block(Z + (int64_t)nguess * ld, ld, npw, mb - nguess,
                                     0x5EED0000ull + (uint64_t)b0, c->sp.kin, st);
         // orthogonal to previous blocks, orthonormal (twice)
+        if (gen) {
+            auto e = tm.begin();
+            apply_O(c, p, m, Z, ld, OZ, ld, mb);
+            tm.end(PhaseTimer::kApply, e);
+        }
         for (int pass = 0; pass < 2; ++pass) {
-            project_out(c, p, tm, (const S *)X, ldx, b0, Z, ld, mb);
-            cholqr(c, p, tm, Z, ld, mb);
+            project_out(c, p, tm, (const S *)X, ldx, b0, Z, ld, mb, OXprev, ld, OZ);
+            cholqr(c, p, tm, Z, ld, mb, OZ);
         }
         {
             auto e = tm.begin();
@@ -396,10 +437,12 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
             auto e2 = tm.begin();
             pw::launch_gemm_nn(Z, ld, p.Cc, 3 * m, npw, mb, mb, 1.0, 0.0, p.Z[1 - cur], ld, st);
             pw::launch_gemm_nn(HZ, ld, p.Cc, 3 * m, npw, mb, mb, 1.0, 0.0, p.HZ[1 - cur], ld, st);
+            if (gen) pw::launch_gemm_nn(OZ, ld, p.Cc, 3 * m, npw, mb, mb, 1.0, 0.0, p.OZ[1 - cur], ld, st);
             tm.end(PhaseTimer::kGemm, e2);
             cur = 1 - cur;
             Z = p.Z[cur];
             HZ = p.HZ[cur];
+            if (gen) OZ = p.OZ[cur];
         }
         // Active set: only columns whose residual is still above tol receive a
         // new direction W and a conjugate direction P, so H.W, the
@@ -415,9 +458,11 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
         for (it = 0; it < max_iter; ++it) {
             {
                 auto e = tm.begin();
-                pw::launch_band_dots(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.rpart, p.theta, p.ekin, st);
-                pw::launch_resid_precond(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.theta, p.ekin, (S *)nullptr,
-                                         0, p.rpart, p.res, st);
+                // R = HZ - theta OZ (OZ = Z when O = I)
+                pw::launch_band_dots(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.rpart, p.theta, p.ekin, st, OZ,
+                                     ld);
+                pw::launch_resid_precond(gen ? OZ : Z, ld, HZ, ld, c->sp.kin, npw, mb, p.theta, p.ekin,
+                                         (S *)nullptr, 0, p.rpart, p.res, st);
                 tm.end(PhaseTimer::kVec, e);
             }
             PW_HIP(hipMemcpyAsync(hres.data(), p.res, sizeof(double) * mb, hipMemcpyDeviceToHost, st));
@@ -458,14 +503,23 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
             S *W = Z + (int64_t)wcol * ld;
             {
                 auto e = tm.begin();
-                pw::launch_precond_map(Z, ld, HZ, ld, c->sp.kin, npw, p.theta, p.ekin, p.act, na, W, ld, st);
+                pw::launch_precond_map(gen ? OZ : Z, ld, HZ, ld, c->sp.kin, npw, p.theta, p.ekin, p.act,
+                                       na, W, ld, st);
                 tm.end(PhaseTimer::kVec, e);
             }
-            // constraint to previous blocks, then orthogonal to [X P] (twice) and orthonormal
-            project_out(c, p, tm, (const S *)X, ldx, b0, W, ld, na);
+            // constraint to previous blocks, then orthogonal to [X P] (twice) and orthonormal;
+            // generalized form: O W is formed after the first projection and then carried
+            S *OW = gen ? OZ + (int64_t)wcol * ld : nullptr;
+            project_out(c, p, tm, (const S *)X, ldx, b0, W, ld, na, OXprev, ld, (S *)nullptr);
             for (int pass = 0; pass < 2; ++pass) {
-                project_out(c, p, tm, (const S *)Z, ld, wcol, W, ld, na);
-                cholqr(c, p, tm, W, ld, na);
+                project_out(c, p, tm, (const S *)Z, ld, wcol, W, ld, na, (const S *)OZ, ld,
+                            pass ? OW : nullptr);
+                if (gen && pass == 0) {
+                    auto e = tm.begin();
+                    apply_O(c, p, m, W, ld, OW, ld, na);
+                    tm.end(PhaseTimer::kApply, e);
+                }
+                cholqr(c, p, tm, W, ld, na, OW);
             }
             {
                 auto e = tm.begin();
@@ -509,11 +563,15 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
                 pw::launch_gemm_nn(Z, ld, p.Cc, 3 * m, npw, nz, mb + na, 1.0, 0.0, p.Z[1 - cur], ld, st);
                 pw::launch_gemm_nn(HZ, ld, p.Cc, 3 * m, npw, nz, mb + na, 1.0, 0.0, p.HZ[1 - cur], ld,
                                    st);
+                if (gen)
+                    pw::launch_gemm_nn(OZ, ld, p.Cc, 3 * m, npw, nz, mb + na, 1.0, 0.0, p.OZ[1 - cur], ld,
+                                       st);
                 tm.end(PhaseTimer::kGemm, e);
             }
             cur = 1 - cur;
             Z = p.Z[cur];
             HZ = p.HZ[cur];
+            if (gen) OZ = p.OZ[cur];
             np = na;
         }
         const bool converged = converged_it >= 0;
@@ -522,6 +580,7 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
         // store the converged columns of the block
         pw::launch_copy_cols(Z, ld, X + (int64_t)b0 * ldx, ldx, npw, keep, st);
         pw::launch_copy_cols(HZ, ld, p.HXall + (int64_t)b0 * ld, ld, npw, keep, st);
+        if (gen) pw::launch_copy_cols(OZ, ld, p.OXall + (int64_t)b0 * ld, ld, npw, keep, st);
         b0 += keep;
     }
 
@@ -534,9 +593,18 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
         pw::launch_copy_cols(p.T, ld, X, ldx, npw, M, st);
         pw::launch_gemm_nn(p.HXall, ld, p.U, M, npw, M, M, 1.0, 0.0, p.T, ld, st);
         pw::launch_copy_cols(p.T, ld, p.HXall, ld, npw, M, st);
-        pw::launch_band_dots(X, ldx, p.HXall, ld, c->sp.kin, npw, M, p.rpart, p.theta, p.ekin, st);
-        pw::launch_resid_precond(X, ldx, p.HXall, ld, c->sp.kin, npw, M, p.theta, p.ekin, (S *)nullptr, 0,
-                                 p.rpart, p.res, st);
+        if (p.OXall && c->d_Q) {
+            pw::launch_gemm_nn(p.OXall, ld, p.U, M, npw, M, M, 1.0, 0.0, p.T, ld, st);
+            pw::launch_copy_cols(p.T, ld, p.OXall, ld, npw, M, st);
+            pw::launch_band_dots(X, ldx, p.HXall, ld, c->sp.kin, npw, M, p.rpart, p.theta, p.ekin, st,
+                                 p.OXall, ld);
+            pw::launch_resid_precond(p.OXall, ld, p.HXall, ld, c->sp.kin, npw, M, p.theta, p.ekin,
+                                     (S *)nullptr, 0, p.rpart, p.res, st);
+        } else {
+            pw::launch_band_dots(X, ldx, p.HXall, ld, c->sp.kin, npw, M, p.rpart, p.theta, p.ekin, st);
+            pw::launch_resid_precond(X, ldx, p.HXall, ld, c->sp.kin, npw, M, p.theta, p.ekin, (S *)nullptr,
+                                     0, p.rpart, p.res, st);
+        }
         tm.end(PhaseTimer::kFinal, ef);
     }
     PW_HIP(hipEventRecord(t_end, st));
@@ -616,6 +684,7 @@ void init_basis(pw_ctx_s *c, const double cell[9], const double kfrac[3], double
     c->d_B = nullptr;
     c->d_B32 = nullptr;
     c->d_D = nullptr;
+    c->d_Q = nullptr;
     c->d_v = nullptr;
     c->d_v32 = nullptr;
     c->d_qvec = nullptr;
@@ -778,9 +847,11 @@ void set_projectors(pw_ctx_s *c, int natom, const double *pos, int nlm, const in
     c->dev_free(c->d_B);
     c->dev_free(c->d_B32);
     c->dev_free(c->d_D);
+    c->dev_free(c->d_Q);
     c->d_B = nullptr;
     c->d_B32 = nullptr;
     c->d_D = nullptr;
+    c->d_Q = nullptr;   // the overlap is defined on the projectors: cleared with them
     c->natom = c->nlm = 0;
     if (natom == 0 || nlm == 0) return;
     PW_REQUIRE(pos && lm && D, PW_ERR_ARG, "null projector argument");
@@ -810,6 +881,20 @@ void set_projectors(pw_ctx_s *c, int natom, const double *pos, int nlm, const in
     c->dev_free(d_lm);
     c->natom = natom;
     c->nlm = nlm;
+}
+
+void set_overlap(pw_ctx_s *c, const double *q) {
+    require_basis(c);
+    require_device(c);
+    c->dev_free(c->d_Q);
+    c->d_Q = nullptr;
+    if (!q) return;
+    const int np = c->nproj();
+    PW_REQUIRE(np > 0, PW_ERR_STATE, "the overlap needs projectors (pw_set_projectors)");
+    for (int i = 0; i < np; ++i)
+        PW_REQUIRE(std::isfinite(q[i]) && q[i] >= 0.0, PW_ERR_ARG, "overlap coefficients must be finite and >= 0");
+    c->d_Q = c->dev_alloc<double>(np);
+    PW_HIP(hipMemcpy(c->d_Q, q, np * sizeof(double), hipMemcpyHostToDevice));
 }
 
 template <class F>
@@ -955,6 +1040,14 @@ pw_status pw_set_projectors(pw_ctx c, int32_t natom, const double *pos, int32_t 
     });
 }
 
+pw_status pw_set_overlap(pw_ctx c, const double *q) {
+    return guard(c, [&] {
+        if (c->device >= 0) PW_HIP(hipSetDevice(c->device));
+        set_overlap(c, q);
+        return PW_OK;
+    });
+}
+
 pw_status pw_workspace_size(pw_ctx c, int32_t nbands, int32_t block, pw_precision prec, size_t *bytes) {
     return guard(c, [&] {
         require_basis(c);
@@ -986,27 +1079,45 @@ pw_status pw_set_workspace(pw_ctx c, void *dptr, size_t bytes) {
     });
 }
 
-pw_status pw_apply_H(pw_ctx c, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nb,
-                     pw_precision prec) {
+// shared body of pw_apply_H and pw_apply_O
+static pw_status apply_entry(pw_ctx c, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nb,
+                             pw_precision prec, bool overlap) {
     return guard(c, [&] {
         require_precision(prec);
         require_basis(c);
         PW_REQUIRE(X && Y, PW_ERR_ARG, "null block");
         PW_REQUIRE(nb >= 0, PW_ERR_ARG, "negative column count");
         PW_REQUIRE(ldx >= c->npw && ldy >= c->npw, PW_ERR_ARG, "leading dimension < npw");
+        PW_REQUIRE(!overlap || c->d_Q, PW_ERR_STATE, "pw_set_overlap has not been called");
         if (nb == 0) return PW_OK;
         const int chunk = c->plan_block > 0 ? c->plan_block : 1;
         if (prec != PW_PREC_FP64) {
             Plan<pw::cf> p = ready_plan<pw::cf>(c, std::max(c->plan_nbands, 1), chunk);
             ensure_mixed_tables(c);
             c->proj_bf16 = prec == PW_PREC_MIXED_BF16;
-            apply_H(c, p, chunk, static_cast<const pw::cf *>(X), ldx, static_cast<pw::cf *>(Y), ldy, nb);
+            auto Xc = static_cast<const pw::cf *>(X);
+            auto Yc = static_cast<pw::cf *>(Y);
+            if (overlap) apply_O(c, p, chunk, Xc, ldx, Yc, ldy, nb);
+            else apply_H(c, p, chunk, Xc, ldx, Yc, ldy, nb);
         } else {
             Plan<cd> p = ready_plan<cd>(c, std::max(c->plan_nbands, 1), chunk);
-            apply_H(c, p, chunk, static_cast<const cd *>(X), ldx, static_cast<cd *>(Y), ldy, nb);
+            auto Xc = static_cast<const cd *>(X);
+            auto Yc = static_cast<cd *>(Y);
+            if (overlap) apply_O(c, p, chunk, Xc, ldx, Yc, ldy, nb);
+            else apply_H(c, p, chunk, Xc, ldx, Yc, ldy, nb);
         }
         return PW_OK;
     });
+}
+
+pw_status pw_apply_H(pw_ctx c, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nb,
+                     pw_precision prec) {
+    return apply_entry(c, X, ldx, Y, ldy, nb, prec, false);
+}
+
+pw_status pw_apply_O(pw_ctx c, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nb,
+                     pw_precision prec) {
+    return apply_entry(c, X, ldx, Y, ldy, nb, prec, true);
 }
 
 pw_status pw_lobpcg_solve(pw_ctx c, int32_t nbands, int32_t block, double tol, int32_t max_iter,

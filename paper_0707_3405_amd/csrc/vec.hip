@@ -39,23 +39,31 @@ __device__ void wg_reduce(double (&v)[NV], double *red) {
     for (int q = 0; q < NV; ++q) v[q] = red[q * kThreads];
 }
 
-// Rayleigh quotient pieces per (chunk, band): Re(x^H Hx), sum T|x|^2, |x|^2.
+// Rayleigh quotient pieces per (chunk, band): Re(x^H Hx), sum T|x|^2 and the
+// norm: |x|^2, or Re(x^H Ox) in the generalized form (OX given).
 template <class S>
 __global__ void __launch_bounds__(kThreads)
     k_band_dots(const S *__restrict__ X, int64_t ldx, const S *__restrict__ HX, int64_t ldhx,
-                const double *__restrict__ kin, int64_t npw, int nb, double *__restrict__ part) {
+                const double *__restrict__ kin, int64_t npw, int nb, double *__restrict__ part,
+                const S *__restrict__ OX, int64_t ldox) {
     __shared__ double red[3 * kThreads];
     const int c = blockIdx.x, b = blockIdx.y;
     const int64_t r0 = (int64_t)c * kChunk, r1 = min(npw, r0 + kChunk);
     const S *x = X + (int64_t)b * ldx;
     const S *h = HX + (int64_t)b * ldhx;
+    const S *o = OX ? OX + (int64_t)b * ldox : nullptr;
     double v[3] = {0.0, 0.0, 0.0};
     for (int64_t r = r0 + threadIdx.x; r < r1; r += kThreads) {
         const cd a = widen(x[r]), hb = widen(h[r]);
         const double n2 = a.x * a.x + a.y * a.y;
         v[0] += a.x * hb.x + a.y * hb.y;
         v[1] += kin[r] * n2;
-        v[2] += n2;
+        if (o) {
+            const cd ob = widen(o[r]);
+            v[2] += a.x * ob.x + a.y * ob.y;
+        } else {
+            v[2] += n2;
+        }
     }
     wg_reduce<3>(v, red);
     if (threadIdx.x == 0) {
@@ -248,20 +256,23 @@ size_t resid_part_elems(int64_t npw, int nb) {
 
 template <class S>
 void band_dots_impl(const S *X, int64_t ldx, const S *HX, int64_t ldhx, const double *kin,
-                    int64_t npw, int nb, double *part, double *theta, double *ekin, hipStream_t st) {
+                    int64_t npw, int nb, double *part, double *theta, double *ekin, hipStream_t st,
+                    const S *OX, int64_t ldox) {
     const int nchunk = (int)((npw + kChunk - 1) / kChunk);
     hipLaunchKernelGGL(k_band_dots<S>, dim3(nchunk, nb), dim3(kThreads), 0, st, X, ldx, HX, ldhx, kin,
-                       npw, nb, part);
+                       npw, nb, part, OX, ldox);
     hipLaunchKernelGGL(k_band_dots_final, dim3(1), dim3(256), 0, st, part, nchunk, nb, theta, ekin);
     PW_HIP(hipGetLastError());
 }
 void launch_band_dots(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
-                      int64_t npw, int nb, double *part, double *theta, double *ekin, hipStream_t st) {
-    band_dots_impl(X, ldx, HX, ldhx, kin, npw, nb, part, theta, ekin, st);
+                      int64_t npw, int nb, double *part, double *theta, double *ekin, hipStream_t st,
+                      const cd *OX, int64_t ldox) {
+    band_dots_impl(X, ldx, HX, ldhx, kin, npw, nb, part, theta, ekin, st, OX, ldox);
 }
 void launch_band_dots(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, const double *kin,
-                      int64_t npw, int nb, double *part, double *theta, double *ekin, hipStream_t st) {
-    band_dots_impl(X, ldx, HX, ldhx, kin, npw, nb, part, theta, ekin, st);
+                      int64_t npw, int nb, double *part, double *theta, double *ekin, hipStream_t st,
+                      const cf *OX, int64_t ldox) {
+    band_dots_impl(X, ldx, HX, ldhx, kin, npw, nb, part, theta, ekin, st, OX, ldox);
 }
 
 template <class S>

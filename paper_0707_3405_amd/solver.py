@@ -11,11 +11,12 @@ class PlaneWaveProblem:
 
     `cell`: 3x3 rows = lattice vectors (bohr); `kfrac`: reduced k; `ecut`: Ha;
     `n`: cubic FFT size; `vgrid`: V(r) on the n^3 grid (Ha, C order);
-    `pos`/`lm`/`D`: Kleinman-Bylander projector data (optional).
+    `pos`/`lm`/`D`: Kleinman-Bylander projector data (optional); `q`: overlap
+    coefficients per projector (generalized form H psi = eps O psi; optional).
     """
 
     def __init__(self, cell, kfrac, ecut, n, vgrid, pos=None, lm=(), D=None, nbands=1,
-                 block=1, device=0, stream=None, prec=PW_PREC_FP64):
+                 block=1, device=0, stream=None, prec=PW_PREC_FP64, q=None):
         import torch
         self.torch = torch
         self.ctx = Context(device, stream)
@@ -23,17 +24,20 @@ class PlaneWaveProblem:
         self.ctx.set_local_potential(np.asarray(vgrid, np.float64))
         if pos is not None and len(lm):
             self.ctx.set_projectors(pos, lm, D)
+        if q is not None:
+            self.ctx.set_overlap(q)
         self.nbands, self.block = nbands, min(block, nbands)
         self.prec = prec
         self.ws = self.ctx.alloc_workspace(nbands, self.block, prec)
         self.device = device
 
     @classmethod
-    def from_workload(cls, w, device=0, stream=None, nbands=None, block=None, prec=PW_PREC_FP64):
+    def from_workload(cls, w, device=0, stream=None, nbands=None, block=None, prec=PW_PREC_FP64,
+                      q=None):
         return cls(w.cell, w.kfrac, w.ecut, w.n, w.vgrid, w.pos if w.lm else None, w.lm, w.D,
                    nbands=w.nbands if nbands is None else nbands,
                    block=w.block if block is None else block, device=device, stream=stream,
-                   prec=prec)
+                   prec=prec, q=q)
 
     def empty_block(self, nb):
         return self.torch.zeros((nb, self.npw), dtype=self.torch.complex128,
@@ -42,6 +46,11 @@ class PlaneWaveProblem:
     def apply_H(self, X):
         Y = self.torch.empty_like(X)
         self.ctx.apply_H(X, Y)
+        return Y
+
+    def apply_O(self, X):
+        Y = self.torch.empty_like(X)
+        self.ctx.apply_O(X, Y)
         return Y
 
     def solve(self, tol, max_iter=300, X=None, allow_not_converged=False, prec=None):
