@@ -241,6 +241,14 @@ pw_status pw_gram_mixed(pw_ctx ctx, const void *A, int64_t lda, const void *B, i
 pw_status pw_block_update_mixed(pw_ctx ctx, const void *A, int64_t lda, const void *C,
                                 int64_t ldc, int64_t K, int32_t p, int32_t q, double alpha,
                                 double beta, void *Y, int64_t ldy);
+/* CholQR factor of a block (row a11 of the hot path; the orthonormalisation
+ * W <- W R^-1 of the LOBPCG iteration, sec. 3.2): for G = R^H R (device,
+ * Hermitian positive definite n x n, ldg >= n; the Hermitian part of the
+ * stored matrix is used) write R^-1 (upper triangular, zeros below the
+ * diagonal, positive real diagonal) to Rinv (device, ldr >= n).  1 <= n <= 64.
+ * A tiny diagonal shift (1e-15 n max_i G_ii) is added; a non-positive pivot
+ * returns PW_ERR_NUMERIC.  Synchronises the stream. */
+pw_status pw_chol_inv(pw_ctx ctx, const void *G, int64_t ldg, int32_t n, void *Rinv, int64_t ldr);
 /* Lowest k eigenpairs of a Hermitian n x n matrix A (lda >= n) -- the small
  * dense Rayleigh-Ritz eigenproblem of Algorithm 1 step 4 and of the final
  * Rayleigh-Ritz (sec. 3.2, sec. 4.2).  Householder tridiagonalisation,

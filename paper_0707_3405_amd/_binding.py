@@ -27,7 +27,7 @@ EXPORTS = ("pw_create", "pw_destroy", "pw_last_error", "pw_init_basis", "pw_fft_
            "pw_workspace_size", "pw_set_workspace", "pw_apply_H", "pw_lobpcg_solve",
            "pw_get_residuals", "pw_get_stats", "pw_gram", "pw_block_update", "pw_small_eigh",
            "pw_residuals", "pw_gram_mixed", "pw_block_update_mixed", "pw_lobpcg_solve_batch",
-           "pw_density", "pw_set_overlap", "pw_apply_O")
+           "pw_density", "pw_set_overlap", "pw_apply_O", "pw_chol_inv")
 
 
 class PWError(RuntimeError):
@@ -81,6 +81,7 @@ def load_library():
         "pw_apply_H": (ctypes.c_int, [P, P, I64, P, I64, I32, ctypes.c_int]),
         "pw_apply_O": (ctypes.c_int, [P, P, I64, P, I64, I32, ctypes.c_int]),
         "pw_set_overlap": (ctypes.c_int, [P, P]),
+        "pw_chol_inv": (ctypes.c_int, [P, P, I64, I32, P, I64]),
         "pw_lobpcg_solve": (ctypes.c_int, [P, I32, I32, D, I32, ctypes.c_int, P, I64, I32, P]),
         "pw_get_residuals": (ctypes.c_int, [P, P]),
         "pw_get_stats": (ctypes.c_int, [P, ctypes.POINTER(PWStats)]),
@@ -292,6 +293,10 @@ class Context:
 
     def small_eigh(self, A, n, k, w, V):
         self._check(self.lib.pw_small_eigh(self.h, _ptr(A), _ld(A), n, k, _ptr(w), _ptr(V), _ld(V)))
+
+    def chol_inv(self, G, n, Rinv):
+        """Rinv = R^-1 for G = R^H R (device complex128 tensors, [col][row] storage)."""
+        self._check(self.lib.pw_chol_inv(self.h, _ptr(G), _ld(G), n, _ptr(Rinv), _ld(Rinv)))
 
     def residuals(self, X, HX, nb, theta, res, W=None):
         self._check(self.lib.pw_residuals(self.h, _ptr(X), _ld(X), _ptr(HX), _ld(HX), nb, _ptr(theta),

@@ -32,85 +32,115 @@ __device__ double block_sum(double v, double *red) {
     return s;
 }
 
-// ---- Cholesky + inverse of the factor (n <= 64, in LDS) ---------------------
+// ---- Cholesky + inverse of the factor (n <= 64, in registers) -----------------
+// Gaussian elimination without pivoting on the augmented matrix [G | I]: the
+// row operations that reduce G (Hermitian positive definite, G = L D L^H) to
+// the upper triangle D L^H turn I into L^-1; scaling row j of both by d_j^-1/2
+// gives [R | R^-H] with G = R^H R.  Step j subtracts conj(g_ja) / d_j times the
+// (unscaled) pivot row from every row a > j, so the only communication is the
+// pivot row, broadcast through LDS (double buffered: one barrier per step).
+// 256 threads as a 16 x 16 grid; thread (ti, tj) holds the 4 x 4 tiles rows
+// 4 ti .., columns 4 tj .. of G (upper part used) and of the augmented half.
+// Rows and columns >= n are padded with the identity (inert pivots).
 constexpr int kCholMax = 64;
 
 __global__ void __launch_bounds__(256) k_chol_inv(const cd *__restrict__ G, int64_t ldg, int n,
                                                   cd *__restrict__ Rinv, int64_t ldr, int *status) {
-    __shared__ cd Rs[kCholMax][kCholMax + 1];   // G, then R (upper), [row][col]
-    __shared__ cd Xs[kCholMax][kCholMax + 1];   // R^-1
-    __shared__ cd part[256];
-    __shared__ double red[4];
-    const int t = threadIdx.x;
-    for (int i = t; i < n * n; i += blockDim.x) {
-        const int r = i % n, c = i / n;
-        Rs[r][c] = G[(int64_t)c * ldg + r];
-    }
+    __shared__ cd pg[2][kCholMax];   // pivot row of G (columns j .. 63 meaningful)
+    __shared__ cd pu[2][kCholMax];   // pivot row of the augmented half (columns 0 .. j)
+    __shared__ double diag[kCholMax];
+    const int t = threadIdx.x, ti = t >> 4, tj = t & 15;
+    const int a0 = 4 * ti, b0 = 4 * tj;
+    cd g[4][4], u[4][4];
+#pragma unroll
+    for (int ia = 0; ia < 4; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+            const int a = a0 + ia, b = b0 + ib;
+            cd v = {a == b ? 1.0 : 0.0, 0.0};
+            if (a < n && b < n) {   // Hermitian part of the stored Gram
+                const cd x = G[(int64_t)b * ldg + a], y = G[(int64_t)a * ldg + b];
+                v = cd{0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
+                if (a == b) v.y = 0.0;
+            }
+            g[ia][ib] = v;
+            u[ia][ib] = cd{a == b ? 1.0 : 0.0, 0.0};
+            if (a == b) diag[a] = v.x;
+            if (a == 0) {
+                pg[0][b] = v;
+                pu[0][b] = u[ia][ib];
+            }
+        }
     __syncthreads();
-    double dm = 0.0;
-    for (int i = t; i < n; i += blockDim.x) dm = fmax(dm, Rs[i][i].x);
-    for (int off = 32; off > 0; off >>= 1) dm = fmax(dm, __shfl_xor(dm, off));
-    if ((t & 63) == 0) red[t >> 6] = dm;
-    __syncthreads();
-    const double dmax = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    double dmax = 0.0;
+    for (int i = 0; i < n; ++i) dmax = fmax(dmax, diag[i]);
     // a tiny diagonal shift keeps a numerically semi-definite Gram factorable
     const double shift = 1e-15 * dmax * n;
     bool fail = false;
-    // right-looking Cholesky; the trailing update uses the unscaled pivot row
-    // (G_ab -= conj(g_ja) g_jb / d), so each step needs one barrier
     for (int j = 0; j < n; ++j) {
-        double d = Rs[j][j].x + shift;
+        const cd *prg = pg[j & 1], *pru = pu[j & 1];
+        double d = prg[j].x + shift;
         if (!(d > 1e-300) || !isfinite(d)) {
             fail = true;
             d = 1.0;
         }
         const double inv_d = 1.0 / d;
-        const int m = n - j - 1;
-        for (int i = t; i < m * m; i += blockDim.x) {
-            const int a = j + 1 + i % m, b = j + 1 + i / m;
-            if (b >= a) {
-                const cd pr = cmulz(cconj(Rs[j][a]), Rs[j][b]);
-                Rs[a][b].x -= pr.x * inv_d;
-                Rs[a][b].y -= pr.y * inv_d;
-            }
+        cd ma[4];
+#pragma unroll
+        for (int ia = 0; ia < 4; ++ia) {
+            const int a = a0 + ia;
+            const cd p = prg[a];
+            ma[ia] = a > j ? cd{p.x * inv_d, -p.y * inv_d} : cd{0.0, 0.0};
         }
-        __syncthreads();
-        // row j of R: g_jb / sqrt(d); every thread has finished reading row j
+        cd gb[4], ub[4];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+            gb[ib] = prg[b0 + ib];
+            ub[ib] = pru[b0 + ib];
+        }
+#pragma unroll
+        for (int ia = 0; ia < 4; ++ia)
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) {
+                const int a = a0 + ia, b = b0 + ib;
+                if (b >= a) {   // columns b > j only, since a > j (ma = 0 otherwise)
+                    const cd pr = cmulz(ma[ia], gb[ib]);
+                    g[ia][ib].x -= pr.x;
+                    g[ia][ib].y -= pr.y;
+                }
+                const cd pu2 = cmulz(ma[ia], ub[ib]);
+                u[ia][ib].x -= pu2.x;
+                u[ia][ib].y -= pu2.y;
+            }
+        // row j of R^-H: the owners scale their augmented row
         const double isd = 1.0 / sqrt(d);
-        for (int c = j + 1 + t; c < n; c += blockDim.x) Rs[j][c] = cd{Rs[j][c].x * isd, Rs[j][c].y * isd};
-        if (t == 0) Rs[j][j] = cd{d * isd, 0.0};
-    }
-    __syncthreads();
-    // R^-1 by rows from the bottom; 4 threads per column share the sum
-    //   X_ic = (delta_ic - sum_{k=i+1..c} R_ik X_kc) / R_ii
-    const int c = t & 63, p = t >> 6;
-    for (int i = n - 1; i >= 0; --i) {
-        double sr = 0.0, si = 0.0;
-        if (c < n && c > i)
-            for (int kk = i + 1 + p; kk <= c; kk += 4) {
-                const cd pr = cmulz(Rs[i][kk], Xs[kk][c]);
-                sr += pr.x;
-                si += pr.y;
-            }
-        part[t] = cd{sr, si};
-        __syncthreads();
-        if (p == 0 && c < n) {
-            if (c < i) {
-                Xs[i][c] = cd{0.0, 0.0};
-            } else {
-                const double tr = (c == i ? 1.0 : 0.0) - (part[c].x + part[64 + c].x + part[128 + c].x + part[192 + c].x);
-                const double ti = -(part[c].y + part[64 + c].y + part[128 + c].y + part[192 + c].y);
-                const double inv = 1.0 / Rs[i][i].x;
-                Xs[i][c] = cd{tr * inv, ti * inv};
-            }
+#pragma unroll
+        for (int ia = 0; ia < 4; ++ia)
+            if (a0 + ia == j)
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) u[ia][ib] = cd{u[ia][ib].x * isd, u[ia][ib].y * isd};
+        // the next pivot row (final after this step) to the other buffer
+        if (j + 1 < n) {
+#pragma unroll
+            for (int ia = 0; ia < 4; ++ia)
+                if (a0 + ia == j + 1)
+#pragma unroll
+                    for (int ib = 0; ib < 4; ++ib) {
+                        pg[(j + 1) & 1][b0 + ib] = g[ia][ib];
+                        pu[(j + 1) & 1][b0 + ib] = u[ia][ib];
+                    }
         }
         __syncthreads();
     }
-    for (int i = t; i < n * n; i += blockDim.x) {
-        const int r = i % n, cc = i / n;
-        Rinv[(int64_t)cc * ldr + r] = Xs[r][cc];
-    }
-    if (t == 0 && fail) atomicOr(status, 1);
+    // R^-1 (upper) = (R^-H)^H
+#pragma unroll
+    for (int ia = 0; ia < 4; ++ia)
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+            const int a = a0 + ia, c = b0 + ib;
+            if (a < n && c < n) Rinv[(int64_t)a * ldr + c] = cd{u[ia][ib].x, -u[ia][ib].y};
+        }
+    if (fail && t == 0) atomicOr(status, 1);
 }
 
 // ---- Hermitian eigensolver ---------------------------------------------------

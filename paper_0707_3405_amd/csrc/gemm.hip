@@ -263,18 +263,30 @@ __global__ void __launch_bounds__(kThreads)
             }
 }
 
+// Sum of the split-K partials: 64 outputs per workgroup, each wave adding
+// every fourth split (s = wave, wave + 4, ...), the four wave sums combined in
+// wave order (fixed order: deterministic).
 template <class T>
-__global__ void k_reduce_parts(const cpx<T> *__restrict__ part, int nsplit, int p, int q, cd *C,
-                               int64_t ldc, const double *__restrict__ scale_row, double beta) {
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= (int64_t)p * q) return;
-    const int i = (int)(idx % p), j = (int)(idx / p);
+__global__ void __launch_bounds__(256)
+    k_reduce_parts(const cpx<T> *__restrict__ part, int nsplit, int p, int q, cd *C, int64_t ldc,
+                   const double *__restrict__ scale_row, double beta) {
+    __shared__ cd red[4][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t n = (int64_t)p * q;
+    const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
     double sr = 0.0, si = 0.0;
-    for (int s = 0; s < nsplit; ++s) {
-        const cpx<T> v = part[(size_t)s * p * q + idx];
-        sr += (double)v.x;
-        si += (double)v.y;
-    }
+    if (idx < n)
+        for (int s = wave; s < nsplit; s += 4) {
+            const cpx<T> v = part[(size_t)s * n + idx];
+            sr += (double)v.x;
+            si += (double)v.y;
+        }
+    red[wave][lane] = cd{sr, si};
+    __syncthreads();
+    if (wave != 0 || idx >= n) return;
+    sr = ((red[0][lane].x + red[1][lane].x) + red[2][lane].x) + red[3][lane].x;
+    si = ((red[0][lane].y + red[1][lane].y) + red[2][lane].y) + red[3][lane].y;
+    const int i = (int)(idx % p), j = (int)(idx / p);
     if (scale_row) {
         sr *= scale_row[i];
         si *= scale_row[i];
@@ -453,8 +465,8 @@ void gemm_tn_impl(const cpx<T> *A, int64_t lda, const cpx<T> *B, int64_t ldb, in
     hipLaunchKernelGGL((k_gemm_tn_lds<T, BF>), dim3(total), dim3(kThreads), 0, st, A, lda, B, ldb, K, p, q,
                        kchunk, tiles_m, tiles_n, ns, pt);
     const int64_t n = (int64_t)p * q;
-    hipLaunchKernelGGL(k_reduce_parts<T>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, pt,
-                       ns, p, q, C, ldc, scale_row, beta);
+    hipLaunchKernelGGL(k_reduce_parts<T>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, pt, ns, p,
+                       q, C, ldc, scale_row, beta);
     PW_HIP(hipGetLastError());
 }
 

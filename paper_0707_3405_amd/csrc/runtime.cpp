@@ -1255,6 +1255,21 @@ pw_status pw_small_eigh(pw_ctx c, void *A, int64_t lda, int32_t n, int32_t k, vo
     });
 }
 
+pw_status pw_chol_inv(pw_ctx c, const void *G, int64_t ldg, int32_t n, void *Rinv, int64_t ldr) {
+    return guard(c, [&] {
+        require_device(c);
+        PW_REQUIRE(G && Rinv, PW_ERR_ARG, "null argument");
+        PW_REQUIRE(n >= 1 && n <= 64 && ldg >= n && ldr >= n, PW_ERR_ARG, "need 1 <= n <= 64");
+        PW_REQUIRE(c->d_status, PW_ERR_STATE, "pw_init_basis has not been called");
+        PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
+        pw::launch_chol_inv_f64(static_cast<const cd *>(G), ldg, n, static_cast<cd *>(Rinv), ldr,
+                                c->d_status, c->stream);
+        const int s = read_status(c);
+        PW_REQUIRE(!(s & 1), PW_ERR_NUMERIC, "Cholesky breakdown (not positive definite)");
+        return PW_OK;
+    });
+}
+
 pw_status pw_residuals(pw_ctx c, const void *X, int64_t ldx, const void *HX, int64_t ldhx,
                        int32_t nb, void *theta, void *res, void *W, int64_t ldw) {
     return guard(c, [&] {
