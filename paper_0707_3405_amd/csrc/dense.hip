@@ -403,7 +403,8 @@ __global__ void __launch_bounds__(1024)
     __shared__ cd vs[NR];        // reflector, zero outside rows j+1..n-1
     __shared__ cd ws[NR];        // w, zero outside rows j+1..n-1
     __shared__ cd pr[2][NR];     // row sums of y, one per DPP row of a half-wave
-    __shared__ cd pc[32][NR];    // column sums of y, one per half-wave
+    __shared__ cd pc[32][NR + 1];   // column sums of y, one per half-wave (padded: the
+                                    // four readers of a row hit different banks)
     __shared__ double sv[16];    // per-wave partials of Re(v^H A v)
     __shared__ cd s_tau;
     const int t = threadIdx.x, tj = t & 31, ti = t >> 5, wave = t >> 6, lane = t & 63;
@@ -456,10 +457,10 @@ __global__ void __launch_bounds__(1024)
             } else {
                 const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
                 beta = alpha.x >= 0.0 ? -nrm : nrm;
-                tau = cd{(beta - alpha.x) / beta, -alpha.y / beta};
                 const double dr = alpha.x - beta, di = alpha.y;
-                const double den = dr * dr + di * di;
-                scale = cd{dr / den, -di / den};
+                const double ib = 1.0 / beta, iden = 1.0 / (dr * dr + di * di);   // independent
+                tau = cd{-dr * ib, -alpha.y * ib};
+                scale = cd{dr * iden, -di * iden};
             }
             const bool reflect = !(tau.x == 0.0 && tau.y == 0.0);
             for (int r = j + 1 + lane; r < n; r += 64) {

@@ -36,6 +36,8 @@
 // v_mfma_f32_16x16x16_bf16 with FP32 accumulation (the split-bfloat16
 // scheme of Henry, Tang and Heinecke, ARITH 2019); the dropped lo*lo term and
 // the rounding of lo leave a relative error near 2^-16 per product.
+#include <atomic>
+
 #include "pw_internal.h"
 
 namespace pw {
@@ -426,9 +428,147 @@ __global__ void __launch_bounds__(kThreads)
             }
 }
 
+// NN with the rows dealt out in 16-row blocks: workgroup (g, tn) takes row
+// blocks [g nblk / G, (g + 1) nblk / G) (at most kNnMaxRb of them) and the 64
+// columns of tile tn; its four waves each own 16 columns and every row block.
+// G is chosen so that the grid fills whole rounds of resident workgroups
+// instead of spilling a few 64-row tiles into an extra round (K = 34181 gives
+// 535 tiles of 64 rows for 512 resident workgroups).  Same LDS staging and
+// double buffering as k_gemm_nn_lds.
+constexpr int kNnMaxRb = 5;
+template <class T>
+__global__ void __launch_bounds__(kThreads)
+    k_gemm_nn_rows(const cpx<T> *__restrict__ A, int64_t lda, const cd *__restrict__ Cm, int64_t ldc,
+                   int64_t K, int p, int q, double alpha, double beta, cpx<T> *Y, int64_t ldy,
+                   int groups) {
+    using M = Mfma<T>;
+    using v4 = typename M::v4;
+    constexpr int KB = 16, NRW = 16 * kNnMaxRb, LDA = NRW + 1, LDCC = KB + 1;
+    __shared__ cpx<T> sA[2][KB * LDA], sC[2][kTile * LDCC];
+    const int lid = xcd_logical(blockIdx.x, gridDim.x);
+    const int g = lid % groups, tn = lid / groups;
+    const int64_t nblk = (K + 15) / 16;
+    const int64_t rb0 = nblk * g / groups, rb1 = nblk * (g + 1) / groups;
+    const int nrb = (int)(rb1 - rb0);   // 1 .. kNnMaxRb (host guarantees)
+    const int64_t rbase = rb0 * 16;
+    const int cbase = tn * kTile;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int li = lane & 15, gq = lane >> 4;
+
+    // global -> LDS: A instruction (u, h) covers column kb + 4 wave + u, rows
+    // 64 h + lane; C instruction u covers columns 16 wave + 4u + gq, k rows li
+    const int nrows = 16 * nrb;
+    const bool arow0 = lane < nrows && rbase + lane < K;
+    const bool arow1 = 64 + lane < nrows && rbase + 64 + lane < K;
+    const cpx<T> *Arow0 = A + (arow0 ? rbase + lane : 0);
+    const cpx<T> *Arow1 = A + (arow1 ? rbase + 64 + lane : 0);
+    const cd *Cc[4];
+    bool cok[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int col = cbase + 16 * wave + 4 * u + gq;
+        cok[u] = col < q;
+        Cc[u] = Cm + (int64_t)(cok[u] ? col : 0) * ldc;
+    }
+    cpx<T> ra0[4], ra1[4], rc[4];
+    auto gload = [&](int kb) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int kk = kb + 4 * wave + u;
+            const int64_t ko = (int64_t)(kk < p ? kk : 0) * lda;
+            ra0[u] = ldg_or_zero(Arow0 + ko, arow0 && kk < p);
+            ra1[u] = ldg_or_zero(Arow1 + ko, arow1 && kk < p);
+            const int kc = kb + li;
+            rc[u] = ldc_or_zero<T>(Cc[u] + (kc < p ? kc : 0), cok[u] && kc < p);
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            sA[buf][(4 * wave + u) * LDA + lane] = ra0[u];
+            if (lane < NRW - 64) sA[buf][(4 * wave + u) * LDA + 64 + lane] = ra1[u];
+            sC[buf][(16 * wave + 4 * u + gq) * LDCC + li] = rc[u];
+        }
+    };
+    // 3-multiplication complex product (as in k_gemm_nn_lds)
+    v4 t1[kNnMaxRb], t2[kNnMaxRb], t3[kNnMaxRb];
+#pragma unroll
+    for (int i = 0; i < kNnMaxRb; ++i) t1[i] = t2[i] = t3[i] = v4{0, 0, 0, 0};
+    const bool colv = cbase + 16 * wave < q;   // this wave's 16 columns (uniform per wave)
+    auto mma = [&](int buf) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const cpx<T> b = sC[buf][(16 * wave + li) * LDCC + 4 * gq + s];
+            const T bs = b.x + b.y;
+#pragma unroll
+            for (int i = 0; i < kNnMaxRb; ++i) {
+                if (i >= nrb) break;
+                const cpx<T> a = sA[buf][(4 * gq + s) * LDA + 16 * i + li];
+                t1[i] = M::op(a.x, b.x, t1[i]);
+                t2[i] = M::op(a.y, b.y, t2[i]);
+                t3[i] = M::op(a.x + a.y, bs, t3[i]);
+            }
+        }
+    };
+    if (p > 0) {   // every wave stages its share of A, also when its columns are idle
+        gload(0);
+        lstore(0);
+    }
+    __syncthreads();
+    if (p > 0) {
+        int buf = 0;
+        for (int kb = 0; kb < p; kb += KB) {
+            const bool more = kb + KB < p;
+            if (more) gload(kb + KB);
+            if (colv) mma(buf);
+            if (more) lstore(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+    }
+    // every read of A finished before the last barrier: Y == A is safe when
+    // one workgroup spans all q (each workgroup writes only its own rows)
+    if (!colv) return;
+#pragma unroll
+    for (int i = 0; i < kNnMaxRb; ++i) {
+        if (i >= nrb) break;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int64_t row = rbase + 16 * i + M::row(gq, r);
+            const int j = cbase + 16 * wave + li;
+            if (row < K && j < q) {
+                cpx<T> *y = Y + (int64_t)j * ldy + row;
+                T yr = T(alpha) * (t1[i][r] - t2[i][r]);
+                T yi = T(alpha) * (t3[i][r] - t1[i][r] - t2[i][r]);
+                if (beta != 0.0) {
+                    const cpx<T> o = *y;
+                    yr += T(beta) * o.x;
+                    yi += T(beta) * o.y;
+                }
+                *y = cpx<T>{yr, yi};
+            }
+        }
+    }
+}
+
 #ifndef PW_SPLIT_WGS
 #define PW_SPLIT_WGS 768   // target workgroup count of a split-K launch
 #endif
+// compute units of the current device (queried once per process and device)
+int device_cu_count() {
+    static std::atomic<int> cached[64];
+    int dev = 0;
+    PW_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) dev = 0;
+    int n = cached[dev].load(std::memory_order_relaxed);
+    if (!n) {
+        PW_HIP(hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev));
+        if (n <= 0) n = 256;
+        cached[dev].store(n, std::memory_order_relaxed);
+    }
+    return n;
+}
+
 int choose_split(int64_t K, int tiles) {
     int64_t ns = (PW_SPLIT_WGS + tiles - 1) / tiles;
     const int64_t kmax = (K + 255) / 256;   // chunks of at least 16 k-blocks
@@ -477,6 +617,29 @@ void gemm_nn_impl(const cpx<T> *A, int64_t lda, const cd *C, int64_t ldc, int64_
     const int tiles_m = (int)((K + kTile - 1) / kTile), tiles_n = (q + kTile - 1) / kTile;
     PW_REQUIRE(!((const void *)A == (const void *)Y) || q <= kTile, PW_ERR_ARG,
                "in-place block update needs q <= 64");
+    if constexpr (!BF) {
+        // row groups of 4-5 blocks of 16 rows, sized to whole rounds of the
+        // resident workgroups when that keeps <= 5 blocks per group
+        const int64_t nblk = (K + 15) / 16;
+        int64_t G = (nblk + 3) / 4;
+        static std::atomic<int> per_cu{0};   // resident workgroups per CU of this kernel
+        int occ = per_cu.load(std::memory_order_relaxed);
+        if (!occ) {
+            PW_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_gemm_nn_rows<T>, kThreads, 0));
+            if (occ <= 0) occ = 1;
+            per_cu.store(occ, std::memory_order_relaxed);
+        }
+        const int64_t slots = (int64_t)occ * device_cu_count();
+        const int64_t rounds = (G * tiles_n + slots - 1) / slots;
+        if (rounds > 1) {
+            const int64_t Gfit = (rounds - 1) * slots / tiles_n;
+            if (Gfit >= (nblk + kNnMaxRb - 1) / kNnMaxRb) G = Gfit;
+        }
+        hipLaunchKernelGGL(k_gemm_nn_rows<T>, dim3((unsigned)(G * tiles_n)), dim3(kThreads), 0, st, A, lda,
+                           C, ldc, K, p, q, alpha, beta, Y, ldy, (int)G);
+        PW_HIP(hipGetLastError());
+        return;
+    }
     hipLaunchKernelGGL((k_gemm_nn_lds<T, BF>), dim3(tiles_m * tiles_n), dim3(kThreads), 0, st, A, lda, C, ldc,
                        K, p, q, alpha, beta, Y, ldy, tiles_m);
     PW_HIP(hipGetLastError());
