@@ -19,6 +19,15 @@ namespace {
 __device__ __forceinline__ cd cconj(cd a) { return {a.x, -a.y}; }
 __device__ __forceinline__ cd cmulz(cd a, cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
+// 1 / d to within an ulp without the division sequence: the hardware
+// reciprocal refined by two Newton steps (d finite and normal, d > 0 here)
+__device__ __forceinline__ double rcp_nr(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(r, fma(-d, r, 1.0), r);
+    r = fma(r, fma(-d, r, 1.0), r);
+    return r;
+}
+
 // Block-wide sum of one double per thread: wave shuffles, then the wave
 // partials added in wave order by every thread (deterministic, 2 barriers).
 __device__ double block_sum(double v, double *red) {
@@ -38,24 +47,29 @@ __device__ double block_sum(double v, double *red) {
 // the upper triangle D L^H turn I into L^-1; scaling row j of both by d_j^-1/2
 // gives [R | R^-H] with G = R^H R.  Step j subtracts conj(g_ja) / d_j times the
 // (unscaled) pivot row from every row a > j, so the only communication is the
-// pivot row, broadcast through LDS (double buffered: one barrier per step).
-// 256 threads as a 16 x 16 grid; thread (ti, tj) holds the 4 x 4 tiles rows
-// 4 ti .., columns 4 tj .. of G (upper part used) and of the augmented half.
-// Rows and columns >= n are padded with the identity (inert pivots).
+// pivot row, broadcast through LDS (double buffered: one barrier per step);
+// rows stay unscaled (the augmented half ends as L^-1) and are scaled by
+// d_a^-1/2 at the end.  1024 threads as a 32 x 32 grid; thread (ti, tj) holds the 2 x 2 tiles rows
+// 2 ti .., columns 2 tj .. of G (upper part used) and of the augmented half.
+// A wave covers rows 4w .. 4w + 3 and stops updating once they are all
+// eliminated; waves of each SIMD cover rows spread over the matrix, so the
+// work per SIMD shrinks with the step.  Rows and columns >= n are padded with
+// the identity (inert pivots).
 constexpr int kCholMax = 64;
 
-__global__ void __launch_bounds__(256) k_chol_inv(const cd *__restrict__ G, int64_t ldg, int n,
-                                                  cd *__restrict__ Rinv, int64_t ldr, int *status) {
+__global__ void __launch_bounds__(1024) k_chol_inv(const cd *__restrict__ G, int64_t ldg, int n,
+                                                   cd *__restrict__ Rinv, int64_t ldr, int *status) {
     __shared__ cd pg[2][kCholMax];   // pivot row of G (columns j .. 63 meaningful)
     __shared__ cd pu[2][kCholMax];   // pivot row of the augmented half (columns 0 .. j)
     __shared__ double diag[kCholMax];
-    const int t = threadIdx.x, ti = t >> 4, tj = t & 15;
-    const int a0 = 4 * ti, b0 = 4 * tj;
-    cd g[4][4], u[4][4];
+    const int t = threadIdx.x, ti = t >> 5, tj = t & 31;
+    const int a0 = 2 * ti, b0 = 2 * tj;
+    const int wrow_last = 4 * (t >> 6) + 3;   // last row of this wave
+    cd g[2][2], u[2][2];
 #pragma unroll
-    for (int ia = 0; ia < 4; ++ia)
+    for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
+        for (int ib = 0; ib < 2; ++ib) {
             const int a = a0 + ia, b = b0 + ib;
             cd v = {a == b ? 1.0 : 0.0, 0.0};
             if (a < n && b < n) {   // Hermitian part of the stored Gram
@@ -77,6 +91,7 @@ __global__ void __launch_bounds__(256) k_chol_inv(const cd *__restrict__ G, int6
     // a tiny diagonal shift keeps a numerically semi-definite Gram factorable
     const double shift = 1e-15 * dmax * n;
     bool fail = false;
+    double dpiv[2] = {1.0, 1.0};   // pivots of this thread's rows (rows stay unscaled)
     for (int j = 0; j < n; ++j) {
         const cd *prg = pg[j & 1], *pru = pu[j & 1];
         double d = prg[j].x + shift;
@@ -84,69 +99,69 @@ __global__ void __launch_bounds__(256) k_chol_inv(const cd *__restrict__ G, int6
             fail = true;
             d = 1.0;
         }
-        const double inv_d = 1.0 / d;
-        cd ma[4];
 #pragma unroll
-        for (int ia = 0; ia < 4; ++ia) {
-            const int a = a0 + ia;
-            const cd p = prg[a];
-            ma[ia] = a > j ? cd{p.x * inv_d, -p.y * inv_d} : cd{0.0, 0.0};
-        }
-        cd gb[4], ub[4];
+        for (int ia = 0; ia < 2; ++ia)
+            if (a0 + ia == j) dpiv[ia] = d;
+        if (wrow_last > j) {   // rows below the pivot in this wave (uniform per wave)
+            const double inv_d = rcp_nr(d);
+            cd ma[2];
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
-            gb[ib] = prg[b0 + ib];
-            ub[ib] = pru[b0 + ib];
-        }
-#pragma unroll
-        for (int ia = 0; ia < 4; ++ia)
-#pragma unroll
-            for (int ib = 0; ib < 4; ++ib) {
-                const int a = a0 + ia, b = b0 + ib;
-                if (b >= a) {   // columns b > j only, since a > j (ma = 0 otherwise)
-                    const cd pr = cmulz(ma[ia], gb[ib]);
-                    g[ia][ib].x -= pr.x;
-                    g[ia][ib].y -= pr.y;
-                }
-                const cd pu2 = cmulz(ma[ia], ub[ib]);
-                u[ia][ib].x -= pu2.x;
-                u[ia][ib].y -= pu2.y;
+            for (int ia = 0; ia < 2; ++ia) {
+                const int a = a0 + ia;
+                const cd p = prg[a];
+                ma[ia] = a > j ? cd{p.x * inv_d, -p.y * inv_d} : cd{0.0, 0.0};
             }
-        // row j of R^-H: the owners scale their augmented row
-        const double isd = 1.0 / sqrt(d);
+            cd gb[2], ub[2];
 #pragma unroll
-        for (int ia = 0; ia < 4; ++ia)
-            if (a0 + ia == j)
+            for (int ib = 0; ib < 2; ++ib) {
+                gb[ib] = prg[b0 + ib];
+                ub[ib] = pru[b0 + ib];
+            }
 #pragma unroll
-                for (int ib = 0; ib < 4; ++ib) u[ia][ib] = cd{u[ia][ib].x * isd, u[ia][ib].y * isd};
-        // the next pivot row (final after this step) to the other buffer
-        if (j + 1 < n) {
+            for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
-            for (int ia = 0; ia < 4; ++ia)
-                if (a0 + ia == j + 1)
-#pragma unroll
-                    for (int ib = 0; ib < 4; ++ib) {
-                        pg[(j + 1) & 1][b0 + ib] = g[ia][ib];
-                        pu[(j + 1) & 1][b0 + ib] = u[ia][ib];
+                for (int ib = 0; ib < 2; ++ib) {
+                    const int a = a0 + ia, b = b0 + ib;
+                    if (b >= a) {   // columns b > j only, since a > j (ma = 0 otherwise)
+                        const cd pr = cmulz(ma[ia], gb[ib]);
+                        g[ia][ib].x -= pr.x;
+                        g[ia][ib].y -= pr.y;
                     }
+                    const cd pu2 = cmulz(ma[ia], ub[ib]);
+                    u[ia][ib].x -= pu2.x;
+                    u[ia][ib].y -= pu2.y;
+                }
+            // the next pivot row (final after this step) to the other buffer
+            if (j + 1 < n) {
+#pragma unroll
+                for (int ia = 0; ia < 2; ++ia)
+                    if (a0 + ia == j + 1)
+#pragma unroll
+                        for (int ib = 0; ib < 2; ++ib) {
+                            pg[(j + 1) & 1][b0 + ib] = g[ia][ib];
+                            pu[(j + 1) & 1][b0 + ib] = u[ia][ib];
+                        }
+            }
         }
         __syncthreads();
     }
-    // R^-1 (upper) = (R^-H)^H
+    // R^-1 (upper) = (R^-H)^H with R^-H = D^-1/2 L^-1
 #pragma unroll
-    for (int ia = 0; ia < 4; ++ia)
+    for (int ia = 0; ia < 2; ++ia) {
+        const double isd = 1.0 / sqrt(dpiv[ia]);
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
+        for (int ib = 0; ib < 2; ++ib) {
             const int a = a0 + ia, c = b0 + ib;
-            if (a < n && c < n) Rinv[(int64_t)a * ldr + c] = cd{u[ia][ib].x, -u[ia][ib].y};
+            if (a < n && c < n) Rinv[(int64_t)a * ldr + c] = cd{u[ia][ib].x * isd, -u[ia][ib].y * isd};
         }
+    }
     if (fail && t == 0) atomicOr(status, 1);
 }
 
 // ---- Hermitian eigensolver ---------------------------------------------------
 // Five kernels on the stream:
 //   k_hetrd  (1 workgroup)   A = Q T Q^H, T real tridiagonal (lower Householder)
-//   k_stebz  (k/64 groups)   lowest k eigenvalues of T by 16-way multisection
+//   k_stebz  (k groups)      lowest k eigenvalues of T by 512-point multisection
 //   k_stein  (k/E groups)    eigenvectors of T by inverse iteration, LU in LDS
 //   k_orth   (1 workgroup)   Gram-Schmidt (twice) in eigenvalue order
 //   k_unmtr  (k/cw groups)   back-transform V = Q Z
@@ -626,44 +641,60 @@ __device__ TriBounds tri_bounds(const double *ds, const double *ee, int n) {
             tnorm};
 }
 
-// 16 lanes per eigenvalue: each round evaluates 16 interior points of the
-// bracket and keeps the sub-interval where the Sturm count crosses the index.
-__global__ void __launch_bounds__(64) k_stebz(const double *__restrict__ dd,
-                                                const double *__restrict__ ee, int n, int k,
-                                                double *__restrict__ w) {
+// One workgroup of 256 threads per eigenvalue: each round evaluates 512
+// interior points of the bracket (two interleaved Sturm chains per thread)
+// and keeps the sub-interval where the count crosses the index, so a bracket
+// shrinks by 513x (9 bits) per round, ~6-7 rounds from the Gershgorin
+// interval to double precision.  The first point with count > idx is found
+// by per-wave ballots and a minimum over the waves in LDS.
+constexpr int kStebzThreads = 256;
+__global__ void __launch_bounds__(kStebzThreads) k_stebz(const double *__restrict__ dd,
+                                                          const double *__restrict__ ee, int n, int k,
+                                                          double *__restrict__ w) {
     extern __shared__ unsigned char smem_raw[];
     double *ds = reinterpret_cast<double *>(smem_raw);
     double *e2 = ds + n;
     __shared__ TriBounds tb;
-    const int t = threadIdx.x;
+    __shared__ int wfirst[2][kStebzThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int NP = 2 * kStebzThreads;   // interior points per round
     for (int i = t; i < n; i += blockDim.x) {
         ds[i] = dd[i];
         e2[i] = (i + 1 < n) ? ee[i] * ee[i] : 0.0;
     }
     if (t == 0) tb = tri_bounds(dd, ee, n);
     __syncthreads();
-    const int grp = t >> 4, s = t & 15;
-    const int idx = blockIdx.x * (blockDim.x >> 4) + grp;
-    if (idx >= k) return;
+    const int idx = blockIdx.x;
     double lo = tb.gl, hi = tb.gu;
-    const int base = (t & 63) & ~15;
-    for (int round = 0; round < 64; ++round) {
+    for (int round = 0; round < 16; ++round) {
         const double width = hi - lo;
         if (width <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + tb.pivmin) break;
-        // 32 interior points; lane s evaluates points s and s + 16
-        const double x1 = lo + width * (double)(s + 1) / 33.0;
-        const double x2 = lo + width * (double)(s + 17) / 33.0;
+        // thread t evaluates points t and t + 256 (1-based: point p at lo + width p / (NP + 1))
+        const double x1 = lo + width * (double)(t + 1) / (double)(NP + 1);
+        const double x2 = lo + width * (double)(t + 1 + kStebzThreads) / (double)(NP + 1);
         int c1, c2;
         sturm_count2(ds, e2, n, x1, x2, tb.pivmin, c1, c2);
-        const unsigned g1 = (unsigned)((__ballot(c1 > idx) >> base) & 0xFFFFull);
-        const unsigned g2 = (unsigned)((__ballot(c2 > idx) >> base) & 0xFFFFull);
-        const int first = g1 ? __ffs(g1) - 1 : (g2 ? 16 + __ffs(g2) - 1 : 32);
-        const double nlo = first == 0 ? lo : lo + width * (double)first / 33.0;
-        const double nhi = first == 32 ? hi : lo + width * (double)(first + 1) / 33.0;
+        const uint64_t b1 = __ballot(c1 > idx), b2 = __ballot(c2 > idx);
+        const int buf = round & 1;
+        if (lane == 0) {
+            wfirst[buf][wave] = b1 ? 64 * wave + __ffsll((unsigned long long)b1) - 1
+                                   : (b2 ? kStebzThreads + 64 * wave + __ffsll((unsigned long long)b2) - 1
+                                         : NP);
+        }
+        __syncthreads();
+        // the first point (0-based) whose count exceeds idx; NP if none
+        int first = NP;
+        for (int q = 0; q < kStebzThreads / 64; ++q) {
+            const int f = wfirst[buf][q];
+            // points of the first half (< 256) come before every point of the second half
+            first = min(first, f);
+        }
+        const double nlo = first == 0 ? lo : lo + width * (double)first / (double)(NP + 1);
+        const double nhi = first == NP ? hi : lo + width * (double)(first + 1) / (double)(NP + 1);
         lo = nlo;
         hi = nhi;
     }
-    if (s == 0) w[idx] = 0.5 * (lo + hi);
+    if (t == 0) w[idx] = 0.5 * (lo + hi);
 }
 
 // Inverse iteration: one thread per eigenvalue, E eigenvalues per workgroup,
@@ -689,36 +720,39 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
     enum { DL = 0, DD, DU, DU2, PIV, ZZ };
     const double lam = w[idx];
     const double eps_t = DBL_EPSILON * fmax(s_tnorm, 1e-300);
-    for (int i = 0; i < n; ++i) {
-        at(DD, i) = ds[i] - lam;
-        at(DU, i) = es[i];
-        at(DU2, i) = 0.0;
-        at(PIV, i) = 0.0;
-    }
+    // LU with partial pivoting of T - lambda I (LAPACK dlagtf order); the
+    // entries that the next step modifies (diagonal d and superdiagonal u of
+    // row i) are carried in registers, so each step's only LDS traffic is
+    // stores and loads of untouched input
+    double d_cur = ds[0] - lam, u_cur = es[0];
     for (int i = 0; i + 1 < n; ++i) {
         const double sub = es[i];
-        const double di = at(DD, i);
-        if (fabs(di) >= fabs(sub)) {
-            const double dp = fabs(di) < eps_t ? (di < 0 ? -eps_t : eps_t) : di;
-            at(DD, i) = dp;
+        const double d_nx = ds[i + 1] - lam, u_nx = es[i + 1];   // row i + 1 as given
+        if (fabs(d_cur) >= fabs(sub)) {
+            const double dp = fabs(d_cur) < eps_t ? (d_cur < 0 ? -eps_t : eps_t) : d_cur;
             const double m = sub / dp;
+            at(DD, i) = dp;
             at(DL, i) = m;
-            at(DD, i + 1) -= m * at(DU, i);
+            at(DU, i) = u_cur;
+            at(DU2, i) = 0.0;
+            at(PIV, i) = 0.0;
+            d_cur = d_nx - m * u_cur;
+            u_cur = u_nx;
         } else {
-            const double m = di / sub;
-            at(DL, i) = m;
-            at(PIV, i) = 1.0;
+            const double m = d_cur / sub;
             at(DD, i) = sub;
-            const double tmp = at(DU, i);
-            at(DU, i) = at(DD, i + 1);
-            at(DD, i + 1) = tmp - m * at(DD, i + 1);
-            if (i + 2 < n) {
-                at(DU2, i) = at(DU, i + 1);
-                at(DU, i + 1) = -m * at(DU, i + 1);
-            }
+            at(DL, i) = m;
+            at(DU, i) = d_nx;
+            at(PIV, i) = 1.0;
+            at(DU2, i) = i + 2 < n ? u_nx : 0.0;
+            d_cur = u_cur - m * d_nx;
+            u_cur = i + 2 < n ? -m * u_nx : u_nx;
         }
     }
-    if (fabs(at(DD, n - 1)) < eps_t) at(DD, n - 1) = eps_t;
+    at(DD, n - 1) = fabs(d_cur) < eps_t ? eps_t : d_cur;
+    at(DU, n - 1) = 0.0;
+    at(DU2, n - 1) = 0.0;
+    at(PIV, n - 1) = 0.0;
     for (int i = 0; i < n; ++i) at(DD, i) = 1.0 / at(DD, i);   // reciprocal pivots
     for (int i = 0; i < n; ++i) {
         uint64_t h = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(idx + 7) * 0xD1B54A32D192ED03ull;
@@ -728,23 +762,27 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
         at(ZZ, i) = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
     }
     for (int iter = 0; iter < 2; ++iter) {
+        // L solve with the row interchanges; z carries the running entry
+        double z = at(ZZ, 0);
         for (int i = 0; i + 1 < n; ++i) {
+            const double znx = at(ZZ, i + 1), l = at(DL, i);
             if (at(PIV, i) != 0.0) {
-                const double tmp = at(ZZ, i);
-                at(ZZ, i) = at(ZZ, i + 1);
-                at(ZZ, i + 1) = tmp - at(DL, i) * at(ZZ, i + 1);
+                at(ZZ, i) = znx;
+                z = z - l * znx;
             } else {
-                at(ZZ, i + 1) -= at(DL, i) * at(ZZ, i);
+                at(ZZ, i) = z;
+                z = znx - l * z;
             }
         }
-        double nrm = 0.0;
+        at(ZZ, n - 1) = z;
+        // U solve from the bottom; z1, z2 carry the two entries below
+        double nrm = 0.0, z1 = 0.0, z2 = 0.0;
         for (int i = n - 1; i >= 0; --i) {
-            double sv = at(ZZ, i);
-            if (i + 1 < n) sv -= at(DU, i) * at(ZZ, i + 1);
-            if (i + 2 < n) sv -= at(DU2, i) * at(ZZ, i + 2);
-            sv *= at(DD, i);
+            const double sv = (at(ZZ, i) - at(DU, i) * z1 - at(DU2, i) * z2) * at(DD, i);
             at(ZZ, i) = sv;
             nrm = fmax(nrm, fabs(sv));
+            z2 = z1;
+            z1 = sv;
         }
         const double inv = nrm > 0 ? 1.0 / nrm : 1.0;
         for (int i = 0; i < n; ++i) at(ZZ, i) *= inv;
@@ -988,106 +1026,135 @@ __global__ void __launch_bounds__(256) k_unmtr(const cd *__restrict__ A, int64_t
     }
 }
 
-// CholQR, twice, of the columns of Z [n][k] (k <= 64, all in LDS): G = Z^T Z
-// with 4 x 4 register blocks per thread, G = R^T R by right-looking Cholesky
-// with the unscaled pivot row (one barrier per column), then Z <- Z R^-1 as a
-// triangular solve with one thread per row and the row in registers.
-// Equivalent to Gram-Schmidt in column (eigenvalue) order.
+// CholQR applied twice to the real eigenvector block Z [n x k] (k <= 64,
+// n <= 217), in LDS, 1024 threads.  G = Z^T Z and Z R^-1 run on the FP64
+// matrix cores (16 x 16 output tiles, one to three per wave).  The factor
+// comes from elimination on [G | I] as in k_chol_inv (pivot row broadcast
+// through LDS, one barrier per step, rows kept unscaled until the end: the
+// augmented half becomes L^-1 and R^-T = D^-1/2 L^-1), with 2 x 2 tiles per
+// thread on a 32 x 32 grid.  Columns >= k carry an identity block of G.
 constexpr int kOc2Ld = 68;   // LDS row stride of Z (doubles)
-constexpr int kOc2Lg = 65;   // LDS row stride of G
+constexpr int kOc2Lr = 65;   // LDS row stride of G and of R^-1
 __host__ __device__ constexpr size_t orth_chol2_lds(int n) {
-    return ((size_t)n * kOc2Ld + 64 * kOc2Lg + 128) * sizeof(double);
+    return ((size_t)((n + 15) / 16 * 16) * kOc2Ld + 64 * kOc2Lr + 4 * 64) * sizeof(double);
 }
-__global__ void __launch_bounds__(256) k_orth_chol2(double *__restrict__ Zg, int n, int k,
-                                                    int *__restrict__ status) {
+__global__ void __launch_bounds__(1024) k_orth_chol2(double *__restrict__ Zg, int n, int k,
+                                                     int *__restrict__ status) {
+    typedef double v4d __attribute__((ext_vector_type(4)));
     extern __shared__ double smd[];
-    double *Z = smd;                        // [n][kOc2Ld], columns >= k zero
-    double *G = Z + (size_t)n * kOc2Ld;     // [64][kOc2Lg]: G, then R (upper)
-    double *dpiv = G + 64 * kOc2Lg;         // [64] pivots used
-    double *rinv = dpiv + 64;               // [64] 1 / R_jj
+    const int n16 = (n + 15) / 16 * 16;     // rows padded with zeros to whole tiles
+    double *Z = smd;                        // [n16][kOc2Ld], columns >= k zero
+    double *Gs = Z + (size_t)n16 * kOc2Ld;  // [64][kOc2Lr]: G, then R^-1
+    double *pg = Gs + 64 * kOc2Lr;          // [2][64] pivot rows of G
+    double *pu = pg + 2 * 64;               // [2][64] pivot rows of the augmented half
     const int t = threadIdx.x, nt = blockDim.x;
-    for (int i = t; i < n * kOc2Ld; i += nt) {
+    const int ti = t >> 5, tj = t & 31, a0 = 2 * ti, b0 = 2 * tj;
+    const int wave = t >> 6, lane = t & 63, li = lane & 15, lg = lane >> 4;
+    const int wrow_last = 4 * wave + 3;
+    for (int i = t; i < n16 * kOc2Ld; i += nt) {
         const int r = i / kOc2Ld, c = i % kOc2Ld;
-        Z[i] = c < k ? Zg[(size_t)r * k + c] : 0.0;
+        Z[i] = (r < n && c < k) ? Zg[(size_t)r * k + c] : 0.0;
     }
-    // rows and columns >= k of G / R and rinv stay zero: the solve below then
-    // runs over all 64 columns without guards
-    for (int i = t; i < 64 * kOc2Lg + 128; i += nt) G[i] = 0.0;
     __syncthreads();
     bool fail = false;
     for (int pass = 0; pass < 2; ++pass) {
-        {   // G = Z^T Z, thread t owns rows a0..a0+3 and columns b0..b0+3
-            const int a0 = 4 * (t >> 4), b0 = 4 * (t & 15);
-            if (a0 < k && b0 < k) {
-                double acc[4][4];
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) acc[i][jj] = 0.0;
-                for (int r = 0; r < n; ++r) {
-                    const double *zr = Z + (size_t)r * kOc2Ld;
-                    double za[4], zb[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        za[i] = zr[a0 + i];
-                        zb[i] = zr[b0 + i];
-                    }
-#pragma unroll
-                    for (int i = 0; i < 4; ++i)
-#pragma unroll
-                        for (int jj = 0; jj < 4; ++jj) acc[i][jj] += za[i] * zb[jj];
-                }
-#pragma unroll
-                for (int i = 0; i < 4; ++i)
-#pragma unroll
-                    for (int jj = 0; jj < 4; ++jj) G[(a0 + i) * kOc2Lg + b0 + jj] = acc[i][jj];
+        {   // G = Z^T Z: wave w computes the 16 x 16 tile (w / 4, w % 4)
+            const int ra = 16 * (wave >> 2), cb = 16 * (wave & 3);
+            v4d acc = {0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < n16; k0 += 4) {
+                const double *zr = Z + (size_t)(k0 + lg) * kOc2Ld;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(zr[ra + li], zr[cb + li], acc, 0, 0, 0);
             }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) Gs[(ra + lg + 4 * r) * kOc2Lr + cb + li] = acc[r];
         }
         __syncthreads();
-        for (int j = 0; j < k; ++j) {   // Cholesky, upper triangle, unscaled pivot row
-            double d = G[j * kOc2Lg + j];
-            if (!(d > 1e-300)) {
+        double g[2][2], u[2][2], dpiv[2] = {1.0, 1.0};
+#pragma unroll
+        for (int ia = 0; ia < 2; ++ia)
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib) {
+                const int a = a0 + ia, b = b0 + ib;
+                g[ia][ib] = (a == b && a >= k) ? 1.0 : Gs[a * kOc2Lr + b];
+                u[ia][ib] = a == b ? 1.0 : 0.0;
+                if (a == 0) {
+                    pg[b] = g[ia][ib];
+                    pu[b] = u[ia][ib];
+                }
+            }
+        __syncthreads();
+        for (int j = 0; j < 64; ++j) {
+            const double *prg = pg + 64 * (j & 1), *pru = pu + 64 * (j & 1);
+            double d = prg[j];
+            if (!(d > 1e-300) || !isfinite(d)) {
                 fail = true;
                 d = 1.0;
             }
-            const double inv_d = 1.0 / d;
-            // thread (t / 16, t % 16) updates rows a = j+1+t/16 (step 16), columns b >= a
-            for (int a = j + 1 + (t >> 4); a < k; a += 16) {
-                const double ga = G[j * kOc2Lg + a] * inv_d;
-                for (int b = a + (t & 15); b < k; b += 16) G[a * kOc2Lg + b] -= ga * G[j * kOc2Lg + b];
-            }
-            if (t == 0) dpiv[j] = d;
-            __syncthreads();
-        }
-        for (int j = t >> 4; j < k; j += 16) {   // R_jc = G_jc / sqrt(d_j)
-            const double sd = sqrt(dpiv[j]), isd = 1.0 / sd;
-            for (int c = j + 1 + (t & 15); c < k; c += 16) G[j * kOc2Lg + c] *= isd;
-            if ((t & 15) == 0) {
-                G[j * kOc2Lg + j] = sd;
-                rinv[j] = isd;
-            }
-        }
-        __syncthreads();
-        if (t < n) {   // row t of Z R^-1 (forward substitution); n <= blockDim
-            const int r = t;
-            double z[64];
-            double *zr = Z + (size_t)r * kOc2Ld;
 #pragma unroll
-            for (int c = 0; c < 64; ++c) z[c] = zr[c];
-            // z (128 VGPRs) plus at most 8 values of R in flight: an empty asm
-            // with a memory clobber after every 8 loads bounds the live range
+            for (int ia = 0; ia < 2; ++ia)
+                if (a0 + ia == j) dpiv[ia] = d;
+            if (wrow_last > j) {   // rows below the pivot in this wave (uniform per wave)
+                const double inv_d = rcp_nr(d);
+                double ma[2];
 #pragma unroll
-            for (int c = 0; c < 64; ++c) {
-                const double xc = z[c] * rinv[c];
-                z[c] = xc;
+                for (int ia = 0; ia < 2; ++ia) ma[ia] = a0 + ia > j ? prg[a0 + ia] * inv_d : 0.0;
+                const double gb0 = prg[b0], gb1 = prg[b0 + 1], ub0 = pru[b0], ub1 = pru[b0 + 1];
 #pragma unroll
-                for (int c2 = c + 1; c2 < 64; ++c2) {
-                    z[c2] -= xc * G[c * kOc2Lg + c2];
-                    if ((c2 & 7) == 7) asm volatile("" ::: "memory");
+                for (int ia = 0; ia < 2; ++ia) {
+                    const int a = a0 + ia;
+                    if (b0 >= a) g[ia][0] -= ma[ia] * gb0;
+                    if (b0 + 1 >= a) g[ia][1] -= ma[ia] * gb1;
+                    u[ia][0] -= ma[ia] * ub0;
+                    u[ia][1] -= ma[ia] * ub1;
+                }
+                if (j + 1 < 64) {
+#pragma unroll
+                    for (int ia = 0; ia < 2; ++ia)
+                        if (a0 + ia == j + 1) {
+                            double *ng = pg + 64 * ((j + 1) & 1), *nu = pu + 64 * ((j + 1) & 1);
+                            ng[b0] = g[ia][0];
+                            ng[b0 + 1] = g[ia][1];
+                            nu[b0] = u[ia][0];
+                            nu[b0 + 1] = u[ia][1];
+                        }
                 }
             }
+            __syncthreads();
+        }
+        // R^-1 (c, a) = (D^-1/2 L^-1)(a, c)
 #pragma unroll
-            for (int c = 0; c < 64; ++c) zr[c] = z[c];   // columns >= k stay zero
+        for (int ia = 0; ia < 2; ++ia) {
+            const double isd = 1.0 / sqrt(dpiv[ia]);
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib) Gs[(b0 + ib) * kOc2Lr + a0 + ia] = u[ia][ib] * isd;
+        }
+        __syncthreads();
+        {   // Z <- Z R^-1: wave w computes column tile w % 4 of row tiles w / 4 + 4 i
+            const int cb = 16 * (wave & 3);
+            v4d acc[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[i] = v4d{0.0, 0.0, 0.0, 0.0};
+            for (int k0 = 0; k0 < 64; k0 += 4) {
+                const double b = Gs[(k0 + lg) * kOc2Lr + cb + li];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int rt = 16 * ((wave >> 2) + 4 * i);
+                    if (rt < n16)
+                        acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(Z[(size_t)(rt + li) * kOc2Ld + k0 + lg], b,
+                                                                      acc[i], 0, 0, 0);
+                }
+            }
+            __syncthreads();   // every read of Z done before it is overwritten
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int rt = 16 * ((wave >> 2) + 4 * i);
+                if (rt < n16)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int row = rt + lg + 4 * r, col = cb + li;
+                        Z[(size_t)row * kOc2Ld + col] = (row < n && col < k) ? acc[i][r] : 0.0;
+                    }
+            }
         }
         __syncthreads();
     }
@@ -1100,7 +1167,7 @@ __global__ void __launch_bounds__(256) k_orth_chol2(double *__restrict__ Zg, int
 // Reflectors are applied in groups of kUwRing with a ring of kUwRing
 // reflectors loaded ahead, so the loads of one group overlap the work of the
 // previous one.
-constexpr int kUwCols = 4;
+constexpr int kUwCols = 1;
 constexpr int kUwRing = 8;
 template <int RPL>
 __global__ void __launch_bounds__(64) k_unmtr_w(const cd *__restrict__ A, int64_t lda, int n, int k,
@@ -1184,7 +1251,7 @@ __global__ void k_check_w(const double *w, int k, int *status) {
 void launch_chol_inv_f64(const cd *G, int64_t ldg, int n, cd *Rinv, int64_t ldr, int *status,
                          hipStream_t st) {
     PW_REQUIRE(n >= 1 && n <= kCholMax, PW_ERR_ARG, "block size must be in [1, 64]");
-    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), 0, st, G, ldg, n, Rinv, ldr, status);
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(1024), 0, st, G, ldg, n, Rinv, ldr, status);
     PW_HIP(hipGetLastError());
 }
 
@@ -1225,8 +1292,8 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     }
     // 2. eigenvalues
     const size_t sm2 = 2 * (size_t)n * 8;
-    // 4 eigenvalues (16 lanes each) per workgroup, spread over k/4 CUs
-    hipLaunchKernelGGL(k_stebz, dim3((k + 3) / 4), dim3(64), sm2, st, d, e, n, k, w);
+    // one workgroup per eigenvalue, spread over k CUs
+    hipLaunchKernelGGL(k_stebz, dim3(k), dim3(kStebzThreads), sm2, st, d, e, n, k, w);
     // 3. inverse iteration
     const size_t budget = 150 * 1024;
     int E = (int)((budget - 16 * (size_t)n) / (48 * (size_t)n));
@@ -1239,7 +1306,7 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     if (k <= 64 && orth_chol2_lds(n) <= 150 * 1024) {
         const size_t sm = orth_chol2_lds(n);
         PW_HIP(hipFuncSetAttribute((const void *)k_orth_chol2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
-        hipLaunchKernelGGL(k_orth_chol2, dim3(1), dim3(256), sm, st, Z, n, k, status);
+        hipLaunchKernelGGL(k_orth_chol2, dim3(1), dim3(1024), sm, st, Z, n, k, status);
     } else if (k <= kOrthMaxK && n <= 256 && smc <= 150 * 1024) {
         PW_HIP(hipFuncSetAttribute((const void *)k_orth_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smc));
         hipLaunchKernelGGL(k_orth_chol, dim3(1), dim3(256), smc, st, Z, n, k, status);
