@@ -159,210 +159,200 @@ __global__ void __launch_bounds__(1024) k_chol_inv(const cd *__restrict__ G, int
 }
 
 // ---- Hermitian eigensolver ---------------------------------------------------
-// Five kernels on the stream:
-//   k_hetrd  (1 workgroup)   A = Q T Q^H, T real tridiagonal (lower Householder)
-//   k_stebz  (k groups)      lowest k eigenvalues of T by 512-point multisection
-//   k_stein  (k/E groups)    eigenvectors of T by inverse iteration, LU in LDS
-//   k_orth   (1 workgroup)   Gram-Schmidt (twice) in eigenvalue order
-//   k_unmtr  (k/cw groups)   back-transform V = Q Z
-constexpr int kTrdThreads = 512;
-
-// One fused pass per column j over the full trailing square (both triangles
-// are kept; the rank-2 update leaves them exact conjugates): the pending
-// update of step j-1 is applied while y = A_trail v_j is accumulated, so the
-// trailing block is read and written once per step.  One lane owns one row,
-// a wave task covers 64 rows x CC columns with CC independent loads in
-// flight, and row sums stay in registers.  The pivot column is kept in LDS
-// between steps, and once the trailing square fits in LDS it moves there for
-// the remaining steps.  Row partials are kept per wave and added in wave
-// order (deterministic).
-struct GlobalSq {
-    cd *A;
-    int64_t lda;
-    __device__ cd &at(int i, int c) const { return A[(int64_t)c * lda + i]; }
+// Five stages on the stream:
+//   reduction  A = Q T Q^H, T real tridiagonal (lower Householder):
+//              k_hetrd_rf (1 workgroup, n <= 192) or k_trd_apply + k_trd_step
+//   k_stebz    (k groups)      lowest k eigenvalues of T by 512-point multisection
+//   k_stein    (k/E groups)    eigenvectors of T by inverse iteration, LU in LDS
+//   k_orth_chol2 / k_orth_chol / k_orth (1 workgroup)  re-orthogonalisation
+//   k_unmtr_w / k_unmtr (k/cw groups)  back-transform V = Q Z
+//
+// ---- multi-workgroup reduction for n > 192 (the final Rayleigh-Ritz) --------
+// H_j = I - tau_j v_j v_j^H, A <- H_j^H A H_j, w = tau y - (|tau|^2 / 2)
+// Re(v^H y) v, A -= w v^H + v w^H, both triangles of the trailing square kept;
+// one column step is two launches:
+//   k_trd_apply (many workgroups): on the trailing square [j+1, n)^2 apply the
+//     pending rank-2 update of step j-1 and accumulate y = A v_j; a workgroup
+//     owns 64 rows (one per lane) and 64 columns (16 per wave), so every
+//     partial of y is a plain per-lane sum; partials go to ypart[chunk][row].
+//   k_trd_step (one workgroup): y = sum of the chunk partials (fixed order),
+//     w_j = tau y - (|tau|^2 / 2) Re(v^H y) v, the pivot column j+1 with the
+//     update of step j applied on the fly, d_{j+1}, and the reflector j+1
+//     (stored below the subdiagonal of column j+1, beta on the subdiagonal).
+// v of consecutive steps alternates between two buffers; rows outside a
+// reflector's range are zero in its buffer.
+struct TrdState {
+    cd *v[2];      // [n] reflectors of even / odd steps
+    cd *w;         // [n] w of the last step
+    cd *ypart;     // [nchunk][n]
 };
-struct LdsSq {   // rows/cols [base, n) in LDS, column-major with leading dim ld
-    cd *p;
-    int base, ld;
-    __device__ cd &at(int i, int c) const { return p[(c - base) * ld + (i - base)]; }
-};
 
-template <class Sq>
-__device__ __forceinline__ void hetrd_pass(const Sq &M, int j, int n, const cd *v, const cd *vp,
-                                           const cd *wp, cd *ypart, cd *colbuf) {
-    constexpr int CC = 16;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    const int r_first = j + 1, L = n - r_first;
-    const int nrb = (L + 63) / 64, ncc = (L + CC - 1) / CC;
-    for (int u = wave; u < nrb * ncc; u += nwaves) {
-        const int rb = u % nrb, cch = u / nrb;
-        const int i = r_first + rb * 64 + lane;
-        const bool rowok = i < n;
-        const int c0 = r_first + cch * CC;
-        const int nc = min(CC, n - c0);
-        cd a[CC];
-#pragma unroll
-        for (int q = 0; q < CC; ++q) a[q] = (rowok && q < nc) ? M.at(i, c0 + q) : cd{0.0, 0.0};
-        const cd vpi = rowok ? vp[i] : cd{0.0, 0.0};
-        const cd wpi = rowok ? wp[i] : cd{0.0, 0.0};
-        double yr4[4] = {0.0, 0.0, 0.0, 0.0}, yi4[4] = {0.0, 0.0, 0.0, 0.0};   // 4 independent chains
-#pragma unroll
-        for (int q = 0; q < CC; ++q) {
-            if (q < nc) {
-                const int c = c0 + q;
-                const cd u1 = cmulz(wpi, cconj(vp[c])), u2 = cmulz(vpi, cconj(wp[c]));
-                cd aa = a[q];
-                aa.x -= u1.x + u2.x;
-                aa.y -= u1.y + u2.y;
-                if (rowok) {
-                    M.at(i, c) = aa;
-                    if (c == r_first) colbuf[i] = aa;   // next pivot column
-                }
-                const cd vc = v[c];
-                yr4[q & 3] += aa.x * vc.x - aa.y * vc.y;
-                yi4[q & 3] += aa.x * vc.y + aa.y * vc.x;
-            }
-        }
-        const double yr = (yr4[0] + yr4[1]) + (yr4[2] + yr4[3]);
-        const double yi = (yi4[0] + yi4[1]) + (yi4[2] + yi4[3]);
-        if (rowok) {
-            cd &yp = ypart[wave * n + i];
-            yp.x += yr;
-            yp.y += yi;
-        }
+__global__ void k_herm_sym(cd *__restrict__ A, int64_t lda, int n) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)n * n) return;
+    const int r = (int)(idx % n), c = (int)(idx / n);
+    if (r > c) {
+        const cd a = A[(int64_t)c * lda + r], b = A[(int64_t)r * lda + c];
+        const cd m = {0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
+        A[(int64_t)c * lda + r] = m;
+        A[(int64_t)r * lda + c] = cconj(m);
+    } else if (r == c) {
+        A[(int64_t)c * lda + r].y = 0.0;
     }
 }
 
-__global__ void __launch_bounds__(kTrdThreads)
-    k_hetrd(cd *__restrict__ A, int64_t lda, int n, double *__restrict__ dd,
-            double *__restrict__ ee, cd *__restrict__ tau_out, int lds_cap) {
-    extern __shared__ unsigned char smem_raw[];
-    const int nwaves = blockDim.x >> 6;
-    cd *vp = reinterpret_cast<cd *>(smem_raw);   // [n] previous v (absolute rows)
-    cd *wp = vp + n;                              // [n] previous w
-    cd *v = wp + n;                               // [n] current v
-    cd *y = v + n;                                // [n] A v
-    cd *colbuf = y + n;                           // [n] current pivot column
-    cd *ypart = colbuf + n;                       // [nwaves][n] per-wave row sums
-    double *red = reinterpret_cast<double *>(ypart + (size_t)nwaves * n);   // [blockDim]
-    cd *sq = reinterpret_cast<cd *>(red + blockDim.x);                     // [lds_cap]
+__global__ void __launch_bounds__(256)
+    k_trd_apply(cd *__restrict__ A, int64_t lda, int n, int j, TrdState S) {
+    __shared__ cd cvp[64], cwp[64], cv[64];
+    __shared__ cd yw[4][64];
+    const int r0 = j + 1;
+    const int L = n - r0;
+    const int nrb = (L + 63) / 64;
+    const int rb = blockIdx.x % nrb, cc = blockIdx.x / nrb;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const cd *vp = S.v[(j + 1) & 1];   // v_{j-1} (zero for j = 0)
+    const cd *v = S.v[j & 1];
+    const cd *wp = S.w;                // w_{j-1} (zero for j = 0)
+    const int c0 = r0 + 64 * cc;
+    if (threadIdx.x < 64) {
+        const int c = c0 + threadIdx.x;
+        const bool ok = c < n;
+        cvp[threadIdx.x] = ok ? vp[c] : cd{0.0, 0.0};
+        cwp[threadIdx.x] = ok ? wp[c] : cd{0.0, 0.0};
+        cv[threadIdx.x] = ok ? v[c] : cd{0.0, 0.0};
+    }
+    __syncthreads();
+    const int i = r0 + 64 * rb + lane;
+    const bool rowok = i < n;
+    const cd vpi = rowok ? vp[i] : cd{0.0, 0.0}, wpi = rowok ? wp[i] : cd{0.0, 0.0};
+    double yr = 0.0, yi = 0.0;
+    if (rowok) {
+#pragma unroll 4
+        for (int q = 16 * wave; q < 16 * wave + 16; ++q) {
+            const int c = c0 + q;
+            if (c >= n) break;
+            cd a = A[(int64_t)c * lda + i];
+            const cd u1 = cmulz(wpi, cconj(cvp[q])), u2 = cmulz(vpi, cconj(cwp[q]));
+            a.x -= u1.x + u2.x;
+            a.y -= u1.y + u2.y;
+            A[(int64_t)c * lda + i] = a;
+            const cd vc = cv[q];
+            yr += a.x * vc.x - a.y * vc.y;
+            yi += a.x * vc.y + a.y * vc.x;
+        }
+    }
+    yw[wave][lane] = cd{yr, yi};
+    __syncthreads();
+    if (wave == 0 && rowok) {
+        const double sr = ((yw[0][lane].x + yw[1][lane].x) + yw[2][lane].x) + yw[3][lane].x;
+        const double si = ((yw[0][lane].y + yw[1][lane].y) + yw[2][lane].y) + yw[3][lane].y;
+        S.ypart[(int64_t)cc * n + i] = cd{sr, si};
+    }
+}
+
+// j = -1: no previous step (w = 0), pivot column 0 as stored
+__global__ void __launch_bounds__(1024)
+    k_trd_step(cd *__restrict__ A, int64_t lda, int n, int j, TrdState S, double *__restrict__ dd,
+               double *__restrict__ ee, cd *__restrict__ tau_out) {
+    __shared__ double red[16];
+    __shared__ cd s_y[1024], s_wl[1024];   // y and w of this step (n <= 1024)
     __shared__ cd s_tau, s_scale;
     __shared__ double s_beta;
     const int t = threadIdx.x, nt = blockDim.x;
-    const GlobalSq G{A, lda};
-    // the trailing square of step j is [j+1, n); it moves to LDS at the first
-    // step where (n - 1 - j)^2 <= lds_cap
-    int jsw = n;
-    for (int j = 0; j < n; ++j) {
-        const long L = n - 1 - j;
-        if (L * L <= lds_cap) {
-            jsw = j;
-            break;
-        }
-    }
-    const LdsSq S{sq, jsw + 1, n - 1 - jsw};
-
-    // exact Hermitian symmetrisation: A <- (A + A^H) / 2
-    for (int idx = t; idx < n * n; idx += nt) {
-        const int r = idx % n, c = idx / n;
-        if (r > c) {
-            const cd a = G.at(r, c), b = G.at(c, r);
-            const cd m = {0.5 * (a.x + b.x), 0.5 * (a.y - b.y)};
-            G.at(r, c) = m;
-            G.at(c, r) = cconj(m);
-        } else if (r == c) {
-            G.at(r, c).y = 0.0;
-        }
-    }
-    __syncthreads();
-    for (int i = t; i < n; i += nt) {
-        vp[i] = wp[i] = cd{0.0, 0.0};
-        colbuf[i] = G.at(i, 0);
-    }
-    __syncthreads();
-    for (int j = 0; j < n; ++j) {
-        {   // pending update of the pivot column (rows j..n-1), in LDS
-            const cd vj = cconj(vp[j]), wj = cconj(wp[j]);
-            for (int i = j + t; i < n; i += nt) {
-                const cd u1 = cmulz(wp[i], vj), u2 = cmulz(vp[i], wj);
-                colbuf[i].x -= u1.x + u2.x;
-                colbuf[i].y -= u1.y + u2.y;
-            }
-        }
-        __syncthreads();
-        if (t == 0) dd[j] = colbuf[j].x;
-        if (j == n - 1) break;
+    const int p = j + 1;   // pivot column of the next reflector
+    cd *v = S.v[j & 1];    // v_j (unused for j = -1)
+    cd *vn = S.v[p & 1];   // receives v_{j+1}
+    if (j >= 0) {
+        const int L = n - p, nch = (L + 63) / 64;
+        const cd tau = tau_out[j];
         double part = 0.0;
-        for (int i = j + 2 + t; i < n; i += nt) part += colbuf[i].x * colbuf[i].x + colbuf[i].y * colbuf[i].y;
-        const double sigma = block_sum(part, red);
-        if (t == 0) {
-            const cd alpha = colbuf[j + 1];
-            if (sigma == 0.0 && alpha.y == 0.0) {
-                s_tau = cd{0.0, 0.0};
-                s_beta = alpha.x;
-                s_scale = cd{0.0, 0.0};
-            } else {
-                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
-                const double beta = alpha.x >= 0.0 ? -nrm : nrm;
-                s_tau = cd{(beta - alpha.x) / beta, -alpha.y / beta};
-                const double dr = alpha.x - beta, di = alpha.y;
-                const double den = dr * dr + di * di;
-                s_scale = cd{dr / den, -di / den};
-                s_beta = beta;
-            }
-        }
-        __syncthreads();
-        const cd tau = s_tau, scale = s_scale;
-        const bool reflect = !(tau.x == 0.0 && tau.y == 0.0);
-        for (int i = j + 1 + t; i < n; i += nt) {
-            cd vv;
-            if (!reflect) vv = cd{0.0, 0.0};
-            else if (i == j + 1) vv = cd{1.0, 0.0};
-            else vv = cmulz(colbuf[i], scale);
-            v[i] = vv;
-            if (i > j + 1) G.at(i, j) = vv;   // reflector kept for the back-transform
-        }
-        for (int i = t; i < nwaves * n; i += nt) ypart[i] = cd{0.0, 0.0};
-        if (t == 0) {
-            tau_out[j] = tau;
-            ee[j] = s_beta;
-            G.at(j + 1, j) = cd{s_beta, 0.0};
-        }
-        if (j == jsw) {   // move the trailing square to LDS
-            const int L = n - 1 - j;
-            for (int idx = t; idx < L * L; idx += nt) {
-                const int r = j + 1 + idx % L, c = j + 1 + idx / L;
-                S.at(r, c) = G.at(r, c);
-            }
-        }
-        __syncthreads();
-        if (j >= jsw) hetrd_pass(S, j, n, v, vp, wp, ypart, colbuf);
-        else hetrd_pass(G, j, n, v, vp, wp, ypart, colbuf);
-        __syncthreads();
-        double pv = 0.0;
-        for (int i = j + 1 + t; i < n; i += nt) {
+        for (int i = p + t; i < n; i += nt) {
             double sr = 0.0, si = 0.0;
-            for (int q = 0; q < nwaves; ++q) {
-                sr += ypart[q * n + i].x;
-                si += ypart[q * n + i].y;
+            for (int q = 0; q < nch; ++q) {
+                const cd y = S.ypart[(int64_t)q * n + i];
+                sr += y.x;
+                si += y.y;
             }
-            y[i] = cd{sr, si};
-            pv += v[i].x * sr + v[i].y * si;
+            s_y[i] = cd{sr, si};
+            const cd vi = v[i];
+            part += vi.x * sr + vi.y * si;
         }
-        const double vhy = block_sum(pv, red);
+        const double vhy = block_sum(part, red);
         const double nu = 0.5 * (tau.x * tau.x + tau.y * tau.y) * vhy;
-        for (int i = j + 1 + t; i < n; i += nt) {
-            const cd ty = cmulz(tau, y[i]);
-            wp[i] = reflect ? cd{ty.x - nu * v[i].x, ty.y - nu * v[i].y} : cd{0.0, 0.0};
-            vp[i] = v[i];
+        for (int i = t; i < n; i += nt) {
+            cd wi = {0.0, 0.0};
+            if (i >= p) {
+                const cd y = s_y[i], vi = v[i];
+                const cd ty = cmulz(tau, y);
+                wi = cd{ty.x - nu * vi.x, ty.y - nu * vi.y};
+            }
+            S.w[i] = wi;
+            s_wl[i] = wi;
         }
         __syncthreads();
+    } else {
+        for (int i = t; i < n; i += nt) {
+            S.w[i] = cd{0.0, 0.0};
+            s_wl[i] = cd{0.0, 0.0};
+        }
+        __syncthreads();
+    }
+    // pivot column p with the update of step j: A(i, p) - v_i conj(w_p) - w_i conj(v_p)
+    const cd w1 = s_wl[p];
+    const cd v1 = j >= 0 ? v[p] : cd{0.0, 0.0};
+    auto col = [&](int i) -> cd {
+        cd a = A[(int64_t)p * lda + i];
+        if (j >= 0) {
+            const cd vi = v[i], wi = s_wl[i];
+            const cd u1 = cmulz(vi, cconj(w1)), u2 = cmulz(wi, cconj(v1));
+            a.x -= u1.x + u2.x;
+            a.y -= u1.y + u2.y;
+        }
+        return a;
+    };
+    if (t == 0) dd[p] = col(p).x;
+    if (p == n - 1) return;
+    double part = 0.0;
+    for (int i = p + 2 + t; i < n; i += nt) {
+        const cd a = col(i);
+        part += a.x * a.x + a.y * a.y;
+    }
+    const double sigma = block_sum(part, red);
+    if (t == 0) {
+        const cd alpha = col(p + 1);
+        if (sigma == 0.0 && alpha.y == 0.0) {
+            s_tau = cd{0.0, 0.0};
+            s_beta = alpha.x;
+            s_scale = cd{0.0, 0.0};
+        } else {
+            const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
+            const double beta = alpha.x >= 0.0 ? -nrm : nrm;
+            const double dr = alpha.x - beta, di = alpha.y;
+            const double ib = 1.0 / beta, iden = 1.0 / (dr * dr + di * di);
+            s_tau = cd{-dr * ib, -alpha.y * ib};
+            s_scale = cd{dr * iden, -di * iden};
+            s_beta = beta;
+        }
+    }
+    __syncthreads();
+    const cd tau = s_tau, scale = s_scale;
+    const bool reflect = !(tau.x == 0.0 && tau.y == 0.0);
+    for (int i = t; i < n; i += nt) {
+        cd vv = {0.0, 0.0};
+        if (reflect && i == p + 1) vv = cd{1.0, 0.0};
+        else if (reflect && i > p + 1) vv = cmulz(col(i), scale);
+        vn[i] = vv;
+        if (i > p + 1) A[(int64_t)p * lda + i] = vv;   // reflector kept for the back-transform
+    }
+    if (t == 0) {
+        tau_out[p] = tau;
+        ee[p] = s_beta;
+        A[(int64_t)p * lda + p + 1] = cd{s_beta, 0.0};
     }
 }
 
 // ---- register-resident reduction for n <= 32 T (T <= 6) ----------------------
-// The same Householder sequence as k_hetrd (H_j = I - tau_j v_j v_j^H,
-// A <- H_j^H A H_j, w = tau y - (|tau|^2 / 2) Re(v^H y) v, A -= w v^H + v w^H),
+// The same Householder sequence as k_trd_apply / k_trd_step,
 // but the whole matrix stays in registers: 1024 threads on a 32 x 32 grid,
 // thread (ti, tj) holds A(ti + 32a, tj + 32b) for tiles b <= a.  Off-diagonal
 // tiles are stored once and used for both triangles of y = A v; diagonal tiles
@@ -1256,7 +1246,9 @@ void launch_chol_inv_f64(const cd *G, int64_t ldg, int n, cd *Rinv, int64_t ldr,
 }
 
 size_t heev_scratch_bytes(int n, int k) {
-    return 4 * 256 + (size_t)n * 16 + 2 * (size_t)n * 8 + (size_t)n * k * 8;
+    const size_t nch = (size_t)(n + 63) / 64;
+    return 8 * 256 + (size_t)n * 16 + 2 * (size_t)n * 8 + (size_t)n * k * 8 +
+           (3 + nch) * (size_t)n * 16;   // reflector pair, w and the y partials (n > 192)
 }
 
 void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t ldv, void *scratch,
@@ -1271,6 +1263,7 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     double *e = reinterpret_cast<double *>(p);
     p += align((size_t)n * 8);
     double *Z = reinterpret_cast<double *>(p);
+    p += align((size_t)n * k * 8);
     // 1. tridiagonalisation (the trailing block of A is overwritten in both triangles)
     if (n <= 32 * kRfMaxT) {
         const int T = (n + 31) / 32;
@@ -1283,12 +1276,24 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
             default: hipLaunchKernelGGL(k_hetrd_rf<6>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
         }
     } else {
-    const size_t base1 = (size_t)(5 + kTrdThreads / 64) * n * sizeof(cd) + kTrdThreads * sizeof(double);
-    const size_t cap_bytes = base1 < 156 * 1024 ? 156 * 1024 - base1 : 0;
-    const int lds_cap = (int)(cap_bytes / sizeof(cd));
-    const size_t sm1 = base1 + (size_t)lds_cap * sizeof(cd);
-    PW_HIP(hipFuncSetAttribute((const void *)k_hetrd, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1));
-    hipLaunchKernelGGL(k_hetrd, dim3(1), dim3(kTrdThreads), sm1, st, A, lda, n, d, e, tau, lds_cap);
+        TrdState S;
+        S.v[0] = reinterpret_cast<cd *>(p);
+        p += align((size_t)n * 16);
+        S.v[1] = reinterpret_cast<cd *>(p);
+        p += align((size_t)n * 16);
+        S.w = reinterpret_cast<cd *>(p);
+        p += align((size_t)n * 16);
+        S.ypart = reinterpret_cast<cd *>(p);
+        hipLaunchKernelGGL(k_herm_sym, dim3((unsigned)(((int64_t)n * n + 255) / 256)), dim3(256), 0, st, A, lda,
+                           n);
+        launch_zero(S.v[0], n, n, 1, st);
+        launch_zero(S.v[1], n, n, 1, st);
+        hipLaunchKernelGGL(k_trd_step, dim3(1), dim3(1024), 0, st, A, lda, n, -1, S, d, e, tau);
+        for (int j = 0; j + 1 < n; ++j) {
+            const int L = n - 1 - j, nb = (L + 63) / 64;
+            hipLaunchKernelGGL(k_trd_apply, dim3(nb * nb), dim3(256), 0, st, A, lda, n, j, S);
+            hipLaunchKernelGGL(k_trd_step, dim3(1), dim3(1024), 0, st, A, lda, n, j, S, d, e, tau);
+        }
     }
     // 2. eigenvalues
     const size_t sm2 = 2 * (size_t)n * 8;

@@ -571,7 +571,9 @@ int device_cu_count() {
 
 int choose_split(int64_t K, int tiles) {
     int64_t ns = (PW_SPLIT_WGS + tiles - 1) / tiles;
-    const int64_t kmax = (K + 255) / 256;   // chunks of at least 16 k-blocks
+    // chunks of at least 16 k-blocks, except for short K (coefficient-space
+    // products, K = 3m), which split down to single k-blocks (at most 16)
+    const int64_t kmax = std::max<int64_t>((K + 255) / 256, std::min<int64_t>((K + 15) / 16, 16));
     if (ns > kmax) ns = kmax;
     if (ns < 1) ns = 1;
     return (int)ns;
