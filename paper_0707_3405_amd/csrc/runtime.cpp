@@ -387,11 +387,17 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
     PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), st));
     bool all_converged = true;
     std::vector<double> hres(std::max(M, 3 * m));
+    // residual norms below this are rounding noise (Ha; the spectrum scale is ~ecut)
+    const double res_floor = 1e-10 * std::max(1.0, c->ecut);
 
     // Each block iterates mb = min(m, keep + guard) columns; the lowest `keep`
     // must converge and are stored, the top `guard` columns only shield them
     // from a near-degenerate neighbour just above the block.
-    const int guard = m / 8;
+    const int guard = m / 5;   // measured best of m/8 .. m/3 with the warm start below
+    // the guard Ritz vectors of the previous block (bands just above it) seed
+    // the next block when the caller gives no guess
+    S *prevZ = nullptr;
+    int prev_keep = 0, prev_mb = 0;
     for (int b0 = 0; b0 < M;) {
         const int keep = std::min(m - guard, M - b0);
         const int mb = (int)std::min<int64_t>(std::min(m, keep + guard), npw - b0);
@@ -406,8 +412,15 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
         // start block: X in slot 0 (caller guess for the stored columns)
         const int nguess = use_guess ? std::min(mb, M - b0) : 0;
         if (nguess > 0) pw::launch_copy_cols(X + (int64_t)b0 * ldx, ldx, Z, ld, npw, nguess, st);
-        if (nguess < mb)
-            pw::launch_random_block(Z + (int64_t)nguess * ld, ld, npw, mb - nguess,
+        int nwarm = 0;
+        if (nguess == 0 && prevZ && prev_mb > prev_keep) {
+            // source columns [prev_keep, prev_mb) never overlap [0, nwarm) (prev_keep >= guard)
+            nwarm = std::min(prev_mb - prev_keep, mb);
+            pw::launch_copy_cols(prevZ + (int64_t)prev_keep * ld, ld, Z, ld, npw, nwarm, st);
+        }
+        const int nfill = std::max(nguess, nwarm);
+        if (nfill < mb)
+            pw::launch_random_block(Z + (int64_t)nfill * ld, ld, npw, mb - nfill,
                                     0x5EED0000ull + (uint64_t)b0, c->sp.kin, st);
         // orthogonal to previous blocks, orthonormal (twice)
         if (gen) {
@@ -494,10 +507,17 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
                     break;
                 }
             }
+            // soft locking: a column at the rounding floor of its residual gets no new
+            // direction either (in the fixed-sweep mode, tol = 0, such a direction
+            // would be rounding noise that CholQR blows up to unit norm)
             act.clear();
             for (int j = 0; j < mb; ++j)
-                if (hres[j] > tol) act.push_back(j);
+                if (hres[j] > std::max(tol, res_floor)) act.push_back(j);
             const int na = (int)act.size();
+            if (na == 0) {   // every column at the floor: the block is stationary
+                if (tol == 0.0) it = max_iter;   // the remaining fixed sweeps are no-ops
+                break;
+            }
             PW_HIP(hipMemcpyAsync(p.act, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
             const int wcol = mb + np;
             S *W = Z + (int64_t)wcol * ld;
@@ -581,6 +601,9 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
         pw::launch_copy_cols(Z, ld, X + (int64_t)b0 * ldx, ldx, npw, keep, st);
         pw::launch_copy_cols(HZ, ld, p.HXall + (int64_t)b0 * ld, ld, npw, keep, st);
         if (gen) pw::launch_copy_cols(OZ, ld, p.OXall + (int64_t)b0 * ld, ld, npw, keep, st);
+        prevZ = Z;
+        prev_keep = keep;
+        prev_mb = mb;
         b0 += keep;
     }
 
