@@ -34,7 +34,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a plain-copy
 # calibration; profiles/hbm_bytes_fcc108_l20.txt) for the kernels as they were profiled;
 # set an entry to None when its kernels change.
-TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 2.82e8, "dense": None}
+TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 2.96e8, "dense": None}
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
 WORKLOAD = "fcc108_l20"
 
@@ -88,6 +88,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=15)
     ap.add_argument("--mixed-steps", type=int, default=2, help="timed solves in the mixed form")
+    ap.add_argument("--autotune", type=int, default=1,
+                    help="also run the autotuner on a fresh context and time one solve with its choice")
     ap.add_argument("--overlap-steps", type=int, default=1,
                     help="timed solves of the same cell in the generalized form (O != I)")
     ap.add_argument("--batch-steps", type=int, default=1,
@@ -198,6 +200,24 @@ def main():
                            "phase_ms": {k: gst[k] for k in ("ms_apply", "ms_gemm", "ms_dense",
                                                             "ms_vec", "ms_final_rr")}}
             del gprob, Xg
+
+        # ---- autotuner on a fresh context of the same cell (FFT tiles, split-K target),
+        # and one FP64 solve with its choice
+        tuned = None
+        if args.autotune:
+            tprob = PlaneWaveProblem.from_workload(w, device=0)
+            tchoice = tprob.ctx.autotune(w.block)
+            Xt = tprob.empty_block(w.nbands)
+            tprob.ctx.lobpcg_solve(w.nbands, w.block, w.tol, 300, Xt)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            eigt, _ = tprob.ctx.lobpcg_solve(w.nbands, w.block, w.tol, 300, Xt)
+            torch.cuda.synchronize()
+            tdt = time.perf_counter() - t0
+            tuned = {"choice": tchoice, "value": w.nbands / tdt, "unit": "eigenpairs/s",
+                     "max_abs_eig_diff_vs_default_ha": float(np.abs(eigt - eig64).max())}
+            log(f"autotuned: {tchoice}, {w.nbands / tdt:.1f} eigenpairs/s")
+            del tprob, Xt
 
         # ---- full H.X (local + 432 projectors) per 64 bands in the three forms
         Xh = torch.randn((w.block, npw), dtype=torch.complex128, device="cuda")
@@ -365,6 +385,7 @@ def main():
         "mixed": mixed,
         "mixed_bf16": mixed_bf16,
         "generalized": generalized,
+        "autotuned": tuned,
         "hx_full_ms_per_64_bands": hx_full,
         "batched_kpoints": batched,
         "served": served,

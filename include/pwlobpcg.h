@@ -160,6 +160,34 @@ pw_status pw_set_workspace(pw_ctx ctx, void *dptr, size_t bytes);
 pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ldy,
                      int32_t nb, pw_precision prec);
 
+/* Launch parameters of a context (0 = built-in default) and, from
+ * pw_autotune, the timings behind the choice (ms per launch).  The choice
+ * changes the partition of the work only: the FFT results are the same, the
+ * split-K sums may differ in rounding. */
+typedef struct {
+    int32_t fft_sticks_per_block;   /* z passes: sticks per workgroup, 0 or 1..64 (default 16) */
+    int32_t fft_plane_rows;         /* plane pass: row chunk, 0 or 1..128 (default 32, capped by LDS) */
+    int32_t gemm_split_workgroups;  /* split-K TN target workgroups, 0 or 1..1024 (default 1024) */
+    double apply_ms_default, apply_ms_tuned;   /* local H X of nb bands */
+    double gemm_ms_default, gemm_ms_tuned;     /* 3m x 3m Gram over npw (+ projector overlaps) */
+} pw_tuning;
+
+/* Autotuner for this context's shapes (batched k-points and served requests
+ * differ in npw, grid and projector count): times the local H X of nb bands
+ * (1 <= nb <= block of the workspace) for sticks per block {16, 32, 64} x
+ * plane rows {8, 16, 32}, and the Rayleigh-Ritz Gram (3 block x 3 block over
+ * npw) plus the projector overlaps for split targets {384, 512, 768, 1024},
+ * with HIP events on the context stream (mean of 5 after a warm-up); keeps
+ * the fastest of each (or the default when nothing beats it) for later
+ * calls on this context and reports it in *out.  Needs basis, potential,
+ * projectors if any, and a workspace; overwrites workspace contents only.
+ * Synchronises the stream. */
+pw_status pw_autotune(pw_ctx ctx, int32_t nb, pw_tuning *out);
+/* Set the three launch parameters (the timing fields are ignored); NULL
+ * restores the defaults.  Out-of-range values -> PW_ERR_ARG.  Contexts given
+ * the same parameters give bitwise the same results. */
+pw_status pw_set_tuning(pw_ctx ctx, const pw_tuning *t);
+
 /* Y = O X (the overlap of pw_set_overlap; PW_ERR_STATE if none is set), with
  * the same blocks, precisions, requirements and stream behaviour as
  * pw_apply_H: a copy of X plus the projector products B diag(q) B^H X. */
@@ -222,8 +250,9 @@ pw_status pw_get_stats(pw_ctx ctx, pw_stats *stats);
 
 /* Gram block C = A^H B (sec. 4.1: Gram blocks by zgemm over the plane-wave
  * coefficients; Algorithm 1 step 4).  A [K x p], B [K x q], C [p x q].
- * Deterministic split-K reduction; needs the workspace (size from
- * pw_workspace_size). */
+ * Deterministic split-K reduction in the workspace: at least p q complex128
+ * (PW_ERR_NOMEM otherwise); a workspace smaller than the split needs only
+ * lowers the number of K chunks. */
 pw_status pw_gram(pw_ctx ctx, const void *A, int64_t lda, const void *B, int64_t ldb,
                   int64_t K, int32_t p, int32_t q, void *C, int64_t ldc);
 /* Block update Y = alpha A C + beta Y (Algorithm 1 steps 4-5: Psi Delta +

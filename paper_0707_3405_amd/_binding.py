@@ -27,7 +27,8 @@ EXPORTS = ("pw_create", "pw_destroy", "pw_last_error", "pw_init_basis", "pw_fft_
            "pw_workspace_size", "pw_set_workspace", "pw_apply_H", "pw_lobpcg_solve",
            "pw_get_residuals", "pw_get_stats", "pw_gram", "pw_block_update", "pw_small_eigh",
            "pw_residuals", "pw_gram_mixed", "pw_block_update_mixed", "pw_lobpcg_solve_batch",
-           "pw_density", "pw_set_overlap", "pw_apply_O", "pw_chol_inv")
+           "pw_density", "pw_set_overlap", "pw_apply_O", "pw_chol_inv", "pw_autotune",
+           "pw_set_tuning")
 
 
 class PWError(RuntimeError):
@@ -35,6 +36,16 @@ class PWError(RuntimeError):
         super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
         self.status = status
         self.message = message
+
+
+class PWTuning(ctypes.Structure):
+    _fields_ = [("fft_sticks_per_block", ctypes.c_int32), ("fft_plane_rows", ctypes.c_int32),
+                ("gemm_split_workgroups", ctypes.c_int32), ("apply_ms_default", ctypes.c_double),
+                ("apply_ms_tuned", ctypes.c_double), ("gemm_ms_default", ctypes.c_double),
+                ("gemm_ms_tuned", ctypes.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class PWStats(ctypes.Structure):
@@ -82,6 +93,8 @@ def load_library():
         "pw_apply_O": (ctypes.c_int, [P, P, I64, P, I64, I32, ctypes.c_int]),
         "pw_set_overlap": (ctypes.c_int, [P, P]),
         "pw_chol_inv": (ctypes.c_int, [P, P, I64, I32, P, I64]),
+        "pw_autotune": (ctypes.c_int, [P, I32, ctypes.POINTER(PWTuning)]),
+        "pw_set_tuning": (ctypes.c_int, [P, ctypes.POINTER(PWTuning)]),
         "pw_lobpcg_solve": (ctypes.c_int, [P, I32, I32, D, I32, ctypes.c_int, P, I64, I32, P]),
         "pw_get_residuals": (ctypes.c_int, [P, P]),
         "pw_get_stats": (ctypes.c_int, [P, ctypes.POINTER(PWStats)]),
@@ -293,6 +306,19 @@ class Context:
 
     def small_eigh(self, A, n, k, w, V):
         self._check(self.lib.pw_small_eigh(self.h, _ptr(A), _ld(A), n, k, _ptr(w), _ptr(V), _ld(V)))
+
+    def autotune(self, nb):
+        """Time the FFT tile and split-K candidates on this context; keep and return the choice."""
+        out = PWTuning()
+        self._check(self.lib.pw_autotune(self.h, nb, ctypes.byref(out)))
+        return out.as_dict()
+
+    def set_tuning(self, fft_sticks_per_block=0, fft_plane_rows=0, gemm_split_workgroups=0, reset=False):
+        if reset:
+            self._check(self.lib.pw_set_tuning(self.h, None))
+            return
+        t = PWTuning(fft_sticks_per_block, fft_plane_rows, gemm_split_workgroups, 0.0, 0.0, 0.0, 0.0)
+        self._check(self.lib.pw_set_tuning(self.h, ctypes.byref(t)))
 
     def chol_inv(self, G, n, Rinv):
         """Rinv = R^-1 for G = R^H R (device complex128 tensors, [col][row] storage)."""

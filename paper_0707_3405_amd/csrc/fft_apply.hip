@@ -339,19 +339,20 @@ __global__ void k_permute_v(const double *__restrict__ v, double scale, double *
 }
 
 // ---- dispatch ---------------------------------------------------------------
-constexpr int kSticksPerBlock = 32;
+constexpr int kSticksPerBlock = 16;   // default sticks per workgroup of the z passes
 
 template <int N, class T>
 void run_apply(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
                int64_t ldy, int nb, cpx<T> *S, hipStream_t st) {
-    const int spb = kSticksPerBlock;
+    const Tuning &tune = thread_tuning();
+    const int spb = tune.fft_spb > 0 ? tune.fft_spb : kSticksPerBlock;
     const size_t e = sizeof(cpx<T>);
     const size_t sm13 = (size_t)N * e + (size_t)spb * (N + 1) * e;
     dim3 g13((sp.nst + spb - 1) / spb, nb);
     // pass 2 LDS: twiddles + kept columns + row chunk; largest row chunk that
     // keeps the workgroup under 150 KB.
     const size_t base2 = (size_t)N * e + (size_t)sp.ncx * (N + 1) * e;
-    int rb = PW_PLANE_RB;
+    int rb = tune.fft_rb > 0 ? tune.fft_rb : PW_PLANE_RB;
     auto sm2_of = [&](int r) { return base2 + (size_t)r * (N + 1) * e; };
     while (rb > 1 && sm2_of(rb) > 150 * 1024) rb /= 2;
     if (rb > N) rb = N;

@@ -552,7 +552,7 @@ __global__ void __launch_bounds__(kThreads)
 }
 
 #ifndef PW_SPLIT_WGS
-#define PW_SPLIT_WGS 768   // target workgroup count of a split-K launch
+#define PW_SPLIT_WGS 1024   // target workgroup count of a split-K launch
 #endif
 // compute units of the current device (queried once per process and device)
 int device_cu_count() {
@@ -569,8 +569,8 @@ int device_cu_count() {
     return n;
 }
 
-int choose_split(int64_t K, int tiles) {
-    int64_t ns = (PW_SPLIT_WGS + tiles - 1) / tiles;
+int choose_split(int64_t K, int tiles, int target) {
+    int64_t ns = (target + tiles - 1) / tiles;
     // chunks of at least 16 k-blocks, except for short K (coefficient-space
     // products, K = 3m), which split down to single k-blocks (at most 16)
     const int64_t kmax = std::max<int64_t>((K + 255) / 256, std::min<int64_t>((K + 15) / 16, 16));
@@ -583,7 +583,7 @@ int choose_split(int64_t K, int tiles) {
 
 size_t gemm_tn_part_elems(int64_t K, int p, int q, int *nsplit_out) {
     const int tiles = ((p + kTile - 1) / kTile) * ((q + kTile - 1) / kTile);
-    const int ns = choose_split(K, tiles);
+    const int ns = choose_split(K, tiles, std::max(PW_SPLIT_WGS, kTnSplitMax));   // any tuned target fits
     if (nsplit_out) *nsplit_out = ns;
     return (size_t)ns * p * q;
 }
@@ -594,7 +594,8 @@ void gemm_tn_impl(const cpx<T> *A, int64_t lda, const cpx<T> *B, int64_t ldb, in
                   hipStream_t st) {
     if (p <= 0 || q <= 0) return;
     const int tiles_m = (p + kTile - 1) / kTile, tiles_n = (q + kTile - 1) / kTile;
-    int ns = choose_split(K, tiles_m * tiles_n);
+    const int target = thread_tuning().tn_split_wgs > 0 ? thread_tuning().tn_split_wgs : PW_SPLIT_WGS;
+    int ns = choose_split(K, tiles_m * tiles_n, target);
     if ((size_t)ns * p * q > part_elems) ns = (int)(part_elems / ((size_t)p * q));
     PW_REQUIRE(ns >= 1, PW_ERR_NOMEM, "GEMM partial buffer too small");
     int64_t kchunk = (K + ns - 1) / ns;

@@ -77,6 +77,18 @@ void launch_density_finish(const double *rho_zyx, int n, double scale, double *r
 bool fft_size_supported(int n);
 std::vector<int> fft_supported_sizes();
 
+// Launch parameters of the FFT passes and the split-K GEMM chosen per context
+// (pw_autotune / pw_set_tuning; 0 = built-in default).  The launchers read the
+// record of the context whose API call is running on this host thread.
+struct Tuning {
+    int fft_spb = 0;        // sticks per workgroup of the z passes
+    int fft_rb = 0;         // row chunk of the plane pass (capped by LDS)
+    int tn_split_wgs = 0;   // target workgroup count of a split-K TN launch
+};
+const Tuning &thread_tuning();
+const Tuning *set_thread_tuning(const Tuning *t);   // returns the previous record
+constexpr int kTnSplitMax = 1024;   // largest split target; partial buffers are sized for it
+
 // Complex GEMMs on MFMA over complex128 (cd) or complex64 (cf) blocks;
 // small outputs and coefficient matrices are always complex128.
 //   tn: part[s] = A^H B over K-chunk s; reduce: C = scale_row * sum_s part[s] (+ beta C)

@@ -75,6 +75,19 @@ struct PhaseTimer {
 
 }  // namespace
 
+namespace pw {
+namespace {
+const Tuning kDefaultTuning{};
+thread_local const Tuning *t_tuning = nullptr;
+}  // namespace
+const Tuning &thread_tuning() { return t_tuning ? *t_tuning : kDefaultTuning; }
+const Tuning *set_thread_tuning(const Tuning *t) {
+    const Tuning *prev = t_tuning;
+    t_tuning = t;
+    return prev;
+}
+}  // namespace pw
+
 struct pw_ctx_s {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -102,6 +115,7 @@ struct pw_ctx_s {
     cd *d_B = nullptr;
     pw::cf *d_B32 = nullptr;   // complex64 copy for the mixed form
     bool proj_bf16 = false;    // complex64 projector products on split-bf16 MFMA
+    pw::Tuning tune;           // launch parameters (pw_autotune / pw_set_tuning)
     double *d_D = nullptr;
     double *d_Q = nullptr;     // overlap coefficients (generalized form); null: O = I
 
@@ -920,9 +934,17 @@ void set_overlap(pw_ctx_s *c, const double *q) {
     PW_HIP(hipMemcpy(c->d_Q, q, np * sizeof(double), hipMemcpyHostToDevice));
 }
 
+// the context's launch parameters for the duration of one API call on this thread
+struct TuningScope {
+    const pw::Tuning *prev;
+    explicit TuningScope(const pw::Tuning *t) : prev(pw::set_thread_tuning(t)) {}
+    ~TuningScope() { pw::set_thread_tuning(prev); }
+};
+
 template <class F>
 pw_status guard(pw_ctx c, F &&f) {
     if (!c) return PW_ERR_ARG;
+    TuningScope scope(&c->tune);
     try {
         c->err.clear();
         return f();
@@ -951,7 +973,9 @@ pw_status gram_impl(pw_ctx c, const void *A, int64_t lda, const void *B, int64_t
                    "bad GEMM shape");
         PW_REQUIRE(c->ws != nullptr, PW_ERR_STATE, "pw_set_workspace has not been called");
         if (p == 0 || q == 0) return PW_OK;
-        const size_t need = pw::gemm_tn_part_elems(K, p, q, nullptr) * sizeof(cd);
+        // one K chunk needs p q partials; a smaller workspace than the full split
+        // only lowers the number of chunks (the launcher clamps it)
+        const size_t need = (size_t)p * q * sizeof(cd);
         PW_REQUIRE(need <= c->ws_bytes, PW_ERR_NOMEM, "workspace too small for this Gram");
         if (K == 0) {
             pw::launch_zero(static_cast<cd *>(C), ldc, p, q, c->stream);
@@ -1187,6 +1211,102 @@ pw_status pw_lobpcg_solve_batch(pw_ctx *ctxs, int32_t n, int32_t nbands, int32_t
     for (int i = 0; i < n; ++i)
         if (status[i] != PW_OK && (worst == PW_OK || worst == PW_ERR_NOT_CONVERGED)) worst = status[i];
     return worst;
+}
+
+pw_status pw_set_tuning(pw_ctx c, const pw_tuning *t) {
+    return guard(c, [&] {
+        if (!t) {
+            c->tune = pw::Tuning{};
+            return PW_OK;
+        }
+        PW_REQUIRE(t->fft_sticks_per_block >= 0 && t->fft_sticks_per_block <= 64, PW_ERR_ARG,
+                   "fft_sticks_per_block must be in [0, 64]");
+        PW_REQUIRE(t->fft_plane_rows >= 0 && t->fft_plane_rows <= 128, PW_ERR_ARG,
+                   "fft_plane_rows must be in [0, 128]");
+        PW_REQUIRE(t->gemm_split_workgroups >= 0 && t->gemm_split_workgroups <= pw::kTnSplitMax, PW_ERR_ARG,
+                   "gemm_split_workgroups must be in [0, 1024]");
+        c->tune.fft_spb = t->fft_sticks_per_block;
+        c->tune.fft_rb = t->fft_plane_rows;
+        c->tune.tn_split_wgs = t->gemm_split_workgroups;
+        return PW_OK;
+    });
+}
+
+pw_status pw_autotune(pw_ctx c, int32_t nb, pw_tuning *out) {
+    return guard(c, [&] {
+        require_basis(c);
+        require_device(c);
+        PW_REQUIRE(out, PW_ERR_ARG, "null output");
+        PW_REQUIRE(c->plan_block > 0, PW_ERR_STATE, "call pw_workspace_size before pw_autotune");
+        PW_REQUIRE(nb >= 1 && nb <= c->plan_block, PW_ERR_ARG, "need 1 <= nb <= block of the workspace");
+        PW_HIP(hipSetDevice(c->device));
+        const int m = c->plan_block;
+        Plan<cd> p = ready_plan<cd>(c, std::max(c->plan_nbands, 1), m);
+        hipStream_t st = c->stream;
+        const int64_t ld = c->ldp, npw = c->npw;
+        const int np = c->nproj(), nz = (int)std::min<int64_t>(3 * m, npw);
+        pw::launch_random_block(p.Z[0], ld, npw, nz, 0xA070ull, c->sp.kin, st);
+        pw::launch_random_block(p.HZ[0], ld, npw, nz, 0xA071ull, c->sp.kin, st);
+        hipEvent_t e0, e1;
+        PW_HIP(hipEventCreate(&e0));
+        PW_HIP(hipEventCreate(&e1));
+        auto timed = [&](auto &&fn) {   // mean of 5 after one warm-up, ms
+            fn();
+            PW_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < 5; ++r) fn();
+            PW_HIP(hipEventRecord(e1, st));
+            PW_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            PW_HIP(hipEventElapsedTime(&ms, e0, e1));
+            return (double)ms / 5.0;
+        };
+        auto apply = [&] { pw::launch_fft_apply(c->sp, c->d_v, p.Z[0], ld, p.HZ[0] + 0, ld, nb, p.Sb, st); };
+        auto gemm = [&] {
+            pw::launch_gemm_tn(p.Z[0], ld, p.HZ[0], ld, npw, nz, nz, p.Agram, nz, nullptr, 0.0, p.part,
+                               p.part_elems, st);
+            if (np > 0)
+                pw::launch_gemm_tn(c->d_B, c->ldp, p.Z[0], ld, npw, np, m, p.Pj, np, c->d_D, 0.0, p.part,
+                                   p.part_elems, st);
+        };
+        c->tune = pw::Tuning{};
+        const double apply_def = timed(apply), gemm_def = timed(gemm);
+        pw::Tuning best{};
+        double apply_best = apply_def, gemm_best = gemm_def;
+        const int spb_c[] = {16, 32, 64}, rb_c[] = {8, 16, 32};
+        for (int spb : spb_c)
+            for (int rb : rb_c) {
+                c->tune = pw::Tuning{};
+                c->tune.fft_spb = spb;
+                c->tune.fft_rb = rb;
+                const double t = timed(apply);
+                if (t < apply_best) {
+                    apply_best = t;
+                    best.fft_spb = spb;
+                    best.fft_rb = rb;
+                }
+            }
+        const int split_c[] = {384, 512, 768, 1024};
+        for (int sw : split_c) {
+            c->tune = pw::Tuning{};
+            c->tune.tn_split_wgs = sw;
+            const double t = timed(gemm);
+            if (t < gemm_best) {
+                gemm_best = t;
+                best.tn_split_wgs = sw;
+            }
+        }
+        c->tune = best;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        out->fft_sticks_per_block = best.fft_spb;
+        out->fft_plane_rows = best.fft_rb;
+        out->gemm_split_workgroups = best.tn_split_wgs;
+        out->apply_ms_default = apply_def;
+        out->apply_ms_tuned = apply_best;
+        out->gemm_ms_default = gemm_def;
+        out->gemm_ms_tuned = gemm_best;
+        return PW_OK;
+    });
 }
 
 pw_status pw_density(pw_ctx c, const void *X, int64_t ldx, int32_t nb, const double *occ,
