@@ -59,11 +59,12 @@ constexpr int kCholMax = 64;
 
 __global__ void __launch_bounds__(1024) k_chol_inv(const cd *__restrict__ G, int64_t ldg, int n,
                                                    cd *__restrict__ Rinv, int64_t ldr, int *status) {
-    __shared__ cd pg[2][kCholMax];   // pivot row of G (columns j .. 63 meaningful)
-    __shared__ cd pu[2][kCholMax];   // pivot row of the augmented half (columns 0 .. j)
+    // pivot rows j, j + 1 of a pair step, double buffered: [buffer][row of the pair][column]
+    __shared__ cd pg[2][2][kCholMax];   // G part (columns >= j meaningful)
+    __shared__ cd pu[2][2][kCholMax];   // augmented part (columns <= j + 1 meaningful)
     __shared__ double diag[kCholMax];
     const int t = threadIdx.x, ti = t >> 5, tj = t & 31;
-    const int a0 = 2 * ti, b0 = 2 * tj;
+    const int a0 = 2 * ti, b0 = 2 * tj;         // rows a0, a0 + 1 form one pivot pair
     const int wrow_last = 4 * (t >> 6) + 3;   // last row of this wave
     cd g[2][2], u[2][2];
 #pragma unroll
@@ -80,9 +81,9 @@ __global__ void __launch_bounds__(1024) k_chol_inv(const cd *__restrict__ G, int
             g[ia][ib] = v;
             u[ia][ib] = cd{a == b ? 1.0 : 0.0, 0.0};
             if (a == b) diag[a] = v.x;
-            if (a == 0) {
-                pg[0][b] = v;
-                pu[0][b] = u[ia][ib];
+            if (ti == 0) {
+                pg[0][ia][b] = v;
+                pu[0][ia][b] = u[ia][ib];
             }
         }
     __syncthreads();
@@ -92,55 +93,78 @@ __global__ void __launch_bounds__(1024) k_chol_inv(const cd *__restrict__ G, int
     const double shift = 1e-15 * dmax * n;
     bool fail = false;
     double dpiv[2] = {1.0, 1.0};   // pivots of this thread's rows (rows stay unscaled)
-    for (int j = 0; j < n; ++j) {
-        const cd *prg = pg[j & 1], *pru = pu[j & 1];
-        double d = prg[j].x + shift;
-        if (!(d > 1e-300) || !isfinite(d)) {
+    // two pivots per barrier: every thread forms row j + 1 after pivot j itself
+    // from the two broadcast rows (row j + 1 arrives without pivot j applied)
+    for (int j = 0; j < n; j += 2) {
+        const int bsel = (j >> 1) & 1;
+        const cd *r0g = pg[bsel][0], *r1g = pg[bsel][1], *r0u = pu[bsel][0], *r1u = pu[bsel][1];
+        double d0 = r0g[j].x + shift;
+        if (!(d0 > 1e-300) || !isfinite(d0)) {
             fail = true;
-            d = 1.0;
+            d0 = 1.0;
         }
+        const double inv0 = rcp_nr(d0);
+        const cd c01 = r0g[j + 1];
+        const cd l = {c01.x * inv0, -c01.y * inv0};   // row j + 1 multiplier of pivot j
+        auto r1gp = [&](int c) {                       // row j + 1 of G after pivot j
+            const cd pr = cmulz(l, r0g[c]);
+            const cd v = r1g[c];
+            return cd{v.x - pr.x, v.y - pr.y};
+        };
+        double d1 = r1gp(j + 1).x + shift;
+        if (j + 1 < n && (!(d1 > 1e-300) || !isfinite(d1))) {
+            fail = true;
+            d1 = 1.0;
+        }
+        if (j + 1 >= n) d1 = 1.0;
 #pragma unroll
-        for (int ia = 0; ia < 2; ++ia)
-            if (a0 + ia == j) dpiv[ia] = d;
-        if (wrow_last > j) {   // rows below the pivot in this wave (uniform per wave)
-            const double inv_d = rcp_nr(d);
-            cd ma[2];
+        for (int ia = 0; ia < 2; ++ia) {
+            if (a0 + ia == j) dpiv[ia] = d0;
+            if (a0 + ia == j + 1) dpiv[ia] = d1;
+        }
+        if (wrow_last > j) {   // rows below pivot j in this wave (uniform per wave)
+            const double inv1 = rcp_nr(d1);
+            cd m0[2], m1[2];
 #pragma unroll
             for (int ia = 0; ia < 2; ++ia) {
                 const int a = a0 + ia;
-                const cd p = prg[a];
-                ma[ia] = a > j ? cd{p.x * inv_d, -p.y * inv_d} : cd{0.0, 0.0};
+                const cd p0 = r0g[a], p1 = r1gp(a);
+                m0[ia] = a > j ? cd{p0.x * inv0, -p0.y * inv0} : cd{0.0, 0.0};
+                m1[ia] = a > j + 1 ? cd{p1.x * inv1, -p1.y * inv1} : cd{0.0, 0.0};
             }
-            cd gb[2], ub[2];
+            cd g0[2], g1[2], u0[2], u1[2];
 #pragma unroll
             for (int ib = 0; ib < 2; ++ib) {
-                gb[ib] = prg[b0 + ib];
-                ub[ib] = pru[b0 + ib];
+                const int b = b0 + ib;
+                g0[ib] = r0g[b];
+                g1[ib] = r1gp(b);
+                u0[ib] = r0u[b];
+                const cd pr = cmulz(l, u0[ib]), v = r1u[b];
+                u1[ib] = cd{v.x - pr.x, v.y - pr.y};
             }
 #pragma unroll
             for (int ia = 0; ia < 2; ++ia)
 #pragma unroll
                 for (int ib = 0; ib < 2; ++ib) {
                     const int a = a0 + ia, b = b0 + ib;
-                    if (b >= a) {   // columns b > j only, since a > j (ma = 0 otherwise)
-                        const cd pr = cmulz(ma[ia], gb[ib]);
-                        g[ia][ib].x -= pr.x;
-                        g[ia][ib].y -= pr.y;
+                    if (b >= a) {
+                        const cd p0 = cmulz(m0[ia], g0[ib]), p1 = cmulz(m1[ia], g1[ib]);
+                        g[ia][ib].x -= p0.x + p1.x;
+                        g[ia][ib].y -= p0.y + p1.y;
                     }
-                    const cd pu2 = cmulz(ma[ia], ub[ib]);
-                    u[ia][ib].x -= pu2.x;
-                    u[ia][ib].y -= pu2.y;
+                    const cd q0 = cmulz(m0[ia], u0[ib]), q1 = cmulz(m1[ia], u1[ib]);
+                    u[ia][ib].x -= q0.x + q1.x;
+                    u[ia][ib].y -= q0.y + q1.y;
                 }
-            // the next pivot row (final after this step) to the other buffer
-            if (j + 1 < n) {
+            // the next pair's rows (j + 2 after pivots <= j + 1, j + 3 likewise) to the other buffer
+            if (j + 2 < n && a0 == j + 2) {
 #pragma unroll
                 for (int ia = 0; ia < 2; ++ia)
-                    if (a0 + ia == j + 1)
 #pragma unroll
-                        for (int ib = 0; ib < 2; ++ib) {
-                            pg[(j + 1) & 1][b0 + ib] = g[ia][ib];
-                            pu[(j + 1) & 1][b0 + ib] = u[ia][ib];
-                        }
+                    for (int ib = 0; ib < 2; ++ib) {
+                        pg[bsel ^ 1][ia][b0 + ib] = g[ia][ib];
+                        pu[bsel ^ 1][ia][b0 + ib] = u[ia][ib];
+                    }
             }
         }
         __syncthreads();
@@ -1026,7 +1050,7 @@ __global__ void __launch_bounds__(256) k_unmtr(const cd *__restrict__ A, int64_t
 constexpr int kOc2Ld = 68;   // LDS row stride of Z (doubles)
 constexpr int kOc2Lr = 65;   // LDS row stride of G and of R^-1
 __host__ __device__ constexpr size_t orth_chol2_lds(int n) {
-    return ((size_t)((n + 15) / 16 * 16) * kOc2Ld + 64 * kOc2Lr + 4 * 64) * sizeof(double);
+    return ((size_t)((n + 15) / 16 * 16) * kOc2Ld + 64 * kOc2Lr + 8 * 64) * sizeof(double);
 }
 __global__ void __launch_bounds__(1024) k_orth_chol2(double *__restrict__ Zg, int n, int k,
                                                      int *__restrict__ status) {
@@ -1035,8 +1059,8 @@ __global__ void __launch_bounds__(1024) k_orth_chol2(double *__restrict__ Zg, in
     const int n16 = (n + 15) / 16 * 16;     // rows padded with zeros to whole tiles
     double *Z = smd;                        // [n16][kOc2Ld], columns >= k zero
     double *Gs = Z + (size_t)n16 * kOc2Ld;  // [64][kOc2Lr]: G, then R^-1
-    double *pg = Gs + 64 * kOc2Lr;          // [2][64] pivot rows of G
-    double *pu = pg + 2 * 64;               // [2][64] pivot rows of the augmented half
+    double *pg = Gs + 64 * kOc2Lr;          // [2][2][64] pivot row pairs of G
+    double *pu = pg + 4 * 64;               // [2][2][64] pivot row pairs of the augmented half
     const int t = threadIdx.x, nt = blockDim.x;
     const int ti = t >> 5, tj = t & 31, a0 = 2 * ti, b0 = 2 * tj;
     const int wave = t >> 6, lane = t & 63, li = lane & 15, lg = lane >> 4;
@@ -1067,46 +1091,70 @@ __global__ void __launch_bounds__(1024) k_orth_chol2(double *__restrict__ Zg, in
                 const int a = a0 + ia, b = b0 + ib;
                 g[ia][ib] = (a == b && a >= k) ? 1.0 : Gs[a * kOc2Lr + b];
                 u[ia][ib] = a == b ? 1.0 : 0.0;
-                if (a == 0) {
-                    pg[b] = g[ia][ib];
-                    pu[b] = u[ia][ib];
+                if (ti == 0) {   // rows 0 and 1: the first pivot pair
+                    pg[64 * ia + b] = g[ia][ib];
+                    pu[64 * ia + b] = u[ia][ib];
                 }
             }
         __syncthreads();
-        for (int j = 0; j < 64; ++j) {
-            const double *prg = pg + 64 * (j & 1), *pru = pu + 64 * (j & 1);
-            double d = prg[j];
-            if (!(d > 1e-300) || !isfinite(d)) {
+        // two pivots per barrier (as in k_chol_inv): rows j, j + 1 arrive with
+        // the pivots < j applied; row j + 1 after pivot j is formed locally
+        for (int j = 0; j < 64; j += 2) {
+            const int bsel = (j >> 1) & 1;
+            const double *r0g = pg + 128 * bsel, *r1g = r0g + 64, *r0u = pu + 128 * bsel, *r1u = r0u + 64;
+            double d0 = r0g[j];
+            if (!(d0 > 1e-300) || !isfinite(d0)) {
                 fail = true;
-                d = 1.0;
+                d0 = 1.0;
+            }
+            const double inv0 = rcp_nr(d0);
+            const double l = r0g[j + 1] * inv0;
+            double d1 = r1g[j + 1] - l * r0g[j + 1];
+            if (!(d1 > 1e-300) || !isfinite(d1)) {
+                fail = true;
+                d1 = 1.0;
             }
 #pragma unroll
-            for (int ia = 0; ia < 2; ++ia)
-                if (a0 + ia == j) dpiv[ia] = d;
-            if (wrow_last > j) {   // rows below the pivot in this wave (uniform per wave)
-                const double inv_d = rcp_nr(d);
-                double ma[2];
-#pragma unroll
-                for (int ia = 0; ia < 2; ++ia) ma[ia] = a0 + ia > j ? prg[a0 + ia] * inv_d : 0.0;
-                const double gb0 = prg[b0], gb1 = prg[b0 + 1], ub0 = pru[b0], ub1 = pru[b0 + 1];
+            for (int ia = 0; ia < 2; ++ia) {
+                if (a0 + ia == j) dpiv[ia] = d0;
+                if (a0 + ia == j + 1) dpiv[ia] = d1;
+            }
+            if (wrow_last > j) {   // rows below pivot j in this wave (uniform per wave)
+                const double inv1 = rcp_nr(d1);
+                double m0[2], m1[2];
 #pragma unroll
                 for (int ia = 0; ia < 2; ++ia) {
                     const int a = a0 + ia;
-                    if (b0 >= a) g[ia][0] -= ma[ia] * gb0;
-                    if (b0 + 1 >= a) g[ia][1] -= ma[ia] * gb1;
-                    u[ia][0] -= ma[ia] * ub0;
-                    u[ia][1] -= ma[ia] * ub1;
+                    m0[ia] = a > j ? r0g[a] * inv0 : 0.0;
+                    m1[ia] = a > j + 1 ? (r1g[a] - l * r0g[a]) * inv1 : 0.0;
                 }
-                if (j + 1 < 64) {
+                double g0[2], g1[2], u0[2], u1[2];
 #pragma unroll
-                    for (int ia = 0; ia < 2; ++ia)
-                        if (a0 + ia == j + 1) {
-                            double *ng = pg + 64 * ((j + 1) & 1), *nu = pu + 64 * ((j + 1) & 1);
-                            ng[b0] = g[ia][0];
-                            ng[b0 + 1] = g[ia][1];
-                            nu[b0] = u[ia][0];
-                            nu[b0 + 1] = u[ia][1];
-                        }
+                for (int ib = 0; ib < 2; ++ib) {
+                    const int b = b0 + ib;
+                    g0[ib] = r0g[b];
+                    g1[ib] = r1g[b] - l * g0[ib];
+                    u0[ib] = r0u[b];
+                    u1[ib] = r1u[b] - l * u0[ib];
+                }
+#pragma unroll
+                for (int ia = 0; ia < 2; ++ia) {
+                    const int a = a0 + ia;
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib) {
+                        if (b0 + ib >= a) g[ia][ib] -= m0[ia] * g0[ib] + m1[ia] * g1[ib];
+                        u[ia][ib] -= m0[ia] * u0[ib] + m1[ia] * u1[ib];
+                    }
+                }
+                if (j + 2 < 64 && a0 == j + 2) {
+                    double *ng = pg + 128 * (bsel ^ 1), *nu = pu + 128 * (bsel ^ 1);
+#pragma unroll
+                    for (int ia = 0; ia < 2; ++ia) {
+                        ng[64 * ia + b0] = g[ia][0];
+                        ng[64 * ia + b0 + 1] = g[ia][1];
+                        nu[64 * ia + b0] = u[ia][0];
+                        nu[64 * ia + b0 + 1] = u[ia][1];
+                    }
                 }
             }
             __syncthreads();

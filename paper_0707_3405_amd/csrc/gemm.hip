@@ -634,7 +634,9 @@ void gemm_nn_impl(const cpx<T> *A, int64_t lda, const cd *C, int64_t ldc, int64_
         }
         const int64_t slots = (int64_t)occ * device_cu_count();
         const int64_t rounds = (G * tiles_n + slots - 1) / slots;
-        if (rounds > 1) {
+        if (nblk * tiles_n <= slots) {
+            G = nblk;   // short K (coefficient space): one block per workgroup, all resident
+        } else if (rounds > 1) {
             const int64_t Gfit = (rounds - 1) * slots / tiles_n;
             if (Gfit >= (nblk + kNnMaxRb - 1) / kNnMaxRb) G = Gfit;
         }
