@@ -614,9 +614,11 @@ __device__ void sturm_count2(const double *d, const double *e2, int n, double x1
     c1 += q1 < 0;
     c2 += q2 < 0;
     for (int i = 1; i < n; ++i) {
+        // e^2 / q by the refined hardware reciprocal (within an ulp, as the
+        // count's backward-error argument needs; |q| >= pivmin keeps it finite)
         const double di = d[i], ei = e2[i - 1];
-        q1 = di - x1 - ei / q1;
-        q2 = di - x2 - ei / q2;
+        q1 = di - x1 - ei * rcp_nr(q1);
+        q2 = di - x2 - ei * rcp_nr(q2);
         if (fabs(q1) < pivmin) q1 = -pivmin;
         if (fabs(q2) < pivmin) q2 = -pivmin;
         c1 += q1 < 0;
@@ -744,7 +746,7 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
         const double d_nx = ds[i + 1] - lam, u_nx = es[i + 1];   // row i + 1 as given
         if (fabs(d_cur) >= fabs(sub)) {
             const double dp = fabs(d_cur) < eps_t ? (d_cur < 0 ? -eps_t : eps_t) : d_cur;
-            const double m = sub / dp;
+            const double m = sub * rcp_nr(dp);
             at(DD, i) = dp;
             at(DL, i) = m;
             at(DU, i) = u_cur;
@@ -753,7 +755,7 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
             d_cur = d_nx - m * u_cur;
             u_cur = u_nx;
         } else {
-            const double m = d_cur / sub;
+            const double m = d_cur * rcp_nr(sub);
             at(DD, i) = sub;
             at(DL, i) = m;
             at(DU, i) = d_nx;
