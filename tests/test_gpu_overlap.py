@@ -174,3 +174,18 @@ def test_overlap_error_paths(torch_cuda):
         ctx.lobpcg_solve(w.nbands, w.block, w.tol, 10, X)
     assert e.value.status == PW_ERR_NOMEM
     del ws
+
+
+def test_solve_overlap_bf16(torch_cuda):
+    """The generalized form with the split-bf16 projector products (O X and the
+    non-local H X share the projector table)."""
+    torch = torch_cuda
+    from paper_0707_3405_amd import PW_PREC_MIXED_BF16
+    w, q, prob = _problem("mid_nl", prec=PW_PREC_MIXED_BF16)
+    eig, X, status = prob.solve(w.tol, max_iter=300)
+    torch.cuda.synchronize()
+    res, st = prob.ctx.get_residuals(prob.nbands), prob.ctx.get_stats()
+    ref = load_golden("mid_nl_ovl")[0][:w.nbands]
+    assert np.abs(eig - ref).max() <= 1e-8, np.abs(eig - ref).max()
+    assert res.max() <= w.tol
+    assert st["mixed_iterations"] > 0
