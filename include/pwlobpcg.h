@@ -166,7 +166,7 @@ pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ld
  * split-K sums may differ in rounding. */
 typedef struct {
     int32_t fft_sticks_per_block;   /* z passes: sticks per workgroup, 0 or 1..64 (default 16) */
-    int32_t fft_plane_rows;         /* plane pass: row chunk, 0 or 1..128 (default 32, capped by LDS) */
+    int32_t fft_plane_rows;         /* plane pass: row chunk, 0 or 1..128 (default 48, capped by LDS) */
     int32_t gemm_split_workgroups;  /* split-K TN target workgroups, 0 or 1..1024 (default 1024) */
     double apply_ms_default, apply_ms_tuned;   /* local H X of nb bands */
     double gemm_ms_default, gemm_ms_tuned;     /* 3m x 3m Gram over npw (+ projector overlaps) */

@@ -29,13 +29,17 @@ namespace {
 using namespace fft;
 
 constexpr int kThreads = 256;
-#ifndef PW_PLANE_THREADS
-#define PW_PLANE_THREADS 512   // workgroup size of the plane pass
-#endif
-#ifndef PW_PLANE_RB
-#define PW_PLANE_RB 32         // largest row chunk of the plane pass
-#endif
-constexpr int kPlaneThreads = PW_PLANE_THREADS;
+// Workgroup size of the plane pass.  An FP64 plane (up to 150 KB of LDS) runs
+// alone on its CU, so it takes 1024 threads (at most 128 VGPRs, no spills up to
+// N = 120): twice the work items per phase to hide LDS and FP64 latency.  A
+// complex64 plane takes 512 so that two workgroups share a CU.
+template <int N, class T>
+constexpr int plane_threads() {
+    return (sizeof(T) == 8 && N <= 120) ? 1024 : 512;
+}
+constexpr int kPlaneRb = 48;       // default row chunk of the plane pass (capped by LDS)
+constexpr int kRhoThreads = 512;   // workgroup size of the density plane pass
+constexpr int kRhoRb = 32;         // row chunk of the density plane pass
 
 template <class T>
 __device__ __forceinline__ void load_twiddles(cpx<T> *tw_s, const double *tw_g, int n) {
@@ -96,7 +100,7 @@ __device__ __forceinline__ int xcd_logical(int lin, int total) {
 }
 
 template <int N, class T>
-__global__ void __launch_bounds__(kPlaneThreads) k_plane(SphereDev sp, const T *__restrict__ vperm,
+__global__ void __launch_bounds__((plane_threads<N, T>())) k_plane(SphereDev sp, const T *__restrict__ vperm,
                                                     cpx<T> *__restrict__ S, int nb, int rb) {
     constexpr int LD = N + 1;
     constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
@@ -199,7 +203,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane(SphereDev sp, const T *
 // plane and adds the bands in order, so no two threads write one element and
 // the sum is deterministic.
 template <int N, class T>
-__global__ void __launch_bounds__(kPlaneThreads)
+__global__ void __launch_bounds__(kRhoThreads)
     k_plane_rho(SphereDev sp, const cpx<T> *__restrict__ S, int nb, const double *__restrict__ occ,
                 double *__restrict__ rho_zyx, int rb) {
     constexpr int LD = N + 1;
@@ -352,7 +356,7 @@ void run_apply(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx
     // pass 2 LDS: twiddles + kept columns + row chunk; largest row chunk that
     // keeps the workgroup under 150 KB.
     const size_t base2 = (size_t)N * e + (size_t)sp.ncx * (N + 1) * e;
-    int rb = tune.fft_rb > 0 ? tune.fft_rb : PW_PLANE_RB;
+    int rb = tune.fft_rb > 0 ? tune.fft_rb : kPlaneRb;
     auto sm2_of = [&](int r) { return base2 + (size_t)r * (N + 1) * e; };
     while (rb > 1 && sm2_of(rb) > 150 * 1024) rb /= 2;
     if (rb > N) rb = N;
@@ -365,7 +369,7 @@ void run_apply(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx
     PW_HIP(hipFuncSetAttribute((const void *)k_zfwd<N, T>,
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm13));
     hipLaunchKernelGGL((k_zinv<N, T>), g13, dim3(kThreads), sm13, st, sp, X, ldx, S, spb);
-    hipLaunchKernelGGL((k_plane<N, T>), dim3(N * nb), dim3(kPlaneThreads), sm2, st, sp, vperm, S, nb,
+    hipLaunchKernelGGL((k_plane<N, T>), dim3(N * nb), dim3(plane_threads<N, T>()), sm2, st, sp, vperm, S, nb,
                        rb);
     hipLaunchKernelGGL((k_zfwd<N, T>), g13, dim3(kThreads), sm13, st, sp, S, X, ldx, Y, ldy, spb);
     PW_HIP(hipGetLastError());
@@ -414,7 +418,7 @@ void run_density(const SphereDev &sp, const cd *X, int64_t ldx, int nb, const do
     const size_t e = sizeof(cd);
     const size_t sm1 = (size_t)N * e + (size_t)spb * (N + 1) * e;
     const size_t base2 = (size_t)N * e + (size_t)sp.ncx * (N + 1) * e;
-    int rb = PW_PLANE_RB;
+    int rb = kRhoRb;
     while (rb > 1 && base2 + (size_t)rb * (N + 1) * e > 150 * 1024) rb /= 2;
     if (rb > N) rb = N;
     const size_t sm2 = base2 + (size_t)rb * (N + 1) * e;
@@ -425,7 +429,7 @@ void run_density(const SphereDev &sp, const cd *X, int64_t ldx, int nb, const do
                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2));
     hipLaunchKernelGGL((k_zinv<N, double>), dim3((sp.nst + spb - 1) / spb, nb), dim3(kThreads), sm1, st,
                        sp, X, ldx, S, spb);
-    hipLaunchKernelGGL((k_plane_rho<N, double>), dim3(N), dim3(kPlaneThreads), sm2, st, sp, S, nb, occ,
+    hipLaunchKernelGGL((k_plane_rho<N, double>), dim3(N), dim3(kRhoThreads), sm2, st, sp, S, nb, occ,
                        rho_zyx, rb);
     PW_HIP(hipGetLastError());
 }

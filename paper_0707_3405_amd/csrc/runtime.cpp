@@ -1272,7 +1272,7 @@ pw_status pw_autotune(pw_ctx c, int32_t nb, pw_tuning *out) {
         const double apply_def = timed(apply), gemm_def = timed(gemm);
         pw::Tuning best{};
         double apply_best = apply_def, gemm_best = gemm_def;
-        const int spb_c[] = {16, 32, 64}, rb_c[] = {8, 16, 32};
+        const int spb_c[] = {16, 32, 64}, rb_c[] = {16, 32, 48, 96};
         for (int spb : spb_c)
             for (int rb : rb_c) {
                 c->tune = pw::Tuning{};

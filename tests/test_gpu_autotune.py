@@ -22,7 +22,7 @@ def test_autotune_choices_and_timings(torch_cuda):
     t = prob.ctx.autotune(w.block)
     print("fcc32_l12 tuning:", t)
     assert t["fft_sticks_per_block"] in (0, 16, 32, 64)
-    assert t["fft_plane_rows"] in (0, 8, 16, 32)
+    assert t["fft_plane_rows"] in (0, 16, 32, 48, 96)
     assert t["gemm_split_workgroups"] in (0, 384, 512, 768, 1024)
     assert 0 < t["apply_ms_tuned"] <= t["apply_ms_default"]
     assert 0 < t["gemm_ms_tuned"] <= t["gemm_ms_default"]
@@ -32,7 +32,7 @@ def test_autotune_choices_and_timings(torch_cuda):
     assert np.abs(eig - ref).max() <= 1e-8
 
 
-@pytest.mark.parametrize("spb,rb", [(16, 8), (64, 16), (32, 32), (1, 1)])
+@pytest.mark.parametrize("spb,rb", [(16, 8), (64, 16), (32, 32), (16, 48), (32, 96), (1, 1)])
 def test_fft_tiling_is_bitwise_neutral(torch_cuda, spb, rb):
     torch = torch_cuda
     from paper_0707_3405_amd import PlaneWaveProblem
