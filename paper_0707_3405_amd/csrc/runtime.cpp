@@ -128,6 +128,27 @@ struct pw_ctx_s {
     int *d_status = nullptr;
     int nst_host = 0, ncx_host = 0;
 
+    // pinned host staging of the per-iteration round trip (residual norms and
+    // status down, active columns up): copies to and from it are asynchronous
+    void *h_pinned = nullptr;
+    size_t h_pinned_bytes = 0;
+    char *pinned(size_t bytes) {
+        if (bytes > h_pinned_bytes) {
+            if (h_pinned) {
+                PW_HIP(hipStreamSynchronize(stream));
+                (void)hipHostFree(h_pinned);
+                h_pinned = nullptr;
+                h_pinned_bytes = 0;
+            }
+            if (hipHostMalloc(&h_pinned, bytes, hipHostMallocDefault) != hipSuccess) {
+                h_pinned = nullptr;
+                throw Error{PW_ERR_NOMEM, "pinned host allocation failed"};
+            }
+            h_pinned_bytes = bytes;
+        }
+        return static_cast<char *>(h_pinned);
+    }
+
     // last solve
     std::vector<double> res;
     pw_stats stats{};
@@ -400,7 +421,11 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
     PW_HIP(hipEventRecord(t_begin, st));
     PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), st));
     bool all_converged = true;
-    std::vector<double> hres(std::max(M, 3 * m));
+    // pinned: residual norms [3m] | status | active columns [3m]
+    char *hp = c->pinned(sizeof(double) * 3 * m + sizeof(int) * (1 + 3 * m));
+    double *hres = reinterpret_cast<double *>(hp);
+    int *hstat = reinterpret_cast<int *>(hp + sizeof(double) * 3 * m);
+    int *hact = hstat + 1;
     // residual norms below this are rounding noise (Ha; the spectrum scale is ~ecut)
     const double res_floor = 1e-10 * std::max(1.0, c->ecut);
 
@@ -492,8 +517,10 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
                                          (S *)nullptr, 0, p.rpart, p.res, st);
                 tm.end(PhaseTimer::kVec, e);
             }
-            PW_HIP(hipMemcpyAsync(hres.data(), p.res, sizeof(double) * mb, hipMemcpyDeviceToHost, st));
-            const int status = read_status(c);
+            PW_HIP(hipMemcpyAsync(hres, p.res, sizeof(double) * mb, hipMemcpyDeviceToHost, st));
+            PW_HIP(hipMemcpyAsync(hstat, c->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+            PW_HIP(hipStreamSynchronize(st));
+            const int status = *hstat;
             tm.collect();
             if (status & 4) throw Error{PW_ERR_NUMERIC, "non-finite value in the iteration"};
             if (status & 1) {
@@ -532,7 +559,9 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
                 if (tol == 0.0) it = max_iter;   // the remaining fixed sweeps are no-ops
                 break;
             }
-            PW_HIP(hipMemcpyAsync(p.act, act.data(), sizeof(int) * na, hipMemcpyHostToDevice, st));
+            // hact is rewritten only after the next synchronisation, when this copy has run
+            std::copy(act.begin(), act.end(), hact);
+            PW_HIP(hipMemcpyAsync(p.act, hact, sizeof(int) * na, hipMemcpyHostToDevice, st));
             const int wcol = mb + np;
             S *W = Z + (int64_t)wcol * ld;
             {
@@ -1029,6 +1058,7 @@ void pw_destroy(pw_ctx c) {
         (void)hipSetDevice(c->device);
         (void)hipStreamSynchronize(c->stream);
         for (void *p : c->dev_allocs) (void)hipFree(p);
+        if (c->h_pinned) (void)hipHostFree(c->h_pinned);
     }
     delete c;
 }
