@@ -736,18 +736,24 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
     enum { DL = 0, DD, DU, DU2, PIV, ZZ };
     const double lam = w[idx];
     const double eps_t = DBL_EPSILON * fmax(s_tnorm, 1e-300);
-    // LU with partial pivoting of T - lambda I (LAPACK dlagtf order); the
+    // LU with partial pivoting of T - lambda I (LAPACK dlagtf order).  The
     // entries that the next step modifies (diagonal d and superdiagonal u of
-    // row i) are carried in registers, so each step's only LDS traffic is
-    // stores and loads of untouched input
+    // row i) are carried in registers and the untouched inputs of step i + 1
+    // are loaded during step i, so the serial chain never waits on LDS.  DD
+    // keeps the reciprocal pivot, the same refined reciprocal that forms the
+    // multiplier.
     double d_cur = ds[0] - lam, u_cur = es[0];
+    double sub = es[0];
+    double d_nx = n > 1 ? ds[1] - lam : 0.0, u_nx = n > 1 ? es[1] : 0.0;
     for (int i = 0; i + 1 < n; ++i) {
-        const double sub = es[i];
-        const double d_nx = ds[i + 1] - lam, u_nx = es[i + 1];   // row i + 1 as given
+        const double sub_n = es[i + 1];   // es holds n entries, the last one zero
+        const double d_nx_n = i + 2 < n ? ds[i + 2] - lam : 0.0;
+        const double u_nx_n = i + 2 < n ? es[i + 2] : 0.0;
         if (fabs(d_cur) >= fabs(sub)) {
             const double dp = fabs(d_cur) < eps_t ? (d_cur < 0 ? -eps_t : eps_t) : d_cur;
-            const double m = sub * rcp_nr(dp);
-            at(DD, i) = dp;
+            const double r = rcp_nr(dp);
+            const double m = sub * r;
+            at(DD, i) = r;
             at(DL, i) = m;
             at(DU, i) = u_cur;
             at(DU2, i) = 0.0;
@@ -755,8 +761,9 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
             d_cur = d_nx - m * u_cur;
             u_cur = u_nx;
         } else {
-            const double m = d_cur * rcp_nr(sub);
-            at(DD, i) = sub;
+            const double r = rcp_nr(sub);
+            const double m = d_cur * r;
+            at(DD, i) = r;
             at(DL, i) = m;
             at(DU, i) = d_nx;
             at(PIV, i) = 1.0;
@@ -764,12 +771,14 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
             d_cur = u_cur - m * d_nx;
             u_cur = i + 2 < n ? -m * u_nx : u_nx;
         }
+        sub = sub_n;
+        d_nx = d_nx_n;
+        u_nx = u_nx_n;
     }
-    at(DD, n - 1) = fabs(d_cur) < eps_t ? eps_t : d_cur;
+    at(DD, n - 1) = 1.0 / (fabs(d_cur) < eps_t ? eps_t : d_cur);
     at(DU, n - 1) = 0.0;
     at(DU2, n - 1) = 0.0;
     at(PIV, n - 1) = 0.0;
-    for (int i = 0; i < n; ++i) at(DD, i) = 1.0 / at(DD, i);   // reciprocal pivots
     for (int i = 0; i < n; ++i) {
         uint64_t h = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(idx + 7) * 0xD1B54A32D192ED03ull;
         h ^= h >> 31;
@@ -777,35 +786,57 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
         h ^= h >> 29;
         at(ZZ, i) = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
     }
+    // two solves; the iterate stays unscaled in LDS and the 1 / max-norm of the
+    // first solve is applied as the second one reads it; inputs of the next
+    // step are again loaded one step ahead
+    double scale = 1.0, n2 = 0.0;
     for (int iter = 0; iter < 2; ++iter) {
         // L solve with the row interchanges; z carries the running entry
-        double z = at(ZZ, 0);
+        double z = at(ZZ, 0) * scale;
+        double znx = n > 1 ? at(ZZ, 1) * scale : 0.0, l = at(DL, 0), piv = at(PIV, 0);
         for (int i = 0; i + 1 < n; ++i) {
-            const double znx = at(ZZ, i + 1), l = at(DL, i);
-            if (at(PIV, i) != 0.0) {
+            const double znx_n = i + 2 < n ? at(ZZ, i + 2) * scale : 0.0;   // not yet overwritten
+            const double l_n = at(DL, i + 1), piv_n = at(PIV, i + 1);
+            if (piv != 0.0) {
                 at(ZZ, i) = znx;
                 z = z - l * znx;
             } else {
                 at(ZZ, i) = z;
                 z = znx - l * z;
             }
+            znx = znx_n;
+            l = l_n;
+            piv = piv_n;
         }
         at(ZZ, n - 1) = z;
         // U solve from the bottom; z1, z2 carry the two entries below
         double nrm = 0.0, z1 = 0.0, z2 = 0.0;
+        n2 = 0.0;
+        double zz = at(ZZ, n - 1), du = at(DU, n - 1), du2 = at(DU2, n - 1), rd = at(DD, n - 1);
         for (int i = n - 1; i >= 0; --i) {
-            const double sv = (at(ZZ, i) - at(DU, i) * z1 - at(DU2, i) * z2) * at(DD, i);
+            double zz_n = 0.0, du_n = 0.0, du2_n = 0.0, rd_n = 0.0;
+            if (i > 0) {   // row i - 1: L-solve output, not yet overwritten
+                zz_n = at(ZZ, i - 1);
+                du_n = at(DU, i - 1);
+                du2_n = at(DU2, i - 1);
+                rd_n = at(DD, i - 1);
+            }
+            const double sv = (zz - du * z1 - du2 * z2) * rd;
             at(ZZ, i) = sv;
             nrm = fmax(nrm, fabs(sv));
+            n2 += sv * sv;
             z2 = z1;
             z1 = sv;
+            zz = zz_n;
+            du = du_n;
+            du2 = du2_n;
+            rd = rd_n;
         }
-        const double inv = nrm > 0 ? 1.0 / nrm : 1.0;
-        for (int i = 0; i < n; ++i) at(ZZ, i) *= inv;
+        scale = nrm > 0 ? 1.0 / nrm : 1.0;
     }
-    double n2 = 0.0;
-    for (int i = 0; i < n; ++i) n2 += at(ZZ, i) * at(ZZ, i);
-    const double inv = 1.0 / sqrt(n2);
+    // unit 2-norm (the second solve's result is at most ~1 / eps_t in size,
+    // so its squares stay far from overflow)
+    const double inv = n2 > 0 ? 1.0 / sqrt(n2) : 1.0;
     for (int i = 0; i < n; ++i) Z[(int64_t)i * k + idx] = at(ZZ, i) * inv;
 }
 

@@ -129,23 +129,12 @@ struct pw_ctx_s {
     int nst_host = 0, ncx_host = 0;
 
     // pinned host staging of the per-iteration round trip (residual norms and
-    // status down, active columns up): copies to and from it are asynchronous
+    // status down, active columns up), allocated with the context: copies to
+    // and from it are asynchronous, and a solve allocates no host memory
+    static constexpr size_t kPinnedBytes = 4096;   // >= 3 * 64 doubles + (1 + 3 * 64) ints
     void *h_pinned = nullptr;
-    size_t h_pinned_bytes = 0;
     char *pinned(size_t bytes) {
-        if (bytes > h_pinned_bytes) {
-            if (h_pinned) {
-                PW_HIP(hipStreamSynchronize(stream));
-                (void)hipHostFree(h_pinned);
-                h_pinned = nullptr;
-                h_pinned_bytes = 0;
-            }
-            if (hipHostMalloc(&h_pinned, bytes, hipHostMallocDefault) != hipSuccess) {
-                h_pinned = nullptr;
-                throw Error{PW_ERR_NOMEM, "pinned host allocation failed"};
-            }
-            h_pinned_bytes = bytes;
-        }
+        PW_REQUIRE(h_pinned && bytes <= kPinnedBytes, PW_ERR_STATE, "pinned staging too small");
         return static_cast<char *>(h_pinned);
     }
 
@@ -1046,6 +1035,10 @@ pw_status pw_create(int device, void *hip_stream, pw_ctx *out) {
     }
     pw_ctx c = new (std::nothrow) pw_ctx_s;
     if (!c) return PW_ERR_NOMEM;
+    if (device >= 0 && hipHostMalloc(&c->h_pinned, pw_ctx_s::kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return PW_ERR_NOMEM;
+    }
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
     *out = c;
