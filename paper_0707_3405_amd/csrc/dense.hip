@@ -382,7 +382,7 @@ __global__ void __launch_bounds__(1024)
 // tiles are stored once and used for both triangles of y = A v; diagonal tiles
 // are stored in full.  Per column: the pivot column goes to LDS, one wave
 // forms the reflector, every thread accumulates its tiles' row and column
-// partials of y (row sums over tj by DPP, column sums per half-wave in LDS),
+// partials of y (row sums over lane quads by DPP, column sums per half-wave, both in LDS),
 // four threads per row add the partials into w, and every thread applies the
 // rank-2 update to its tiles.  Tiles whose rows or columns are all finished
 // are skipped.  All sums run in a fixed order (deterministic).
@@ -431,7 +431,7 @@ __global__ void __launch_bounds__(1024)
     __shared__ cd xs[NR];        // pivot column
     __shared__ cd vs[NR];        // reflector, zero outside rows j+1..n-1
     __shared__ cd ws[NR];        // w, zero outside rows j+1..n-1
-    __shared__ cd pr[2][NR];     // row sums of y, one per DPP row of a half-wave
+    __shared__ cd pr[8][NR];     // row sums of y, one per lane quad of a half-wave
     __shared__ cd pc[32][NR + 1];   // column sums of y, one per half-wave (padded: the
                                     // four readers of a row hit different banks)
     __shared__ double sv[16];    // per-wave partials of Re(v^H A v)
@@ -527,9 +527,9 @@ __global__ void __launch_bounds__(1024)
                 });
                 const cd vi = vs[ti + 32 * a];
                 vpart += vi.x * rr + vi.y * ri;
-                rr = row16_sum(rr);
-                ri = row16_sum(ri);
-                if ((tj & 15) == 0) pr[tj >> 4][ti + 32 * a] = cd{rr, ri};
+                rr = quad_sum(rr);   // the eight quad sums of a row are added in the w step
+                ri = quad_sum(ri);
+                if ((tj & 3) == 0) pr[tj >> 2][ti + 32 * a] = cd{rr, ri};
             });
             unroll_for<0, T - 1>([&](auto b_) {   // conj(e) v_i into y_j, off-diagonal tiles
                 constexpr int b = b_;
@@ -563,10 +563,8 @@ __global__ void __launch_bounds__(1024)
                         si += pc[8 * q + h][r].y;
                     }
                 }
-                if (q == 0) {
-                    sr += pr[0][r].x + pr[1][r].x;
-                    si += pr[0][r].y + pr[1][r].y;
-                }
+                sr += pr[2 * q][r].x + pr[2 * q + 1][r].x;
+                si += pr[2 * q][r].y + pr[2 * q + 1][r].y;
             }
             sr = quad_sum(sr);
             si = quad_sum(si);
