@@ -7,8 +7,9 @@ jittered fcc sites in a 20 bohr cube, Ecut 20 Ha (34181 plane waves), k =
 residual tolerance 1e-6, FP64.
 
 Prints ONE JSON line (rank 0).  Besides the headline value (FP64) it reports
-the same solve in the mixed-precision form (complex64 iteration + FP64
-refinement) with its per-eigenvalue difference from the FP64 result, the H.X
+the same solve in the mixed-precision forms (complex64 iteration + FP64
+refinement; FP32 products, split-bf16 projector products, split-bf16 projector
+and Gram products) with their per-eigenvalue differences from the FP64 result, the H.X
 FFT throughput in both precisions, the roofline of the dominant phase and of
 the other two (each timed with HIP events on the stream it runs on at its
 canonical launch shape), solve-latency percentiles, and the CPU oracle timed on
@@ -106,7 +107,7 @@ def main():
 
     import torch
     from paper_0707_3405_amd import (PlaneWaveProblem, PW_PREC_FP64, PW_PREC_MIXED,
-                                     PW_PREC_MIXED_BF16, solve_batch)
+                                     PW_PREC_MIXED_BF16, PW_PREC_MIXED_BF16_GRAM, solve_batch)
     from workloads import make_workload, make_kpoint_workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -146,7 +147,8 @@ def main():
         eig64 = eig.copy()
 
         # ---- the same cell in the mixed forms (complex64 iteration + FP64 refinement;
-        # the BF16 form also runs the projector products on split-bf16 matrix cores)
+        # the BF16 forms also run the projector products, and the second one the
+        # Rayleigh-Ritz Gram, on split-bf16 matrix cores)
         def run_mixed(prec, label):
             solve(prec)
             torch.cuda.synchronize()
@@ -172,10 +174,11 @@ def main():
                     "phase_ms": {k: mst[k] for k in ("ms_apply", "ms_gemm", "ms_dense", "ms_vec",
                                                      "ms_final_rr")}}
 
-        mixed = mixed_bf16 = None
+        mixed = mixed_bf16 = mixed_bf16_gram = None
         if args.mixed_steps > 0:
             mixed = run_mixed(PW_PREC_MIXED, "mixed")
             mixed_bf16 = run_mixed(PW_PREC_MIXED_BF16, "mixed-bf16")
+            mixed_bf16_gram = run_mixed(PW_PREC_MIXED_BF16_GRAM, "mixed-bf16-gram")
 
         # ---- the same cell as the pencil (H, O), O = I + sum_p q_p |beta_p><beta_p|
         generalized = None
@@ -384,6 +387,7 @@ def main():
         "roofline_all": roofs,
         "mixed": mixed,
         "mixed_bf16": mixed_bf16,
+        "mixed_bf16_gram": mixed_bf16_gram,
         "generalized": generalized,
         "autotuned": tuned,
         "hx_full_ms_per_64_bands": hx_full,

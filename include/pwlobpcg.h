@@ -62,14 +62,19 @@ typedef enum {
  * eigenpairs meet the same residual test as PW_PREC_FP64.
  * PW_PREC_MIXED_BF16 is the same iteration with the nonlocal projector
  * products on BF16 matrix cores (sec. 4.1's projector "zgemm"s, the largest
- * GEMMs of H X). */
+ * GEMMs of H X); PW_PREC_MIXED_BF16_GRAM also forms the Rayleigh-Ritz Gram
+ * matrix Z^H (H Z) of the complex64 stage on BF16 matrix cores (the CholQR
+ * Grams, constraint products and block updates stay FP32).  Both BF16 forms
+ * refine in FP64 exactly like PW_PREC_MIXED. */
 typedef enum {
     PW_PREC_FP64 = 0,          /* every step in complex128 / float64 */
     PW_PREC_MIXED = 1,         /* complex64 iteration, FP64 small dense steps and refinement */
-    PW_PREC_MIXED_BF16 = 2     /* PW_PREC_MIXED with the projector products (B^H X and
+    PW_PREC_MIXED_BF16 = 2,    /* PW_PREC_MIXED with the projector products (B^H X and
                                   B (D B^H X)) on BF16 matrix cores: complex64 operands
                                   split into hi + lo bf16 pairs, three products per real
                                   product, FP32 accumulation */
+    PW_PREC_MIXED_BF16_GRAM = 3  /* PW_PREC_MIXED_BF16 with the Rayleigh-Ritz Gram of the
+                                    complex64 stage on the same split-bf16 products */
 } pw_precision;
 
 /* Per-solve counters and phase times (milliseconds, measured with HIP events

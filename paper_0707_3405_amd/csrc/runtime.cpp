@@ -115,6 +115,7 @@ struct pw_ctx_s {
     cd *d_B = nullptr;
     pw::cf *d_B32 = nullptr;   // complex64 copy for the mixed form
     bool proj_bf16 = false;    // complex64 projector products on split-bf16 MFMA
+    bool gram_bf16 = false;    // complex64 Rayleigh-Ritz Gram on split-bf16 MFMA
     pw::Tuning tune;           // launch parameters (pw_autotune / pw_set_tuning)
     double *d_D = nullptr;
     double *d_Q = nullptr;     // overlap coefficients (generalized form); null: O = I
@@ -264,8 +265,9 @@ size_t plan_bytes(const pw_ctx_s &c, int M, int m, pw_precision prec) {
 }
 
 void require_precision(pw_precision prec) {
-    PW_REQUIRE(prec == PW_PREC_FP64 || prec == PW_PREC_MIXED || prec == PW_PREC_MIXED_BF16, PW_ERR_ARG,
-               "unknown precision");
+    PW_REQUIRE(prec == PW_PREC_FP64 || prec == PW_PREC_MIXED || prec == PW_PREC_MIXED_BF16 ||
+                   prec == PW_PREC_MIXED_BF16_GRAM,
+               PW_ERR_ARG, "unknown precision");
 }
 
 void require_basis(const pw_ctx_s *c) {
@@ -324,6 +326,21 @@ void proj_add(pw_ctx_s *c, const Plan<S> &p, const double *s, const S *X, int64_
     pw::launch_gemm_tn(B, c->ldp, X, ldx, c->npw, np, nc, p.Pj, np, s, 0.0, p.part, p.part_elems,
                        c->stream);
     pw::launch_gemm_nn(B, c->ldp, p.Pj, np, c->npw, np, nc, 1.0, 1.0, Y, ldy, c->stream);
+}
+
+// Rayleigh-Ritz Gram A = Z^H (HZ) [nz x nz] (Algorithm 1 step 4); in the
+// complex64 stage of PW_PREC_MIXED_BF16_GRAM on split-bf16 MFMA
+template <class S>
+void rr_gram(pw_ctx_s *c, const Plan<S> &p, const S *Z, const S *HZ, int64_t ld, int nz) {
+    if constexpr (std::is_same<S, pw::cf>::value) {
+        if (c->gram_bf16) {
+            pw::launch_gemm_tn_bf16(Z, ld, HZ, ld, c->npw, nz, nz, p.Agram, nz, nullptr, 0.0, p.part,
+                                    p.part_elems, c->stream);
+            return;
+        }
+    }
+    pw::launch_gemm_tn(Z, ld, HZ, ld, c->npw, nz, nz, p.Agram, nz, nullptr, 0.0, p.part, p.part_elems,
+                       c->stream);
 }
 
 template <class S>
@@ -469,8 +486,7 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
         // initial Rayleigh-Ritz on span(X)
         {
             auto e0 = tm.begin();
-            pw::launch_gemm_tn(Z, ld, HZ, ld, npw, mb, mb, p.Agram, mb, nullptr, 0.0, p.part,
-                               p.part_elems, st);
+            rr_gram(c, p, Z, HZ, ld, mb);
             tm.end(PhaseTimer::kGemm, e0);
             auto e1 = tm.begin();
             pw::launch_heev_f64(p.Agram, mb, mb, mb, p.w, p.Cc, 3 * m, p.heev_scratch, c->d_status, st);
@@ -583,8 +599,7 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
             // Rayleigh-Ritz on span{X, P, W} (orthonormal basis)
             {
                 auto e0 = tm.begin();
-                pw::launch_gemm_tn(Z, ld, HZ, ld, npw, nz, nz, p.Agram, nz, nullptr, 0.0, p.part,
-                                   p.part_elems, st);
+                rr_gram(c, p, Z, HZ, ld, nz);
                 tm.end(PhaseTimer::kGemm, e0);
                 auto e1 = tm.begin();
                 pw::launch_heev_f64(p.Agram, nz, nz, mb, p.w, p.Cc, 3 * m, p.heev_scratch, c->d_status,
@@ -705,7 +720,8 @@ pw_status solve(pw_ctx_s *c, int M, int m, double tol, int max_iter, pw_precisio
     pw_status rc;
     if (prec != PW_PREC_FP64) {
         ensure_mixed_tables(c);
-        c->proj_bf16 = prec == PW_PREC_MIXED_BF16;
+        c->proj_bf16 = prec == PW_PREC_MIXED_BF16 || prec == PW_PREC_MIXED_BF16_GRAM;
+        c->gram_bf16 = prec == PW_PREC_MIXED_BF16_GRAM;
         Plan<pw::cf> p32 = ready_plan<pw::cf>(c, M, m);
         if (use_guess) pw::launch_copy_cols(X, ldx, p32.Xs, c->ldp, c->npw, M, c->stream);
         // an unconverged block here is not an error: the FP64 stage continues from it
@@ -1164,7 +1180,7 @@ static pw_status apply_entry(pw_ctx c, const void *X, int64_t ldx, void *Y, int6
         if (prec != PW_PREC_FP64) {
             Plan<pw::cf> p = ready_plan<pw::cf>(c, std::max(c->plan_nbands, 1), chunk);
             ensure_mixed_tables(c);
-            c->proj_bf16 = prec == PW_PREC_MIXED_BF16;
+            c->proj_bf16 = prec == PW_PREC_MIXED_BF16 || prec == PW_PREC_MIXED_BF16_GRAM;
             auto Xc = static_cast<const pw::cf *>(X);
             auto Yc = static_cast<pw::cf *>(Y);
             if (overlap) apply_O(c, p, chunk, Xc, ldx, Yc, ldy, nb);

@@ -173,20 +173,42 @@ def test_apply_bf16_paper_scale(torch_cuda, oracle_problem):
     assert np.all(err <= bound), np.max(err / bound)
 
 
+@pytest.mark.parametrize("prec_name", ["PW_PREC_MIXED_BF16", "PW_PREC_MIXED_BF16_GRAM"])
 @pytest.mark.parametrize("name", ["mid_nl", "fcc32_l12", "fcc108_l20"])
-def test_solve_bf16_vs_oracle(torch_cuda, name):
+def test_solve_bf16_vs_oracle(torch_cuda, name, prec_name):
+    """Both BF16 forms: projector products on split-bf16 matrix cores, and in
+    the second also the Rayleigh-Ritz Gram of the complex64 stage; the FP64
+    refinement brings every eigenvalue to the oracle's."""
     torch = torch_cuda
-    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_MIXED_BF16
+    import paper_0707_3405_amd as pkg
     from workloads import make_workload
     w = make_workload(name)
-    prob = PlaneWaveProblem.from_workload(w, device=0, prec=PW_PREC_MIXED_BF16)
+    prob = pkg.PlaneWaveProblem.from_workload(w, device=0, prec=getattr(pkg, prec_name))
     eig, X, status = prob.solve(w.tol, max_iter=300)
     torch.cuda.synchronize()
     res, st = prob.ctx.get_residuals(prob.nbands), prob.ctx.get_stats()
     ref = load_golden(name)[0][:w.nbands]
     err = np.abs(eig - ref)
-    print(f"{name} bf16: max |eig - oracle| = {err.max():.3e} (mean {err.mean():.3e}), "
+    print(f"{name} {prec_name}: max |eig - oracle| = {err.max():.3e} (mean {err.mean():.3e}), "
           f"max residual {res.max():.3e}, stats {st}")
     assert err.max() <= 1e-6, err.max()
     assert res.max() <= w.tol
     assert st["mixed_iterations"] > 0
+
+
+def test_bf16_gram_is_its_own_path(torch_cuda):
+    """The BF16-Gram form runs a different complex64 stage from the BF16-projector
+    one (so its vectors differ in the last bits) and reaches the same eigenvalues."""
+    torch = torch_cuda
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_MIXED_BF16, PW_PREC_MIXED_BF16_GRAM
+    from workloads import make_workload
+    w = make_workload("mid_nl")
+    out = {}
+    for prec in (PW_PREC_MIXED_BF16, PW_PREC_MIXED_BF16_GRAM):
+        prob = PlaneWaveProblem.from_workload(w, device=0, prec=prec)
+        eig, X, _ = prob.solve(w.tol, max_iter=300)
+        torch.cuda.synchronize()
+        out[prec] = (eig, X.clone())
+    (e1, x1), (e2, x2) = out[PW_PREC_MIXED_BF16], out[PW_PREC_MIXED_BF16_GRAM]
+    assert not torch.equal(x1, x2)
+    assert np.abs(e1 - e2).max() <= 1e-8
