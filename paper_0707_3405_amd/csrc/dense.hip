@@ -840,7 +840,8 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
 
 // Gram-Schmidt (twice) of the columns of Z [n][k] in eigenvalue order.  In
 // LDS when it fits; otherwise only within clusters of eigenvalues closer than
-// ctol (vectors of separated eigenvalues are already orthogonal to ~eps ||T|| / gap).
+// ctol (vectors of separated eigenvalues are already orthogonal to ~n eps ||T|| / gap,
+// the backward error of the inverse-iteration solves over the gap).
 __global__ void __launch_bounds__(1024) k_orth(double *__restrict__ Zg, int n, int k, int in_lds,
                                                const double *__restrict__ w, double ctol_rel,
                                                const double *__restrict__ dd,
@@ -985,16 +986,16 @@ __global__ void __launch_bounds__(256) k_orth_chol(double *__restrict__ Zg, int 
 }
 
 // V[:, c] = H_0 ... H_{n-2} Z[:, c] for a chunk of cw columns held in LDS.
-// Reflectors are staged into LDS kRefl at a time.
-constexpr int kRefl = 8;
+// Reflectors are staged into LDS nrefl at a time (the host picks cw and nrefl
+// so that both fit; the staging depth does not change the arithmetic).
 __global__ void __launch_bounds__(256) k_unmtr(const cd *__restrict__ A, int64_t lda, int n, int k,
-                                               int cw, const cd *__restrict__ tau,
+                                               int cw, int nrefl, const cd *__restrict__ tau,
                                                const double *__restrict__ Z, cd *__restrict__ V,
                                                int64_t ldv) {
     extern __shared__ unsigned char smem_raw[];
     cd *Vs = reinterpret_cast<cd *>(smem_raw);   // [n][cw + 1]
-    cd *vb = Vs + (size_t)n * (cw + 1);          // [kRefl][n] staged reflectors
-    cd *sp = vb + (size_t)kRefl * n;             // [blockDim] partial dots
+    cd *vb = Vs + (size_t)n * (cw + 1);          // [nrefl][n] staged reflectors
+    cd *sp = vb + (size_t)nrefl * n;             // [blockDim] partial dots
     cd *sc = sp + blockDim.x;                    // [cw]
     const int t = threadIdx.x, nt = blockDim.x;
     const int c0 = blockIdx.x * cw;
@@ -1005,11 +1006,11 @@ __global__ void __launch_bounds__(256) k_unmtr(const cd *__restrict__ A, int64_t
         Vs[r * LD + c] = cd{c < ncol ? Z[(int64_t)r * k + c0 + c] : 0.0, 0.0};
     }
     const int parts = nt / cw;   // threads per column in the dot products
-    for (int jhi = n - 2; jhi >= 0; jhi -= kRefl) {
-        const int jlo = max(0, jhi - kRefl + 1);
+    for (int jhi = n - 2; jhi >= 0; jhi -= nrefl) {
+        const int jlo = max(0, jhi - nrefl + 1);
         __syncthreads();
         // stage reflectors jhi..jlo: slot q holds reflector jhi - q, rows j+1..n-1
-        for (int idx = t; idx < kRefl * n; idx += nt) {
+        for (int idx = t; idx < nrefl * n; idx += nt) {
             const int q = idx / n, i = idx % n;
             const int j = jhi - q;
             if (j >= jlo) {
@@ -1413,15 +1414,23 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
         PW_HIP(hipGetLastError());
         return;
     }
-    int cw = 32;
-    auto sm5_of = [&](int w_) {
-        return (size_t)n * (w_ + 1) * 16 + (size_t)kRefl * n * 16 + 256 * 16 + (size_t)w_ * 16;
+    // columns per workgroup and staged reflectors: up to 32 and 8; past n ~ 930
+    // both shrink (columns down to 4 first, then the staging depth) to fit LDS
+    int cw = 32, nrefl = 8;
+    auto sm5_of = [&](int w_, int r_) {
+        return (size_t)n * (w_ + 1) * 16 + (size_t)r_ * n * 16 + 256 * 16 + (size_t)w_ * 16;
     };
-    while (cw > 1 && sm5_of(cw) > 150 * 1024) cw /= 2;
-    const size_t sm5 = sm5_of(cw);
+    while (sm5_of(cw, nrefl) > 150 * 1024) {
+        if (cw > 4) cw /= 2;
+        else if (nrefl > 1) nrefl /= 2;
+        else if (cw > 1) cw /= 2;
+        else break;
+    }
+    const size_t sm5 = sm5_of(cw, nrefl);
+    PW_REQUIRE(sm5 <= 150 * 1024, PW_ERR_ARG, "eigenproblem too large for the back-transform");
     PW_HIP(hipFuncSetAttribute((const void *)k_unmtr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm5));
-    hipLaunchKernelGGL(k_unmtr, dim3((k + cw - 1) / cw), dim3(256), sm5, st, A, lda, n, k, cw, tau, Z,
-                       V, ldv);
+    hipLaunchKernelGGL(k_unmtr, dim3((k + cw - 1) / cw), dim3(256), sm5, st, A, lda, n, k, cw, nrefl, tau,
+                       Z, V, ldv);
     hipLaunchKernelGGL(k_check_w, dim3(1), dim3(256), 0, st, w, k, status);
     PW_HIP(hipGetLastError());
 }

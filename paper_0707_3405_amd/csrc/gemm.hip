@@ -593,6 +593,7 @@ void gemm_tn_impl(const cpx<T> *A, int64_t lda, const cpx<T> *B, int64_t ldb, in
                   cd *C, int64_t ldc, const double *scale_row, double beta, cd *part, size_t part_elems,
                   hipStream_t st) {
     if (p <= 0 || q <= 0) return;
+    PW_REQUIRE(K > 0, PW_ERR_ARG, "empty contraction (callers form a zero product themselves)");
     const int tiles_m = (p + kTile - 1) / kTile, tiles_n = (q + kTile - 1) / kTile;
     const int target = thread_tuning().tn_split_wgs > 0 ? thread_tuning().tn_split_wgs : PW_SPLIT_WGS;
     int ns = choose_split(K, tiles_m * tiles_n, target);

@@ -81,12 +81,14 @@ def test_block_update_in_place(torch_cuda):
 
 # sizes straddle the kernel variants: register-resident reduction (n <= 192),
 # LDS CholQR2 of the eigenvectors (k <= 64, n <= 219), one-wave back-transform
-# (n <= 256) and the general forms above those sizes
+# (n <= 256) and the general forms above those sizes, up to the largest
+# Rayleigh-Ritz (n = 1024, where the back-transform also shrinks its LDS staging)
 @pytest.mark.parametrize("n,k,kind", [(1, 1, "rand"), (2, 2, "rand"), (5, 3, "rand"), (33, 7, "rand"),
                                       (48, 16, "rand"), (64, 64, "rand"), (100, 1, "rand"),
                                       (130, 40, "rand"), (192, 64, "rand"), (192, 64, "degenerate"),
                                       (128, 64, "graded"), (193, 64, "rand"), (230, 70, "rand"),
-                                      (300, 32, "degenerate"), (512, 512, "rand")])
+                                      (300, 32, "degenerate"), (512, 512, "rand"),
+                                      (1000, 64, "degenerate"), (1024, 1024, "rand")])
 def test_small_eigh(torch_cuda, n, k, kind):
     torch = torch_cuda
     prob = _ctx(torch)
@@ -115,7 +117,12 @@ def test_small_eigh(torch_cuda, n, k, kind):
     nrm = np.abs(np.linalg.eigvalsh(A)).max()
     assert np.abs(wn - ref).max() <= 1e-13 * nrm * max(1, np.sqrt(n) / 4), np.abs(wn - ref).max()
     assert np.abs(A @ Vn - Vn * wn).max() <= 1e-12 * nrm
-    assert np.abs(Vn.conj().T @ Vn - np.eye(k)).max() <= 1e-12
+    # eigenvectors of separated clusters come from inverse iteration alone once
+    # n k is too large for a full re-orthogonalisation in LDS: their overlaps are
+    # bounded by the solve's backward error over the gap, ~ n eps ||T|| / gap
+    # (gap = 1 between the clusters of the degenerate matrices)
+    orth = 1e-12 if kind != "degenerate" else max(1e-12, n * np.finfo(float).eps * nrm / 1.0)
+    assert np.abs(Vn.conj().T @ Vn - np.eye(k)).max() <= orth
 
 
 def test_residuals_and_preconditioner(torch_cuda, oracle_problem):

@@ -1,0 +1,106 @@
+"""Maximum sizes and empty inputs.
+
+The largest request of the served stream (L = 24 bohr, Ecut = 25 Ha, 187 wells
+with 748 projectors, 82561 plane waves at k = (0.3, 0.1, 0.7), 1024 bands) on
+the 120^3 grid of the serving rule and on the largest supported grid, 128^3:
+H.X (local + nonlocal) against the oracle's matrix-free operator on every
+output (FP64 to 1e-13 ||H|| ||x||, complex64 to 1e-6 ||H|| ||x||), and a
+1024-band solve (20 blocks of 64, final Rayleigh-Ritz over all 1024 bands
+through the multi-workgroup reduction) checked by the oracle's operator on
+sampled bands.  Empty inputs (no bands, no columns, an empty contraction) are
+no-ops or zero products.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _hnorm(w):
+    # ||H|| <= Ecut + max|V| + sum_p |D_p| ||beta_p||^2, with ||beta_p|| ~ 1
+    return w.ecut + np.abs(w.vgrid).max() + np.abs(w.D).sum()
+
+
+@pytest.mark.parametrize("name", ["max_l24", "max_l24_n128"])
+def test_apply_max_grid(torch_cuda, oracle_problem, name):
+    torch = torch_cuda
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_MIXED
+    from workloads import start_block
+    w, mil, _, mf = oracle_problem(name, dense=False)
+    prob = PlaneWaveProblem.from_workload(w, device=0, nbands=64, block=64, prec=PW_PREC_MIXED)
+    assert prob.npw == mil.shape[0]
+    hn = _hnorm(w)
+    X = start_block(31, mil.shape[0], 8)
+    ref = mf.apply(X)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+    Yd = torch.empty_like(Xd)
+    prob.ctx.apply_H(Xd, Yd)
+    torch.cuda.synchronize()
+    err = np.linalg.norm(Yd.cpu().numpy().T - ref, axis=0) / (hn * np.linalg.norm(X, axis=0))
+    X32 = Xd.to(torch.complex64)
+    Y32 = torch.empty_like(X32)
+    prob.ctx.apply_H(X32, Y32, prec=PW_PREC_MIXED)
+    torch.cuda.synchronize()
+    x32 = X32.cpu().numpy().T
+    ref32 = mf.apply(x32.astype(np.complex128))
+    err32 = np.linalg.norm(Y32.cpu().numpy().T - ref32, axis=0) / (hn * np.linalg.norm(x32, axis=0))
+    print(f"{name} (npw {mil.shape[0]}, {w.n}^3, {w.nproj} projectors): FP64 err {err.max():.2e}, "
+          f"complex64 err {err32.max():.2e}")
+    assert err.max() <= 1e-13, err.max()
+    assert err32.max() <= 1e-6, err32.max()
+
+
+def test_solve_max_bands(torch_cuda, oracle_problem):
+    torch = torch_cuda
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_OK
+    w, mil, _, mf = oracle_problem("max_l24", dense=False)
+    prob = PlaneWaveProblem.from_workload(w, device=0)
+    assert prob.nbands == 1024
+    eig, X, status = prob.solve(w.tol, max_iter=300)
+    torch.cuda.synchronize()
+    res, st = prob.ctx.get_residuals(w.nbands), prob.ctx.get_stats()
+    print(f"max_l24: 1024 bands, eig[0] {eig[0]:.8f} eig[-1] {eig[-1]:.8f}, max residual {res.max():.2e}, "
+          f"stats {st}")
+    assert status == PW_OK
+    assert res.max() <= w.tol
+    assert np.all(np.diff(eig) >= -1e-12)
+    # sampled bands through the oracle's operator: Rayleigh quotient and residual
+    sel = np.array([0, 1, 300, 511, 512, 777, 1022, 1023])
+    Xs = X[sel].cpu().numpy().T
+    HX = mf.apply(Xs)
+    theta = np.einsum("gn,gn->n", Xs.conj(), HX).real
+    assert np.abs(theta - eig[sel]).max() <= 1e-9
+    r = np.linalg.norm(HX - Xs * theta[None, :], axis=0)
+    assert r.max() <= w.tol * 1.01, r.max()
+    # orthonormality on 64 sampled columns
+    cols = np.sort(np.random.default_rng(2).choice(w.nbands, 64, replace=False))
+    Xc = X[cols].cpu().numpy().T
+    G = Xc.conj().T @ Xc
+    assert np.abs(G - np.eye(64)).max() <= 1e-10
+
+
+def test_empty_inputs(torch_cuda):
+    torch = torch_cuda
+    from paper_0707_3405_amd import PlaneWaveProblem, PWError, PW_ERR_ARG
+    from workloads import make_workload
+    w = make_workload("tiny_nl")
+    prob = PlaneWaveProblem.from_workload(w, device=0)
+    npw = prob.npw
+    X = torch.ones((4, npw), dtype=torch.complex128, device="cuda")
+    Y = torch.full_like(X, 7.0)
+    prob.ctx.apply_H(X, Y, nb=0)                         # no bands: Y untouched
+    C = torch.full((4, 4), 3.0, dtype=torch.complex128, device="cuda")
+    prob.ctx.gram(X, X, C, p=0)                          # no columns: C untouched
+    Yu = torch.full_like(X, 5.0)
+    prob.ctx.block_update(X, C, Yu, q=0)                 # no columns: Yu untouched
+    torch.cuda.synchronize()
+    assert torch.all(Y == 7.0) and torch.all(C == 3.0) and torch.all(Yu == 5.0)
+    prob.ctx.gram(X, X, C, K=0)                          # empty contraction: C = 0
+    Yb = torch.full_like(X, 2.0)
+    prob.ctx.block_update(X, C, Yb, alpha=1.0, beta=0.5, p=0)   # empty contraction: Y = beta Y
+    torch.cuda.synchronize()
+    assert torch.all(C == 0.0)
+    assert torch.all(Yb == 1.0)
+    with pytest.raises(PWError) as e:
+        prob.ctx.lobpcg_solve(0, 1, w.tol, 10, X)
+    assert e.value.status == PW_ERR_ARG

@@ -182,4 +182,11 @@ WORKLOADS = {
                      proj=True, M=256, m=32, tol=1e-6),
     "fcc32_l12": dict(seed=5, L=12.0, ecut=12.0, n=48, k=(0.25, 0.25, 0.25),
                       fcc=2, proj=True, M=128, m=32, tol=1e-6),
+    # the largest request of the served stream (L = 24 bohr, Ecut = 25 Ha,
+    # round(0.0135 L^3) = 187 wells with 748 projectors, 1024 bands) on the
+    # 120^3 grid the serving rule picks, and on the largest supported grid
+    "max_l24": dict(seed=4, L=24.0, ecut=25.0, n=120, k=(0.3, 0.1, 0.7), natom=187,
+                    proj=True, M=1024, m=64, tol=1e-6),
+    "max_l24_n128": dict(seed=4, L=24.0, ecut=25.0, n=128, k=(0.3, 0.1, 0.7), natom=187,
+                         proj=True, M=1024, m=64, tol=1e-6),
 }
