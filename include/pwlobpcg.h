@@ -147,8 +147,9 @@ pw_status pw_set_projectors(pw_ctx ctx, int32_t natom, const double *pos,
 pw_status pw_set_overlap(pw_ctx ctx, const double *q);
 
 /* Device workspace the caller allocates: bytes needed by pw_lobpcg_solve for
- * (nbands, block) at precision prec, and by pw_apply_H (which works in chunks
- * of `block` columns).  A workspace sized for either mixed form also serves
+ * (nbands, block) at precision prec, by pw_apply_H (which works in chunks
+ * of `block` columns) and by pw_density of up to nbands bands (an N^3 grid of
+ * doubles besides the stick buffer).  A workspace sized for a mixed form also serves
  * PW_PREC_FP64.  Also answers on a host-only context (device < 0), so a
  * caller can size device memory before touching the GPU. */
 pw_status pw_workspace_size(pw_ctx ctx, int32_t nbands, int32_t block, pw_precision prec,

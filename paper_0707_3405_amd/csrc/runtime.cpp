@@ -258,10 +258,21 @@ Plan<S> make_plan(const pw_ctx_s &c, int M, int m, char *base) {
     return p;
 }
 
+// scratch of pw_density for nb bands in chunks of `chunk` (laid out as it takes it)
+size_t density_bytes(const pw_ctx_s &c, int chunk, int nb) {
+    Arena a;
+    const int64_t n3 = (int64_t)c.n * c.n * c.n;
+    a.take<cd>((size_t)chunk * c.n * c.sp.ldst);
+    a.take<double>((size_t)n3);
+    a.take<double>((size_t)nb);
+    return align_up(a.used, 256);
+}
+
+// the solver's plan, and enough for pw_density of up to M bands with the same block
 size_t plan_bytes(const pw_ctx_s &c, int M, int m, pw_precision prec) {
     size_t b = make_plan<cd>(c, M, m, nullptr).bytes;
     if (prec != PW_PREC_FP64) b = std::max(b, make_plan<pw::cf>(c, M, m, nullptr).bytes);
-    return b;
+    return std::max(b, density_bytes(c, m, M));
 }
 
 void require_precision(pw_precision prec) {
@@ -1359,12 +1370,12 @@ pw_status pw_density(pw_ctx c, const void *X, int64_t ldx, int32_t nb, const dou
         for (int i = 0; i < nb; ++i) PW_REQUIRE(std::isfinite(occ[i]), PW_ERR_ARG, "non-finite occupation");
         const int chunk = c->plan_block > 0 ? c->plan_block : 1;
         const int64_t n3 = (int64_t)c->n * c->n * c->n;
+        PW_REQUIRE(density_bytes(*c, chunk, nb) <= c->ws_bytes, PW_ERR_NOMEM, "workspace too small for the density");
         Arena a;
         a.base = c->ws;
         cd *S = a.take<cd>((size_t)chunk * c->n * c->sp.ldst);
         double *rz = a.take<double>((size_t)n3);
         double *docc = a.take<double>((size_t)nb);
-        PW_REQUIRE(align_up(a.used, 256) <= c->ws_bytes, PW_ERR_NOMEM, "workspace too small for the density");
         hipStream_t st = c->stream;
         pw::launch_zero(reinterpret_cast<cd *>(rz), n3 / 2, n3 / 2, 1, st);   // N is even
         PW_HIP(hipMemcpyAsync(docc, occ, sizeof(double) * nb, hipMemcpyHostToDevice, st));

@@ -92,3 +92,44 @@ def test_apply_potential_on_device(torch_cuda, oracle_problem):
     X = start_block(4, mil.shape[0], 3)
     Y = _run(torch, prob, X)
     assert np.abs(Y - H @ X).max() <= 1e-12
+
+
+@pytest.mark.parametrize("N", [16, 20, 24, 32, 36, 40, 48, 60, 64, 72, 80, 96, 108, 120, 128])
+def test_every_fft_size(torch_cuda, N):
+    """Every supported grid size (each has its own compile-time radix split):
+    the wells, projectors and k-point of tiny_nl sampled on an N^3 grid; H.X of
+    five bands (a ragged block) against the dense Galerkin matrix of that same
+    V grid in FP64 and complex64, and the density against the oracle's."""
+    torch = torch_cuda
+    from oracle import pw
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_MIXED, fft_sizes
+    from workloads import make_workload, well_potential, start_block
+    assert N in fft_sizes()
+    w = make_workload("tiny_nl")
+    v = well_potential(w.L, N, w.pos)
+    prob = PlaneWaveProblem(w.cell, w.kfrac, w.ecut, N, v, w.pos, w.lm, w.D, nbands=8, block=4, device=0,
+                            prec=PW_PREC_MIXED)
+    mil = prob.ctx.get_miller()
+    H = pw.dense_hamiltonian(w.cell, w.kfrac, mil, v, w.pos, w.lm, w.D)
+    hn = np.abs(np.linalg.eigvalsh(H)).max()
+    X = start_block(17, mil.shape[0], 5)
+    xn = np.linalg.norm(X, axis=0)
+    Y = _run(torch, prob, X)
+    err = np.linalg.norm(Y - H @ X, axis=0) / (hn * xn)
+    X32 = X.astype(np.complex64)
+    Xd32 = torch.from_numpy(np.ascontiguousarray(X32.T)).to("cuda")
+    Yd32 = torch.empty_like(Xd32)
+    prob.ctx.apply_H(Xd32, Yd32, prec=PW_PREC_MIXED)
+    occ = np.array([2.0, 1.5, 1.0, 0.5, 0.25])
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).to("cuda")
+    rho = torch.empty((N, N, N), dtype=torch.float64, device="cuda")
+    prob.ctx.density(Xd, occ, rho)
+    torch.cuda.synchronize()
+    err32 = (np.linalg.norm(Yd32.cpu().numpy().T - H @ X32.astype(np.complex128), axis=0)
+             / (hn * np.linalg.norm(X32, axis=0)))
+    ref = pw.density(w.cell, w.kfrac, mil, N, X, occ)
+    rerr = np.abs(rho.cpu().numpy() - ref).max() / ref.max()
+    print(f"N={N}: FP64 {err.max():.2e}, complex64 {err32.max():.2e}, density {rerr:.2e}")
+    assert err.max() <= 1e-13, err.max()
+    assert err32.max() <= 1e-6, err32.max()
+    assert rerr <= 1e-12, rerr
