@@ -156,3 +156,44 @@ def test_fixed_sweep_mode(torch_cuda, oracle_problem):
             assert eig.sum() <= prev.sum() + 1e-10
         prev = eig
     assert np.abs(eig - ref).max() <= 1e-8, np.abs(eig - ref).max()
+
+
+@pytest.mark.parametrize("block", [1, 7, 63])
+def test_solve_odd_block_sizes(torch_cuda, oracle_problem, block):
+    """Blocks of one column (single-vector LOBPCG), an odd width with a ragged last
+    block, and a width above nbands (one block of all 48 bands)."""
+    torch = torch_cuda
+    w, prob, eig, X, status, res = _solve(torch, "mid_nl", block=block)
+    ref = load_golden("mid_nl")[0][:w.nbands]
+    print(f"block {block}: max |eig - oracle| {np.abs(eig - ref).max():.2e}, stats {prob.ctx.get_stats()}")
+    assert np.abs(eig - ref).max() <= 1e-8
+    assert res.max() <= w.tol
+    _, _, _, mf = oracle_problem("mid_nl", dense=False)
+    _check_vectors(torch, w, X, eig, res, mf)
+
+
+def test_padded_leading_dimension(torch_cuda):
+    """Blocks stored with a leading dimension above npw (views into wider
+    buffers) give bitwise the results of packed blocks, and the padding rows
+    are left alone."""
+    torch = torch_cuda
+    from paper_0707_3405_amd import PlaneWaveProblem
+    from workloads import make_workload, start_block
+    w = make_workload("mid_nl")
+    prob = PlaneWaveProblem.from_workload(w, device=0)
+    npw, pad = prob.npw, 13
+    X = torch.from_numpy(np.ascontiguousarray(start_block(3, npw, 20).T)).cuda()
+    Y = prob.apply_H(X)
+    Xw = torch.full((20, npw + pad), 9.0, dtype=torch.complex128, device="cuda")
+    Yw = torch.full_like(Xw, 9.0)
+    Xw[:, :npw] = X
+    prob.ctx.apply_H(Xw[:, :npw], Yw[:, :npw])
+    eig, Xs, _ = prob.solve(w.tol, max_iter=300)
+    Zw = torch.full((w.nbands, npw + pad), 9.0, dtype=torch.complex128, device="cuda")
+    eig_w, _ = prob.ctx.lobpcg_solve(w.nbands, w.block, w.tol, 300, Zw[:, :npw])
+    torch.cuda.synchronize()
+    assert torch.equal(Yw[:, :npw], Y)
+    assert torch.all(Yw[:, npw:] == 9.0)
+    assert np.array_equal(eig_w, eig)
+    assert torch.equal(Zw[:, :npw], Xs)
+    assert torch.all(Zw[:, npw:] == 9.0)
