@@ -74,7 +74,14 @@ def cpu_baseline(w, gpu_iterations, cores, sample_iters=6):
     t2 = time.perf_counter()
     t_iter = ((t2 - t1) - (t1 - t0)) / sample_iters
     est = t_iter * gpu_iterations
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=w.nbands / est, unit="eigenpairs/s", cores=cores, kind="oracle",
+                cpu_model=model, affinity_cpus=len(os.sched_getaffinity(0)),
                 sample=(f"oracle block LOBPCG ({WORKLOAD}, block 0, {w.block} bands), "
                         f"{sample_iters} iterations timed ({t_iter:.2f} s/iteration), "
                         f"extrapolated to the GPU solve's {gpu_iterations} iterations"),

@@ -624,19 +624,6 @@ __device__ void sturm_count2(const double *d, const double *e2, int n, double x1
     }
 }
 
-__device__ int sturm_count(const double *d, const double *e2, int n, double x, double pivmin) {
-    int cnt = 0;
-    double q = d[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    if (q < 0) ++cnt;
-    for (int i = 1; i < n; ++i) {
-        q = d[i] - x - e2[i - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        if (q < 0) ++cnt;
-    }
-    return cnt;
-}
-
 struct TriBounds {
     double gl, gu, pivmin, tnorm;
 };
@@ -663,7 +650,7 @@ __device__ TriBounds tri_bounds(const double *ds, const double *ee, int n) {
 // by per-wave ballots and a minimum over the waves in LDS.
 constexpr int kStebzThreads = 256;
 __global__ void __launch_bounds__(kStebzThreads) k_stebz(const double *__restrict__ dd,
-                                                          const double *__restrict__ ee, int n, int k,
+                                                          const double *__restrict__ ee, int n, int /*k*/,
                                                           double *__restrict__ w) {
     extern __shared__ unsigned char smem_raw[];
     double *ds = reinterpret_cast<double *>(smem_raw);

@@ -153,7 +153,7 @@ __global__ void k_resid_final(const double *__restrict__ part, int nchunk, int n
 }
 
 // beta_{a,lm}(q) = pref exp(-|q|^2/2) Y_lm(q^) exp(-i q.R_a)
-__global__ void k_build_projectors(const double *__restrict__ qvec, int64_t npw, int natom,
+__global__ void k_build_projectors(const double *__restrict__ qvec, int64_t npw, int /*natom*/,
                                    const double *__restrict__ pos, int nlm,
                                    const int *__restrict__ lm, double pref, cd *__restrict__ B,
                                    int64_t ldb) {
