@@ -283,6 +283,7 @@ def main():
         Aw.copy_(Ah)
         prob.ctx.small_eigh(Aw, ncol, w.block, wv, Vv)
     t_eig = event_time_ms(torch, prob.ctx.stream, eig_once, 10)
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     # Householder reduction 16/3 n^3 + back-transform 8 n^2 k real FLOPs
     eig_flops = 16.0 / 3.0 * ncol ** 3 + 8.0 * ncol ** 2 * w.block
     eig_tflops = eig_flops / (t_eig * 1e-3) / 1e12
@@ -291,7 +292,9 @@ def main():
         "dense": dict(bound="alu", kernel="pw_small_eigh 192x192 lowest 64 (k_hetrd_rf<6>, k_stebz, "
                       "k_stein, k_orth_chol2, k_unmtr_w<3>, k_check_w)", achieved=eig_tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                       frac=eig_tflops / FP64_PEAK_TFLOPS, traffic=TRAFFIC_MEASURED["dense"],
-                      algorithmic=f"{eig_flops:.3e} FLOP per call (16/3 n^3 + 8 n^2 k)", launch_ms=t_eig),
+                      algorithmic=f"{eig_flops:.3e} FLOP per call (16/3 n^3 + 8 n^2 k)", launch_ms=t_eig,
+                      # the reduction is one workgroup, i.e. one CU, by construction
+                      one_cu_peak=FP64_PEAK_TFLOPS / n_cu, one_cu_frac=eig_tflops / (FP64_PEAK_TFLOPS / n_cu)),
         "gemm": dict(bound="mfma", kernel="k_gemm_tn_lds (+k_reduce_parts), Rayleigh-Ritz Gram 192x192, "
                      "K=34181",
                      achieved=gram_tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
