@@ -172,6 +172,10 @@ namespace {
 constexpr double kMixedTol = 1e-5;
 constexpr int kMixedMaxIter = 200;
 constexpr int kMixedFloorIters = 10;
+// complex64 stage: H X (and O X) formed from X itself every this many
+// iterations instead of carried by the block updates, so the FP32 rounding of
+// the updates does not accumulate into the Rayleigh quotients and residuals
+constexpr int kMixedRefresh = 10;
 
 // ---- workspace plan ----------------------------------------------------------
 // S is the block storage type: cd (complex128) or cf (complex64).  Small
@@ -524,6 +528,13 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
         int since_best = 0;
         int it = 0;
         for (it = 0; it < max_iter; ++it) {
+            if (std::is_same<S, pw::cf>::value && it > 0 && it % kMixedRefresh == 0) {
+                auto e = tm.begin();
+                apply_H(c, p, m, Z, ld, HZ, ld, mb);
+                if (gen) apply_O(c, p, m, Z, ld, OZ, ld, mb);
+                tm.end(PhaseTimer::kApply, e);
+                stats.h_applies += mb;
+            }
             {
                 auto e = tm.begin();
                 // R = HZ - theta OZ (OZ = Z when O = I)
