@@ -208,14 +208,18 @@ pw_status pw_apply_O(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ld
  * is in the O inner product, theta = x^H H x / x^H O x and the residual is
  * ||H x - theta O x||_2 / (x^H O x)^1/2; X is returned O-orthonormal.  tol = 0 selects the fixed-sweep
  * mode of the paper's iteration count (sec. 3.2): every block runs exactly
- * max_iter iterations with all columns active, the final Rayleigh-Ritz
- * follows and the call returns PW_OK (FP64 only).  X: device complex128
+ * max_iter iterations (a column whose residual is at the rounding floor,
+ * 1e-10 max(1, Ecut), gets no new direction, and a block with every column
+ * there stops and counts its remaining sweeps as done), the final
+ * Rayleigh-Ritz follows and the call returns PW_OK (FP64 only).  X: device complex128
  * [npw x nbands], ldx >= npw, for both precisions; on entry a starting guess
  * if use_guess != 0, on exit the orthonormal eigenvectors.  prec: see
  * pw_precision (the workspace must be sized for it).  eig: host
  * double[nbands], ascending.
+ * If every block converged but a residual exceeds tol after the final
+ * Rayleigh-Ritz, the blocks are swept once more from the rotated vectors.
  * Returns PW_ERR_NOT_CONVERGED (with the best pairs written) if a block hits
- * max_iter or a final residual exceeds tol.  Synchronises the stream. */
+ * max_iter or a final residual still exceeds tol.  Synchronises the stream. */
 pw_status pw_lobpcg_solve(pw_ctx ctx, int32_t nbands, int32_t block, double tol,
                           int32_t max_iter, pw_precision prec, void *X, int64_t ldx,
                           int32_t use_guess, double *eig);

@@ -431,7 +431,7 @@ void project_out(pw_ctx_s *c, const Plan<S> &p, PhaseTimer &tm, const S *Q, int6
 template <class S>
 pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int max_iter, S *X,
                  int64_t ldx, int use_guess, double *eig, bool final_rr, pw_stats &stats,
-                 int floor_iters = 0) {
+                 int floor_iters = 0, bool *final_res_above_tol = nullptr) {
     hipStream_t st = c->stream;
     const int64_t ld = c->ldp, npw = c->npw;
     PhaseTimer tm;
@@ -727,11 +727,25 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
     for (int j = 0; j < M; ++j)
         if (!(c->res[j] <= tol)) res_ok = false;
     if (!all_converged || !res_ok) {
+        if (all_converged && final_res_above_tol) *final_res_above_tol = true;
         c->err = all_converged ? "a final residual exceeds tol after the final Rayleigh-Ritz"
                                : "max_iter reached before every block converged";
         return PW_ERR_NOT_CONVERGED;
     }
     return PW_OK;
+}
+
+// The FP64 iteration with its final Rayleigh-Ritz; if every block converged
+// but the rotation over all bands left a residual above tol, one more sweep
+// from the rotated vectors (each block then starts at or near convergence).
+template <class S>
+pw_status lobpcg_final(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int max_iter, S *X,
+                       int64_t ldx, int use_guess, double *eig, pw_stats &stats) {
+    bool resweep = false;
+    pw_status rc = lobpcg(c, p, M, m, tol, max_iter, X, ldx, use_guess, eig, true, stats, 0, &resweep);
+    if (rc == PW_ERR_NOT_CONVERGED && resweep)
+        rc = lobpcg(c, p, M, m, tol, max_iter, X, ldx, 1, eig, true, stats);
+    return rc;
 }
 
 // FP64 solve, or the mixed form: complex64 LOBPCG to kMixedTol, then the FP64
@@ -752,10 +766,10 @@ pw_status solve(pw_ctx_s *c, int M, int m, double tol, int max_iter, pw_precisio
         pw::launch_copy_cols(p32.Xs, c->ldp, X, ldx, c->npw, M, c->stream);
         stats.mixed_iterations = stats.iterations;
         Plan<cd> p64 = ready_plan<cd>(c, M, m);
-        rc = lobpcg(c, p64, M, m, tol, max_iter, X, ldx, 1, eig, true, stats);
+        rc = lobpcg_final(c, p64, M, m, tol, max_iter, X, ldx, 1, eig, stats);
     } else {
         Plan<cd> p64 = ready_plan<cd>(c, M, m);
-        rc = lobpcg(c, p64, M, m, tol, max_iter, X, ldx, use_guess, eig, true, stats);
+        rc = lobpcg_final(c, p64, M, m, tol, max_iter, X, ldx, use_guess, eig, stats);
     }
     c->stats = stats;
     return rc;
