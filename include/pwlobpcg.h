@@ -6,7 +6,8 @@
  * Knyazev, Zerah, Comput. Mater. Sci. 2007 -- sec. 2.1: the wave-function is
  * expanded over plane waves e^{i(k+G).r} and the projected eigenproblem is
  * solved; with norm-conserving potentials the overlap operator is the
- * identity).  The iteration is the block LOBPCG of sec. 3.2, Algorithm 1,
+ * identity), or the generalized form H c = eps O c once an overlap operator
+ * is set (pw_set_overlap).  The iteration is the block LOBPCG of sec. 3.2, Algorithm 1,
  * run multiband-by-multiband with each block orthogonal to the previous ones,
  * followed by a final Rayleigh-Ritz over all bands.
  *
@@ -181,7 +182,7 @@ typedef struct {
 /* Autotuner for this context's shapes (batched k-points and served requests
  * differ in npw, grid and projector count): times the local H X of nb bands
  * (1 <= nb <= block of the workspace) for sticks per block {16, 32, 64} x
- * plane rows {8, 16, 32}, and the Rayleigh-Ritz Gram (3 block x 3 block over
+ * plane rows {16, 32, 48, 96}, and the Rayleigh-Ritz Gram (3 block x 3 block over
  * npw) plus the projector overlaps for split targets {384, 512, 768, 1024},
  * with HIP events on the context stream (mean of 5 after a warm-up); keeps
  * the fastest of each (or the default when nothing beats it) for later
@@ -291,8 +292,9 @@ pw_status pw_chol_inv(pw_ctx ctx, const void *G, int64_t ldg, int32_t n, void *R
 /* Lowest k eigenpairs of a Hermitian n x n matrix A (lda >= n) -- the small
  * dense Rayleigh-Ritz eigenproblem of Algorithm 1 step 4 and of the final
  * Rayleigh-Ritz (sec. 3.2, sec. 4.2).  Householder tridiagonalisation,
- * bisection, inverse iteration, re-orthogonalisation, back-transform; one
- * workgroup, FP64.  w: device double[k] ascending; V: device [n x k], ldv >= n.
+ * bisection, inverse iteration, re-orthogonalisation, back-transform, FP64;
+ * the reduction runs in one workgroup for n <= 192 and over many above.
+ * w: device double[k] ascending; V: device [n x k], ldv >= n.
  * A is overwritten.  1 <= k <= n <= 1024.  Needs the workspace. */
 pw_status pw_small_eigh(pw_ctx ctx, void *A, int64_t lda, int32_t n, int32_t k,
                         void *w, void *V, int64_t ldv);
