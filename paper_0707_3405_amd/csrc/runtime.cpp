@@ -483,14 +483,43 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
             pw::launch_random_block(Z + (int64_t)nfill * ld, ld, npw, mb - nfill,
                                     0x5EED0000ull + (uint64_t)b0, c->sp.kin, st);
         // orthogonal to previous blocks, orthonormal (twice)
-        if (gen) {
-            auto e = tm.begin();
-            apply_O(c, p, m, Z, ld, OZ, ld, mb);
-            tm.end(PhaseTimer::kApply, e);
-        }
-        for (int pass = 0; pass < 2; ++pass) {
-            project_out(c, p, tm, (const S *)X, ldx, b0, Z, ld, mb, OXprev, ld, OZ);
-            cholqr(c, p, tm, Z, ld, mb, OZ);
+        auto orthonormalise_start = [&]() {
+            if (gen) {
+                auto e = tm.begin();
+                apply_O(c, p, m, Z, ld, OZ, ld, mb);
+                tm.end(PhaseTimer::kApply, e);
+            }
+            for (int pass = 0; pass < 2; ++pass) {
+                project_out(c, p, tm, (const S *)X, ldx, b0, Z, ld, mb, OXprev, ld, OZ);
+                cholqr(c, p, tm, Z, ld, mb, OZ);
+            }
+        };
+        orthonormalise_start();
+        if (nguess > 0) {
+            // columns of the caller's guess with nothing independent left (zero,
+            // repeated, or spanned by the earlier blocks) leave the
+            // orthonormalisation as null columns, which would pass as converged:
+            // they are replaced by random columns from a seed range of their own
+            // (distinct per block, round and column) until every column is unit
+            std::vector<cd> g((size_t)mb * mb);
+            for (int round = 0; round < 3; ++round) {
+                pw::launch_gemm_tn(Z, ld, gen ? OZ : Z, ld, npw, mb, mb, p.Gs, mb, nullptr, 0.0, p.part,
+                                   p.part_elems, st);
+                PW_HIP(hipMemcpyAsync(g.data(), p.Gs, sizeof(cd) * g.size(), hipMemcpyDeviceToHost, st));
+                PW_HIP(hipStreamSynchronize(st));
+                PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), st));   // breakdowns of the guess
+                bool redo = false;
+                for (int j = 0; j < mb; ++j) {
+                    if (!(std::fabs(g[(size_t)j * mb + j].x - 1.0) <= 1e-6)) {
+                        const uint64_t seed = 0x5EED0000ull + ((uint64_t)(b0 + 1) << 16) +
+                                              ((uint64_t)round << 12) + (uint64_t)j;
+                        pw::launch_random_block(Z + (int64_t)j * ld, ld, npw, 1, seed, c->sp.kin, st);
+                        redo = true;
+                    }
+                }
+                if (!redo) break;
+                orthonormalise_start();
+            }
         }
         {
             auto e = tm.begin();

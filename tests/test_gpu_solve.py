@@ -197,3 +197,28 @@ def test_padded_leading_dimension(torch_cuda):
     assert np.array_equal(eig_w, eig)
     assert torch.equal(Zw[:, :npw], Xs)
     assert torch.all(Zw[:, npw:] == 9.0)
+
+
+@pytest.mark.parametrize("kind", ["zero", "duplicated"])
+def test_degenerate_guess(torch_cuda, kind):
+    """A starting guess without independent columns (all zero) or with repeated
+    columns still gives the oracle's eigenpairs: null columns are never taken
+    for converged vectors."""
+    torch = torch_cuda
+    from workloads import make_workload, start_block
+    w = make_workload("mid_nl")
+    from paper_0707_3405_amd import PlaneWaveProblem
+    prob = PlaneWaveProblem.from_workload(w, device=0)
+    X = prob.empty_block(w.nbands)
+    if kind == "duplicated":
+        G = torch.from_numpy(np.ascontiguousarray(start_block(9, prob.npw, w.nbands // 2).T)).cuda()
+        X[0::2] = G
+        X[1::2] = G
+    eig, X, status = prob.solve(w.tol, max_iter=300, X=X)
+    torch.cuda.synchronize()
+    res = prob.ctx.get_residuals(w.nbands)
+    ref = load_golden("mid_nl")[0][:w.nbands]
+    assert np.abs(eig - ref).max() <= 1e-8, np.abs(eig - ref).max()
+    assert res.max() <= w.tol
+    Xn = X.cpu().numpy().T
+    assert np.abs(Xn.conj().T @ Xn - np.eye(w.nbands)).max() <= 1e-10
