@@ -222,3 +222,30 @@ def test_degenerate_guess(torch_cuda, kind):
     assert res.max() <= w.tol
     Xn = X.cpu().numpy().T
     assert np.abs(Xn.conj().T @ Xn - np.eye(w.nbands)).max() <= 1e-10
+
+
+def test_context_reuse_across_cells(torch_cuda):
+    """One context, two cells: pw_init_basis resets the potential, projectors,
+    their complex64 copies and the workspace, and each solve matches its own
+    oracle (mixed form first, so the complex64 tables of the first cell exist
+    when the basis changes)."""
+    torch = torch_cuda
+    from paper_0707_3405_amd import Context, PW_PREC_MIXED, PWError, PW_ERR_STATE
+    from workloads import make_workload
+    ctx = Context(0)
+    for name, prec in (("mid_nl", PW_PREC_MIXED), ("gamma_l10", 0), ("mid_nl", 0)):
+        w = make_workload(name)
+        npw = ctx.init_basis(w.cell, w.kfrac, w.ecut, (w.n,) * 3)
+        X = torch.zeros((w.nbands, npw), dtype=torch.complex128, device="cuda")
+        with pytest.raises(PWError) as e:          # potential and workspace of the previous cell are gone
+            ctx.lobpcg_solve(w.nbands, w.block, w.tol, 300, X, prec=prec)
+        assert e.value.status == PW_ERR_STATE
+        ctx.set_local_potential(w.vgrid)
+        if w.lm:
+            ctx.set_projectors(w.pos, w.lm, w.D)
+        ws = ctx.alloc_workspace(w.nbands, w.block, prec)
+        eig, _ = ctx.lobpcg_solve(w.nbands, w.block, w.tol, 300, X, prec=prec)
+        torch.cuda.synchronize()
+        ref = load_golden(name)[0][:w.nbands]
+        assert np.abs(eig - ref).max() <= 1e-8, (name, np.abs(eig - ref).max())
+        del ws
