@@ -221,6 +221,9 @@ pw_status pw_apply_O(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ld
  * double[nbands], ascending.
  * If every block converged but a residual exceeds tol after the final
  * Rayleigh-Ritz, the blocks are swept once more from the rotated vectors.
+ * Limits: 1 <= block <= 64, nbands <= 1024 and nbands + 3 block <= npw (so
+ * every block has room for its basis [X P W] beside the earlier bands);
+ * else PW_ERR_ARG (also from pw_workspace_size).
  * Returns PW_ERR_NOT_CONVERGED (with the best pairs written) if a block hits
  * max_iter or a final residual still exceeds tol.  Synchronises the stream. */
 pw_status pw_lobpcg_solve(pw_ctx ctx, int32_t nbands, int32_t block, double tol,

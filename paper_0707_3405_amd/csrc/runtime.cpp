@@ -1205,7 +1205,8 @@ pw_status pw_workspace_size(pw_ctx c, int32_t nbands, int32_t block, pw_precisio
         PW_REQUIRE(bytes, PW_ERR_ARG, "null output");
         require_precision(prec);
         PW_REQUIRE(nbands >= 1 && block >= 1 && block <= 64, PW_ERR_ARG, "need nbands >= 1 and 1 <= block <= 64");
-        PW_REQUIRE(nbands <= 1024 && nbands <= c->npw, PW_ERR_ARG, "nbands must be <= min(npw, 1024)");
+        PW_REQUIRE(nbands <= 1024 && (int64_t)nbands + 3 * std::min(block, nbands) <= c->npw, PW_ERR_ARG,
+                   "need nbands <= 1024 and nbands + 3 * block <= npw");
         const int m = std::min(block, nbands);
         c->plan_nbands = nbands;
         c->plan_block = m;
@@ -1278,8 +1279,9 @@ pw_status pw_lobpcg_solve(pw_ctx c, int32_t nbands, int32_t block, double tol, i
         require_basis(c);
         PW_REQUIRE(X && eig, PW_ERR_ARG, "null argument");
         PW_REQUIRE(nbands >= 1 && block >= 1 && block <= 64, PW_ERR_ARG, "need nbands >= 1, 1 <= block <= 64");
-        PW_REQUIRE(nbands <= 1024 && nbands <= c->npw, PW_ERR_ARG, "nbands must be <= min(npw, 1024)");
-        PW_REQUIRE(3 * std::min(block, nbands) <= c->npw, PW_ERR_ARG, "3 * block must not exceed npw");
+        // every block needs room for its whole basis [X P W] beside the earlier bands
+        PW_REQUIRE(nbands <= 1024 && (int64_t)nbands + 3 * std::min(block, nbands) <= c->npw, PW_ERR_ARG,
+                   "need nbands <= 1024 and nbands + 3 * block <= npw");
         PW_REQUIRE(ldx >= c->npw, PW_ERR_ARG, "ldx < npw");
         PW_REQUIRE(tol >= 0 && max_iter >= 1, PW_ERR_ARG, "need tol >= 0 and max_iter >= 1");
         PW_REQUIRE(tol > 0 || prec == PW_PREC_FP64, PW_ERR_ARG, "the fixed-sweep mode (tol = 0) is FP64 only");

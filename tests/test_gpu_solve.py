@@ -249,3 +249,30 @@ def test_context_reuse_across_cells(torch_cuda):
         ref = load_golden(name)[0][:w.nbands]
         assert np.abs(eig - ref).max() <= 1e-8, (name, np.abs(eig - ref).max())
         del ws
+
+
+@pytest.mark.parametrize("frac", [0.5, 1.0])
+def test_many_bands_up_to_limit(torch_cuda, oracle_problem, frac):
+    """nbands up to the limit npw - 3 block: the last block still has room for
+    [X P W] beside the earlier bands, and the eigenvalues match the dense
+    oracle's spectrum; one band more is refused."""
+    torch = torch_cuda
+    from paper_0707_3405_amd import PlaneWaveProblem, Context, PWError, PW_ERR_ARG
+    w, mil, H, mf = oracle_problem("tiny_nl", dense=True)
+    npw, block = mil.shape[0], 16
+    M = int(round(0.5 * npw)) if frac < 1 else npw - 3 * block
+    prob = PlaneWaveProblem.from_workload(w, device=0, nbands=M, block=block)
+    eig, X, status = prob.solve(w.tol, max_iter=300)
+    torch.cuda.synchronize()
+    res = prob.ctx.get_residuals(M)
+    ref = np.linalg.eigvalsh(H)[:M]
+    print(f"nbands {M} of npw {npw}: max |eig - dense| {np.abs(eig - ref).max():.2e}, "
+          f"max residual {res.max():.2e}, stats {prob.ctx.get_stats()}")
+    assert np.abs(eig - ref).max() <= 1e-8
+    assert res.max() <= w.tol
+    Xn = X.cpu().numpy().T
+    assert np.abs(Xn.conj().T @ Xn - np.eye(M)).max() <= 1e-10
+    if frac == 1.0:
+        with pytest.raises(PWError) as e:
+            prob.ctx.workspace_size(M + 1, block)
+        assert e.value.status == PW_ERR_ARG
