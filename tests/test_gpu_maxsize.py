@@ -50,17 +50,21 @@ def test_apply_max_grid(torch_cuda, oracle_problem, name):
     assert err32.max() <= 1e-6, err32.max()
 
 
-def test_solve_max_bands(torch_cuda, oracle_problem):
+@pytest.mark.parametrize("mixed", [False, True])
+def test_solve_max_bands(torch_cuda, oracle_problem, mixed):
+    """FP64, and the mixed form (its complex64 stage over K = 82561 in FP32
+    stops at its precision floor if 1e-5 is out of reach; the FP64 stage
+    refines every band to tol)."""
     torch = torch_cuda
-    from paper_0707_3405_amd import PlaneWaveProblem, PW_OK
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_OK, PW_PREC_FP64, PW_PREC_MIXED
     w, mil, _, mf = oracle_problem("max_l24", dense=False)
-    prob = PlaneWaveProblem.from_workload(w, device=0)
+    prob = PlaneWaveProblem.from_workload(w, device=0, prec=PW_PREC_MIXED if mixed else PW_PREC_FP64)
     assert prob.nbands == 1024
     eig, X, status = prob.solve(w.tol, max_iter=300)
     torch.cuda.synchronize()
     res, st = prob.ctx.get_residuals(w.nbands), prob.ctx.get_stats()
-    print(f"max_l24: 1024 bands, eig[0] {eig[0]:.8f} eig[-1] {eig[-1]:.8f}, max residual {res.max():.2e}, "
-          f"stats {st}")
+    print(f"max_l24 ({'mixed' if mixed else 'FP64'}): 1024 bands, eig[0] {eig[0]:.8f} eig[-1] {eig[-1]:.8f}, "
+          f"max residual {res.max():.2e}, stats {st}")
     assert status == PW_OK
     assert res.max() <= w.tol
     assert np.all(np.diff(eig) >= -1e-12)
