@@ -212,3 +212,35 @@ def test_bf16_gram_is_its_own_path(torch_cuda):
     (e1, x1), (e2, x2) = out[PW_PREC_MIXED_BF16], out[PW_PREC_MIXED_BF16_GRAM]
     assert not torch.equal(x1, x2)
     assert np.abs(e1 - e2).max() <= 1e-8
+
+
+def test_complex64_tables_follow_new_inputs(torch_cuda):
+    """A new potential or projector set (as in a self-consistent loop) reaches
+    the complex64 H.X too: its float copies are rebuilt, never reused stale."""
+    torch = torch_cuda
+    from oracle import pw
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_MIXED
+    from workloads import make_workload, start_block
+    w = make_workload("tiny_nl")
+    prob = PlaneWaveProblem.from_workload(w, device=0, prec=PW_PREC_MIXED)
+    mil = prob.ctx.get_miller()
+    X = start_block(41, mil.shape[0], 6).astype(np.complex64)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+
+    def check(v, D):
+        Y = torch.empty_like(Xd)
+        prob.ctx.apply_H(Xd, Y, prec=PW_PREC_MIXED)
+        torch.cuda.synchronize()
+        H = pw.dense_hamiltonian(w.cell, w.kfrac, mil, v, w.pos, w.lm, D)
+        ref = H @ X.astype(np.complex128)
+        hn = np.abs(np.linalg.eigvalsh(H)).max()
+        err = np.linalg.norm(Y.cpu().numpy().T - ref, axis=0) / (hn * np.linalg.norm(X, axis=0))
+        assert err.max() <= 1e-6, err.max()
+
+    check(w.vgrid, w.D)
+    v2 = 0.5 * w.vgrid + 0.1
+    prob.ctx.set_local_potential(v2)
+    check(v2, w.D)
+    D2 = w.D[::-1].copy()
+    prob.ctx.set_projectors(w.pos, w.lm, D2)
+    check(v2, D2)
