@@ -189,3 +189,20 @@ def test_solve_overlap_bf16(torch_cuda):
     assert np.abs(eig - ref).max() <= 1e-8, np.abs(eig - ref).max()
     assert res.max() <= w.tol
     assert st["mixed_iterations"] > 0
+
+
+def test_overlap_warm_restart(torch_cuda):
+    """A second solve of the pencil from the first one's (O-orthonormal) vectors
+    keeps them (the start-block check runs in the O metric) and converges at
+    once."""
+    torch = torch_cuda
+    w, q, prob = _problem("mid_nl")
+    eig, X, _ = prob.solve(w.tol, max_iter=300)
+    torch.cuda.synchronize()
+    it1 = prob.ctx.get_stats()["iterations"]
+    eig2, X2, _ = prob.solve(w.tol, max_iter=300, X=X.clone())
+    torch.cuda.synchronize()
+    st = prob.ctx.get_stats()
+    print(f"first solve {it1} iterations, warm restart {st['iterations']} over {st['blocks']} blocks")
+    assert st["iterations"] <= 2 * st["blocks"]
+    assert np.abs(eig2 - eig).max() <= 1e-10
