@@ -35,7 +35,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a plain-copy
 # calibration; profiles/hbm_bytes_fcc108_l20.txt) for the kernels as they were profiled;
 # set an entry to None when its kernels change.
-TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 2.96e8, "dense": None}
+TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 2.96e8, "dense": 5.15e6}
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
 WORKLOAD = "fcc108_l20"
 
