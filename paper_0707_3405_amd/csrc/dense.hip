@@ -1373,21 +1373,21 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     int E = (int)((budget - 16 * (size_t)n) / (48 * (size_t)n));
     E = std::max(1, std::min(4, E));   // few eigenvalues per workgroup: spread over CUs
     const size_t sm3 = 16 * (size_t)n + 48 * (size_t)n * E;
-    PW_HIP(hipFuncSetAttribute((const void *)k_stein, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm3));
+    ensure_smem_limit((const void *)k_stein, sm3);
     hipLaunchKernelGGL(k_stein, dim3((k + E - 1) / E), dim3(64), sm3, st, d, e, n, k, E, w, Z);
     // 4. orthogonalisation
     const size_t smc = ((size_t)n * (k + 1) + (size_t)k * (k + 1) + k) * 8;
     if (k <= 64 && orth_chol2_lds(n) <= 150 * 1024) {
         const size_t sm = orth_chol2_lds(n);
-        PW_HIP(hipFuncSetAttribute((const void *)k_orth_chol2, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm));
+        ensure_smem_limit((const void *)k_orth_chol2, sm);
         hipLaunchKernelGGL(k_orth_chol2, dim3(1), dim3(1024), sm, st, Z, n, k, status);
     } else if (k <= kOrthMaxK && n <= 256 && smc <= 150 * 1024) {
-        PW_HIP(hipFuncSetAttribute((const void *)k_orth_chol, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smc));
+        ensure_smem_limit((const void *)k_orth_chol, smc);
         hipLaunchKernelGGL(k_orth_chol, dim3(1), dim3(256), smc, st, Z, n, k, status);
     } else {
     const bool in_lds = (size_t)n * (k + 1) * 8 + (size_t)(k + 1024) * 8 <= 140 * 1024;
     const size_t sm4 = (size_t)(k + 1024) * 8 + (in_lds ? (size_t)n * (k + 1) * 8 : 0);
-    PW_HIP(hipFuncSetAttribute((const void *)k_orth, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm4));
+    ensure_smem_limit((const void *)k_orth, sm4);
     hipLaunchKernelGGL(k_orth, dim3(1), dim3(1024), sm4, st, Z, n, k, in_lds ? 1 : 0, w, 2e-5, d, e);
     }
     // 5. back-transform
@@ -1417,7 +1417,7 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     }
     const size_t sm5 = sm5_of(cw, nrefl);
     PW_REQUIRE(sm5 <= 150 * 1024, PW_ERR_ARG, "eigenproblem too large for the back-transform");
-    PW_HIP(hipFuncSetAttribute((const void *)k_unmtr, hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm5));
+    ensure_smem_limit((const void *)k_unmtr, sm5);
     hipLaunchKernelGGL(k_unmtr, dim3((k + cw - 1) / cw), dim3(256), sm5, st, A, lda, n, k, cw, nrefl, tau,
                        Z, V, ldv);
     hipLaunchKernelGGL(k_check_w, dim3(1), dim3(256), 0, st, w, k, status);

@@ -362,12 +362,9 @@ void run_apply(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx
     if (rb > N) rb = N;
     const size_t sm2 = sm2_of(rb);
     PW_REQUIRE(sm2 <= 160 * 1024, PW_ERR_ARG, "FFT plane does not fit in LDS");
-    PW_HIP(hipFuncSetAttribute((const void *)k_zinv<N, T>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm13));
-    PW_HIP(hipFuncSetAttribute((const void *)k_plane<N, T>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2));
-    PW_HIP(hipFuncSetAttribute((const void *)k_zfwd<N, T>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm13));
+    ensure_smem_limit((const void *)k_zinv<N, T>, sm13);
+    ensure_smem_limit((const void *)k_plane<N, T>, sm2);
+    ensure_smem_limit((const void *)k_zfwd<N, T>, sm13);
     hipLaunchKernelGGL((k_zinv<N, T>), g13, dim3(kThreads), sm13, st, sp, X, ldx, S, spb);
     hipLaunchKernelGGL((k_plane<N, T>), dim3(N * nb), dim3(plane_threads<N, T>()), sm2, st, sp, vperm, S, nb,
                        rb);
@@ -423,10 +420,8 @@ void run_density(const SphereDev &sp, const cd *X, int64_t ldx, int nb, const do
     if (rb > N) rb = N;
     const size_t sm2 = base2 + (size_t)rb * (N + 1) * e;
     PW_REQUIRE(sm2 <= 160 * 1024, PW_ERR_ARG, "FFT plane does not fit in LDS");
-    PW_HIP(hipFuncSetAttribute((const void *)k_zinv<N, double>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm1));
-    PW_HIP(hipFuncSetAttribute((const void *)k_plane_rho<N, double>,
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)sm2));
+    ensure_smem_limit((const void *)k_zinv<N, double>, sm1);
+    ensure_smem_limit((const void *)k_plane_rho<N, double>, sm2);
     hipLaunchKernelGGL((k_zinv<N, double>), dim3((sp.nst + spb - 1) / spb, nb), dim3(kThreads), sm1, st,
                        sp, X, ldx, S, spb);
     hipLaunchKernelGGL((k_plane_rho<N, double>), dim3(N), dim3(kRhoThreads), sm2, st, sp, S, nb, occ,

@@ -59,6 +59,13 @@ struct SphereDev {
     double *twid = nullptr;       // [n] exp(+2 pi i j / n), interleaved
 };
 
+// Dynamic LDS limit of a kernel: raised through the runtime only when a launch
+// needs more than the largest limit already set for that kernel on the current
+// device, and never lowered, so launches of one kernel from several call sites
+// or host threads cannot undercut each other (and the runtime call is not paid
+// on every launch).
+void ensure_smem_limit(const void *kernel, size_t bytes);
+
 // ---- kernel launchers (implemented in the .hip files) ----------------------
 
 // FFT apply (rows a2-a6): Y = T X + (V psi)(G) for nb columns.  S is the stick

@@ -9,6 +9,8 @@
 #include <new>
 #include <thread>
 #include <type_traits>
+#include <map>
+#include <mutex>
 
 #include "pw_internal.h"
 
@@ -76,6 +78,17 @@ struct PhaseTimer {
 }  // namespace
 
 namespace pw {
+void ensure_smem_limit(const void *kernel, size_t bytes) {
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, size_t> done;
+    int dev = 0;
+    PW_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lock(mu);
+    size_t &cur = done[{kernel, dev}];
+    if (bytes <= cur) return;
+    PW_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes));
+    cur = bytes;
+}
 namespace {
 const Tuning kDefaultTuning{};
 thread_local const Tuning *t_tuning = nullptr;
