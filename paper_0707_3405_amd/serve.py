@@ -18,6 +18,7 @@ from __future__ import annotations
 import argparse
 import collections
 import json
+import sys
 import threading
 import time
 
@@ -67,10 +68,11 @@ def solve_one(w, prec, device=0, torch=None):
 class Server:
     """Admission control and continuous batching over independent solves."""
 
-    def __init__(self, device=0, budget_bytes=None, max_active=8):
+    def __init__(self, device=0, budget_bytes=None, max_active=8, log=None):
         import torch
         self.torch = torch
         self.device = device
+        self.log = log   # optional callable taking one line per finished request
         if budget_bytes is None:
             free, _total = torch.cuda.mem_get_info(device)
             budget_bytes = int(0.8 * free)
@@ -97,6 +99,9 @@ class Server:
             with lock:
                 results[i].update(r)
                 results[i]["done_s"] = time.perf_counter() - t0
+                if self.log:
+                    self.log(f"request {i}: {r['nbands']} bands, solve {r['solve_s']:.2f} s, latency "
+                             f"{results[i]['done_s'] - results[i]['arrival_s']:.2f} s")
                 state["used"] -= sizes[i]
                 state["active"] -= 1
                 state["done"] += 1
@@ -159,7 +164,7 @@ def main():
     for i in range(args.requests):
         w, mixed = make_request(i, L_range=(8.0, args.lmax), ecut_range=(5.0, args.ecut_max))
         reqs.append((float(arr[i]), w, PW_PREC_MIXED if mixed else PW_PREC_FP64))
-    srv = Server(max_active=args.max_active)
+    srv = Server(max_active=args.max_active, log=lambda line: print(f"[serve] {line}", file=sys.stderr, flush=True))
     _, summary = srv.run(reqs)
     print(json.dumps(summary))
 
