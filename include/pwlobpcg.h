@@ -215,7 +215,8 @@ pw_status pw_apply_O(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ld
  * Rayleigh-Ritz follows and the call returns PW_OK (FP64 only).  X: device complex128
  * [npw x nbands], ldx >= npw, for both precisions; on entry a starting guess
  * if use_guess != 0 (columns of it with nothing independent left -- zero,
- * repeated, or spanned by earlier bands -- are replaced by random columns),
+ * repeated, spanned by earlier bands -- or with non-finite entries are
+ * replaced by random columns),
  * on exit the orthonormal eigenvectors.  prec: see
  * pw_precision (the workspace must be sized for it).  eig: host
  * double[nbands], ascending.

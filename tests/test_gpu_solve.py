@@ -199,11 +199,11 @@ def test_padded_leading_dimension(torch_cuda):
     assert torch.all(Zw[:, npw:] == 9.0)
 
 
-@pytest.mark.parametrize("kind", ["zero", "duplicated"])
+@pytest.mark.parametrize("kind", ["zero", "duplicated", "nan"])
 def test_degenerate_guess(torch_cuda, kind):
-    """A starting guess without independent columns (all zero) or with repeated
-    columns still gives the oracle's eigenpairs: null columns are never taken
-    for converged vectors."""
+    """A starting guess without independent columns (all zero), with repeated
+    columns, or with a non-finite column still gives the oracle's eigenpairs:
+    null or non-finite columns are never taken for converged vectors."""
     torch = torch_cuda
     from workloads import make_workload, start_block
     w = make_workload("mid_nl")
@@ -214,6 +214,9 @@ def test_degenerate_guess(torch_cuda, kind):
         G = torch.from_numpy(np.ascontiguousarray(start_block(9, prob.npw, w.nbands // 2).T)).cuda()
         X[0::2] = G
         X[1::2] = G
+    elif kind == "nan":
+        X.copy_(torch.from_numpy(np.ascontiguousarray(start_block(9, prob.npw, w.nbands).T)).cuda())
+        X[5, 17] = complex(float("nan"), 0.0)
     eig, X, status = prob.solve(w.tol, max_iter=300, X=X)
     torch.cuda.synchronize()
     res = prob.ctx.get_residuals(w.nbands)
