@@ -94,3 +94,19 @@ def test_argument_and_state_errors():
         c.workspace_size(16, 128)
     assert e.value.status == PW_ERR_ARG
     assert c.workspace_size(16, 16) > 0
+
+
+def test_band_count_limit_and_density_room():
+    """nbands + 3 block <= npw is enforced on the host (every block keeps room
+    for [X P W] beside the earlier bands), and the workspace size covers the
+    density's N^3 grid however few the bands."""
+    from paper_0707_3405_amd import Context, PWError, PW_ERR_ARG
+    w = make_workload("gamma_l10")
+    c = Context(-1)
+    npw = c.init_basis(w.cell, w.kfrac, w.ecut, (w.n,) * 3)
+    assert npw == 515
+    assert c.workspace_size(npw - 48, 16) > 0
+    with pytest.raises(PWError) as e:
+        c.workspace_size(npw - 47, 16)
+    assert e.value.status == PW_ERR_ARG
+    assert c.workspace_size(1, 1) >= w.n ** 3 * 8
