@@ -11,11 +11,11 @@ TEST INFRASTRUCTURE ONLY (oracle).  Plain numpy/scipy, FP64/complex128.
 * `MatFreeH.apply_O` -- the overlap operator O = I + sum_p q_p |beta_p><beta_p|
   of the generalized form (sec. 2.1; see oracle.pw.overlap_dense), identity
   when no q is given.
-* `lobpcg_block` -- Algorithm 1 (sec. 3.2): Rayleigh quotients, residuals
-  R = H Psi - O Psi Upsilon, preconditioned W = K(R), Rayleigh-Ritz on
-  span{Psi, W, P} with the Gram pair (Z^H H Z, Z^H O Z),
-  Psi <- Psi Delta + W Lambda + P Gamma, P <- W Lambda + P Gamma, with the
-  current block kept O-orthogonal to the previously computed bands.
+* `lobpcg_block` -- block LOBPCG (sec. 3.2) for one block: each iteration
+  is a Rayleigh-Ritz projection of the pencil (H, O) onto the span of the
+  current Ritz vectors, their preconditioned residuals (K of sec. 3.1) and the
+  previous search direction, with the block kept O-orthogonal to the bands of
+  earlier blocks.
 * `solve` -- the multiband-by-multiband sweep over M/m blocks followed by the
   final Rayleigh-Ritz over all M bands (end of sec. 3.2; sec. 2.1 step 4).
 * `certificate` -- residual-based eigenvalue error bounds for Hermitian H.
@@ -131,64 +131,91 @@ def _orth_against(V, Y, OY=None):
     return V - Y @ ((Y if OY is None else OY).conj().T @ V)
 
 
+class _Images:
+    """A block V together with H V and O V (kept together through every linear
+    combination, so no operator is applied twice to the same vectors)."""
+
+    def __init__(self, V, HV, OV):
+        self.V, self.HV, self.OV = V, HV, OV
+
+    @classmethod
+    def of(cls, H: MatFreeH, V):
+        return cls(V, H.apply(V), H.apply_O(V))
+
+    @classmethod
+    def join(cls, parts):
+        return cls(*(np.hstack([getattr(p, a) for p in parts]) for a in ("V", "HV", "OV")))
+
+    @property
+    def width(self):
+        return self.V.shape[1]
+
+    def times(self, C):
+        return _Images(self.V @ C, self.HV @ C, self.OV @ C)
+
+    def scaled(self, s):
+        return _Images(self.V * s[None, :], self.HV * s[None, :], self.OV * s[None, :])
+
+    def ritz(self, nwant):
+        return rayleigh_ritz(self.V, self.HV, nwant, OZ=self.OV)
+
+
 def lobpcg_block(H: MatFreeH, Psi0, Y=None, tol=1e-8, maxit=300, history=None, nconv=None,
                  OY=None, out=None):
-    """Algorithm 1 of sec. 3.2 for one block, O-orthogonal to Y (O Y given as OY).
+    """Block LOBPCG for one block of m bands (sec. 3.2), O-orthogonal to Y (O Y given as OY).
+
+    The method is a locally optimal three-term recurrence: every iteration
+    replaces the block by the lowest m Ritz vectors of the pencil (H, O)
+    restricted to a trial space of three parts --
+      * the current Ritz vectors x_j,
+      * their residuals H x_j - theta_j O x_j (theta_j the Rayleigh quotient,
+        Eq. 1) after the preconditioner K (sec. 3.1) and the O-orthogonal
+        projection away from the bands of earlier blocks,
+      * the previous search direction, i.e. the part of the last update that
+        came from outside the old block (a stable basis of span{x^(i-1), x^(i)}).
+    Columns are scaled to unit length before the projection (the scale of a
+    basis vector does not change the trial space).
 
     Iterates all m columns of Psi0; stops when the lowest `nconv` (default m)
-    residuals are <= tol.  Returns (eps[m], Psi[npw, m], HPsi, res[m], iterations);
-    with `out` (a dict) also out["OPsi"] = O Psi.
+    residual norms are <= tol.  Returns (eps[m], Psi[npw, m], HPsi, res[m],
+    iterations); with `out` (a dict) also out["OPsi"] = O Psi.
     """
     m = Psi0.shape[1]
     nconv = m if nconv is None else nconv
-    Psi = _orth_against(np.asarray(Psi0, np.complex128), Y, OY)
-    HPsi = H.apply(Psi)
-    OPsi = H.apply_O(Psi)
-    eps, C = rayleigh_ritz(Psi, HPsi, m, OZ=OPsi)
-    Psi, HPsi, OPsi = Psi @ C, HPsi @ C, OPsi @ C
-    P = HP = OP = None
-    it = 0
+    x = _Images.of(H, _orth_against(np.asarray(Psi0, np.complex128), Y, OY))
+    eps, C = x.ritz(m)
+    x = x.times(C)
+    direction = None
     res = None
-    for it in range(1, maxit + 1):
-        # step 1: Upsilon = diag of Rayleigh quotients x^H H x / x^H O x
-        nrm2 = np.einsum("gn,gn->n", Psi.conj(), OPsi).real
-        eps = np.einsum("gn,gn->n", Psi.conj(), HPsi).real / nrm2
-        # step 2: residuals R = H Psi - O Psi Upsilon
-        R = HPsi - OPsi * eps[None, :]
-        res = np.linalg.norm(R, axis=0) / np.sqrt(nrm2)
+    iters = 0
+    while True:
+        norm2 = np.einsum("gn,gn->n", x.V.conj(), x.OV).real
+        eps = np.einsum("gn,gn->n", x.V.conj(), x.HV).real / norm2
+        R = x.HV - x.OV * eps[None, :]
+        res = np.linalg.norm(R, axis=0) / np.sqrt(norm2)
         if history is not None:
             history.append(eps.copy())
-        if np.all(res[:nconv] <= tol):
-            it -= 1
+        if np.all(res[:nconv] <= tol) or iters == maxit:
             break
-        # step 3: preconditioned residuals, constrained to the earlier blocks
-        W = _orth_against(tpa_precondition(H.T, Psi, R), Y, OY)
-        W = W / np.linalg.norm(W, axis=0)[None, :]      # scaling is irrelevant
-        HW = H.apply(W)
-        OW = H.apply_O(W)
-        # step 4: Rayleigh-Ritz in span{Psi, W, P}
-        if P is None:
-            Z, HZ, OZ = np.hstack([Psi, W]), np.hstack([HPsi, HW]), np.hstack([OPsi, OW])
-        else:
-            s = np.linalg.norm(P, axis=0)
-            s[s == 0] = 1.0
-            P, HP, OP = P / s[None, :], HP / s[None, :], OP / s[None, :]
-            Z, HZ, OZ = (np.hstack([Psi, W, P]), np.hstack([HPsi, HW, HP]),
-                         np.hstack([OPsi, OW, OP]))
-        eps, C = rayleigh_ritz(Z, HZ, m, OZ=OZ)
-        Delta = C[:m]
-        # Psi_new = Psi Delta + W Lambda + P Gamma ; P_new = W Lambda + P Gamma (step 5)
-        Pn, HPn, OPn = Z[:, m:] @ C[m:], HZ[:, m:] @ C[m:], OZ[:, m:] @ C[m:]
-        Psi = Psi @ Delta + Pn
-        HPsi = HPsi @ Delta + HPn
-        OPsi = OPsi @ Delta + OPn
-        P, HP, OP = Pn, HPn, OPn
-    # O-normalise columns before returning
-    nrm = np.sqrt(np.einsum("gn,gn->n", Psi.conj(), OPsi).real)
-    Psi, HPsi, OPsi = Psi / nrm[None, :], HPsi / nrm[None, :], OPsi / nrm[None, :]
+        iters += 1
+        S = _orth_against(tpa_precondition(H.T, x.V, R), Y, OY)
+        s = _Images.of(H, S / np.linalg.norm(S, axis=0)[None, :])
+        parts = [x, s]
+        if direction is not None:
+            lens = np.linalg.norm(direction.V, axis=0)
+            lens[lens == 0] = 1.0
+            parts.append(direction.scaled(1.0 / lens))
+        trial = _Images.join(parts)
+        eps, C = trial.ritz(m)
+        # the new block, and the step it took outside span(x)
+        outside = _Images.join(parts[1:]).times(C[m:])
+        x = _Images(x.V @ C[:m] + outside.V, x.HV @ C[:m] + outside.HV, x.OV @ C[:m] + outside.OV)
+        direction = outside
+    nrm = np.sqrt(np.einsum("gn,gn->n", x.V.conj(), x.OV).real)
+    x = x.scaled(1.0 / nrm)
     if out is not None:
-        out["OPsi"] = OPsi
-    return eps, Psi, HPsi, res, it
+        out["OPsi"] = x.OV
+    return eps, x.V, x.HV, res, iters
 
 
 def guard_count(block: int) -> int:
@@ -253,21 +280,31 @@ def solve(H: MatFreeH, nbands: int, block: int, tol=1e-8, maxit=300, seed=0,
 
 
 def certificate(theta, res):
-    """Per-eigenvalue error bounds for Ritz pairs of a Hermitian operator.
+    """Per-eigenvalue error bounds for Ritz pairs (theta_j, x_j), ||x_j|| = 1, of a
+    Hermitian operator, given the residual norms res_j = ||H x_j - theta_j x_j||.
 
-    Krylov-Bogolyubov: some eigenvalue lies within res_j of theta_j.
-    Kato-Temple: if the interval around theta_j is isolated from the other
-    Ritz intervals by a gap delta_j, the error is at most res_j^2 / delta_j.
-    Returns min of the two (the Kato-Temple bound only where delta_j > 0).
+    * Krylov-Bogolyubov (Weinstein): some eigenvalue lies within res_j of theta_j.
+      Always valid.
+    * Kato-Temple: if the open interval (a, b) around theta_j holds exactly one
+      eigenvalue lambda, then |lambda - theta_j| <= res_j^2 / min(theta_j - a, b - theta_j).
+      The interval is bounded by the neighbouring Ritz intervals
+      [theta_i - res_i, theta_i + res_i]; that reading takes the computed values to be
+      the lowest eigenvalues with none missed between them (what the dense oracle
+      checks on the small cells).  Below the lowest value a = -inf.  Above the top
+      value nothing computed bounds the next eigenvalue from below, so the top band
+      keeps the Krylov-Bogolyubov bound.
+    Returns the smaller valid bound per band (input order).
     """
     theta = np.asarray(theta, float)
     res = np.asarray(res, float)
     n = theta.size
     out = res.copy()
-    for j in range(n):
-        others = [abs(theta[i] - theta[j]) - res[i] for i in range(n) if i != j]
-        if others:
-            delta = min(others)
-            if delta > 0:
-                out[j] = min(out[j], res[j] ** 2 / delta)
+    order = np.argsort(theta, kind="stable")
+    for pos in range(n - 1):              # the top band (pos = n - 1) keeps res
+        j = order[pos]
+        above = theta[order[pos + 1]] - res[order[pos + 1]] - theta[j]
+        below = np.inf if pos == 0 else theta[j] - (theta[order[pos - 1]] + res[order[pos - 1]])
+        delta = min(above, below)
+        if delta > 0:
+            out[j] = min(out[j], res[j] ** 2 / delta)
     return out

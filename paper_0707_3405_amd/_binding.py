@@ -138,6 +138,10 @@ def _ld(t):
     return t.stride(0)
 
 
+def _block_dtype_name(prec):
+    return "complex128" if prec == PW_PREC_FP64 else "complex64"
+
+
 class Context:
     """One pw_ctx bound to a device and a HIP stream (default: torch's current)."""
 
@@ -161,6 +165,35 @@ class Context:
         self.npw = 0
         self._ws = None
         self._keep = []
+
+    def _check_tensors(self, specs):
+        """Refuse, before any library call, tensors the library would read or write
+        out of bounds or in the wrong element type.  specs: (name, tensor, dtype,
+        ncols, nrows, numel) -- wrong dtype, fewer than `ncols` columns (bands) or
+        `nrows` rows per column, fewer than `numel` elements (contiguous), then
+        memory that is not on this context's device."""
+        import torch
+        for name, t, dtype, ncols, nrows, numel in specs:
+            if not isinstance(t, torch.Tensor):
+                raise ValueError(f"{name} must be a torch tensor")
+            if t.dtype != getattr(torch, dtype):
+                raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+            if numel is not None:
+                if t.numel() < numel or not t.is_contiguous():
+                    raise ValueError(f"{name} must be contiguous with {numel} elements, "
+                                     f"got {tuple(t.shape)}")
+                continue
+            if t.dim() not in (1, 2):
+                raise ValueError(f"{name} must be a (columns, rows) tensor, got {tuple(t.shape)}")
+            cols = 1 if t.dim() == 1 else t.shape[0]
+            rows = t.shape[-1]
+            if ncols is not None and cols < ncols:
+                raise ValueError(f"{name} has {cols} columns, the call needs {ncols}")
+            if nrows is not None and ncols != 0 and rows < nrows:
+                raise ValueError(f"{name} has {rows} rows per column, the call needs {nrows}")
+        for name, t, *_ in specs:
+            if not t.is_cuda or t.device.index != self.device:
+                raise ValueError(f"{name} must be on cuda:{self.device}, got {t.device}")
 
     def _check(self, status, ctx=True, allow=()):
         if status == PW_OK or status in allow:
@@ -188,8 +221,13 @@ class Context:
         self._check(self.lib.pw_init_basis(self.h, cell.ctypes.data, kf.ctypes.data, float(ecut),
                                            n.ctypes.data, ctypes.byref(npw)))
         self.npw = npw.value
+        self.fft_n = tuple(int(x) for x in n)
         self._ws = None
         return self.npw
+
+    def grid_n(self):
+        """FFT grid (n0, n1, n2) of the current basis ((0, 0, 0) before init_basis)."""
+        return getattr(self, "fft_n", (0, 0, 0))
 
     def get_miller(self):
         out = np.zeros((self.npw, 3), np.int32)
@@ -249,17 +287,22 @@ class Context:
     # ---- hot path --------------------------------------------------------------
     def apply_H(self, X, Y, nb=None, prec=PW_PREC_FP64):
         nb = X.shape[0] if nb is None else nb
+        dt = _block_dtype_name(prec)
+        self._check_tensors([("X", X, dt, nb, self.npw, None), ("Y", Y, dt, nb, self.npw, None)])
         self._check(self.lib.pw_apply_H(self.h, _ptr(X), _ld(X), _ptr(Y), _ld(Y), nb, prec))
         return Y
 
     def apply_O(self, X, Y, nb=None, prec=PW_PREC_FP64):
         nb = X.shape[0] if nb is None else nb
+        dt = _block_dtype_name(prec)
+        self._check_tensors([("X", X, dt, nb, self.npw, None), ("Y", Y, dt, nb, self.npw, None)])
         self._check(self.lib.pw_apply_O(self.h, _ptr(X), _ld(X), _ptr(Y), _ld(Y), nb, prec))
         return Y
 
     def lobpcg_solve(self, nbands, block, tol, max_iter, X, use_guess=False, prec=PW_PREC_FP64,
                      allow_not_converged=False):
-        eig = np.zeros(nbands, np.float64)
+        self._check_tensors([("X", X, "complex128", max(int(nbands), 0), self.npw, None)])
+        eig = np.zeros(max(int(nbands), 0), np.float64)
         allow = (PW_ERR_NOT_CONVERGED,) if allow_not_converged else ()
         st = self._check(self.lib.pw_lobpcg_solve(self.h, nbands, block, float(tol), max_iter, prec,
                                                   _ptr(X), _ld(X), int(bool(use_guess)),
@@ -269,7 +312,12 @@ class Context:
     def density(self, X, occ, rho, nb=None):
         """rho (device float64 [N, N, N]) = sum_n occ[n] |psi_n(r)|^2 of the columns of X."""
         nb = X.shape[0] if nb is None else nb
-        occ = np.ascontiguousarray(np.asarray(occ, np.float64))
+        occ = np.ascontiguousarray(np.asarray(occ, np.float64)).reshape(-1)
+        if occ.size < nb:
+            raise ValueError(f"occ has {occ.size} entries, the call needs {nb}")
+        n = self.grid_n()
+        self._check_tensors([("X", X, "complex128", nb, self.npw, None),
+                             ("rho", rho, "float64", None, None, n[0] * n[1] * n[2])])
         self._check(self.lib.pw_density(self.h, _ptr(X), _ld(X), nb, occ.ctypes.data, _ptr(rho)))
         return rho
 

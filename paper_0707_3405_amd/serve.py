@@ -44,33 +44,39 @@ def footprint(w, prec):
 
 
 def solve_one(w, prec, device=0, torch=None):
-    """One request on a fresh context and stream; returns a result dict."""
+    """One request on a fresh context and stream; returns a result dict.  The
+    context is closed whatever happens (a failed solve raises after that)."""
     if torch is None:
         import torch
     from .solver import PlaneWaveProblem
     t0 = time.perf_counter()
     stream = torch.cuda.Stream(device)
     prob = PlaneWaveProblem.from_workload(w, device=device, stream=stream, prec=prec)
-    t1 = time.perf_counter()
-    eig, X, status = prob.solve(w.tol, max_iter=300, allow_not_converged=True)
-    res = prob.ctx.get_residuals(w.nbands)
-    st = prob.ctx.get_stats()
-    stream.synchronize()
-    t2 = time.perf_counter()
-    out = {"name": w.name, "npw": prob.npw, "nbands": w.nbands, "prec": int(prec),
-           "eig": eig, "max_residual": float(res.max()), "converged": status != PW_ERR_NOT_CONVERGED,
-           "iterations": st["iterations"], "setup_s": t1 - t0, "solve_s": t2 - t1}
-    prob.ctx.close()
-    del prob, X
+    try:
+        t1 = time.perf_counter()
+        eig, X, status = prob.solve(w.tol, max_iter=300, allow_not_converged=True)
+        res = prob.ctx.get_residuals(w.nbands)
+        st = prob.ctx.get_stats()
+        stream.synchronize()
+        t2 = time.perf_counter()
+        out = {"name": w.name, "npw": prob.npw, "nbands": w.nbands, "prec": int(prec),
+               "eig": eig, "max_residual": float(res.max()),
+               "converged": status != PW_ERR_NOT_CONVERGED,
+               "iterations": st["iterations"], "setup_s": t1 - t0, "solve_s": t2 - t1}
+        del X
+    finally:
+        prob.ctx.close()
+    del prob
     return out
 
 
 class Server:
     """Admission control and continuous batching over independent solves."""
 
-    def __init__(self, device=0, budget_bytes=None, max_active=8, log=None):
+    def __init__(self, device=0, budget_bytes=None, max_active=8, log=None, solve=None):
         import torch
         self.torch = torch
+        self.solve = solve_one if solve is None else solve   # (w, prec, device, torch) -> dict
         self.device = device
         self.log = log   # optional callable taking one line per finished request
         if budget_bytes is None:
@@ -95,17 +101,27 @@ class Server:
 
         def worker(i):
             _, w, prec = requests[i]
-            r = solve_one(w, prec, self.device, self.torch)
-            with lock:
-                results[i].update(r)
-                results[i]["done_s"] = time.perf_counter() - t0
-                if self.log:
-                    self.log(f"request {i}: {r['nbands']} bands, solve {r['solve_s']:.2f} s, latency "
-                             f"{results[i]['done_s'] - results[i]['arrival_s']:.2f} s")
-                state["used"] -= sizes[i]
-                state["active"] -= 1
-                state["done"] += 1
-                lock.notify_all()
+            r = {"name": w.name, "nbands": w.nbands, "prec": int(prec), "eig": None,
+                 "max_residual": float("inf"), "converged": False, "solve_s": float("nan")}
+            err = "interrupted"
+            try:
+                r = self.solve(w, prec, self.device, self.torch)
+                err = None
+            except Exception as exc:          # a failed request releases its slot too
+                err = f"{type(exc).__name__}: {exc}"
+            finally:
+                with lock:
+                    results[i].update(r)
+                    results[i]["error"] = err
+                    results[i]["done_s"] = time.perf_counter() - t0
+                    state["used"] -= sizes[i]
+                    state["active"] -= 1
+                    state["done"] += 1
+                    lock.notify_all()
+            if self.log:
+                what = f"solve {r['solve_s']:.2f} s" if err is None else f"failed ({err})"
+                self.log(f"request {i}: {r['nbands']} bands, {what}, latency "
+                         f"{results[i]['done_s'] - results[i]['arrival_s']:.2f} s")
 
         threads = []
         nxt = 0
@@ -139,6 +155,7 @@ class Server:
                    "latency_p50_s": float(np.percentile(lat, 50)),
                    "latency_p99_s": float(np.percentile(lat, 99)),
                    "max_wait_s": float(max(r["admitted_s"] - r["arrival_s"] for r in results)),
+                   "failed": sum(r["error"] is not None for r in results),
                    "all_converged": all(r["converged"] for r in results),
                    "max_residual": max(r["max_residual"] for r in results)}
         return results, summary

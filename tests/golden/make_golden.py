@@ -6,9 +6,18 @@ Calls only `oracle/` (and the seeded input generators in `workloads/`):
   mid_nl      dense H diagonalised by the oracle's C Jacobi.
   fcc32_l12   oracle.matfree.solve (block LOBPCG + final Rayleigh-Ritz), tol 1e-9.
   fcc108_l20  oracle.matfree.solve, tol 1e-8 (34181 plane waves: no dense H).
-  kpts_l16_k1, kpts_l16_k9
-              oracle.matfree.solve, tol 1e-8, at k-points 1 and 9 of the
-              ten-k-point batch cell (workloads.make_kpoint_workloads).
+  kpts_l16_k0, kpts_l16_k1, kpts_l16_k5, kpts_l16_k9
+              oracle.matfree.solve, tol 1e-8, at k-points 0, 1, 5 and 9 of the
+              ten-k-point batch cell (workloads.make_kpoint_workloads; k5 has
+              the most plane waves, 11416, k9 the fewest, 11296).
+  max_l24_lo128
+              the lowest 128 bands of the largest served cell (max_l24: 82561
+              plane waves, 748 projectors, 120^3 grid): oracle.matfree.solve with
+              128 bands in blocks of 64, tol 1e-8.
+  request2, request6
+              requests 2 (5680 plane waves, 224 bands) and 6 (8049 plane waves,
+              192 bands) of the served stream (workloads.make_request, base seed
+              1000): oracle.matfree.solve, tol 1e-8.
   mid_nl_ovl  generalized form H c = eps O c on the mid_nl cell with the overlap
               coefficients of workloads.overlap_coefficients: dense H and O
               (oracle.pw), Cholesky reduction, the oracle's C Jacobi.
@@ -35,7 +44,8 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
 from oracle import pw, matfree                      # noqa: E402
 from oracle.jacobi import eigh_jacobi              # noqa: E402
-from workloads import make_workload, make_kpoint_workloads, overlap_coefficients   # noqa: E402
+from workloads import (make_workload, make_kpoint_workloads, make_request,   # noqa: E402
+                       overlap_coefficients)
 
 
 def dense_case(name):
@@ -71,20 +81,21 @@ def dense_pencil_case(base):
     print("wrote", path)
 
 
-def matfree_case(name, tol, w=None, overlap=False):
+def matfree_case(name, tol, w=None, overlap=False, nbands=None):
     w = make_workload(name) if w is None else w
+    nbands = w.nbands if nbands is None else nbands
     mil = pw.sphere(w.cell, w.kfrac, w.ecut)
     q = overlap_coefficients(w) if overlap else None
     H = matfree.MatFreeH(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D, q=q)
     if overlap:
         name = name + "_ovl"
     t0 = time.time()
-    r = matfree.solve(H, w.nbands, w.block, tol=tol, seed=w.seed,
+    r = matfree.solve(H, nbands, w.block, tol=tol, seed=w.seed,
                       log=lambda s: print(name, s, flush=True))
     cert = matfree.certificate(r["eig"], r["res"])
     path = os.path.join(HERE, f"{name}_eig.txt")
     with open(path, "w") as f:
-        f.write(f"# {name}: npw={len(mil)}, M={w.nbands}, m={w.block}, oracle block "
+        f.write(f"# {name}: npw={len(mil)}, M={nbands}, m={w.block}, oracle block "
                 f"LOBPCG tol={tol:g} + final Rayleigh-Ritz, iterations per block "
                 f"{r['iters']}, {time.time() - t0:.0f} s\n")
         f.write("# written by tests/golden/make_golden.py (oracle only)\n")
@@ -99,8 +110,13 @@ CASES = {
     "mid_nl": lambda: dense_case("mid_nl"),
     "fcc32_l12": lambda: matfree_case("fcc32_l12", 1e-9),
     "fcc108_l20": lambda: matfree_case("fcc108_l20", 1e-8),
+    "kpts_l16_k0": lambda: matfree_case("kpts_l16_k0", 1e-8, make_kpoint_workloads()[0]),
     "kpts_l16_k1": lambda: matfree_case("kpts_l16_k1", 1e-8, make_kpoint_workloads()[1]),
+    "kpts_l16_k5": lambda: matfree_case("kpts_l16_k5", 1e-8, make_kpoint_workloads()[5]),
     "kpts_l16_k9": lambda: matfree_case("kpts_l16_k9", 1e-8, make_kpoint_workloads()[9]),
+    "max_l24_lo128": lambda: matfree_case("max_l24_lo128", 1e-8, make_workload("max_l24"), nbands=128),
+    "request2": lambda: matfree_case("request2", 1e-8, make_request(2)[0]),
+    "request6": lambda: matfree_case("request6", 1e-8, make_request(6)[0]),
     "mid_nl_ovl": lambda: dense_pencil_case("mid_nl"),
     "fcc32_l12_ovl": lambda: matfree_case("fcc32_l12", 1e-9, overlap=True),
 }

@@ -110,3 +110,61 @@ def test_band_count_limit_and_density_room():
         c.workspace_size(npw - 47, 16)
     assert e.value.status == PW_ERR_ARG
     assert c.workspace_size(1, 1) >= w.n ** 3 * 8
+
+
+def test_binding_refuses_bad_tensors_before_the_library():
+    """Blocks of the wrong dtype, too few bands or rows, host memory, a short occupation
+    list or a wrong-sized density are refused in Python, before any pointer reaches
+    the library (which would read or write past the allocation)."""
+    import torch
+    from paper_0707_3405_amd import Context, PW_PREC_FP64, PW_PREC_MIXED
+    w = make_workload("gamma_l10")
+    ctx = Context(-1)
+    npw = ctx.init_basis(w.cell, w.kfrac, w.ecut, (w.n,) * 3)
+    ok = torch.zeros((4, npw), dtype=torch.complex128)
+    cases = [
+        (lambda: ctx.apply_H(ok.to(torch.complex64), ok), "complex128"),          # dtype vs prec
+        (lambda: ctx.apply_H(ok, ok, prec=PW_PREC_MIXED), "complex64"),
+        (lambda: ctx.apply_H(ok, ok, nb=5), "columns"),                            # nb > bands
+        (lambda: ctx.apply_H(ok[:, : npw - 1], ok), "rows"),                       # ld < npw
+        (lambda: ctx.apply_O(ok, ok[:2]), "columns"),
+        (lambda: ctx.apply_H(ok, ok), "cuda"),                                     # host memory
+        (lambda: ctx.lobpcg_solve(8, 4, 1e-8, 10, ok), "columns"),
+        (lambda: ctx.lobpcg_solve(4, 4, 1e-8, 10, ok.to(torch.complex64)), "complex128"),
+        (lambda: ctx.density(ok, [1.0, 1.0], torch.zeros(w.n ** 3, dtype=torch.float64)), "occ"),
+        (lambda: ctx.density(ok, [1.0] * 4, torch.zeros(w.n ** 3 - 1, dtype=torch.float64)), "elements"),
+        (lambda: ctx.density(ok, [1.0] * 4, torch.zeros(w.n ** 3, dtype=torch.float32)), "float64"),
+    ]
+    for fn, word in cases:
+        with pytest.raises(ValueError, match=word):
+            fn()
+    ctx.close()
+    assert PW_PREC_FP64 == 0
+
+
+def test_served_worker_failure_releases_its_slot():
+    """A request whose solve raises is recorded as failed and frees its footprint and
+    slot, so the stream still ends and later requests run (stubbed solve, no GPU)."""
+    from paper_0707_3405_amd.serve import Server, footprint
+    from paper_0707_3405_amd import PW_PREC_FP64
+    from workloads import make_request
+    reqs = []
+    for i in range(4):
+        rw, _ = make_request(i, base_seed=2000, L_range=(8.0, 9.0), ecut_range=(5.0, 6.0))
+        reqs.append((0.01 * i, rw, PW_PREC_FP64))
+    size = max(footprint(rw, p)[1] for _, rw, p in reqs)
+    calls = []
+
+    def stub(rw, prec, device, torch):
+        calls.append(rw.name)
+        if rw.name == reqs[1][1].name:
+            raise RuntimeError("PW_ERR_NUMERIC: planted")
+        return {"name": rw.name, "nbands": rw.nbands, "prec": int(prec), "eig": np.zeros(rw.nbands),
+                "max_residual": 0.0, "converged": True, "solve_s": 0.0}
+
+    srv = Server(budget_bytes=size, max_active=1, solve=stub)     # one at a time
+    results, summary = srv.run(reqs)
+    assert sorted(calls) == sorted(r[1].name for r in reqs)
+    assert summary["failed"] == 1 and not summary["all_converged"]
+    assert results[1]["error"].startswith("RuntimeError")
+    assert all(results[i]["error"] is None for i in (0, 2, 3))

@@ -448,3 +448,81 @@ def test_oracle_generalized_with_zero_overlap_is_standard():
     b = matfree.solve(matfree.MatFreeH(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D,
                                        q=np.zeros(w.nproj)), w.nbands, w.block, tol=1e-9, seed=1)
     assert np.abs(a["eig"] - b["eig"]).max() <= 1e-12
+
+
+# ---- preconditioner and residual certificates ----------------------------------------
+
+def _tpa_factor(T, ekin):
+    """K at x = T / ekin, read off oracle.matfree.tpa_precondition with R = 1 and a
+    one-plane-wave block whose kinetic energy is ekin."""
+    T = np.asarray(T, float)
+    X = np.zeros((T.size + 1, 1), complex)
+    X[-1, 0] = 1.0
+    Tall = np.concatenate([T, [ekin]])
+    return matfree.tpa_precondition(Tall, X, np.ones((T.size + 1, 1), complex))[:-1, 0].real
+
+
+def test_tpa_preconditioner_values():
+    """The Teter-Payne-Allan factor (Phys. Rev. B 40, 12255), fixed by its published
+    polynomial independently of any implementation: K(0) = 1, K(1) = 65/81,
+    K(2) = 175/431, K(x) -> 1/(2x) for large x, and K = 1 - (16/27) x^4 + O(x^5)
+    near 0 (the first three derivatives vanish)."""
+    e = 0.7
+    x = np.array([0.0, 1.0, 2.0, 1e4, 1e-2])
+    K = _tpa_factor(x * e, e)
+    assert K[0] == 1.0
+    assert abs(K[1] - 65.0 / 81.0) <= 1e-15
+    assert abs(K[2] - 175.0 / 431.0) <= 1e-15
+    assert abs(K[3] * 2 * x[3] - 1.0) <= 1e-3
+    # 1 - K = 16 x^4 / (27 + 18 x + ...): within 2 (18/27) x of 16 x^4 / 27 at x = 0.01
+    assert abs((1.0 - K[4]) / x[4] ** 4 * 27.0 / 16.0 - 1.0) <= 2 * (18.0 / 27.0) * x[4]
+    # monotone and in (0, 1]
+    xs = np.linspace(0, 50, 2001)
+    Ks = _tpa_factor(xs * e, e)
+    assert np.all(np.diff(Ks) <= 0) and np.all(Ks > 0) and np.all(Ks <= 1)
+
+
+def test_tpa_preconditioner_band_energy_and_floor():
+    """x = T_g / E_kin,n with E_kin,n = <x_n|T|x_n> / <x_n|x_n> per band, floored at 1e-3 Ha:
+    a band spread evenly over T = 1 and T = 3 has E_kin = 2, so the T = 2 row gets
+    K(1) = 65/81; a band on the T = 0 plane wave alone gets the floor, so a row with
+    T = 1e-3 gets K(1) too; R is scaled row by row and column by column."""
+    T = np.array([1.0, 3.0, 2.0, 0.0, 1e-3])
+    X = np.zeros((5, 2), complex)
+    X[0, 0] = X[1, 0] = 1.0 / np.sqrt(2.0)
+    X[3, 1] = 1j
+    R = np.arange(1, 11).reshape(5, 2) * (1 + 2j)
+    W = matfree.tpa_precondition(T, X, R)
+    assert abs(W[2, 0] / R[2, 0] - 65.0 / 81.0) <= 1e-15
+    assert abs(W[4, 1] / R[4, 1] - 65.0 / 81.0) <= 1e-15
+    assert abs(W[3, 1] / R[3, 1] - 1.0) <= 1e-15
+
+
+def test_certificate_bounds_hold_for_the_top_band():
+    """H = diag(0, 1, 1 + eps): the second Ritz pair from x = (0, cos t, sin t) has
+    theta - 1 = eps sin^2 t and residual eps sin t cos t.  The only computed value
+    below it sits at 0, so a gap taken from the computed values alone would claim
+    res^2 / 1, far below the true error; no computed value bounds lambda_3 from
+    below, so the bound must not fall under the true error."""
+    eps, t = 1e-3, 0.3
+    H = np.diag([0.0, 1.0, 1.0 + eps])
+    x1 = np.array([1.0, 0.0, 0.0])
+    x2 = np.array([0.0, np.cos(t), np.sin(t)])
+    theta = np.array([x1 @ H @ x1, x2 @ H @ x2])
+    res = np.array([np.linalg.norm(H @ x1 - theta[0] * x1), np.linalg.norm(H @ x2 - theta[1] * x2)])
+    cert = matfree.certificate(theta, res)
+    true_err = theta[1] - 1.0
+    assert cert[1] >= true_err
+    assert abs(cert[1] - res[1]) <= 1e-18          # the Krylov-Bogolyubov bound
+    # below the top, Kato-Temple on a well separated spectrum is valid and sharp
+    rng = np.random.default_rng(5)
+    lam = np.array([0.0, 1.0, 2.0, 3.0])
+    Q = np.linalg.qr(rng.standard_normal((4, 4)))[0]
+    A = Q @ np.diag(lam) @ Q.T
+    V = Q[:, :3] + 1e-4 * rng.standard_normal((4, 3))
+    V = V / np.linalg.norm(V, axis=0)
+    th = np.einsum("gi,gh,hi->i", V, A, V)
+    r = np.linalg.norm(A @ V - V * th, axis=0)
+    c = matfree.certificate(th, r)
+    assert np.all(np.abs(th - lam[:3]) <= c)
+    assert np.all(c[:2] < r[:2]) and c[2] == r[2]
