@@ -266,13 +266,13 @@ pw_status pw_get_stats(pw_ctx ctx, pw_stats *stats);
  * the context stream; no workspace needed unless stated. */
 
 /* Gram block C = A^H B (sec. 4.1: Gram blocks by zgemm over the plane-wave
- * coefficients; Algorithm 1 step 4).  A [K x p], B [K x q], C [p x q].
+ * coefficients; the Rayleigh-Ritz of sec. 3.2, Algorithm 1).  A [K x p], B [K x q], C [p x q].
  * Deterministic split-K reduction in the workspace: at least p q complex128
  * (PW_ERR_NOMEM otherwise); a workspace smaller than the split needs only
  * lowers the number of K chunks. */
 pw_status pw_gram(pw_ctx ctx, const void *A, int64_t lda, const void *B, int64_t ldb,
                   int64_t K, int32_t p, int32_t q, void *C, int64_t ldc);
-/* Block update Y = alpha A C + beta Y (Algorithm 1 steps 4-5: Psi Delta +
+/* Block update Y = alpha A C + beta Y (the Ritz-vector update of sec. 3.2, Algorithm 1: Psi Delta +
  * W Lambda + P Gamma).  A [K x p], C [p x q], Y [K x q]; alpha, beta real.
  * Y must not overlap A unless q <= 64 and Y == A (in-place right multiply). */
 pw_status pw_block_update(pw_ctx ctx, const void *A, int64_t lda, const void *C, int64_t ldc,
@@ -296,7 +296,7 @@ pw_status pw_block_update_mixed(pw_ctx ctx, const void *A, int64_t lda, const vo
  * returns PW_ERR_NUMERIC.  Synchronises the stream. */
 pw_status pw_chol_inv(pw_ctx ctx, const void *G, int64_t ldg, int32_t n, void *Rinv, int64_t ldr);
 /* Lowest k eigenpairs of a Hermitian n x n matrix A (lda >= n) -- the small
- * dense Rayleigh-Ritz eigenproblem of Algorithm 1 step 4 and of the final
+ * dense Rayleigh-Ritz eigenproblem of sec. 3.2 (Algorithm 1) and of the final
  * Rayleigh-Ritz (sec. 3.2, sec. 4.2).  Householder tridiagonalisation,
  * bisection, inverse iteration, re-orthogonalisation, back-transform, FP64;
  * the reduction runs in one workgroup for n <= 192 and over many above.
@@ -304,8 +304,8 @@ pw_status pw_chol_inv(pw_ctx ctx, const void *G, int64_t ldg, int32_t n, void *R
  * A is overwritten.  1 <= k <= n <= 1024.  Needs the workspace. */
 pw_status pw_small_eigh(pw_ctx ctx, void *A, int64_t lda, int32_t n, int32_t k,
                         void *w, void *V, int64_t ldv);
-/* Residuals and preconditioned residuals (Eq. (1) with O = I; Algorithm 1
- * steps 1-3): theta_j = Re(x_j^H Hx_j) (columns of X assumed unit norm),
+/* Residuals and preconditioned residuals (Eq. (1) with O = I; the residual
+ * and preconditioning of sec. 3.1-3.2): theta_j = Re(x_j^H Hx_j) (columns of X assumed unit norm),
  * R = HX - X diag(theta), res_j = ||R_j||_2, and W = K(R) with the
  * Teter-Payne-Allan factor K(x) = (27+18x+12x^2+8x^3)/(27+18x+12x^2+8x^3+16x^4),
  * x = T_g / max(E_kin,j, 1e-3), E_kin,j = sum_g T_g |x_gj|^2.

@@ -17,7 +17,7 @@ TEST INFRASTRUCTURE ONLY (oracle).  Plain numpy/scipy, FP64/complex128.
   previous search direction, with the block kept O-orthogonal to the bands of
   earlier blocks.
 * `solve` -- the multiband-by-multiband sweep over M/m blocks followed by the
-  final Rayleigh-Ritz over all M bands (end of sec. 3.2; sec. 2.1 step 4).
+  final Rayleigh-Ritz over all M bands (end of sec. 3.2; the subspace diagonalisation of sec. 2.1).
 * `certificate` -- residual-based eigenvalue error bounds for Hermitian H.
 
 The preconditioner K is called "PW optimized" in sec. 3.1 without a formula;

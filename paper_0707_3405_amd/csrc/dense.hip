@@ -3,7 +3,7 @@
 //  * k_chol_inv: Cholesky factor of a Gram matrix G = R^H R and R^-1, used to
 //    orthonormalise a block (W <- W R^-1; BLOPEX-style LOBPCG, sec. 3.2).
 //  * k_heev: lowest k eigenpairs of a Hermitian matrix -- the Rayleigh-Ritz
-//    eigenproblem of Algorithm 1 step 4 (size 3m) and of the final
+//    eigenproblem of the LOBPCG iteration (sec. 3.2, Algorithm 1; size 3m) and of the final
 //    Rayleigh-Ritz over all bands (sec. 3.2, sec. 4.2).  Householder
 //    reduction to real tridiagonal form, bisection with Sturm counts,
 //    inverse iteration, classical Gram-Schmidt applied twice, back-transform.

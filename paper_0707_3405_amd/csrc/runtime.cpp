@@ -356,7 +356,7 @@ void proj_add(pw_ctx_s *c, const Plan<S> &p, const double *s, const S *X, int64_
     pw::launch_gemm_nn(B, c->ldp, p.Pj, np, c->npw, np, nc, 1.0, 1.0, Y, ldy, c->stream);
 }
 
-// Rayleigh-Ritz Gram A = Z^H (HZ) [nz x nz] (Algorithm 1 step 4); in the
+// Rayleigh-Ritz Gram A = Z^H (HZ) [nz x nz] (the Rayleigh-Ritz of sec. 3.2, Algorithm 1); in the
 // complex64 stage of PW_PREC_MIXED_BF16_GRAM on split-bf16 MFMA
 template <class S>
 void rr_gram(pw_ctx_s *c, const Plan<S> &p, const S *Z, const S *HZ, int64_t ld, int nz) {

@@ -1,9 +1,9 @@
 """Per-step parity of the HIP building blocks against their plain definitions.
 
-Gram blocks and block updates (Algorithm 1 steps 4-5, sec. 4.1 zgemm) against
+Gram blocks and block updates (the Rayleigh-Ritz and block update of sec. 3.2, Algorithm 1; sec. 4.1 zgemm) against
 numpy products; the small Hermitian eigensolver (Rayleigh-Ritz, sec. 3.2 /
 4.2) against LAPACK through numpy; residuals and the preconditioner (Eq. (1),
-Algorithm 1 steps 1-3) against their formulas.
+Rayleigh quotients, residuals and preconditioning of sec. 3.2) against their formulas.
 """
 import numpy as np
 import pytest
