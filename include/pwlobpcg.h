@@ -304,6 +304,21 @@ pw_status pw_chol_inv(pw_ctx ctx, const void *G, int64_t ldg, int32_t n, void *R
  * A is overwritten.  1 <= k <= n <= 1024.  Needs the workspace. */
 pw_status pw_small_eigh(pw_ctx ctx, void *A, int64_t lda, int32_t n, int32_t k,
                         void *w, void *V, int64_t ldv);
+/* pw_small_eigh without the workspace, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc): the same kernels, with their scratch in a fixed
+ * 4 MiB array the library holds on every GPU it runs on until the process
+ * ends.  Needs only a context on a device (no pw_init_basis, no workspace);
+ * allocates nothing, and clears its status word with a kernel (no memset).
+ * Limit: 256 + heev_scratch(n, k) <= 4 MiB, i.e. k = n up to n ~ 700 and
+ * k = 64 up to n = 1024 (heev_scratch(n, k) = 8*256 + 16n + 16n + 8nk +
+ * 16n(3 + ceil(n/64)) bytes); larger (n, k) return PW_ERR_ARG naming the limit.
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents: calls that overlap on one GPU (several streams or host threads)
+ * race and must be serialised by the caller.  Synchronises the context
+ * stream (to report PW_ERR_NUMERIC); A is overwritten as in pw_small_eigh. */
+pw_status pw_small_eigh_noalloc(pw_ctx ctx, void *A, int64_t lda, int32_t n, int32_t k,
+                                void *w, void *V, int64_t ldv);
 /* Residuals and preconditioned residuals (Eq. (1) with O = I; the residual
  * and preconditioning of sec. 3.1-3.2): theta_j = Re(x_j^H Hx_j) (columns of X assumed unit norm),
  * R = HX - X diag(theta), res_j = ||R_j||_2, and W = K(R) with the

@@ -28,7 +28,7 @@ EXPORTS = ("pw_create", "pw_destroy", "pw_last_error", "pw_init_basis", "pw_fft_
            "pw_get_residuals", "pw_get_stats", "pw_gram", "pw_block_update", "pw_small_eigh",
            "pw_residuals", "pw_gram_mixed", "pw_block_update_mixed", "pw_lobpcg_solve_batch",
            "pw_density", "pw_set_overlap", "pw_apply_O", "pw_chol_inv", "pw_autotune",
-           "pw_set_tuning")
+           "pw_set_tuning", "pw_small_eigh_noalloc")
 
 
 class PWError(RuntimeError):
@@ -105,6 +105,7 @@ def load_library():
         "pw_density": (ctypes.c_int, [P, P, I64, I32, P, P]),
         "pw_block_update_mixed": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, D, D, P, I64]),
         "pw_small_eigh": (ctypes.c_int, [P, P, I64, I32, I32, P, P, I64]),
+        "pw_small_eigh_noalloc": (ctypes.c_int, [P, P, I64, I32, I32, P, P, I64]),
         "pw_residuals": (ctypes.c_int, [P, P, I64, P, I64, I32, P, P, P, I64]),
     }
     for name, (res, args) in sig.items():
@@ -354,6 +355,11 @@ class Context:
 
     def small_eigh(self, A, n, k, w, V):
         self._check(self.lib.pw_small_eigh(self.h, _ptr(A), _ld(A), n, k, _ptr(w), _ptr(V), _ld(V)))
+
+    def small_eigh_noalloc(self, A, n, k, w, V):
+        """pw_small_eigh on the library's static scratch (no workspace, allocates nothing)."""
+        self._check(self.lib.pw_small_eigh_noalloc(self.h, _ptr(A), _ld(A), n, k, _ptr(w), _ptr(V),
+                                                   _ld(V)))
 
     def autotune(self, nb):
         """Time the FFT tile and split-K candidates on this context; keep and return the choice."""

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "obj")
 LIB = os.path.join(HERE, "libpwlobpcg.so")
 ARCH = "gfx950"
-SOURCES = ["fft_apply.hip", "gemm.hip", "dense.hip", "vec.hip", "runtime.cpp"]
+SOURCES = ["fft_apply.hip", "gemm.hip", "dense.hip", "vec.hip", "noalloc.hip", "runtime.cpp"]
 FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC",
          "-I" + os.path.join(ROOT, "include"), "-I" + CSRC,
          # packed FP32 instructions are kept out of every kernel

@@ -122,6 +122,14 @@ void launch_gemm_nn_bf16(const cf *A, int64_t lda, const cd *C, int64_t ldc, int
 size_t heev_scratch_bytes(int n, int k);
 void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t ldv,
                      void *scratch, int *status, hipStream_t st);
+// Library-owned device scratch of the entry point that allocates nothing
+// (noalloc.hip): a fixed array per GPU.  static_scratch_setup resolves its
+// device address with `device` current (once per device, from pw_create);
+// static_scratch returns that address (null until then).
+size_t static_scratch_bytes();
+hipError_t static_scratch_setup(int device);
+void *static_scratch(int device);
+void launch_clear_ints(int *p, int count, hipStream_t st);   // fill kernel, no memset node
 // CholQR factor: G (n x n, Hermitian PD) -> Rinv (upper, G = R^H R, Rinv = R^-1)
 // with a diagonal shift for robustness; status[0] |= 1 on breakdown.
 void launch_chol_inv_f64(const cd *G, int64_t ldg, int n, cd *Rinv, int64_t ldr, int *status,

@@ -141,6 +141,7 @@ struct pw_ctx_s {
 
     int *d_status = nullptr;
     int nst_host = 0, ncx_host = 0;
+    hipError_t static_scratch_status = hipSuccess;   // pw::static_scratch_setup at pw_create
 
     // pinned host staging of the per-iteration round trip (residual norms and
     // status down, active columns up), allocated with the context: copies to
@@ -1129,6 +1130,9 @@ pw_status pw_create(int device, void *hip_stream, pw_ctx *out) {
     }
     pw_ctx c = new (std::nothrow) pw_ctx_s;
     if (!c) return PW_ERR_NOMEM;
+    // device address of the library's static scratch on this device (once per
+    // device; pw_small_eigh_noalloc reports a failure here when it is called)
+    if (device >= 0) c->static_scratch_status = pw::static_scratch_setup(device);
     if (device >= 0 && hipHostMalloc(&c->h_pinned, pw_ctx_s::kPinnedBytes, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return PW_ERR_NOMEM;
@@ -1513,6 +1517,37 @@ pw_status pw_small_eigh(pw_ctx c, void *A, int64_t lda, int32_t n, int32_t k, vo
                             static_cast<cd *>(V), ldv, c->ws, c->d_status, c->stream);
         const int s = read_status(c);
         PW_REQUIRE(!(s & 4), PW_ERR_NUMERIC, "non-finite eigenvalue");
+        return PW_OK;
+    });
+}
+
+pw_status pw_small_eigh_noalloc(pw_ctx c, void *A, int64_t lda, int32_t n, int32_t k, void *w,
+                                void *V, int64_t ldv) {
+    return guard(c, [&] {
+        require_device(c);
+        PW_REQUIRE(A && w && V, PW_ERR_ARG, "null argument");
+        PW_REQUIRE(n >= 1 && n <= 1024 && k >= 1 && k <= n && lda >= n && ldv >= n, PW_ERR_ARG,
+                   "need 1 <= k <= n <= 1024");
+        const size_t need = 256 + pw::heev_scratch_bytes(n, k);
+        if (need > pw::static_scratch_bytes())
+            throw Error{PW_ERR_ARG, "n = " + std::to_string(n) + ", k = " + std::to_string(k) + " needs " +
+                                        std::to_string(need) + " bytes of scratch, more than the " +
+                                        std::to_string(pw::static_scratch_bytes()) +
+                                        " of the library's static array; use pw_small_eigh"};
+        if (c->static_scratch_status != hipSuccess)
+            throw Error{PW_ERR_DEVICE, std::string("hipGetSymbolAddress of the static scratch failed: ") +
+                                           hipGetErrorString(c->static_scratch_status)};
+        char *base = static_cast<char *>(pw::static_scratch(c->device));
+        PW_REQUIRE(base, PW_ERR_STATE, "static scratch not resolved on this device");
+        // [0, 256): status word; [256, need): the eigensolver's scratch
+        int *status = reinterpret_cast<int *>(base);
+        pw::launch_clear_ints(status, 1, c->stream);
+        pw::launch_heev_f64(static_cast<cd *>(A), lda, n, k, static_cast<double *>(w),
+                            static_cast<cd *>(V), ldv, base + 256, status, c->stream);
+        int *h = reinterpret_cast<int *>(c->pinned(sizeof(int)));
+        PW_HIP(hipMemcpyAsync(h, status, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+        PW_HIP(hipStreamSynchronize(c->stream));
+        PW_REQUIRE(!(*h & 4), PW_ERR_NUMERIC, "non-finite eigenvalue");
         return PW_OK;
     });
 }
