@@ -37,6 +37,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # set an entry to None when its kernels change.
 TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 2.96e8, "dense": 5.15e6}
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
+FP32_PEAK_TFLOPS = 157.3       # MI355X dense FP32 (matrix)
 WORKLOAD = "fcc108_l20"
 
 
@@ -59,11 +60,35 @@ def event_time_ms(torch, stream, fn, reps):
     return start.elapsed_time(end) / reps
 
 
-def cpu_baseline(w, gpu_iterations, cores, sample_iters=6):
-    """The oracle's block LOBPCG on the same cell, first block only, a few
-    iterations; eigenpairs/s extrapolated with the GPU solve's iteration count."""
+def cpu_model_name():
+    """The host CPU's model string (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as f:
+            return next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
+    except OSError:
+        return ""
+
+
+def cpu_baseline(w, gpu_iterations, cores, sample_iters=6, full_block=True):
+    """The oracle on the host cores, three ways:
+    * the paper-scale cell: block 0 of the oracle's block LOBPCG, `sample_iters`
+      iterations timed and extrapolated to the GPU solve's iteration count (the
+      headline value), and -- with full_block -- block 0 iterated to the GPU's
+      tolerance, extrapolated over the ten blocks;
+    * the small Gamma-point cell (515 plane waves, 16 bands): dense H built and
+      diagonalised by the oracle's plain C Jacobi on one core, with
+      numpy.linalg.eigh on all cores as context."""
     from oracle import matfree, pw
-    from workloads import start_block
+    from oracle.jacobi import eigh_jacobi
+    from workloads import start_block, make_workload
     mil = pw.sphere(w.cell, w.kfrac, w.ecut)
     mf = matfree.MatFreeH(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D, workers=cores)
     X0 = start_block(0, mil.shape[0], w.block)
@@ -74,18 +99,63 @@ def cpu_baseline(w, gpu_iterations, cores, sample_iters=6):
     t2 = time.perf_counter()
     t_iter = ((t2 - t1) - (t1 - t0)) / sample_iters
     est = t_iter * gpu_iterations
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((l.split(":", 1)[1].strip() for l in f if l.startswith("model name")), "")
-    except OSError:
-        pass
-    return dict(value=w.nbands / est, unit="eigenpairs/s", cores=cores, kind="oracle",
-                cpu_model=model, affinity_cpus=len(os.sched_getaffinity(0)),
-                sample=(f"oracle block LOBPCG ({WORKLOAD}, block 0, {w.block} bands), "
-                        f"{sample_iters} iterations timed ({t_iter:.2f} s/iteration), "
-                        f"extrapolated to the GPU solve's {gpu_iterations} iterations"),
-                seconds_per_iteration=t_iter, sample_seconds=t2 - t0)
+    out = dict(value=w.nbands / est, unit="eigenpairs/s", cores=cores, kind="oracle",
+               cpu_model=cpu_model_name(), affinity_cpus=len(os.sched_getaffinity(0)),
+               sample=(f"oracle block LOBPCG ({WORKLOAD}, block 0, {w.block} bands), "
+                       f"{sample_iters} iterations timed ({t_iter:.2f} s/iteration), "
+                       f"extrapolated to the GPU solve's {gpu_iterations} iterations"),
+               seconds_per_iteration=t_iter, sample_seconds=t2 - t0)
+    # H.X throughput of the oracle on the same byte model as the GPU apply
+    Xh = start_block(1, mil.shape[0], w.block)
+    t3 = time.perf_counter()
+    mf.apply_local(Xh)
+    t_apply = time.perf_counter() - t3
+    out["hx_local_seconds_per_64_bands"] = t_apply
+    if full_block:
+        guard = w.block // 8
+        t4 = time.perf_counter()
+        _, _, _, res, iters = matfree.lobpcg_block(mf, X0, None, tol=w.tol, maxit=300,
+                                                    nconv=w.block - guard)
+        t_block = time.perf_counter() - t4
+        nblocks = -(-w.nbands // (w.block - guard))
+        out["full_block0"] = dict(
+            seconds=t_block, iterations=iters, max_residual=float(res[:w.block - guard].max()),
+            eigenpairs_per_s_extrapolated=w.nbands / (t_block * nblocks),
+            sample=(f"block 0 of {WORKLOAD} iterated to tol {w.tol:g} ({w.block} columns, "
+                    f"{w.block - guard} kept), time x {nblocks} blocks"))
+    # the small cell: dense build + plain C Jacobi on one core; LAPACK as context
+    w0 = make_workload("gamma_l10")
+    t5 = time.perf_counter()
+    mil0 = pw.sphere(w0.cell, w0.kfrac, w0.ecut)
+    H0 = pw.dense_hamiltonian(w0.cell, w0.kfrac, mil0, w0.vgrid)
+    t6 = time.perf_counter()
+    ev, _, sweeps = eigh_jacobi(H0)
+    t7 = time.perf_counter()
+    np.linalg.eigh(H0)
+    t8 = time.perf_counter()
+    out["gamma_l10"] = dict(
+        npw=int(mil0.shape[0]), nbands=w0.nbands, build_seconds=t6 - t5, jacobi_seconds=t7 - t6,
+        jacobi_sweeps=int(sweeps), eigenpairs_per_s=w0.nbands / (t7 - t5), jacobi_cores=1,
+        numpy_eigh_seconds=t8 - t7, numpy_eigh_cores=cores,
+        sample="dense H of the 8-well Gamma-point cell built by the oracle and fully diagonalised "
+               "by its cyclic Jacobi (plain C, one thread); numpy.linalg.eigh of the same H on all "
+               "cores as context")
+    return out
+
+
+def eig_error_quantiles(eig, ref):
+    """Per-eigenvalue |eig - ref| summarised (Ha): quantiles over the bands."""
+    err = np.abs(np.asarray(eig) - np.asarray(ref))
+    return {"max": float(err.max()), "p99": float(np.percentile(err, 99)),
+            "p90": float(np.percentile(err, 90)), "p50": float(np.percentile(err, 50)),
+            "mean": float(err.mean()), "bands": int(err.size)}
+
+
+def load_oracle_golden(name):
+    """Eigenvalues the oracle wrote under tests/golden/ (index, eigenvalue, ...)."""
+    path = os.path.join(ROOT, "tests", "golden", f"{name}_eig.txt")
+    rows = [l.split() for l in open(path) if l.strip() and not l.startswith("#")]
+    return np.array([float(r[1]) for r in rows])
 
 
 def main():
@@ -103,7 +173,13 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=1,
                     help="timed batches of the ten-k-point cell (0: skip)")
     ap.add_argument("--serve-requests", type=int, default=16,
-                    help="requests in the served-stream sample (0: skip)")
+                    help="requests in the narrowed served-stream sample (0: skip)")
+    ap.add_argument("--serve-full-requests", type=int, default=60,
+                    help="requests of the full-range served stream (L 8-24 bohr, Ecut 5-25 Ha; 0: skip)")
+    ap.add_argument("--serve-full-cap-s", type=float, default=220.0,
+                    help="cap on the full-range served stream's arrival span (seconds)")
+    ap.add_argument("--cpu-full-block", type=int, default=1,
+                    help="also time one complete oracle block of the paper-scale cell on the CPU")
     ap.add_argument("--roofline-only", action="store_true",
                     help="only the per-kernel roofline timings (for profiling runs)")
     args = ap.parse_args()
@@ -152,6 +228,9 @@ def main():
         res = prob.ctx.get_residuals(w.nbands)
         stats = prob.ctx.get_stats()
         eig64 = eig.copy()
+        # the oracle's eigenvalues of the same cell (block LOBPCG to 1e-8, tests/golden)
+        golden = load_oracle_golden(WORKLOAD)[:w.nbands]
+        fp64_err = eig_error_quantiles(eig64, golden)
 
         # ---- the same cell in the mixed forms (complex64 iteration + FP64 refinement;
         # the BF16 forms also run the projector products, and the second one the
@@ -169,6 +248,7 @@ def main():
             mst = prob.ctx.get_stats()
             mres = prob.ctx.get_residuals(w.nbands)
             err = np.abs(eigm - eig64)
+            per_eig = eig_error_quantiles(eigm, golden)
             return {"value": w.nbands / float(np.mean(mlat)), "unit": "eigenpairs/s",
                     "ms_per_solve": 1e3 * float(np.mean(mlat)),
                     "latency_p50_ms": float(np.percentile(np.array(mlat) * 1e3, 50)),
@@ -176,6 +256,7 @@ def main():
                     "speedup_vs_fp64": (w.nbands / float(np.mean(mlat))) / value,
                     "max_abs_eig_diff_vs_fp64_ha": float(err.max()),
                     "mean_abs_eig_diff_vs_fp64_ha": float(err.mean()),
+                    "abs_eig_err_vs_oracle_ha": per_eig,
                     "max_residual": float(mres.max()),
                     "iterations": mst["iterations"], "complex64_iterations": mst["mixed_iterations"],
                     "phase_ms": {k: mst[k] for k in ("ms_apply", "ms_gemm", "ms_dense", "ms_vec",
@@ -270,6 +351,10 @@ def main():
     t_gram = event_time_ms(torch, prob.ctx.stream, lambda: prob.ctx.gram(Z, HZ, G), 20)
     gram_flops = 8.0 * ncol * ncol * npw
     gram_tflops = gram_flops / (t_gram * 1e-3) / 1e12
+    # the same Gram on complex64 blocks (the mixed form's Rayleigh-Ritz; FP32 MFMA)
+    Z32, HZ32 = Z.to(torch.complex64), HZ.to(torch.complex64)
+    t_gram32 = event_time_ms(torch, prob.ctx.stream, lambda: prob.ctx.gram(Z32, HZ32, G), 20)
+    gram32_tflops = gram_flops / (t_gram32 * 1e-3) / 1e12
 
     # ---- small dense eigensolver at the Rayleigh-Ritz shape (192 x 192, lowest 64)
     rng = np.random.default_rng(0)
@@ -300,6 +385,12 @@ def main():
                      achieved=gram_tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                      frac=gram_tflops / FP64_PEAK_TFLOPS, traffic=TRAFFIC_MEASURED["gemm"],
                      algorithmic=f"{gram_flops:.3e} FLOP per launch (8 p q K)", launch_ms=t_gram),
+        "gemm_complex64": dict(bound="mfma", kernel="k_gemm_tn_lds<float> (+k_reduce_parts), Rayleigh-Ritz "
+                               "Gram 192x192, K=34181, complex64 blocks on FP32 MFMA",
+                               achieved=gram32_tflops, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
+                               frac=gram32_tflops / FP32_PEAK_TFLOPS, traffic=None,
+                               algorithmic=f"{gram_flops:.3e} FLOP per launch (8 p q K)",
+                               launch_ms=t_gram32),
         "apply": dict(bound="hbm", kernel="k_zinv + k_plane + k_zfwd (local H.X, 64 bands)",
                       achieved=fft_gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=fft_gbs / HBM_PEAK_GBS,
                       traffic=TRAFFIC_MEASURED["apply"], algorithmic=f"{b_alg_design:.3e} B per 64-band apply",
@@ -352,6 +443,46 @@ def main():
                             "k ~ U[0,1)^3, FP64 or mixed with p = 1/2")
         log(f"served stream: {served['solves_per_s']:.2f} solves/s, p99 {served['latency_p99_s']:.3f} s")
 
+    # ---- served stream over the full request range (L ~ U[8, 24] bohr, Ecut ~ U[5, 25] Ha,
+    # up to 1024 bands): capacity measured first on a closed-loop calibration set, then
+    # Poisson arrivals at 0.7 x that capacity
+    served_full = None
+    if args.serve_full_requests > 0 and not args.roofline_only:
+        from paper_0707_3405_amd.serve import Server, poisson_arrivals
+        from workloads import make_request
+
+        def reqs_of(ids, times):
+            out = []
+            for t, i in zip(times, ids):
+                wr, mixed_r = make_request(i)
+                out.append((float(t), wr, PW_PREC_MIXED if mixed_r else PW_PREC_FP64))
+            return out
+        calib_ids = list(range(500, 510))
+        t0 = time.perf_counter()
+        _, calib = Server(max_active=8).run(reqs_of(calib_ids, [0.0] * len(calib_ids)))
+        capacity = calib["solves_per_s"]
+        rate = 0.7 * capacity
+        nreq = args.serve_full_requests
+        arr = poisson_arrivals(nreq, rate)
+        keep = int(np.searchsorted(arr, args.serve_full_cap_s, side="right"))
+        results_f, served_full = Server(max_active=8).run(reqs_of(range(keep), arr[:keep]))
+        served_full["capacity_solves_per_s"] = capacity
+        served_full["capacity_sample"] = (f"{len(calib_ids)} requests (stream indices 500-509) admitted "
+                                          f"at once, closed loop, {calib['eigenpairs_per_s']:.1f} eigenpairs/s")
+        served_full["arrival_rate_per_s"] = rate
+        served_full["npw_range"] = [int(min(r.get("npw", 0) for r in results_f)),
+                                    int(max(r.get("npw", 0) for r in results_f))]
+        served_full["nbands_range"] = [int(min(r["nbands"] for r in results_f)),
+                                       int(max(r["nbands"] for r in results_f))]
+        served_full["sample"] = (f"{keep} requests, Poisson arrivals at 0.7 x the measured capacity; "
+                                 "L ~ U[8,24] bohr, Ecut ~ U[5,25] Ha, round(0.0135 L^3) wells with 4 "
+                                 "projectors, bands 32 round(5.5 atoms/32) in [32, 1024], k ~ U[0,1)^3, "
+                                 "FP64 or mixed with p = 1/2")
+        served_full["leg_seconds"] = time.perf_counter() - t0
+        log(f"served stream (full range): {served_full['solves_per_s']:.2f} solves/s, "
+            f"p50 {served_full['latency_p50_s']:.2f} s, p99 {served_full['latency_p99_s']:.2f} s, "
+            f"{keep} requests")
+
     if args.roofline_only:
         # plain device copy of known size: reference for HBM byte counters
         src = torch.empty(1 << 28, dtype=torch.uint8, device="cuda")
@@ -387,12 +518,15 @@ def main():
         "hx_fft_ms_per_64_bands_complex64": t_fft32,
         "gram_tflops": gram_tflops,
         "gram_ms": t_gram,
+        "gram_complex64_tflops": gram32_tflops,
+        "gram_complex64_ms": t_gram32,
         "latency_p50_ms": float(np.percentile(np.array(lat) * 1e3, 50)),
         "latency_p99_ms": float(np.percentile(np.array(lat) * 1e3, 99)),
         "iterations": stats["iterations"],
         "blocks": stats["blocks"],
         "phase_ms": phases,
         "max_residual": float(res.max()),
+        "abs_eig_err_vs_oracle_ha": fp64_err,
         "roofline": roof,
         "roofline_all": roofs,
         "mixed": mixed,
@@ -403,6 +537,7 @@ def main():
         "hx_full_ms_per_64_bands": hx_full,
         "batched_kpoints": batched,
         "served": served,
+        "served_full_range": served_full,
     }
     if not args.no_cpu:
         cores = len(os.sched_getaffinity(0))
@@ -410,7 +545,8 @@ def main():
         if omp and omp.isdigit():
             cores = min(cores, int(omp))
         log(f"cpu baseline on {cores} threads ...")
-        out["cpu_baseline"] = cpu_baseline(w, stats["iterations"], cores, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(w, stats["iterations"], cores, args.cpu_iters,
+                                           full_block=bool(args.cpu_full_block))
     print(json.dumps(out), flush=True)
 
 

@@ -51,3 +51,30 @@ def test_served_stream_matches_solo_and_oracle(torch_cuda):
             err = np.abs(r["eig"] - ref).max()
             print(w.name, "npw", mil.shape[0], "prec", prec, "max |eig - oracle|", err)
             assert err <= (1e-8 if prec == PW_PREC_FP64 else 1e-6), err
+
+
+def test_served_stream_large_requests_match_oracle_goldens(torch_cuda):
+    """Requests 2 (FP64: 5680 plane waves, 224 bands) and 6 (mixed: 8049 plane
+    waves, 192 bands) of the served stream (L in [8, 24] bohr, Ecut in [5, 25] Ha),
+    admitted beside two small requests, against the oracle's eigenvalues
+    (block LOBPCG to 1e-8): FP64 1e-8 Ha, mixed 1e-6 Ha."""
+    from conftest import load_golden
+    from paper_0707_3405_amd import PW_PREC_FP64, PW_PREC_MIXED
+    from paper_0707_3405_amd.serve import Server
+    from workloads import make_request
+    reqs = []
+    for t, i in ((0.0, 2), (0.05, 4), (0.1, 6), (0.15, 9)):
+        w, mixed = make_request(i)
+        reqs.append((t, w, PW_PREC_MIXED if mixed else PW_PREC_FP64))
+    results, summary = Server(max_active=4).run(reqs)
+    print(summary)
+    assert summary["all_converged"] and summary["failed"] == 0
+    for (arr, w, prec), r in zip(reqs, results):
+        assert r["max_residual"] <= w.tol
+    for pos, i in ((0, 2), (2, 6)):
+        w, prec = reqs[pos][1], reqs[pos][2]
+        ref = load_golden(f"request{i}")[0][:w.nbands]
+        err = np.abs(results[pos]["eig"] - ref).max()
+        print(f"request {i} (npw {results[pos]['npw']}, {w.nbands} bands, prec {prec}): "
+              f"max |eig - oracle| = {err:.2e}")
+        assert err <= (1e-8 if prec == PW_PREC_FP64 else 1e-6), err
