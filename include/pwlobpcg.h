@@ -168,21 +168,26 @@ pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ld
                      int32_t nb, pw_precision prec);
 
 /* Launch parameters of a context (0 = built-in default) and, from
- * pw_autotune, the timings behind the choice (ms per launch).  The choice
- * changes the partition of the work only: the FFT results are the same, the
- * split-K sums may differ in rounding. */
+ * pw_autotune, the timings behind the choice (ms per launch).  The sticks and
+ * rows change the partition of the work only (the FFT results are bitwise the
+ * same); the radix split changes the order of the FFT's operations and the
+ * split-K target that of the Gram sums, so both may change the rounding. */
 typedef struct {
     int32_t fft_sticks_per_block;   /* z passes: sticks per workgroup, 0 or 1..64 (default 16) */
     int32_t fft_plane_rows;         /* plane pass: row chunk, 0 or 1..128 (default 48, capped by LDS) */
     int32_t gemm_split_workgroups;  /* split-K TN target workgroups, 0 or 1..1024 (default 1024) */
     double apply_ms_default, apply_ms_tuned;   /* local H X of nb bands */
     double gemm_ms_default, gemm_ms_tuned;     /* 3m x 3m Gram over npw (+ projector overlaps) */
+    int32_t fft_radix2;   /* radix split of the length-N FFTs: N = (N / R2) R2, both factors
+                             products of 2, 3, 5 in [2, 16]; 0 = the default (R1 = 8 where
+                             it fits, else the largest R2 <= sqrt(N)); the stored
+                             potential follows the split's order */
 } pw_tuning;
 
 /* Autotuner for this context's shapes (batched k-points and served requests
  * differ in npw, grid and projector count): times the local H X of nb bands
- * (1 <= nb <= block of the workspace) for sticks per block {16, 32, 64} x
- * plane rows {16, 32, 48, 96}, and the Rayleigh-Ritz Gram (3 block x 3 block over
+ * (1 <= nb <= block of the workspace) for every radix split of the grid's FFT
+ * length x sticks per block {16, 32, 64} x plane rows {16, 32, 48, 96}, and the Rayleigh-Ritz Gram (3 block x 3 block over
  * npw) plus the projector overlaps for split targets {384, 512, 768, 1024},
  * with HIP events on the context stream (mean of 5 after a warm-up); keeps
  * the fastest of each (or the default when nothing beats it) for later

@@ -42,7 +42,7 @@ class PWTuning(ctypes.Structure):
     _fields_ = [("fft_sticks_per_block", ctypes.c_int32), ("fft_plane_rows", ctypes.c_int32),
                 ("gemm_split_workgroups", ctypes.c_int32), ("apply_ms_default", ctypes.c_double),
                 ("apply_ms_tuned", ctypes.c_double), ("gemm_ms_default", ctypes.c_double),
-                ("gemm_ms_tuned", ctypes.c_double)]
+                ("gemm_ms_tuned", ctypes.c_double), ("fft_radix2", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -367,11 +367,13 @@ class Context:
         self._check(self.lib.pw_autotune(self.h, nb, ctypes.byref(out)))
         return out.as_dict()
 
-    def set_tuning(self, fft_sticks_per_block=0, fft_plane_rows=0, gemm_split_workgroups=0, reset=False):
+    def set_tuning(self, fft_sticks_per_block=0, fft_plane_rows=0, gemm_split_workgroups=0, reset=False,
+                   fft_radix2=0):
         if reset:
             self._check(self.lib.pw_set_tuning(self.h, None))
             return
-        t = PWTuning(fft_sticks_per_block, fft_plane_rows, gemm_split_workgroups, 0.0, 0.0, 0.0, 0.0)
+        t = PWTuning(fft_sticks_per_block, fft_plane_rows, gemm_split_workgroups, 0.0, 0.0, 0.0, 0.0,
+                     fft_radix2)
         self._check(self.lib.pw_set_tuning(self.h, ctypes.byref(t)))
 
     def chol_inv(self, G, n, Rinv):

@@ -48,11 +48,11 @@ __device__ __forceinline__ void load_twiddles(cpx<T> *tw_s, const double *tw_g, 
 }
 
 // ---- pass 1: inverse z-FFT per stick ---------------------------------------
-template <int N, class T>
+template <class P, class T>
 __global__ void __launch_bounds__(kThreads) k_zinv(SphereDev sp, const cpx<T> *__restrict__ X,
                                                    int64_t ldx, cpx<T> *__restrict__ S, int spb) {
-    constexpr int LD = N + 1;
-    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+    constexpr int N = P::N, LD = N + 1;
+    constexpr int R1 = P::R1, R2 = P::R2;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *tw = reinterpret_cast<cpx<T> *>(smem_raw);
     cpx<T> *buf = tw + N;
@@ -76,14 +76,14 @@ __global__ void __launch_bounds__(kThreads) k_zinv(SphereDev sp, const cpx<T> *_
     __syncthreads();
     for (int it = threadIdx.x; it < ns * R2; it += blockDim.x) {
         const int seq = it % ns, n2 = it / ns;
-        dit_a<N, +1>(buf + seq * LD, n2, tw);
+        dit_a<P, +1>(buf + seq * LD, n2, tw);
     }
     __syncthreads();
     cpx<T> *Sb = S + (int64_t)band * N * sp.ldst + s0;
     for (int it = threadIdx.x; it < ns * R1; it += blockDim.x) {
         const int seq = it % ns, k1 = it / ns;
         cpx<T> out[R2];
-        dit_b<N, +1>(buf + seq * LD, k1, out);
+        dit_b<P, +1>(buf + seq * LD, k1, out);
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) Sb[(int64_t)(k1 + R1 * k2) * sp.ldst + seq] = out[k2];
     }
@@ -99,11 +99,11 @@ __device__ __forceinline__ int xcd_logical(int lin, int total) {
     return xcd * q + min(xcd, r) + local;
 }
 
-template <int N, class T>
-__global__ void __launch_bounds__((plane_threads<N, T>())) k_plane(SphereDev sp, const T *__restrict__ vperm,
+template <class P, class T>
+__global__ void __launch_bounds__((plane_threads<P::N, T>())) k_plane(SphereDev sp, const T *__restrict__ vperm,
                                                     cpx<T> *__restrict__ S, int nb, int rb) {
-    constexpr int LD = N + 1;
-    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+    constexpr int N = P::N, LD = N + 1;
+    constexpr int R1 = P::R1, R2 = P::R2;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *tw = reinterpret_cast<cpx<T> *>(smem_raw);
     cpx<T> *A = tw + N;                 // [ncx][LD], y along the row
@@ -124,13 +124,13 @@ __global__ void __launch_bounds__((plane_threads<N, T>())) k_plane(SphereDev sp,
     // inverse y-FFT on the kept columns (natural -> digit-reversed)
     for (int it = threadIdx.x; it < ncx * R2; it += blockDim.x) {
         const int c = it % ncx, n2 = it / ncx;
-        dit_a<N, +1>(A + c * LD, n2, tw);
+        dit_a<P, +1>(A + c * LD, n2, tw);
     }
     __syncthreads();
     for (int it = threadIdx.x; it < ncx * R1; it += blockDim.x) {
         const int c = it % ncx, k1 = it / ncx;
         cpx<T> out[R2];
-        dit_b<N, +1>(A + c * LD, k1, out);
+        dit_b<P, +1>(A + c * LD, k1, out);
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) A[c * LD + k1 * R2 + k2] = out[k2];
     }
@@ -143,12 +143,12 @@ __global__ void __launch_bounds__((plane_threads<N, T>())) k_plane(SphereDev sp,
             const int r = i / N, x = i - r * N;
             int xc = x - xmin_g;
             xc += (xc < 0) ? N : 0;
-            R[r * LD + x] = (xc < ncx) ? A[xc * LD + digit_rev<N>(y0 + r)] : cpx<T>{T(0), T(0)};
+            R[r * LD + x] = (xc < ncx) ? A[xc * LD + digit_rev<P>(y0 + r)] : cpx<T>{T(0), T(0)};
         }
         __syncthreads();
         for (int it = threadIdx.x; it < nr * R2; it += blockDim.x) {
             const int r = it % nr, n2 = it / nr;
-            dit_a<N, +1>(R + r * LD, n2, tw);
+            dit_a<P, +1>(R + r * LD, n2, tw);
         }
         __syncthreads();
         // second inverse stage, V multiply and first forward stage act on the
@@ -156,7 +156,7 @@ __global__ void __launch_bounds__((plane_threads<N, T>())) k_plane(SphereDev sp,
         for (int it = threadIdx.x; it < nr * R1; it += blockDim.x) {
             const int r = it % nr, k1 = it / nr;
             cpx<T> out[R2];
-            dit_b<N, +1>(R + r * LD, k1, out);
+            dit_b<P, +1>(R + r * LD, k1, out);
             const T *vrow = Vz + (int64_t)(y0 + r) * N + k1 * R2;
 #pragma unroll
             for (int k2 = 0; k2 < R2; ++k2) out[k2] = cscale(out[k2], vrow[k2]);
@@ -168,8 +168,8 @@ __global__ void __launch_bounds__((plane_threads<N, T>())) k_plane(SphereDev sp,
         for (int it = threadIdx.x; it < nr * R2; it += blockDim.x) {
             const int r = it % nr, n2 = it / nr;
             cpx<T> out[R1];
-            dif_a<N, -1>(R + r * LD, n2, tw, out);
-            const int ypos = digit_rev<N>(y0 + r);
+            dif_a<P, -1>(R + r * LD, n2, tw, out);
+            const int ypos = digit_rev<P>(y0 + r);
 #pragma unroll
             for (int n1 = 0; n1 < R1; ++n1) {
                 const int x = n1 * R2 + n2;
@@ -183,13 +183,13 @@ __global__ void __launch_bounds__((plane_threads<N, T>())) k_plane(SphereDev sp,
     // forward y-FFT on the kept columns (digit-reversed -> natural)
     for (int it = threadIdx.x; it < ncx * R1; it += blockDim.x) {
         const int c = it % ncx, k1 = it / ncx;
-        dif_b<N, -1>(A + c * LD, k1);
+        dif_b<P, -1>(A + c * LD, k1);
     }
     __syncthreads();
     for (int it = threadIdx.x; it < ncx * R2; it += blockDim.x) {
         const int c = it % ncx, n2 = it / ncx;
         cpx<T> out[R1];
-        dif_a<N, -1>(A + c * LD, n2, tw, out);
+        dif_a<P, -1>(A + c * LD, n2, tw, out);
 #pragma unroll
         for (int n1 = 0; n1 < R1; ++n1) A[c * LD + n1 * R2 + n2] = out[n1];
     }
@@ -206,8 +206,9 @@ template <int N, class T>
 __global__ void __launch_bounds__(kRhoThreads)
     k_plane_rho(SphereDev sp, const cpx<T> *__restrict__ S, int nb, const double *__restrict__ occ,
                 double *__restrict__ rho_zyx, int rb) {
+    using P = Split<N>;   // the density pass uses the default split (its output is in natural order)
     constexpr int LD = N + 1;
-    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+    constexpr int R1 = P::R1, R2 = P::R2;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *tw = reinterpret_cast<cpx<T> *>(smem_raw);
     cpx<T> *A = tw + N;                 // [ncx][LD], y along the row
@@ -227,13 +228,13 @@ __global__ void __launch_bounds__(kRhoThreads)
         __syncthreads();
         for (int it = threadIdx.x; it < ncx * R2; it += blockDim.x) {
             const int c = it % ncx, n2 = it / ncx;
-            dit_a<N, +1>(A + c * LD, n2, tw);
+            dit_a<P, +1>(A + c * LD, n2, tw);
         }
         __syncthreads();
         for (int it = threadIdx.x; it < ncx * R1; it += blockDim.x) {
             const int c = it % ncx, k1 = it / ncx;
             cpx<T> out[R2];
-            dit_b<N, +1>(A + c * LD, k1, out);
+            dit_b<P, +1>(A + c * LD, k1, out);
 #pragma unroll
             for (int k2 = 0; k2 < R2; ++k2) A[c * LD + k1 * R2 + k2] = out[k2];
         }
@@ -244,22 +245,22 @@ __global__ void __launch_bounds__(kRhoThreads)
                 const int r = i / N, x = i - r * N;
                 int xc = x - xmin_g;
                 xc += (xc < 0) ? N : 0;
-                R[r * LD + x] = (xc < ncx) ? A[xc * LD + digit_rev<N>(y0 + r)] : cpx<T>{T(0), T(0)};
+                R[r * LD + x] = (xc < ncx) ? A[xc * LD + digit_rev<P>(y0 + r)] : cpx<T>{T(0), T(0)};
             }
             __syncthreads();
             for (int it = threadIdx.x; it < nr * R2; it += blockDim.x) {
                 const int r = it % nr, n2 = it / nr;
-                dit_a<N, +1>(R + r * LD, n2, tw);
+                dit_a<P, +1>(R + r * LD, n2, tw);
             }
             __syncthreads();
             for (int it = threadIdx.x; it < nr * R1; it += blockDim.x) {
                 const int r = it % nr, k1 = it / nr;
                 cpx<T> out[R2];
-                dit_b<N, +1>(R + r * LD, k1, out);
+                dit_b<P, +1>(R + r * LD, k1, out);
                 double *row = rz + (int64_t)(y0 + r) * N;
 #pragma unroll
                 for (int k2 = 0; k2 < R2; ++k2) {
-                    const int x = freq_at<N>(k1 * R2 + k2);
+                    const int x = freq_at<P>(k1 * R2 + k2);
                     const double a = (double)out[k2].x, b = (double)out[k2].y;
                     row[x] += f * (a * a + b * b);
                 }
@@ -279,12 +280,12 @@ __global__ void k_rho_permute(const double *__restrict__ rho_zyx, int n, double 
 }
 
 // ---- pass 3: forward z-FFT per stick, gather, kinetic -----------------------
-template <int N, class T>
+template <class P, class T>
 __global__ void __launch_bounds__(kThreads) k_zfwd(SphereDev sp, const cpx<T> *__restrict__ S,
                                                    const cpx<T> *__restrict__ X, int64_t ldx,
                                                    cpx<T> *__restrict__ Y, int64_t ldy, int spb) {
-    constexpr int LD = N + 1;
-    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+    constexpr int N = P::N, LD = N + 1;
+    constexpr int R1 = P::R1, R2 = P::R2;
     extern __shared__ unsigned char smem_raw[];
     cpx<T> *tw = reinterpret_cast<cpx<T> *>(smem_raw);
     cpx<T> *buf = tw + N;
@@ -297,18 +298,18 @@ __global__ void __launch_bounds__(kThreads) k_zfwd(SphereDev sp, const cpx<T> *_
     const cpx<T> *Sb = S + (int64_t)band * N * sp.ldst + s0;
     for (int i = threadIdx.x; i < ns * N; i += blockDim.x) {
         const int z = i / ns, seq = i - z * ns;
-        buf[seq * LD + digit_rev<N>(z)] = Sb[(int64_t)z * sp.ldst + seq];
+        buf[seq * LD + digit_rev<P>(z)] = Sb[(int64_t)z * sp.ldst + seq];
     }
     __syncthreads();
     for (int it = threadIdx.x; it < ns * R1; it += blockDim.x) {
         const int seq = it % ns, k1 = it / ns;
-        dif_b<N, -1>(buf + seq * LD, k1);
+        dif_b<P, -1>(buf + seq * LD, k1);
     }
     __syncthreads();
     for (int it = threadIdx.x; it < ns * R2; it += blockDim.x) {
         const int seq = it % ns, n2 = it / ns;
         cpx<T> out[R1];
-        dif_a<N, -1>(buf + seq * LD, n2, tw, out);
+        dif_a<P, -1>(buf + seq * LD, n2, tw, out);
 #pragma unroll
         for (int n1 = 0; n1 < R1; ++n1) buf[seq * LD + n1 * R2 + n2] = out[n1];
     }
@@ -328,26 +329,40 @@ __global__ void __launch_bounds__(kThreads) k_zfwd(SphereDev sp, const cpx<T> *_
 }
 
 // ---- potential layout: vperm[z][y][p] = scale * V[x(p)][y][z] ---------------
-// p is the digit-reversed x position produced by the inverse x-FFT of pass 2,
-// so the multiply in pass 2 reads V contiguously.
-template <int N>
+// p is the digit-reversed x position produced by the inverse x-FFT of pass 2
+// (it depends on the radix split P), so the multiply in pass 2 reads V
+// contiguously.
+template <class P>
 __global__ void k_permute_v(const double *__restrict__ v, double scale, double *__restrict__ out,
                             int *bad) {
+    constexpr int N = P::N;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= (int64_t)N * N * N) return;
     const int p = (int)(i % N), y = (int)((i / N) % N), z = (int)(i / ((int64_t)N * N));
-    const int x = freq_at<N>(p);
+    const int x = freq_at<P>(p);
     const double val = v[((int64_t)x * N + y) * N + z];
     if (!isfinite(val)) atomicOr(bad, 1);
     out[i] = val * scale;
 }
 
+// the same potential moved from the layout of split PF to that of split PT
+template <class PF, class PT>
+__global__ void k_repermute_v(const double *__restrict__ in, double *__restrict__ out) {
+    constexpr int N = PT::N;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)N * N * N) return;
+    const int p = (int)(i % N);
+    const int64_t row = i - p;
+    out[i] = in[row + digit_rev<PF>(freq_at<PT>(p))];
+}
+
 // ---- dispatch ---------------------------------------------------------------
 constexpr int kSticksPerBlock = 16;   // default sticks per workgroup of the z passes
 
-template <int N, class T>
-void run_apply(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
-               int64_t ldy, int nb, cpx<T> *S, hipStream_t st) {
+template <class P, class T>
+void run_apply_split(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
+                     int64_t ldy, int nb, cpx<T> *S, hipStream_t st) {
+    constexpr int N = P::N;
     const Tuning &tune = thread_tuning();
     const int spb = tune.fft_spb > 0 ? tune.fft_spb : kSticksPerBlock;
     const size_t e = sizeof(cpx<T>);
@@ -362,14 +377,43 @@ void run_apply(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx
     if (rb > N) rb = N;
     const size_t sm2 = sm2_of(rb);
     PW_REQUIRE(sm2 <= 160 * 1024, PW_ERR_ARG, "FFT plane does not fit in LDS");
-    ensure_smem_limit((const void *)k_zinv<N, T>, sm13);
-    ensure_smem_limit((const void *)k_plane<N, T>, sm2);
-    ensure_smem_limit((const void *)k_zfwd<N, T>, sm13);
-    hipLaunchKernelGGL((k_zinv<N, T>), g13, dim3(kThreads), sm13, st, sp, X, ldx, S, spb);
-    hipLaunchKernelGGL((k_plane<N, T>), dim3(N * nb), dim3(plane_threads<N, T>()), sm2, st, sp, vperm, S, nb,
+    ensure_smem_limit((const void *)k_zinv<P, T>, sm13);
+    ensure_smem_limit((const void *)k_plane<P, T>, sm2);
+    ensure_smem_limit((const void *)k_zfwd<P, T>, sm13);
+    hipLaunchKernelGGL((k_zinv<P, T>), g13, dim3(kThreads), sm13, st, sp, X, ldx, S, spb);
+    hipLaunchKernelGGL((k_plane<P, T>), dim3(N * nb), dim3(plane_threads<N, T>()), sm2, st, sp, vperm, S, nb,
                        rb);
-    hipLaunchKernelGGL((k_zfwd<N, T>), g13, dim3(kThreads), sm13, st, sp, S, X, ldx, Y, ldy, spb);
+    hipLaunchKernelGGL((k_zfwd<P, T>), g13, dim3(kThreads), sm13, st, sp, S, X, ldx, Y, ldy, spb);
     PW_HIP(hipGetLastError());
+}
+
+// host-side compile-time loop over the candidate second factors 2..16
+template <int B, int E, class F>
+void host_for(F &&f) {
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        host_for<B + 1, E>(static_cast<F &&>(f));
+    }
+}
+
+// the split a context's tuning selects for length N (0: the default)
+int effective_r2(int n, int r2) { return r2 > 0 ? r2 : choose_r2(n); }
+
+template <int N, class T>
+void run_apply(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
+               int64_t ldy, int nb, cpx<T> *S, hipStream_t st) {
+    const int r2 = effective_r2(N, thread_tuning().fft_r2);
+    bool done = false;
+    host_for<2, 17>([&](auto R) {
+        constexpr int r = R;
+        if constexpr (split_ok(N, r)) {
+            if (!done && r == r2) {
+                run_apply_split<Split<N, r>, T>(sp, vperm, X, ldx, Y, ldy, nb, S, st);
+                done = true;
+            }
+        }
+    });
+    PW_REQUIRE(done, PW_ERR_ARG, "radix split not available for this FFT length");
 }
 
 #define PW_FFT_SIZES(X) X(16) X(20) X(24) X(32) X(36) X(40) X(48) X(60) X(64) X(72) X(80) X(96) X(108) X(120) X(128)
@@ -391,14 +435,52 @@ std::vector<int> fft_supported_sizes() {
     return v;
 }
 
-void launch_permute_potential(const double *v, int n, double scale, double *v_zyx, int *bad,
-                              hipStream_t st) {
-    const int64_t tot = (int64_t)n * n * n;
+template <int N>
+void permute_for(int r2, const double *v, double scale, double *v_zyx, int *bad, hipStream_t st) {
+    const int64_t tot = (int64_t)N * N * N;
     const dim3 grid((unsigned)((tot + 255) / 256));
+    bool done = false;
+    host_for<2, 17>([&](auto R) {
+        constexpr int r = R;
+        if constexpr (split_ok(N, r)) {
+            if (!done && r == r2) {
+                hipLaunchKernelGGL((k_permute_v<Split<N, r>>), grid, dim3(256), 0, st, v, scale, v_zyx, bad);
+                done = true;
+            }
+        }
+    });
+    PW_REQUIRE(done, PW_ERR_ARG, "radix split not available for this FFT length");
+}
+
+template <int N>
+void repermute_for(int r2_from, int r2_to, const double *in, double *out, hipStream_t st) {
+    const int64_t tot = (int64_t)N * N * N;
+    const dim3 grid((unsigned)((tot + 255) / 256));
+    bool done = false;
+    host_for<2, 17>([&](auto RF) {
+        constexpr int rf = RF;
+        if constexpr (split_ok(N, rf)) {
+            host_for<2, 17>([&](auto RT) {
+                constexpr int rt = RT;
+                if constexpr (split_ok(N, rt)) {
+                    if (!done && rf == r2_from && rt == r2_to) {
+                        hipLaunchKernelGGL((k_repermute_v<Split<N, rf>, Split<N, rt>>), grid, dim3(256), 0, st,
+                                           in, out);
+                        done = true;
+                    }
+                }
+            });
+        }
+    });
+    PW_REQUIRE(done, PW_ERR_ARG, "radix split not available for this FFT length");
+}
+
+void launch_permute_potential(const double *v, int n, double scale, double *v_zyx, int *bad, int r2,
+                              hipStream_t st) {
     switch (n) {
-#define PW_CASE(NN)                                                                      \
-    case NN:                                                                             \
-        hipLaunchKernelGGL(k_permute_v<NN>, grid, dim3(256), 0, st, v, scale, v_zyx, bad); \
+#define PW_CASE(NN)                                                              \
+    case NN:                                                                     \
+        permute_for<NN>(effective_r2(NN, r2), v, scale, v_zyx, bad, st);        \
         break;
         PW_FFT_SIZES(PW_CASE)
 #undef PW_CASE
@@ -407,6 +489,30 @@ void launch_permute_potential(const double *v, int n, double scale, double *v_zy
     }
     PW_HIP(hipGetLastError());
 }
+
+void launch_repermute_potential(const double *in, int n, int r2_from, int r2_to, double *out,
+                                hipStream_t st) {
+    switch (n) {
+#define PW_CASE(NN)                                                                                 \
+    case NN:                                                                                        \
+        repermute_for<NN>(effective_r2(NN, r2_from), effective_r2(NN, r2_to), in, out, st);         \
+        break;
+        PW_FFT_SIZES(PW_CASE)
+#undef PW_CASE
+        default:
+            throw Error{PW_ERR_ARG, "unsupported FFT size"};
+    }
+    PW_HIP(hipGetLastError());
+}
+
+std::vector<int> fft_radix_splits(int n) {
+    std::vector<int> v;
+    for (int r = 2; r <= 16; ++r)
+        if (split_ok(n, r)) v.push_back(r);
+    return v;
+}
+
+int fft_default_r2(int n) { return choose_r2(n); }
 
 template <int N>
 void run_density(const SphereDev &sp, const cd *X, int64_t ldx, int nb, const double *occ,
@@ -420,9 +526,9 @@ void run_density(const SphereDev &sp, const cd *X, int64_t ldx, int nb, const do
     if (rb > N) rb = N;
     const size_t sm2 = base2 + (size_t)rb * (N + 1) * e;
     PW_REQUIRE(sm2 <= 160 * 1024, PW_ERR_ARG, "FFT plane does not fit in LDS");
-    ensure_smem_limit((const void *)k_zinv<N, double>, sm1);
+    ensure_smem_limit((const void *)k_zinv<Split<N>, double>, sm1);
     ensure_smem_limit((const void *)k_plane_rho<N, double>, sm2);
-    hipLaunchKernelGGL((k_zinv<N, double>), dim3((sp.nst + spb - 1) / spb, nb), dim3(kThreads), sm1, st,
+    hipLaunchKernelGGL((k_zinv<Split<N>, double>), dim3((sp.nst + spb - 1) / spb, nb), dim3(kThreads), sm1, st,
                        sp, X, ldx, S, spb);
     hipLaunchKernelGGL((k_plane_rho<N, double>), dim3(N), dim3(kRhoThreads), sm2, st, sp, S, nb, occ,
                        rho_zyx, rb);

@@ -2,7 +2,8 @@
 // plane-wave H.X apply.
 //
 // A length-N transform (N = R1 * R2, both factors products of 2, 3, 5 and at
-// most 16) is done in place in LDS in two stages separated by one barrier:
+// most 16; the split is a type P = Split<N, R2>) is done in place in LDS in
+// two stages separated by one barrier:
 //
 //   dit  (natural order in -> digit-reversed out):
 //     stage A, item n2:  DFT_R1 over x[n1*R2 + n2], twiddle W_N^{S n2 k1},
@@ -223,29 +224,37 @@ constexpr int isqrt(int n) {
     while ((r + 1) * (r + 1) <= n) ++r;
     return r;
 }
+// Default split: a first-stage radix R1 = 8 where it fits (measured fastest for
+// the plane pass at N = 72, 96 and 120), else the largest R2 <= sqrt(N).
 constexpr int choose_r2(int n) {
+    if (n % 8 == 0 && n / 8 >= 2 && n / 8 <= 16 && smooth(n / 8)) return n / 8;
     for (int r2 = isqrt(n); r2 >= 1; --r2)
         if (n % r2 == 0 && n / r2 <= 16 && smooth(r2) && smooth(n / r2)) return r2;
     return 0;
 }
-template <int N>
+// N = R1 * R2 with both factors in [2, 16] and products of 2, 3, 5: the
+// alternative radix splits a context may be tuned to (choose_r2 is the default)
+constexpr bool split_ok(int n, int r2) {
+    return r2 >= 2 && r2 <= 16 && n % r2 == 0 && n / r2 >= 2 && n / r2 <= 16 && smooth(r2) &&
+           smooth(n / r2);
+}
+template <int N_, int R2_ = 0>
 struct Split {
-    static constexpr int R2 = choose_r2(N);
-    static constexpr int R1 = N / R2;
-    static_assert(R2 > 0 && R2 <= 16, "unsupported FFT length");
+    static constexpr int N = N_;
+    static constexpr int R2 = R2_ > 0 ? R2_ : choose_r2(N_);
+    static constexpr int R1 = N_ / R2;
+    static_assert(R2 > 0 && R2 <= 16 && R1 <= 16 && R1 * R2 == N_, "unsupported FFT length or split");
 };
 
 // Position of frequency k in a dit result.
-template <int N>
+template <class P>
 __device__ __forceinline__ int digit_rev(int k) {
-    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
-    return (k % R1) * R2 + k / R1;
+    return (k % P::R1) * P::R2 + k / P::R1;
 }
 // Frequency held at position p of a dit result.
-template <int N>
+template <class P>
 __device__ __forceinline__ int freq_at(int p) {
-    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
-    return (p / R2) + R1 * (p % R2);
+    return (p / P::R2) + P::R1 * (p % P::R2);
 }
 
 template <int S, class T>
@@ -256,9 +265,9 @@ __device__ __forceinline__ cpx<T> twiddle(const cpx<T> *tw, int idx) {
 }
 
 // dit stage A on one sequence (element stride 1): item n2 in [0, R2).
-template <int N, int S, class T>
+template <class P, int S, class T>
 __device__ __forceinline__ void dit_a(cpx<T> *x, int n2, const cpx<T> *tw) {
-    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+    constexpr int N = P::N, R1 = P::R1, R2 = P::R2;
     cpx<T> u[R1];
 #pragma unroll
     for (int n1 = 0; n1 < R1; ++n1) u[n1] = x[n1 * R2 + n2];
@@ -269,17 +278,17 @@ __device__ __forceinline__ void dit_a(cpx<T> *x, int n2, const cpx<T> *tw) {
     for (int k1 = 0; k1 < R1; ++k1) x[k1 * R2 + n2] = u[k1];
 }
 // dit stage B: item k1 in [0, R1); leaves X[k1 + R1 k2] in out[k2].
-template <int N, int S, class T>
+template <class P, int S, class T>
 __device__ __forceinline__ void dit_b(const cpx<T> *x, int k1, cpx<T> *out) {
-    constexpr int R2 = Split<N>::R2;
+    constexpr int R2 = P::R2;
 #pragma unroll
     for (int n2 = 0; n2 < R2; ++n2) out[n2] = x[k1 * R2 + n2];
     Dft<R2, S, T>::run(out);
 }
 // dif stage B': item k1 in [0, R1), in place.
-template <int N, int S, class T>
+template <class P, int S, class T>
 __device__ __forceinline__ void dif_b(cpx<T> *x, int k1) {
-    constexpr int R2 = Split<N>::R2;
+    constexpr int R2 = P::R2;
     cpx<T> u[R2];
 #pragma unroll
     for (int k2 = 0; k2 < R2; ++k2) u[k2] = x[k1 * R2 + k2];
@@ -288,9 +297,9 @@ __device__ __forceinline__ void dif_b(cpx<T> *x, int k1) {
     for (int n2 = 0; n2 < R2; ++n2) x[k1 * R2 + n2] = u[n2];
 }
 // dif stage A': item n2 in [0, R2); leaves x[n1 R2 + n2] in out[n1].
-template <int N, int S, class T>
+template <class P, int S, class T>
 __device__ __forceinline__ void dif_a(const cpx<T> *x, int n2, const cpx<T> *tw, cpx<T> *out) {
-    constexpr int R1 = Split<N>::R1, R2 = Split<N>::R2;
+    constexpr int N = P::N, R1 = P::R1, R2 = P::R2;
     out[0] = x[n2];
 #pragma unroll
     for (int k1 = 1; k1 < R1; ++k1) out[k1] = cmul(x[k1 * R2 + n2], twiddle<S>(tw, (n2 * k1) % N));

@@ -91,7 +91,11 @@ struct Tuning {
     int fft_spb = 0;        // sticks per workgroup of the z passes
     int fft_rb = 0;         // row chunk of the plane pass (capped by LDS)
     int tn_split_wgs = 0;   // target workgroup count of a split-K TN launch
+    int fft_r2 = 0;         // second factor R2 of the radix split N = R1 R2 (0: default)
 };
+// radix splits N = R1 R2 available for length n (R2 values) and the default R2
+std::vector<int> fft_radix_splits(int n);
+int fft_default_r2(int n);
 const Tuning &thread_tuning();
 const Tuning *set_thread_tuning(const Tuning *t);   // returns the previous record
 constexpr int kTnSplitMax = 1024;   // largest split target; partial buffers are sized for it
@@ -155,8 +159,12 @@ void launch_resid_precond(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, 
 void launch_build_projectors_f64(const double *qvec, int64_t npw, int natom, const double *pos,
                                  int nlm, const int *lm, double pref, cd *B, int64_t ldb,
                                  hipStream_t st);
+// v_zyx in the layout of radix split r2 (0: the default split)
 void launch_permute_potential(const double *v, int n, double scale, double *v_zyx,
-                              int *bad, hipStream_t st);
+                              int *bad, int r2, hipStream_t st);
+// a permuted potential moved from the layout of split r2_from to that of r2_to
+void launch_repermute_potential(const double *in, int n, int r2_from, int r2_to, double *out,
+                                hipStream_t st);
 // column copy, with conversion when the storage types differ
 void launch_copy_cols(const cd *A, int64_t lda, cd *B, int64_t ldb, int64_t rows, int cols, hipStream_t st);
 void launch_copy_cols(const cf *A, int64_t lda, cf *B, int64_t ldb, int64_t rows, int cols, hipStream_t st);

@@ -121,6 +121,7 @@ struct pw_ctx_s {
     // potential (V / N^3 in [z][y][x]); float copy for the mixed form
     bool has_v = false;
     double *d_v = nullptr;
+    int v_r2 = 0;   // radix split (second factor) whose x-order d_v is stored in
     float *d_v32 = nullptr;
 
     // projectors
@@ -330,6 +331,28 @@ void ensure_mixed_tables(pw_ctx_s *c) {
         c->d_B32 = c->dev_alloc<pw::cf>((size_t)c->ldp * np);
         pw::launch_copy_cols(c->d_B, c->ldp, c->d_B32, c->ldp, c->ldp, np, c->stream);
     }
+}
+
+// R2 of the radix split the context's tuning selects for its grid
+int tuned_r2(const pw_ctx_s *c) { return c->tune.fft_r2 > 0 ? c->tune.fft_r2 : pw::fft_default_r2(c->n); }
+bool split_available(int n, int r2) {
+    const std::vector<int> v = pw::fft_radix_splits(n);
+    return std::find(v.begin(), v.end(), r2) != v.end();
+}
+// keep the stored potential in the x-order of the tuned radix split
+void relayout_potential(pw_ctx_s *c) {
+    if (!c->has_v) return;
+    const int want = tuned_r2(c);
+    if (want == c->v_r2) return;
+    const size_t n3 = (size_t)c->n * c->n * c->n;
+    double *nv = c->dev_alloc<double>(n3);
+    pw::launch_repermute_potential(c->d_v, c->n, c->v_r2, want, nv, c->stream);
+    PW_HIP(hipStreamSynchronize(c->stream));
+    c->dev_free(c->d_v);
+    c->d_v = nv;
+    c->v_r2 = want;
+    c->dev_free(c->d_v32);   // the float copy is rebuilt on the next mixed-form call
+    c->d_v32 = nullptr;
 }
 
 const double *potential_of(const pw_ctx_s *c, const cd *) { return c->d_v; }
@@ -825,7 +848,9 @@ void init_basis(pw_ctx_s *c, const double cell[9], const double kfrac[3], double
     PW_REQUIRE(ecut > 0 && std::isfinite(ecut), PW_ERR_ARG, "ecut must be positive");
     PW_REQUIRE(fft_n[0] == fft_n[1] && fft_n[1] == fft_n[2], PW_ERR_ARG, "FFT grid must be cubic");
     PW_REQUIRE(pw::fft_size_supported(fft_n[0]), PW_ERR_ARG, "unsupported FFT size");
-    // reset everything that depends on the basis
+    // reset everything that depends on the basis (a tuned radix split the new
+    // grid cannot use falls back to the default)
+    if (c->tune.fft_r2 > 0 && !split_available(fft_n[0], c->tune.fft_r2)) c->tune.fft_r2 = 0;
     if (c->device >= 0)
         for (void *p : c->dev_allocs) (void)hipFree(p);
     c->dev_allocs.clear();
@@ -981,7 +1006,10 @@ void set_potential(pw_ctx_s *c, const double *v, int on_device) {
     c->dev_free(c->d_v32);   // the float copy is rebuilt on the next mixed-form call
     c->d_v32 = nullptr;
     PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
-    pw::launch_permute_potential(src, N, 1.0 / (double(N) * N * N), c->d_v, c->d_status, c->stream);
+    const int r2 = tuned_r2(c);
+    PW_REQUIRE(split_available(N, r2), PW_ERR_ARG, "the tuned radix split does not divide this FFT size");
+    pw::launch_permute_potential(src, N, 1.0 / (double(N) * N * N), c->d_v, c->d_status, r2, c->stream);
+    c->v_r2 = r2;
     const int s = read_status(c);
     c->dev_free(tmp);
     PW_HIP(hipMemsetAsync(c->d_status, 0, sizeof(int), c->stream));
@@ -1340,6 +1368,7 @@ pw_status pw_set_tuning(pw_ctx c, const pw_tuning *t) {
     return guard(c, [&] {
         if (!t) {
             c->tune = pw::Tuning{};
+            relayout_potential(c);
             return PW_OK;
         }
         PW_REQUIRE(t->fft_sticks_per_block >= 0 && t->fft_sticks_per_block <= 64, PW_ERR_ARG,
@@ -1348,9 +1377,14 @@ pw_status pw_set_tuning(pw_ctx c, const pw_tuning *t) {
                    "fft_plane_rows must be in [0, 128]");
         PW_REQUIRE(t->gemm_split_workgroups >= 0 && t->gemm_split_workgroups <= pw::kTnSplitMax, PW_ERR_ARG,
                    "gemm_split_workgroups must be in [0, 1024]");
+        PW_REQUIRE(t->fft_radix2 == 0 || (c->n > 0 ? split_available(c->n, t->fft_radix2)
+                                                      : (t->fft_radix2 >= 2 && t->fft_radix2 <= 16)),
+                   PW_ERR_ARG, "fft_radix2 must be 0 or the second factor of an available radix split");
         c->tune.fft_spb = t->fft_sticks_per_block;
         c->tune.fft_rb = t->fft_plane_rows;
         c->tune.tn_split_wgs = t->gemm_split_workgroups;
+        c->tune.fft_r2 = t->fft_radix2;
+        relayout_potential(c);
         return PW_OK;
     });
 }
@@ -1383,7 +1417,8 @@ pw_status pw_autotune(pw_ctx c, int32_t nb, pw_tuning *out) {
             PW_HIP(hipEventElapsedTime(&ms, e0, e1));
             return (double)ms / 5.0;
         };
-        auto apply = [&] { pw::launch_fft_apply(c->sp, c->d_v, p.Z[0], ld, p.HZ[0] + 0, ld, nb, p.Sb, st); };
+        const double *vapply = c->d_v;   // the potential in the layout of the split being timed
+        auto apply = [&] { pw::launch_fft_apply(c->sp, vapply, p.Z[0], ld, p.HZ[0] + 0, ld, nb, p.Sb, st); };
         auto gemm = [&] {
             pw::launch_gemm_tn(p.Z[0], ld, p.HZ[0], ld, npw, nz, nz, p.Agram, nz, nullptr, 0.0, p.part,
                                p.part_elems, st);
@@ -1392,22 +1427,38 @@ pw_status pw_autotune(pw_ctx c, int32_t nb, pw_tuning *out) {
                                    p.part_elems, st);
         };
         c->tune = pw::Tuning{};
+        relayout_potential(c);   // default split
         const double apply_def = timed(apply), gemm_def = timed(gemm);
         pw::Tuning best{};
         double apply_best = apply_def, gemm_best = gemm_def;
         const int spb_c[] = {16, 32, 64}, rb_c[] = {16, 32, 48, 96};
-        for (int spb : spb_c)
-            for (int rb : rb_c) {
-                c->tune = pw::Tuning{};
-                c->tune.fft_spb = spb;
-                c->tune.fft_rb = rb;
-                const double t = timed(apply);
-                if (t < apply_best) {
-                    apply_best = t;
-                    best.fft_spb = spb;
-                    best.fft_rb = rb;
-                }
+        const std::vector<int> r2_c = pw::fft_radix_splits(c->n);
+        const int r2_def = pw::fft_default_r2(c->n);
+        double *vtmp = c->dev_alloc<double>((size_t)c->n * c->n * c->n);
+        for (int r2 : r2_c) {
+            vapply = c->d_v;
+            if (r2 != r2_def) {   // the potential in this split's x-order
+                pw::launch_repermute_potential(c->d_v, c->n, r2_def, r2, vtmp, st);
+                vapply = vtmp;
             }
+            for (int spb : spb_c)
+                for (int rb : rb_c) {
+                    c->tune = pw::Tuning{};
+                    c->tune.fft_spb = spb;
+                    c->tune.fft_rb = rb;
+                    c->tune.fft_r2 = r2 == r2_def ? 0 : r2;
+                    const double t = timed(apply);
+                    if (t < apply_best) {
+                        apply_best = t;
+                        best.fft_spb = spb;
+                        best.fft_rb = rb;
+                        best.fft_r2 = c->tune.fft_r2;
+                    }
+                }
+        }
+        PW_HIP(hipStreamSynchronize(st));
+        c->dev_free(vtmp);
+        vapply = c->d_v;
         const int split_c[] = {384, 512, 768, 1024};
         for (int sw : split_c) {
             c->tune = pw::Tuning{};
@@ -1419,11 +1470,13 @@ pw_status pw_autotune(pw_ctx c, int32_t nb, pw_tuning *out) {
             }
         }
         c->tune = best;
+        relayout_potential(c);
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         out->fft_sticks_per_block = best.fft_spb;
         out->fft_plane_rows = best.fft_rb;
         out->gemm_split_workgroups = best.tn_split_wgs;
+        out->fft_radix2 = best.fft_r2;
         out->apply_ms_default = apply_def;
         out->apply_ms_tuned = apply_best;
         out->gemm_ms_default = gemm_def;

@@ -168,3 +168,26 @@ def test_served_worker_failure_releases_its_slot():
     assert summary["failed"] == 1 and not summary["all_converged"]
     assert results[1]["error"].startswith("RuntimeError")
     assert all(results[i]["error"] is None for i in (0, 2, 3))
+
+
+def test_radix_split_tuning_is_checked_on_the_host():
+    """fft_radix2 must be 0 or a second factor R2 of N = R1 R2 with both factors in
+    [2, 16] made of 2, 3, 5; a basis change drops a split the new grid cannot use."""
+    from paper_0707_3405_amd import Context, PWError, PW_ERR_ARG
+    w = make_workload("gamma_l10")            # N = 24
+    ctx = Context(-1)
+    ctx.init_basis(w.cell, w.kfrac, w.ecut, (w.n,) * 3)
+    for bad in (1, 5, 7, 24, 17):
+        with pytest.raises(PWError) as e:
+            ctx.set_tuning(fft_radix2=bad)
+        assert e.value.status == PW_ERR_ARG
+    for ok in (2, 3, 4, 6, 8, 12):
+        ctx.set_tuning(fft_radix2=ok)
+    ctx.set_tuning(fft_radix2=12)
+    w2 = make_workload("mid_nl")              # N = 36: 12 divides, so it stays
+    ctx.init_basis(w2.cell, w2.kfrac, w2.ecut, (w2.n,) * 3)
+    ctx.set_tuning(fft_radix2=9)              # 36 = 4 x 9
+    w3 = make_workload("tiny_nl")             # N = 20: 9 does not divide it: back to the default
+    ctx.init_basis(w3.cell, w3.kfrac, w3.ecut, (w3.n,) * 3)
+    ctx.set_tuning(fft_radix2=5)
+    ctx.close()

@@ -69,3 +69,75 @@ def test_same_tuning_same_result(torch_cuda):
         prob.ctx.set_tuning(fft_sticks_per_block=65)
     assert e.value.status == PW_ERR_ARG
     prob.ctx.set_tuning(reset=True)
+
+
+@pytest.mark.parametrize("name", ["gamma_l10", "fcc32_l12"])
+def test_every_radix_split_matches_the_oracle(torch_cuda, oracle_problem, name):
+    """Every radix split N = R1 R2 of the grid (24: R2 in 2..12; 48: R2 in 3..16) gives
+    the local + non-local H.X of the oracle's matrix-free operator to 1e-13 ||H|| ||x||
+    (FP64) and 1e-6 (complex64), with the potential moved into each split's order;
+    switching back to the default split gives the default result bitwise."""
+    torch = torch_cuda
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_MIXED
+    from workloads import start_block
+    w, mil, _, mf = oracle_problem(name, dense=False)
+    prob = PlaneWaveProblem.from_workload(w, device=0, nbands=16, block=16, prec=PW_PREC_MIXED)
+    X = start_block(8, mil.shape[0], 16)
+    ref = mf.apply(X)
+    hn = w.ecut + np.abs(w.vgrid).max() + (np.abs(w.D).sum() if w.D is not None else 0.0)
+    Xd = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+    Ydef = torch.empty_like(Xd)
+    prob.ctx.apply_H(Xd, Ydef)
+    splits = [r for r in range(2, 17) if w.n % r == 0 and 2 <= w.n // r <= 16
+              and all(f in (2, 3, 5) for f in _factors(r) + _factors(w.n // r))]
+    assert len(splits) >= 2
+    for r2 in splits:
+        prob.ctx.set_tuning(fft_radix2=r2)
+        Y = torch.empty_like(Xd)
+        prob.ctx.apply_H(Xd, Y)
+        X32 = Xd.to(torch.complex64)
+        Y32 = torch.empty_like(X32)
+        prob.ctx.apply_H(X32, Y32, prec=PW_PREC_MIXED)
+        torch.cuda.synchronize()
+        err = np.linalg.norm(Y.cpu().numpy().T - ref, axis=0) / (hn * np.linalg.norm(X, axis=0))
+        x32 = X32.cpu().numpy().T.astype(np.complex128)
+        err32 = (np.linalg.norm(Y32.cpu().numpy().T - mf.apply(x32), axis=0)
+                 / (hn * np.linalg.norm(x32, axis=0)))
+        print(f"{name} N={w.n} R2={r2}: FP64 {err.max():.2e} complex64 {err32.max():.2e}")
+        assert err.max() <= 1e-13 and err32.max() <= 1e-6
+    prob.ctx.set_tuning(reset=True)
+    Yb = torch.empty_like(Xd)
+    prob.ctx.apply_H(Xd, Yb)
+    torch.cuda.synchronize()
+    assert torch.equal(Yb, Ydef)
+
+
+def _factors(n):
+    out, p = [], 2
+    while n > 1:
+        while n % p == 0:
+            out.append(p)
+            n //= p
+        p += 1
+    return out
+
+
+def test_solve_with_a_non_default_split(torch_cuda):
+    """A solve on a context tuned to another radix split (set before the potential)
+    matches the oracle's eigenvalues."""
+    torch = torch_cuda
+    from paper_0707_3405_amd import Context
+    from workloads import make_workload
+    w = make_workload("mid_nl")   # 36^3: default 6 x 6, here 9 x 4
+    ctx = Context(0)
+    ctx.init_basis(w.cell, w.kfrac, w.ecut, (w.n,) * 3)
+    ctx.set_tuning(fft_radix2=4)
+    ctx.set_local_potential(w.vgrid)
+    ctx.set_projectors(w.pos, w.lm, w.D)
+    ws = ctx.alloc_workspace(w.nbands, w.block)
+    X = torch.zeros((w.nbands, ctx.npw), dtype=torch.complex128, device="cuda")
+    eig, _ = ctx.lobpcg_solve(w.nbands, w.block, w.tol, 300, X)
+    torch.cuda.synchronize()
+    ref = load_golden("mid_nl")[0][:w.nbands]
+    assert np.abs(eig - ref).max() <= 1e-8
+    del ws
