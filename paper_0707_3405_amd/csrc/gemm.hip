@@ -569,11 +569,21 @@ int device_cu_count() {
     return n;
 }
 
-int choose_split(int64_t K, int tiles, int target) {
-    int64_t ns = (target + tiles - 1) / tiles;
-    // chunks of at least 16 k-blocks, except for short K (coefficient-space
-    // products, K = 3m), which split down to single k-blocks (at most 16)
-    const int64_t kmax = std::max<int64_t>((K + 255) / 256, std::min<int64_t>((K + 15) / 16, 16));
+// for_size: an upper bound over every device (sizing the partial buffer on any
+// context, host-only ones included), without the CU-count cap
+int choose_split(int64_t K, int tiles, int target, bool for_size = false) {
+    // outputs of one or two 64 x 64 tiles (the CholQR Grams and the overlaps with
+    // [X P]) have too little work per k-block for several workgroups per CU: one
+    // round of at most one workgroup per CU, chunks of at least 4 k-blocks
+    const bool small = tiles <= 2;
+    const int64_t cap = (small && !for_size) ? std::min<int64_t>(target, device_cu_count()) : target;
+    int64_t ns = (small && !for_size) ? cap / tiles : (cap + tiles - 1) / tiles;
+    // chunks of at least 16 k-blocks (4 for small outputs), except for short K
+    // (coefficient-space products, K = 3m), which split down to single k-blocks
+    // (at most 16)
+    const int64_t minkb = small ? 4 : 16;
+    const int64_t kmax = std::max<int64_t>((K + 16 * minkb - 1) / (16 * minkb),
+                                           std::min<int64_t>((K + 15) / 16, 16));
     if (ns > kmax) ns = kmax;
     if (ns < 1) ns = 1;
     return (int)ns;
@@ -583,7 +593,7 @@ int choose_split(int64_t K, int tiles, int target) {
 
 size_t gemm_tn_part_elems(int64_t K, int p, int q, int *nsplit_out) {
     const int tiles = ((p + kTile - 1) / kTile) * ((q + kTile - 1) / kTile);
-    const int ns = choose_split(K, tiles, std::max(PW_SPLIT_WGS, kTnSplitMax));   // any tuned target fits
+    const int ns = choose_split(K, tiles, std::max(PW_SPLIT_WGS, kTnSplitMax), true);   // any tuned target fits
     if (nsplit_out) *nsplit_out = ns;
     return (size_t)ns * p * q;
 }
