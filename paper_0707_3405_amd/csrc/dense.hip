@@ -489,7 +489,8 @@ __global__ void __launch_bounds__(1024)
                 const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
                 beta = alpha.x >= 0.0 ? -nrm : nrm;
                 const double dr = alpha.x - beta, di = alpha.y;
-                const double ib = 1.0 / beta, iden = 1.0 / (dr * dr + di * di);   // independent
+                // refined hardware reciprocals (within an ulp) instead of two divisions
+                const double ib = rcp_nr(beta), iden = rcp_nr(dr * dr + di * di);   // independent
                 tau = cd{-dr * ib, -alpha.y * ib};
                 scale = cd{dr * iden, -di * iden};
             }
@@ -556,23 +557,30 @@ __global__ void __launch_bounds__(1024)
         if (t < 4 * NR) {
             const int r = t >> 2, q = t & 3;
             const bool live = r > j && r < n;
+            // the ten partials of this thread in two interleaved chains (half the add
+            // latency of one chain, few values live), then the quad
             double sr = 0.0, si = 0.0;
             if (live) {
+                double er = 0.0, ei = 0.0;
                 if (r < 32 * (T - 1)) {   // the last row tile has no tile below the diagonal
 #pragma unroll
-                    for (int h = 0; h < 8; ++h) {
+                    for (int h = 0; h < 8; h += 2) {
                         sr += pc[8 * q + h][r].x;
                         si += pc[8 * q + h][r].y;
+                        er += pc[8 * q + h + 1][r].x;
+                        ei += pc[8 * q + h + 1][r].y;
                     }
                 }
-                sr += pr[2 * q][r].x + pr[2 * q + 1][r].x;
-                si += pr[2 * q][r].y + pr[2 * q + 1][r].y;
+                sr += pr[2 * q][r].x + er;
+                si += pr[2 * q][r].y + ei;
+                sr += pr[2 * q + 1][r].x;
+                si += pr[2 * q + 1][r].y;
             }
             sr = quad_sum(sr);
             si = quad_sum(si);
-            double vhy = 0.0;
-#pragma unroll
-            for (int w = 0; w < 16; ++w) vhy += sv[w];
+            // v^H A v: a quarter of the wave partials per thread, then the quad
+            double vhy = (sv[4 * q] + sv[4 * q + 1]) + (sv[4 * q + 2] + sv[4 * q + 3]);
+            vhy = quad_sum(vhy);
             const cd tau = s_tau;
             const double nu = 0.5 * (tau.x * tau.x + tau.y * tau.y) * vhy;
             if (live && q == 0) {
