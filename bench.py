@@ -33,9 +33,10 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE (scaled by a plain-copy
-# calibration; profiles/hbm_bytes_fcc108_l20.txt) for the kernels as they were profiled;
+# calibration; profiles/hbm_bytes_fcc108_l20.txt) for the kernels as they were profiled,
+# over the same kernels as the launch time (the Grams include k_reduce_parts);
 # set an entry to None when its kernels change.
-TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 2.96e8, "dense": 5.15e6}
+TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 3.63e8, "gemm_complex64": 1.84e8, "dense": 5.16e6}
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
 FP32_PEAK_TFLOPS = 157.3       # MI355X dense FP32 (matrix)
 WORKLOAD = "fcc108_l20"
@@ -388,7 +389,8 @@ def main():
         "gemm_complex64": dict(bound="mfma", kernel="k_gemm_tn_lds<float> (+k_reduce_parts), Rayleigh-Ritz "
                                "Gram 192x192, K=34181, complex64 blocks on FP32 MFMA",
                                achieved=gram32_tflops, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s",
-                               frac=gram32_tflops / FP32_PEAK_TFLOPS, traffic=None,
+                               frac=gram32_tflops / FP32_PEAK_TFLOPS,
+                               traffic=TRAFFIC_MEASURED["gemm_complex64"],
                                algorithmic=f"{gram_flops:.3e} FLOP per launch (8 p q K)",
                                launch_ms=t_gram32),
         "apply": dict(bound="hbm", kernel="k_zinv + k_plane + k_zfwd (local H.X, 64 bands)",
