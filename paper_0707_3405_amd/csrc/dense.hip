@@ -30,6 +30,12 @@ __device__ __forceinline__ double rcp_nr(double d) {
     return r;
 }
 
+// value of v in lane `lane` (uniform), as a wave-uniform value
+__device__ __forceinline__ double lane_read(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
 // Block-wide sum of one double per thread: wave shuffles, then the wave
 // partials added in wave order by every thread (deterministic, 2 barriers).
 __device__ double block_sum(double v, double *red) {
@@ -188,8 +194,9 @@ __global__ void __launch_bounds__(1024) k_chol_inv(const cd *__restrict__ G, int
 // Five stages on the stream:
 //   reduction  A = Q T Q^H, T real tridiagonal (lower Householder):
 //              k_hetrd_rf (1 workgroup, n <= 192) or k_trd_apply + k_trd_step
-//   k_stebz    (k groups)      lowest k eigenvalues of T by 512-point multisection
-//   k_stein    (k/E groups)    eigenvectors of T by inverse iteration, LU in LDS
+//   k_stebz_w / k_stebz (k groups)  lowest k eigenvalues of T by 512-point multisection
+//   k_stein_w  (k waves)       eigenvectors of T by inverse iteration, in registers (n <= 256)
+//   k_stein    (k/E groups)    the same with the LU in LDS (n > 256)
 //   k_orth_chol2 / k_orth_chol / k_orth (1 workgroup)  re-orthogonalisation
 //   k_unmtr_w / k_unmtr (k/cw groups)  back-transform V = Q Z
 //
@@ -417,11 +424,23 @@ __device__ __forceinline__ double quad_sum(double x) {
     x += dpp_f64<0x4E>(x);
     return x;
 }
-__device__ __forceinline__ double wave_sum(double x) {
+// lanes whose DPP row is disabled by ROW_MASK read 0
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64_rows(double x) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+// Wave sum returned as a wave-uniform value, without LDS: the row sums, then
+// row_bcast:15 adds row 0 into row 1 and row 2 into row 3, row_bcast:31 adds
+// rows 0 + 1 into rows 2 and 3, and lane 63 holds the total (same order of
+// additions in every wave).
+__device__ __forceinline__ double wave_total(double x) {
     x = row16_sum(x);
-    x += __shfl_xor(x, 16);
-    x += __shfl_xor(x, 32);
-    return x;
+    x += dpp_f64_rows<0x142, 0xA>(x);   // row_bcast:15
+    x += dpp_f64_rows<0x143, 0xC>(x);   // row_bcast:31
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 63),
+                            __builtin_amdgcn_readlane(__double2loint(x), 63));
 }
 
 template <int T>
@@ -477,7 +496,7 @@ __global__ void __launch_bounds__(1024)
         if (wave == 0) {
             double sg = 0.0;
             for (int r = j + 2 + lane; r < n; r += 64) sg += xs[r].x * xs[r].x + xs[r].y * xs[r].y;
-            const double sigma = wave_sum(sg);
+            const double sigma = wave_total(sg);
             const cd alpha = xs[j + 1];
             cd tau, scale;
             double beta;
@@ -549,7 +568,7 @@ __global__ void __launch_bounds__(1024)
                 vpart += vj.x * cr + vj.y * ci;
                 pc[ti][tj + 32 * b] = cd{cr, ci};
             });
-            vpart = wave_sum(vpart);
+            vpart = wave_total(vpart);
             if (lane == 0) sv[wave] = vpart;
         }
         __syncthreads();
@@ -708,6 +727,87 @@ __global__ void __launch_bounds__(kStebzThreads) k_stebz(const double *__restric
     if (t == 0) w[idx] = 0.5 * (lo + hi);
 }
 
+// The same multisection with d_i and e_{i-1}^2 held in registers of every wave
+// (entry i in lane i % 64, slot i / 64) and read with readlane, so the Sturm
+// chains never wait on LDS; the bounds come from wave reductions (min / max,
+// exact in any order).  Same points, counts and rounds as k_stebz.  n <= 64 RPL.
+template <int RPL>
+__global__ void __launch_bounds__(kStebzThreads) k_stebz_w(const double *__restrict__ dd,
+                                                           const double *__restrict__ ee, int n, int /*k*/,
+                                                           double *__restrict__ w) {
+    __shared__ int wfirst[2][kStebzThreads / 64];
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+    constexpr int NP = 2 * kStebzThreads;
+    double dreg[RPL], e2reg[RPL];
+    double gl = DBL_MAX, gu = -DBL_MAX, tnorm = 0.0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int i = lane + 64 * q;
+        dreg[q] = i < n ? dd[i] : 0.0;
+        e2reg[q] = (i >= 1 && i < n) ? ee[i - 1] * ee[i - 1] : 0.0;
+        if (i < n) {
+            const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
+            gl = fmin(gl, dd[i] - r);
+            gu = fmax(gu, dd[i] + r);
+            tnorm = fmax(tnorm, fabs(dd[i]) + r);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        gl = fmin(gl, __shfl_xor(gl, off));
+        gu = fmax(gu, __shfl_xor(gu, off));
+        tnorm = fmax(tnorm, __shfl_xor(tnorm, off));
+    }
+    const double pivmin = DBL_MIN * fmax(1.0, tnorm * tnorm);
+    {
+        const double span = fmax(gu - gl, DBL_EPSILON * fmax(1.0, tnorm));
+        gl = gl - 2.0 * DBL_EPSILON * span - 1e-300;
+        gu = gu + 2.0 * DBL_EPSILON * span + 1e-300;
+    }
+    const int idx = blockIdx.x;
+    double lo = gl, hi = gu;
+    for (int round = 0; round < 16; ++round) {
+        const double width = hi - lo;
+        if (width <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+        const double x1 = lo + width * (double)(t + 1) / (double)(NP + 1);
+        const double x2 = lo + width * (double)(t + 1 + kStebzThreads) / (double)(NP + 1);
+        // Sturm counts at x1 and x2 (the recurrence of sturm_count2)
+        int c1 = 0, c2 = 0;
+        double q1 = lane_read(dreg[0], 0) - x1, q2 = lane_read(dreg[0], 0) - x2;
+        if (fabs(q1) < pivmin) q1 = -pivmin;
+        if (fabs(q2) < pivmin) q2 = -pivmin;
+        c1 += q1 < 0;
+        c2 += q2 < 0;
+        unroll_for<0, RPL>([&](auto q_) {
+            constexpr int q = q_;
+            const int lim = min(64, n - 64 * q);
+            for (int l = q == 0 ? 1 : 0; l < lim; ++l) {
+                const double di = lane_read(dreg[q], l), ei = lane_read(e2reg[q], l);
+                q1 = di - x1 - ei * rcp_nr(q1);
+                q2 = di - x2 - ei * rcp_nr(q2);
+                if (fabs(q1) < pivmin) q1 = -pivmin;
+                if (fabs(q2) < pivmin) q2 = -pivmin;
+                c1 += q1 < 0;
+                c2 += q2 < 0;
+            }
+        });
+        const uint64_t b1 = __ballot(c1 > idx), b2 = __ballot(c2 > idx);
+        const int buf = round & 1;
+        if (lane == 0) {
+            wfirst[buf][wave] = b1 ? 64 * wave + __ffsll((unsigned long long)b1) - 1
+                                   : (b2 ? kStebzThreads + 64 * wave + __ffsll((unsigned long long)b2) - 1
+                                         : NP);
+        }
+        __syncthreads();
+        int first = NP;
+        for (int q = 0; q < kStebzThreads / 64; ++q) first = min(first, wfirst[buf][q]);
+        const double nlo = first == 0 ? lo : lo + width * (double)first / (double)(NP + 1);
+        const double nhi = first == NP ? hi : lo + width * (double)(first + 1) / (double)(NP + 1);
+        lo = nlo;
+        hi = nhi;
+    }
+    if (t == 0) w[idx] = 0.5 * (lo + hi);
+}
+
 // Inverse iteration: one thread per eigenvalue, E eigenvalues per workgroup,
 // the LU factors of T - lambda I and the iterate in LDS, interleaved [i][e].
 __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
@@ -833,6 +933,148 @@ __global__ void __launch_bounds__(64) k_stein(const double *__restrict__ dd,
     // so its squares stay far from overflow)
     const double inv = n2 > 0 ? 1.0 / sqrt(n2) : 1.0;
     for (int i = 0; i < n; ++i) Z[(int64_t)i * k + idx] = at(ZZ, i) * inv;
+}
+
+// Inverse iteration, one eigenvalue per wave, with no memory access inside the
+// recurrences: every lane runs the same (wave-uniform) LU factorisation and
+// solves, entry i of each per-step array (the LU factors, the iterate, d and e)
+// is kept by lane i % 64 in register slot i / 64, written with a lane select and
+// read back with readlane.  The arithmetic and its order are those of k_stein
+// (LU with partial pivoting of T - lambda I in dlagtf order, two solves from a
+// hashed start vector, unit 2-norm), with the pivot choice taken by selects.
+// n <= 64 RPL.
+template <int RPL>
+__global__ void __launch_bounds__(64) k_stein_w(const double *__restrict__ dd,
+                                                const double *__restrict__ ee, int n, int k,
+                                                const double *__restrict__ w, double *__restrict__ Z) {
+    const int L = threadIdx.x;
+    const int idx = blockIdx.x;
+    double dv[RPL], ev[RPL];   // d_i and e_i (e_{n-1} = 0) of entry i = L + 64 q
+    double tn = 0.0;           // max_i |d_i| + |e_{i-1}| + |e_i|, as in tri_bounds
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int i = L + 64 * q;
+        dv[q] = i < n ? dd[i] : 0.0;
+        ev[q] = i + 1 < n ? ee[i] : 0.0;
+        if (i < n) {
+            const double r = (i > 0 ? fabs(ee[i - 1]) : 0.0) + (i + 1 < n ? fabs(ee[i]) : 0.0);
+            tn = fmax(tn, fabs(dd[i]) + r);
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) tn = fmax(tn, __shfl_xor(tn, off));
+    const double lam = w[idx];
+    const double eps_t = DBL_EPSILON * fmax(tn, 1e-300);
+    double fdd[RPL], fdl[RPL], fdu[RPL], fdu2[RPL], zz[RPL];
+    int fpiv[RPL];
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        fdd[q] = fdl[q] = fdu[q] = fdu2[q] = 0.0;
+        fpiv[q] = 0;
+        const int i = L + 64 * q;
+        uint64_t h = (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull ^ (uint64_t)(idx + 7) * 0xD1B54A32D192ED03ull;
+        h ^= h >> 31;
+        h *= 0xBF58476D1CE4E5B9ull;
+        h ^= h >> 29;
+        zz[q] = (double)(h >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+    }
+    // ---- LU of T - lambda I: step i eliminates row i + 1 ----
+    double d_cur = lane_read(dv[0], 0) - lam, u_cur = lane_read(ev[0], 0), sub = u_cur;
+    // step i (slot Q, lane l) with the entries i + 1 read from slot QN, lane ln
+    auto lu_step = [&](auto Q_, auto QN_, int l, int ln) {
+        constexpr int Q = decltype(Q_)::value, QN = decltype(QN_)::value;
+        double d_nx = 0.0, u_nx = 0.0;
+        if constexpr (QN < RPL) {
+            d_nx = lane_read(dv[QN], ln) - lam;
+            u_nx = lane_read(ev[QN], ln);
+        }
+        const bool piv = fabs(d_cur) < fabs(sub);
+        const double dp = fabs(d_cur) < eps_t ? (d_cur < 0 ? -eps_t : eps_t) : d_cur;
+        const double r = rcp_nr(piv ? sub : dp);
+        const double m = (piv ? d_cur : sub) * r;
+        const double du = piv ? d_nx : u_cur;
+        const bool me = L == l;
+        fdd[Q] = me ? r : fdd[Q];
+        fdl[Q] = me ? m : fdl[Q];
+        fdu[Q] = me ? du : fdu[Q];
+        fdu2[Q] = me ? (piv ? u_nx : 0.0) : fdu2[Q];
+        fpiv[Q] = me ? (int)piv : fpiv[Q];
+        d_cur = fma(-m, du, piv ? u_cur : d_nx);
+        u_cur = piv ? -m * u_nx : u_nx;
+        sub = u_nx;
+    };
+    unroll_for<0, RPL>([&](auto q_) {
+        constexpr int q = q_;
+        const int lim = min(63, n - 1 - 64 * q);   // steps i = 64 q + l <= n - 2 with i + 1 in slot q
+        for (int l = 0; l < lim; ++l) lu_step(std::integral_constant<int, q>{}, std::integral_constant<int, q>{}, l, l + 1);
+        if (64 * q + 63 < n - 1)
+            lu_step(std::integral_constant<int, q>{}, std::integral_constant<int, q + 1>{}, 63, 0);
+    });
+    {   // row n - 1
+        const int qn = (n - 1) >> 6, ln = (n - 1) & 63;
+        const double r = 1.0 / (fabs(d_cur) < eps_t ? eps_t : d_cur);
+        const bool me = L == ln;
+#pragma unroll
+        for (int q = 0; q < RPL; ++q) {
+            if (q != qn) continue;
+            fdd[q] = me ? r : fdd[q];
+            fdu[q] = me ? 0.0 : fdu[q];
+            fdu2[q] = me ? 0.0 : fdu2[q];
+            fpiv[q] = me ? 0 : fpiv[q];
+        }
+    }
+    // ---- two solves; the first one's 1 / max-norm is applied as the second reads it ----
+    double scale = 1.0, n2 = 0.0;
+    for (int iter = 0; iter < 2; ++iter) {
+        // L solve with the row interchanges: z is the running entry of row i
+        double z = lane_read(zz[0], 0) * scale;
+        auto l_step = [&](auto Q_, auto QN_, int l, int ln) {
+            constexpr int Q = decltype(Q_)::value, QN = decltype(QN_)::value;
+            double znx = 0.0;
+            if constexpr (QN < RPL) znx = lane_read(zz[QN], ln) * scale;
+            const double lm = lane_read(fdl[Q], l);
+            const bool piv = __builtin_amdgcn_readlane(fpiv[Q], l) != 0;
+            const double out = piv ? znx : z;
+            zz[Q] = L == l ? out : zz[Q];
+            z = fma(-lm, out, piv ? z : znx);
+        };
+        unroll_for<0, RPL>([&](auto q_) {
+            constexpr int q = q_;
+            const int lim = min(63, n - 1 - 64 * q);
+            for (int l = 0; l < lim; ++l) l_step(std::integral_constant<int, q>{}, std::integral_constant<int, q>{}, l, l + 1);
+            if (64 * q + 63 < n - 1)
+                l_step(std::integral_constant<int, q>{}, std::integral_constant<int, q + 1>{}, 63, 0);
+        });
+        {
+            const int qn = (n - 1) >> 6, ln = (n - 1) & 63;
+#pragma unroll
+            for (int q = 0; q < RPL; ++q)
+                if (q == qn) zz[q] = L == ln ? z : zz[q];
+        }
+        // U solve from the bottom; z1, z2 are the two entries below
+        double nrm = 0.0, z1 = 0.0, z2 = 0.0;
+        n2 = 0.0;
+        unroll_for<0, RPL>([&](auto qr_) {
+            constexpr int q = RPL - 1 - decltype(qr_)::value;
+            const int top = min(63, n - 1 - 64 * q);
+            for (int l = top; l >= 0; --l) {
+                const double zi = lane_read(zz[q], l), du = lane_read(fdu[q], l), du2 = lane_read(fdu2[q], l),
+                             rd = lane_read(fdd[q], l);
+                const double sv = (zi - du * z1 - du2 * z2) * rd;
+                zz[q] = L == l ? sv : zz[q];
+                nrm = fmax(nrm, fabs(sv));
+                n2 += sv * sv;
+                z2 = z1;
+                z1 = sv;
+            }
+        });
+        scale = nrm > 0 ? 1.0 / nrm : 1.0;
+    }
+    const double inv = n2 > 0 ? 1.0 / sqrt(n2) : 1.0;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+        const int i = L + 64 * q;
+        if (i < n) Z[(int64_t)i * k + idx] = zz[q] * inv;
+    }
 }
 
 // Gram-Schmidt (twice) of the columns of Z [n][k] in eigenvalue order.  In
@@ -1230,7 +1472,7 @@ __global__ void __launch_bounds__(1024) k_orth_chol2(double *__restrict__ Zg, in
 }
 
 // V[:, c] = H_0 ... H_{n-2} Z[:, c] for n <= 64 RPL: one wave per kUwCols
-// columns, RPL rows per lane, column sums by DPP and shuffles, no barriers.
+// columns, RPL rows per lane, column sums by DPP alone (wave_total), no barriers.
 // Reflectors are applied in groups of kUwRing with a ring of kUwRing
 // reflectors loaded ahead, so the loads of one group overlap the work of the
 // previous one.
@@ -1285,8 +1527,8 @@ __global__ void __launch_bounds__(64) k_unmtr_w(const cd *__restrict__ A, int64_
                     dr += v[q].x * x[q][c].x + v[q].y * x[q][c].y;
                     di += v[q].x * x[q][c].y - v[q].y * x[q][c].x;
                 }
-                dr = wave_sum(dr);
-                di = wave_sum(di);
+                dr = wave_total(dr);
+                di = wave_total(di);
                 const cd sc = cmulz(tj, cd{dr, di});
 #pragma unroll
                 for (int q = 0; q < RPL; ++q) {
@@ -1375,14 +1617,29 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     // 2. eigenvalues
     const size_t sm2 = 2 * (size_t)n * 8;
     // one workgroup per eigenvalue, spread over k CUs
-    hipLaunchKernelGGL(k_stebz, dim3(k), dim3(kStebzThreads), sm2, st, d, e, n, k, w);
+    switch ((n + 63) / 64) {
+        case 1: hipLaunchKernelGGL(k_stebz_w<1>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w); break;
+        case 2: hipLaunchKernelGGL(k_stebz_w<2>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w); break;
+        case 3: hipLaunchKernelGGL(k_stebz_w<3>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w); break;
+        case 4: hipLaunchKernelGGL(k_stebz_w<4>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w); break;
+        default: hipLaunchKernelGGL(k_stebz, dim3(k), dim3(kStebzThreads), sm2, st, d, e, n, k, w); break;
+    }
     // 3. inverse iteration
+    if (n <= 256) {
+        switch ((n + 63) / 64) {
+            case 1: hipLaunchKernelGGL(k_stein_w<1>, dim3(k), dim3(64), 0, st, d, e, n, k, w, Z); break;
+            case 2: hipLaunchKernelGGL(k_stein_w<2>, dim3(k), dim3(64), 0, st, d, e, n, k, w, Z); break;
+            case 3: hipLaunchKernelGGL(k_stein_w<3>, dim3(k), dim3(64), 0, st, d, e, n, k, w, Z); break;
+            default: hipLaunchKernelGGL(k_stein_w<4>, dim3(k), dim3(64), 0, st, d, e, n, k, w, Z); break;
+        }
+    } else {
     const size_t budget = 150 * 1024;
     int E = (int)((budget - 16 * (size_t)n) / (48 * (size_t)n));
     E = std::max(1, std::min(4, E));   // few eigenvalues per workgroup: spread over CUs
     const size_t sm3 = 16 * (size_t)n + 48 * (size_t)n * E;
     ensure_smem_limit((const void *)k_stein, sm3);
     hipLaunchKernelGGL(k_stein, dim3((k + E - 1) / E), dim3(64), sm3, st, d, e, n, k, E, w, Z);
+    }
     // 4. orthogonalisation
     const size_t smc = ((size_t)n * (k + 1) + (size_t)k * (k + 1) + k) * 8;
     if (k <= 64 && orth_chol2_lds(n) <= 150 * 1024) {
