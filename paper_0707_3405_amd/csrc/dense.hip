@@ -193,7 +193,7 @@ __global__ void __launch_bounds__(1024) k_chol_inv(const cd *__restrict__ G, int
 // ---- Hermitian eigensolver ---------------------------------------------------
 // Five stages on the stream:
 //   reduction  A = Q T Q^H, T real tridiagonal (lower Householder):
-//              k_hetrd_rf (1 workgroup, n <= 192) or k_trd_apply + k_trd_step
+//              k_hetrd_la (1 workgroup, n <= 192) or k_trd_apply + k_trd_step
 //   k_stebz_w / k_stebz (k groups)  lowest k eigenvalues of T by 512-point multisection
 //   k_stein_w  (k waves)       eigenvectors of T by inverse iteration, in registers (n <= 256)
 //   k_stein    (k/E groups)    the same with the LU in LDS (n > 256)
@@ -385,16 +385,12 @@ __global__ void __launch_bounds__(1024)
 }
 
 // ---- register-resident reduction for n <= 32 T (T <= 6) ----------------------
-// The same Householder sequence as k_trd_apply / k_trd_step,
-// but the whole matrix stays in registers: 1024 threads on a 32 x 32 grid,
-// thread (ti, tj) holds A(ti + 32a, tj + 32b) for tiles b <= a.  Off-diagonal
-// tiles are stored once and used for both triangles of y = A v; diagonal tiles
-// are stored in full.  Per column: the pivot column goes to LDS, one wave
-// forms the reflector, every thread accumulates its tiles' row and column
-// partials of y (row sums over lane quads by DPP, column sums per half-wave, both in LDS),
-// four threads per row add the partials into w, and every thread applies the
-// rank-2 update to its tiles.  Tiles whose rows or columns are all finished
-// are skipped.  All sums run in a fixed order (deterministic).
+// The same Householder sequence as k_trd_apply / k_trd_step, but the whole
+// matrix stays in registers: 1024 threads on a 32 x 32 grid, each holding one
+// element of every tile b <= a (off-diagonal tiles are stored once and used
+// for both triangles of y = A v; diagonal tiles are stored in full).  Tiles
+// whose rows or columns are all finished are skipped.  All sums run in a fixed
+// order (deterministic).  The kernel is k_hetrd_la below.
 constexpr int kRfMaxT = 6;
 
 template <int B, int E, class F>
@@ -443,21 +439,29 @@ __device__ __forceinline__ double wave_total(double x) {
                             __builtin_amdgcn_readlane(__double2loint(x), 63));
 }
 
+// Look-ahead form of the register-resident reduction (same Householder
+// sequence and storage of the reflectors): thread (ti, tj) = (t % 32, t / 32)
+// holds A(ti + 32a, tj + 32b) for tiles b <= a, so column c of the matrix is
+// held by the 32 lanes of one half-wave.  Step j: every wave applies the rank-2
+// update of step j - 1 to its live tiles; the wave holding column j does so
+// with raised priority, then forms reflector j from its own registers (norm by
+// DPP over the half-wave) and writes it to LDS while the other waves are still
+// updating.  Then the partials of y = A v (row partials one per half-wave,
+// column partials summed over lane quads by DPP, both in LDS) and w = tau y -
+// nu v by four threads per row: three barriers per column instead of four.
 template <int T>
 __global__ void __launch_bounds__(1024)
-    k_hetrd_rf(cd *__restrict__ A, int64_t lda, int n, double *__restrict__ dd,
+    k_hetrd_la(cd *__restrict__ A, int64_t lda, int n, double *__restrict__ dd,
                double *__restrict__ ee, cd *__restrict__ tau_out) {
     constexpr int NR = 32 * T;
     constexpr int NE = T * (T + 1) / 2;
-    __shared__ cd xs[NR];        // pivot column
-    __shared__ cd vs[NR];        // reflector, zero outside rows j+1..n-1
-    __shared__ cd ws[NR];        // w, zero outside rows j+1..n-1
-    __shared__ cd pr[8][NR];     // row sums of y, one per lane quad of a half-wave
-    __shared__ cd pc[32][NR + 1];   // column sums of y, one per half-wave (padded: the
-                                    // four readers of a row hit different banks)
-    __shared__ double sv[16];    // per-wave partials of Re(v^H A v)
-    __shared__ cd s_tau;
-    const int t = threadIdx.x, tj = t & 31, ti = t >> 5, wave = t >> 6, lane = t & 63;
+    __shared__ cd vs[2][NR];          // reflectors of steps of both parities
+    __shared__ cd ws[NR];             // w of the last step, zero outside its live rows
+    __shared__ cd pr[32][NR + 1];     // row sums of y, one per half-wave (padded)
+    __shared__ cd pc[8][NR + 1];      // column sums of y, one per lane quad (padded)
+    __shared__ double sv[16];         // per-wave partials of Re(v^H A v)
+    __shared__ cd s_tau[2];
+    const int t = threadIdx.x, ti = t & 31, tj = t >> 5, wave = t >> 6, lane = t & 63;
 
     cd E[NE];
     unroll_for<0, T>([&](auto a_) {
@@ -474,30 +478,64 @@ __global__ void __launch_bounds__(1024)
             E[a * (a + 1) / 2 + b] = m;
         });
     });
-    for (int i = t; i < NR; i += 1024) vs[i] = ws[i] = cd{0.0, 0.0};
-    // pivot column of step j: rows j..n-1 of column j, from its owners
-    auto gather = [&](int j) {
-        if (tj != (j & 31)) return;
-        const int jb = j >> 5;
-        unroll_for<0, T>([&](auto b_) {
-            constexpr int b = b_;
-            if (b != jb) return;
-            unroll_for<b, T>([&](auto a_) {
-                constexpr int a = a_;
-                const int i = ti + 32 * a;
-                if (i >= j && i < n) xs[i] = E[a * (a + 1) / 2 + b];
+    for (int i = t; i < NR; i += 1024) vs[0][i] = vs[1][i] = ws[i] = cd{0.0, 0.0};
+    __syncthreads();
+    // A -= w v^H + v w^H on the live tiles of step jm (v = vs[par], w = ws)
+    auto update = [&](int jm, int par) {
+        unroll_for<0, T>([&](auto a_) {
+            constexpr int a = a_;
+            if (32 * a + 31 <= jm) return;
+            const cd vi = vs[par][ti + 32 * a], wi = ws[ti + 32 * a];
+            unroll_for<0, a + 1>([&](auto b_) {
+                constexpr int b = b_;
+                if (32 * b + 31 <= jm) return;
+                const cd vj = cconj(vs[par][tj + 32 * b]), wj = cconj(ws[tj + 32 * b]);
+                const cd u1 = cmulz(wi, vj), u2 = cmulz(vi, wj);
+                cd &e = E[a * (a + 1) / 2 + b];
+                e.x -= u1.x + u2.x;
+                e.y -= u1.y + u2.y;
             });
         });
     };
-    gather(0);
-    __syncthreads();
+    // entry (ti + 32 a, col) of this lane for the column tile jb (zero above it)
+    auto col_entry = [&](auto a_, int jb) -> cd {
+        constexpr int a = decltype(a_)::value;
+        cd x = {0.0, 0.0};
+        unroll_for<0, a + 1>([&](auto b_) {
+            constexpr int b = b_;
+            if (b == jb) x = E[a * (a + 1) / 2 + b];
+        });
+        return x;
+    };
     for (int j = 0; j + 1 < n; ++j) {
-        // ---- reflector from the pivot column (wave 0) ----
-        if (wave == 0) {
+        const int par = j & 1, own = j & 31, jb = j >> 5;
+        const bool owner = wave == (own >> 1);   // uniform per wave
+        if (owner) __builtin_amdgcn_s_setprio(2);
+        if (j > 0) update(j - 1, par ^ 1);
+        if (owner) {
+            // ---- reflector j from column j, held by half-wave `own` ----
+            const int base = (own & 1) * 32;
             double sg = 0.0;
-            for (int r = j + 2 + lane; r < n; r += 64) sg += xs[r].x * xs[r].x + xs[r].y * xs[r].y;
-            const double sigma = wave_total(sg);
-            const cd alpha = xs[j + 1];
+            unroll_for<0, T>([&](auto a_) {
+                constexpr int a = a_;
+                const int r = ti + 32 * a;
+                if (r >= j + 2 && r < n) {
+                    const cd x = col_entry(a_, jb);
+                    sg += x.x * x.x + x.y * x.y;
+                }
+            });
+            sg = row16_sum(sg);
+            sg += dpp_f64_rows<0x142, 0xA>(sg);   // lanes 31 and 63: the two half-wave totals
+            const double sigma = lane_read(sg, base + 31);
+            const int a1 = (j + 1) >> 5;
+            cd xa = {0.0, 0.0}, xd = {0.0, 0.0};
+            unroll_for<0, T>([&](auto a_) {
+                constexpr int a = a_;
+                if (a == a1) xa = col_entry(a_, jb);
+                if (a == jb) xd = col_entry(a_, jb);
+            });
+            const cd alpha = {lane_read(xa.x, base + ((j + 1) & 31)), lane_read(xa.y, base + ((j + 1) & 31))};
+            const double djj = lane_read(xd.x, base + own);
             cd tau, scale;
             double beta;
             if (sigma == 0.0 && alpha.y == 0.0) {
@@ -508,50 +546,49 @@ __global__ void __launch_bounds__(1024)
                 const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
                 beta = alpha.x >= 0.0 ? -nrm : nrm;
                 const double dr = alpha.x - beta, di = alpha.y;
-                // refined hardware reciprocals (within an ulp) instead of two divisions
-                const double ib = rcp_nr(beta), iden = rcp_nr(dr * dr + di * di);   // independent
+                const double ib = rcp_nr(beta), iden = rcp_nr(dr * dr + di * di);
                 tau = cd{-dr * ib, -alpha.y * ib};
                 scale = cd{dr * iden, -di * iden};
             }
             const bool reflect = !(tau.x == 0.0 && tau.y == 0.0);
-            for (int r = j + 1 + lane; r < n; r += 64) {
-                cd vv;
-                if (!reflect) vv = cd{0.0, 0.0};
-                else if (r == j + 1) vv = cd{1.0, 0.0};
-                else vv = cmulz(xs[r], scale);
-                vs[r] = vv;
-                if (r > j + 1) A[(int64_t)j * lda + r] = vv;   // kept for the back-transform
+            if (tj == own) {   // the owning half-wave writes the whole reflector
+                unroll_for<0, T>([&](auto a_) {
+                    constexpr int a = a_;
+                    const int r = ti + 32 * a;
+                    cd vv = {0.0, 0.0};
+                    if (reflect && r > j && r < n) vv = r == j + 1 ? cd{1.0, 0.0} : cmulz(col_entry(a_, jb), scale);
+                    vs[par][r] = vv;
+                    if (r > j + 1 && r < n) A[(int64_t)j * lda + r] = vv;   // kept for the back-transform
+                });
+                if (ti == own) {
+                    dd[j] = djj;
+                    ee[j] = beta;
+                    tau_out[j] = tau;
+                    A[(int64_t)j * lda + j + 1] = cd{beta, 0.0};
+                    s_tau[par] = tau;
+                }
             }
-            if (lane == 0) {
-                dd[j] = xs[j].x;
-                ee[j] = beta;
-                tau_out[j] = tau;
-                A[(int64_t)j * lda + j + 1] = cd{beta, 0.0};
-                vs[j] = ws[j] = cd{0.0, 0.0};
-                s_tau = tau;
-            }
+            __builtin_amdgcn_s_setprio(0);
         }
         __syncthreads();
-        // ---- partials of y = A v: row sums, then column sums (few live registers) ----
+        // ---- partials of y = A v ----
         {
             double vpart = 0.0;
-            unroll_for<0, T>([&](auto a_) {
+            unroll_for<0, T>([&](auto a_) {   // row sums over this lane's tiles of row ti + 32a
                 constexpr int a = a_;
-                if (32 * a + 31 <= j) return;   // rows all finished
+                if (32 * a + 31 <= j) return;
                 double rr = 0.0, ri = 0.0;
                 unroll_for<0, a + 1>([&](auto b_) {
                     constexpr int b = b_;
-                    if (32 * b + 31 <= j) return;   // columns all finished
+                    if (32 * b + 31 <= j) return;
                     const cd e = E[a * (a + 1) / 2 + b];
-                    const cd vj = vs[tj + 32 * b];
+                    const cd vj = vs[par][tj + 32 * b];
                     rr += e.x * vj.x - e.y * vj.y;
                     ri += e.x * vj.y + e.y * vj.x;
                 });
-                const cd vi = vs[ti + 32 * a];
+                const cd vi = vs[par][ti + 32 * a];
                 vpart += vi.x * rr + vi.y * ri;
-                rr = quad_sum(rr);   // the eight quad sums of a row are added in the w step
-                ri = quad_sum(ri);
-                if ((tj & 3) == 0) pr[tj >> 2][ti + 32 * a] = cd{rr, ri};
+                pr[tj][ti + 32 * a] = cd{rr, ri};
             });
             unroll_for<0, T - 1>([&](auto b_) {   // conj(e) v_i into y_j, off-diagonal tiles
                 constexpr int b = b_;
@@ -560,13 +597,15 @@ __global__ void __launch_bounds__(1024)
                 unroll_for<b + 1, T>([&](auto a_) {
                     constexpr int a = a_;
                     const cd e = E[a * (a + 1) / 2 + b];
-                    const cd vi = vs[ti + 32 * a];
+                    const cd vi = vs[par][ti + 32 * a];
                     cr += e.x * vi.x + e.y * vi.y;
                     ci += e.x * vi.y - e.y * vi.x;
                 });
-                const cd vj = vs[tj + 32 * b];
+                const cd vj = vs[par][tj + 32 * b];
                 vpart += vj.x * cr + vj.y * ci;
-                pc[ti][tj + 32 * b] = cd{cr, ci};
+                cr = quad_sum(cr);   // the eight quad sums of a column are added in the w step
+                ci = quad_sum(ci);
+                if ((ti & 3) == 0) pc[ti >> 2][tj + 32 * b] = cd{cr, ci};
             });
             vpart = wave_total(vpart);
             if (lane == 0) sv[wave] = vpart;
@@ -576,58 +615,53 @@ __global__ void __launch_bounds__(1024)
         if (t < 4 * NR) {
             const int r = t >> 2, q = t & 3;
             const bool live = r > j && r < n;
-            // the ten partials of this thread in two interleaved chains (half the add
-            // latency of one chain, few values live), then the quad
             double sr = 0.0, si = 0.0;
             if (live) {
                 double er = 0.0, ei = 0.0;
-                if (r < 32 * (T - 1)) {   // the last row tile has no tile below the diagonal
 #pragma unroll
-                    for (int h = 0; h < 8; h += 2) {
-                        sr += pc[8 * q + h][r].x;
-                        si += pc[8 * q + h][r].y;
-                        er += pc[8 * q + h + 1][r].x;
-                        ei += pc[8 * q + h + 1][r].y;
-                    }
+                for (int h = 0; h < 8; h += 2) {
+                    sr += pr[8 * q + h][r].x;
+                    si += pr[8 * q + h][r].y;
+                    er += pr[8 * q + h + 1][r].x;
+                    ei += pr[8 * q + h + 1][r].y;
                 }
-                sr += pr[2 * q][r].x + er;
-                si += pr[2 * q][r].y + ei;
-                sr += pr[2 * q + 1][r].x;
-                si += pr[2 * q + 1][r].y;
+                if (r < 32 * (T - 1)) {   // the last column tile has no tile below the diagonal
+                    sr += pc[2 * q][r].x;
+                    si += pc[2 * q][r].y;
+                    er += pc[2 * q + 1][r].x;
+                    ei += pc[2 * q + 1][r].y;
+                }
+                sr += er;
+                si += ei;
             }
             sr = quad_sum(sr);
             si = quad_sum(si);
-            // v^H A v: a quarter of the wave partials per thread, then the quad
             double vhy = (sv[4 * q] + sv[4 * q + 1]) + (sv[4 * q + 2] + sv[4 * q + 3]);
             vhy = quad_sum(vhy);
-            const cd tau = s_tau;
+            const cd tau = s_tau[par];
             const double nu = 0.5 * (tau.x * tau.x + tau.y * tau.y) * vhy;
-            if (live && q == 0) {
-                const cd ty = cmulz(tau, cd{sr, si});
-                const cd vr = vs[r];
-                ws[r] = cd{ty.x - nu * vr.x, ty.y - nu * vr.y};
+            if (q == 0) {
+                cd wr = {0.0, 0.0};
+                if (live) {
+                    const cd ty = cmulz(tau, cd{sr, si});
+                    const cd vr = vs[par][r];
+                    wr = cd{ty.x - nu * vr.x, ty.y - nu * vr.y};
+                }
+                ws[r] = wr;
             }
         }
         __syncthreads();
-        // ---- A -= w v^H + v w^H on the live tiles ----
-        unroll_for<0, T>([&](auto a_) {
-            constexpr int a = a_;
-            if (32 * a + 31 <= j) return;
-            const cd vi = vs[ti + 32 * a], wi = ws[ti + 32 * a];
-            unroll_for<0, a + 1>([&](auto b_) {
-                constexpr int b = b_;
-                if (32 * b + 31 <= j) return;
-                const cd vj = cconj(vs[tj + 32 * b]), wj = cconj(ws[tj + 32 * b]);
-                const cd u1 = cmulz(wi, vj), u2 = cmulz(vi, wj);
-                cd &e = E[a * (a + 1) / 2 + b];
-                e.x -= u1.x + u2.x;
-                e.y -= u1.y + u2.y;
-            });
-        });
-        gather(j + 1);
-        __syncthreads();
     }
-    if (t == 0) dd[n - 1] = xs[n - 1].x;
+    if (n >= 2) update(n - 2, (n - 2) & 1);
+    {   // d_{n-1}: element (n-1, n-1) after the last update
+        const int m = n - 1, mb = m >> 5;
+        if (ti == (m & 31) && tj == (m & 31)) {
+            unroll_for<0, T>([&](auto a_) {
+                constexpr int a = a_;
+                if (a == mb) dd[m] = E[a * (a + 1) / 2 + a].x;
+            });
+        }
+    }
 }
 
 // Sturm counts (number of eigenvalues below x) at two shifts at once: the two
@@ -1587,12 +1621,12 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     if (n <= 32 * kRfMaxT) {
         const int T = (n + 31) / 32;
         switch (T) {
-            case 1: hipLaunchKernelGGL(k_hetrd_rf<1>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
-            case 2: hipLaunchKernelGGL(k_hetrd_rf<2>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
-            case 3: hipLaunchKernelGGL(k_hetrd_rf<3>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
-            case 4: hipLaunchKernelGGL(k_hetrd_rf<4>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
-            case 5: hipLaunchKernelGGL(k_hetrd_rf<5>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
-            default: hipLaunchKernelGGL(k_hetrd_rf<6>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            case 1: hipLaunchKernelGGL(k_hetrd_la<1>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            case 2: hipLaunchKernelGGL(k_hetrd_la<2>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            case 3: hipLaunchKernelGGL(k_hetrd_la<3>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            case 4: hipLaunchKernelGGL(k_hetrd_la<4>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            case 5: hipLaunchKernelGGL(k_hetrd_la<5>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            default: hipLaunchKernelGGL(k_hetrd_la<6>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
         }
     } else {
         TrdState S;

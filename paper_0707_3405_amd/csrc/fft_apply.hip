@@ -12,7 +12,8 @@
 //                     write S (only sticks, not the full grid).
 //   pass 2 (k_plane): per (band, z-plane): scatter the plane's sticks into the
 //                     kept x-columns, inverse y-FFT on those columns, then row
-//                     by row inverse x-FFT, multiply by V(r)/N^3, forward
+//                     by row inverse x-FFT (its first stage reading the kept
+//                     columns directly), multiply by V(r)/N^3, forward
 //                     x-FFT (keeping only the kept columns), forward y-FFT,
 //                     gather the sticks back into S.
 //   pass 3 (k_zfwd):  per (band, group of sticks): forward z-FFT, gather the
@@ -139,16 +140,21 @@ __global__ void __launch_bounds__((plane_threads<P::N, T>())) k_plane(SphereDev 
     const int xmin_g = ((sp.xmin % N) + N) % N;
     for (int y0 = 0; y0 < N; y0 += rb) {
         const int nr = min(rb, N - y0);
-        for (int i = threadIdx.x; i < nr * N; i += blockDim.x) {
-            const int r = i / N, x = i - r * N;
-            int xc = x - xmin_g;
-            xc += (xc < 0) ? N : 0;
-            R[r * LD + x] = (xc < ncx) ? A[xc * LD + digit_rev<P>(y0 + r)] : cpx<T>{T(0), T(0)};
-        }
-        __syncthreads();
+        // first inverse x stage, its inputs read straight from the kept columns
+        // of A (the other x are zero): no row buffer fill, no barrier for it
         for (int it = threadIdx.x; it < nr * R2; it += blockDim.x) {
             const int r = it % nr, n2 = it / nr;
-            dit_a<P, +1>(R + r * LD, n2, tw);
+            const int ypos = digit_rev<P>(y0 + r);
+            cpx<T> u[R1];
+#pragma unroll
+            for (int n1 = 0; n1 < R1; ++n1) {
+                int xc = n1 * R2 + n2 - xmin_g;
+                xc += (xc < 0) ? N : 0;
+                u[n1] = (xc < ncx) ? A[xc * LD + ypos] : cpx<T>{T(0), T(0)};
+            }
+            dit_a_regs<P, +1>(u, n2, tw);
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) R[r * LD + k1 * R2 + n2] = u[k1];
         }
         __syncthreads();
         // second inverse stage, V multiply and first forward stage act on the

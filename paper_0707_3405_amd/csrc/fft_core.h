@@ -264,16 +264,23 @@ __device__ __forceinline__ cpx<T> twiddle(const cpx<T> *tw, int idx) {
     return w;
 }
 
-// dit stage A on one sequence (element stride 1): item n2 in [0, R2).
+// dit stage A of item n2 on its R1 inputs u[n1] = x[n1 R2 + n2], in registers:
+// leaves the value for position k1 R2 + n2 in u[k1].
 template <class P, int S, class T>
-__device__ __forceinline__ void dit_a(cpx<T> *x, int n2, const cpx<T> *tw) {
-    constexpr int N = P::N, R1 = P::R1, R2 = P::R2;
-    cpx<T> u[R1];
-#pragma unroll
-    for (int n1 = 0; n1 < R1; ++n1) u[n1] = x[n1 * R2 + n2];
+__device__ __forceinline__ void dit_a_regs(cpx<T> *u, int n2, const cpx<T> *tw) {
+    constexpr int N = P::N, R1 = P::R1;
     Dft<R1, S, T>::run(u);
 #pragma unroll
     for (int k1 = 1; k1 < R1; ++k1) u[k1] = cmul(u[k1], twiddle<S>(tw, (n2 * k1) % N));
+}
+// dit stage A on one sequence (element stride 1): item n2 in [0, R2).
+template <class P, int S, class T>
+__device__ __forceinline__ void dit_a(cpx<T> *x, int n2, const cpx<T> *tw) {
+    constexpr int R1 = P::R1, R2 = P::R2;
+    cpx<T> u[R1];
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) u[n1] = x[n1 * R2 + n2];
+    dit_a_regs<P, S>(u, n2, tw);
 #pragma unroll
     for (int k1 = 0; k1 < R1; ++k1) x[k1 * R2 + n2] = u[k1];
 }
