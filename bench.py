@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # calibration; profiles/hbm_bytes_fcc108_l20.txt) for the kernels as they were profiled,
 # over the same kernels as the launch time (the Grams include k_reduce_parts);
 # set an entry to None when its kernels change.
-TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 3.63e8, "gemm_complex64": 1.84e8, "dense": None}
+TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 3.63e8, "gemm_complex64": 1.84e8, "dense": 5.42e6}
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
 FP32_PEAK_TFLOPS = 157.3       # MI355X dense FP32 (matrix)
 WORKLOAD = "fcc108_l20"
