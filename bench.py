@@ -427,6 +427,25 @@ def main():
         batched["max_abs_eig_diff_mixed_vs_fp64_ha"] = float(np.abs(res_eigs["mixed"] -
                                                                     res_eigs["fp64"]).max())
         del probs
+        # multi-k-point H.X: the ten k-points' full H (local + projectors) on 32 bands in
+        # one pw_apply_H_batch (one launch per FFT pass over all (k, band) items) against
+        # ten pw_apply_H calls on the same stream
+        from paper_0707_3405_amd import apply_H_batch
+        sb = torch.cuda.Stream()
+        probs = [PlaneWaveProblem.from_workload(x, device=0, stream=sb, prec=PW_PREC_MIXED) for x in wk]
+        ctxs = [p.ctx for p in probs]
+        nbk = wk[0].block
+        batched["apply_batch"] = {"bands_per_kpoint": nbk}
+        for name, prec, dt in (("fp64", PW_PREC_FP64, torch.complex128),
+                               ("mixed", PW_PREC_MIXED, torch.complex64)):
+            Xk = [torch.randn((nbk, p.npw), dtype=dt, device="cuda") for p in probs]
+            Yk = [torch.empty_like(x) for x in Xk]
+            t_b = event_time_ms(torch, sb, lambda: apply_H_batch(ctxs, Xk, Yk, prec=prec), 10)
+            t_s = event_time_ms(torch, sb, lambda: [c.apply_H(x, y, prec=prec) for c, x, y in zip(ctxs, Xk, Yk)],
+                                10)
+            batched["apply_batch"][name] = {"batched_ms": t_b, "separate_ms": t_s}
+            log(f"multi-k H.X {name}: batched {t_b:.3f} ms, separate {t_s:.3f} ms")
+        del probs, ctxs
 
     # ---- served stream sample: Poisson arrivals (4/s) of cells with L in [8, 16] bohr,
     # Ecut in [5, 15] Ha, bands ~ atoms, random k, FP64 or mixed

@@ -167,6 +167,24 @@ pw_status pw_set_workspace(pw_ctx ctx, void *dptr, size_t bytes);
 pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ldy,
                      int32_t nb, pw_precision prec);
 
+/* Y_k = H_k X_k for the nk (1..16) contexts of one cell's k-points at once
+ * (sec. 5.2: the k-points are the third level of parallelism; one GPU takes
+ * them together).  The contexts share one device, one stream and one FFT
+ * grid; their spheres, kinetic energies, projectors and stick buffers are
+ * their own, and the local potential of ctxs[0] (its radix split too) serves
+ * them all.  Each of the three FFT passes is one launch over every (k-point,
+ * band) work item; the projector products of each context follow on the same
+ * stream.  X[k], Y[k]: device, column-major [npw_k x nb], ldx[k], ldy[k] >=
+ * npw_k, complex128 for PW_PREC_FP64 and complex64 for the mixed forms, as in
+ * pw_apply_H, whose result it gives for every context bitwise.  Every context
+ * needs a workspace sized for prec; none may be in use elsewhere during the
+ * call.  Errors (bad argument, mismatched contexts) are recorded on ctxs[0].
+ * Only kernel launches go to the stream (no allocation, copy or
+ * synchronisation once the contexts' mixed-form tables exist), so the call
+ * can be recorded into a graph.  Asynchronous. */
+pw_status pw_apply_H_batch(pw_ctx const *ctxs, int32_t nk, const void *const *X, const int64_t *ldx,
+                           void *const *Y, const int64_t *ldy, int32_t nb, pw_precision prec);
+
 /* Launch parameters of a context (0 = built-in default) and, from
  * pw_autotune, the timings behind the choice (ms per launch).  The sticks and
  * rows change the partition of the work only (the FFT results are bitwise the

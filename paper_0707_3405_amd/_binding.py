@@ -28,7 +28,7 @@ EXPORTS = ("pw_create", "pw_destroy", "pw_last_error", "pw_init_basis", "pw_fft_
            "pw_get_residuals", "pw_get_stats", "pw_gram", "pw_block_update", "pw_small_eigh",
            "pw_residuals", "pw_gram_mixed", "pw_block_update_mixed", "pw_lobpcg_solve_batch",
            "pw_density", "pw_set_overlap", "pw_apply_O", "pw_chol_inv", "pw_autotune",
-           "pw_set_tuning", "pw_small_eigh_noalloc")
+           "pw_set_tuning", "pw_small_eigh_noalloc", "pw_apply_H_batch")
 
 
 class PWError(RuntimeError):
@@ -91,6 +91,7 @@ def load_library():
         "pw_set_workspace": (ctypes.c_int, [P, P, SZ]),
         "pw_apply_H": (ctypes.c_int, [P, P, I64, P, I64, I32, ctypes.c_int]),
         "pw_apply_O": (ctypes.c_int, [P, P, I64, P, I64, I32, ctypes.c_int]),
+        "pw_apply_H_batch": (ctypes.c_int, [P, I32, P, P, P, P, I32, ctypes.c_int]),
         "pw_set_overlap": (ctypes.c_int, [P, P]),
         "pw_chol_inv": (ctypes.c_int, [P, P, I64, I32, P, I64]),
         "pw_autotune": (ctypes.c_int, [P, I32, ctypes.POINTER(PWTuning)]),
@@ -114,6 +115,26 @@ def load_library():
         fn.argtypes = args
     _lib = lib
     return lib
+
+
+def apply_H_batch(ctxs, Xs, Ys, nb=None, prec=PW_PREC_FP64):
+    """Y_k = H_k X_k for the contexts of one cell's k-points in one call
+    (pw_apply_H_batch): X_k, Y_k are [nb, npw_k] tensors as for Context.apply_H;
+    the contexts share a device, a stream and an FFT grid."""
+    if not (len(ctxs) == len(Xs) == len(Ys)) or not ctxs:
+        raise ValueError("need one X and one Y per context")
+    nb = Xs[0].shape[0] if nb is None else nb
+    dt = _block_dtype_name(prec)
+    for c, X, Y in zip(ctxs, Xs, Ys):
+        c._check_tensors([("X", X, dt, nb, c.npw, None), ("Y", Y, dt, nb, c.npw, None)])
+    n = len(ctxs)
+    hs = (ctypes.c_void_p * n)(*[c.h.value for c in ctxs])
+    xp = (ctypes.c_void_p * n)(*[_ptr(X).value for X in Xs])
+    yp = (ctypes.c_void_p * n)(*[_ptr(Y).value for Y in Ys])
+    lx = (ctypes.c_int64 * n)(*[_ld(X) for X in Xs])
+    ly = (ctypes.c_int64 * n)(*[_ld(Y) for Y in Ys])
+    ctxs[0]._check(ctxs[0].lib.pw_apply_H_batch(hs, n, xp, lx, yp, ly, nb, prec))
+    return Ys
 
 
 def fft_sizes():

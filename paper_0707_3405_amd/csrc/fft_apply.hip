@@ -42,6 +42,12 @@ constexpr int kPlaneRb = 48;       // default row chunk of the plane pass (cappe
 constexpr int kRhoThreads = 512;   // workgroup size of the density plane pass
 constexpr int kRhoRb = 32;         // row chunk of the density plane pass
 
+// the k-point items of one launch, passed by value (blockIdx.z picks one)
+template <class T>
+struct ApplyItems {
+    FftApplyItem<T> it[kMaxApplyBatch];
+};
+
 template <class T>
 __device__ __forceinline__ void load_twiddles(cpx<T> *tw_s, const double *tw_g, int n) {
     for (int i = threadIdx.x; i < n; i += blockDim.x)
@@ -50,8 +56,12 @@ __device__ __forceinline__ void load_twiddles(cpx<T> *tw_s, const double *tw_g, 
 
 // ---- pass 1: inverse z-FFT per stick ---------------------------------------
 template <class P, class T>
-__global__ void __launch_bounds__(kThreads) k_zinv(SphereDev sp, const cpx<T> *__restrict__ X,
-                                                   int64_t ldx, cpx<T> *__restrict__ S, int spb) {
+__global__ void __launch_bounds__(kThreads) k_zinv(const ApplyItems<T> items, int spb) {
+    const FftApplyItem<T> &item = items.it[blockIdx.z];
+    const SphereDev &sp = item.sp;
+    const cpx<T> *__restrict__ X = item.X;
+    const int64_t ldx = item.ldx;
+    cpx<T> *__restrict__ S = item.S;
     constexpr int N = P::N, LD = N + 1;
     constexpr int R1 = P::R1, R2 = P::R2;
     extern __shared__ unsigned char smem_raw[];
@@ -101,8 +111,11 @@ __device__ __forceinline__ int xcd_logical(int lin, int total) {
 }
 
 template <class P, class T>
-__global__ void __launch_bounds__((plane_threads<P::N, T>())) k_plane(SphereDev sp, const T *__restrict__ vperm,
-                                                    cpx<T> *__restrict__ S, int nb, int rb) {
+__global__ void __launch_bounds__((plane_threads<P::N, T>())) k_plane(const ApplyItems<T> items,
+                                                                       const T *__restrict__ vperm, int nb, int rb) {
+    const FftApplyItem<T> &item = items.it[blockIdx.z];
+    const SphereDev &sp = item.sp;
+    cpx<T> *__restrict__ S = item.S;
     constexpr int N = P::N, LD = N + 1;
     constexpr int R1 = P::R1, R2 = P::R2;
     extern __shared__ unsigned char smem_raw[];
@@ -287,9 +300,14 @@ __global__ void k_rho_permute(const double *__restrict__ rho_zyx, int n, double 
 
 // ---- pass 3: forward z-FFT per stick, gather, kinetic -----------------------
 template <class P, class T>
-__global__ void __launch_bounds__(kThreads) k_zfwd(SphereDev sp, const cpx<T> *__restrict__ S,
-                                                   const cpx<T> *__restrict__ X, int64_t ldx,
-                                                   cpx<T> *__restrict__ Y, int64_t ldy, int spb) {
+__global__ void __launch_bounds__(kThreads) k_zfwd(const ApplyItems<T> items, int spb) {
+    const FftApplyItem<T> &item = items.it[blockIdx.z];
+    const SphereDev &sp = item.sp;
+    const cpx<T> *__restrict__ S = item.S;
+    const cpx<T> *__restrict__ X = item.X;
+    const int64_t ldx = item.ldx;
+    cpx<T> *__restrict__ Y = item.Y;
+    const int64_t ldy = item.ldy;
     constexpr int N = P::N, LD = N + 1;
     constexpr int R1 = P::R1, R2 = P::R2;
     extern __shared__ unsigned char smem_raw[];
@@ -366,17 +384,21 @@ __global__ void k_repermute_v(const double *__restrict__ in, double *__restrict_
 constexpr int kSticksPerBlock = 16;   // default sticks per workgroup of the z passes
 
 template <class P, class T>
-void run_apply_split(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
-                     int64_t ldy, int nb, cpx<T> *S, hipStream_t st) {
+void run_apply_split(const ApplyItems<T> &items, int nk, const T *vperm, int nb, hipStream_t st) {
     constexpr int N = P::N;
     const Tuning &tune = thread_tuning();
     const int spb = tune.fft_spb > 0 ? tune.fft_spb : kSticksPerBlock;
     const size_t e = sizeof(cpx<T>);
     const size_t sm13 = (size_t)N * e + (size_t)spb * (N + 1) * e;
-    dim3 g13((sp.nst + spb - 1) / spb, nb);
+    int nst_max = 0, ncx_max = 0;
+    for (int k = 0; k < nk; ++k) {
+        nst_max = std::max(nst_max, items.it[k].sp.nst);
+        ncx_max = std::max(ncx_max, items.it[k].sp.ncx);
+    }
+    dim3 g13((nst_max + spb - 1) / spb, nb, nk);
     // pass 2 LDS: twiddles + kept columns + row chunk; largest row chunk that
     // keeps the workgroup under 150 KB.
-    const size_t base2 = (size_t)N * e + (size_t)sp.ncx * (N + 1) * e;
+    const size_t base2 = (size_t)N * e + (size_t)ncx_max * (N + 1) * e;
     int rb = tune.fft_rb > 0 ? tune.fft_rb : kPlaneRb;
     auto sm2_of = [&](int r) { return base2 + (size_t)r * (N + 1) * e; };
     while (rb > 1 && sm2_of(rb) > 150 * 1024) rb /= 2;
@@ -386,10 +408,10 @@ void run_apply_split(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64
     ensure_smem_limit((const void *)k_zinv<P, T>, sm13);
     ensure_smem_limit((const void *)k_plane<P, T>, sm2);
     ensure_smem_limit((const void *)k_zfwd<P, T>, sm13);
-    hipLaunchKernelGGL((k_zinv<P, T>), g13, dim3(kThreads), sm13, st, sp, X, ldx, S, spb);
-    hipLaunchKernelGGL((k_plane<P, T>), dim3(N * nb), dim3(plane_threads<N, T>()), sm2, st, sp, vperm, S, nb,
-                       rb);
-    hipLaunchKernelGGL((k_zfwd<P, T>), g13, dim3(kThreads), sm13, st, sp, S, X, ldx, Y, ldy, spb);
+    hipLaunchKernelGGL((k_zinv<P, T>), g13, dim3(kThreads), sm13, st, items, spb);
+    hipLaunchKernelGGL((k_plane<P, T>), dim3(N * nb, 1, nk), dim3(plane_threads<N, T>()), sm2, st, items, vperm,
+                       nb, rb);
+    hipLaunchKernelGGL((k_zfwd<P, T>), g13, dim3(kThreads), sm13, st, items, spb);
     PW_HIP(hipGetLastError());
 }
 
@@ -406,15 +428,14 @@ void host_for(F &&f) {
 int effective_r2(int n, int r2) { return r2 > 0 ? r2 : choose_r2(n); }
 
 template <int N, class T>
-void run_apply(const SphereDev &sp, const T *vperm, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
-               int64_t ldy, int nb, cpx<T> *S, hipStream_t st) {
+void run_apply(const ApplyItems<T> &items, int nk, const T *vperm, int nb, hipStream_t st) {
     const int r2 = effective_r2(N, thread_tuning().fft_r2);
     bool done = false;
     host_for<2, 17>([&](auto R) {
         constexpr int r = R;
         if constexpr (split_ok(N, r)) {
             if (!done && r == r2) {
-                run_apply_split<Split<N, r>, T>(sp, vperm, X, ldx, Y, ldy, nb, S, st);
+                run_apply_split<Split<N, r>, T>(items, nk, vperm, nb, st);
                 done = true;
             }
         }
@@ -534,8 +555,10 @@ void run_density(const SphereDev &sp, const cd *X, int64_t ldx, int nb, const do
     PW_REQUIRE(sm2 <= 160 * 1024, PW_ERR_ARG, "FFT plane does not fit in LDS");
     ensure_smem_limit((const void *)k_zinv<Split<N>, double>, sm1);
     ensure_smem_limit((const void *)k_plane_rho<N, double>, sm2);
+    ApplyItems<double> items{};
+    items.it[0] = FftApplyItem<double>{sp, X, ldx, nullptr, 0, S};
     hipLaunchKernelGGL((k_zinv<Split<N>, double>), dim3((sp.nst + spb - 1) / spb, nb), dim3(kThreads), sm1, st,
-                       sp, X, ldx, S, spb);
+                       items, spb);
     hipLaunchKernelGGL((k_plane_rho<N, double>), dim3(N), dim3(kRhoThreads), sm2, st, sp, S, nb, occ,
                        rho_zyx, rb);
     PW_HIP(hipGetLastError());
@@ -564,13 +587,13 @@ void launch_density_finish(const double *rho_zyx, int n, double scale, double *r
 }
 
 template <class T>
-void fft_apply_impl(const SphereDev &sp, const T *v_zyx, const cpx<T> *X, int64_t ldx, cpx<T> *Y,
-                    int64_t ldy, int nb, cpx<T> *S, hipStream_t st) {
-    if (nb <= 0) return;
-    switch (sp.n) {
-#define PW_CASE(NN)                                                  \
-    case NN:                                                         \
-        run_apply<NN, T>(sp, v_zyx, X, ldx, Y, ldy, nb, S, st);      \
+void fft_apply_impl(const ApplyItems<T> &items, int nk, const T *v_zyx, int nb, hipStream_t st) {
+    if (nb <= 0 || nk <= 0) return;
+    const int n = items.it[0].sp.n;
+    switch (n) {
+#define PW_CASE(NN)                                     \
+    case NN:                                            \
+        run_apply<NN, T>(items, nk, v_zyx, nb, st);     \
         return;
         PW_FFT_SIZES(PW_CASE)
 #undef PW_CASE
@@ -579,13 +602,34 @@ void fft_apply_impl(const SphereDev &sp, const T *v_zyx, const cpx<T> *X, int64_
     }
 }
 
+template <class T>
+void fft_apply_batch(const FftApplyItem<T> *items, int nk, const T *v_zyx, int nb, hipStream_t st) {
+    PW_REQUIRE(nk >= 1 && nk <= kMaxApplyBatch, PW_ERR_ARG, "k-points per batched apply must be in [1, 16]");
+    ApplyItems<T> all{};
+    for (int k = 0; k < nk; ++k) {
+        PW_REQUIRE(items[k].sp.n == items[0].sp.n, PW_ERR_ARG, "batched apply needs one FFT grid");
+        all.it[k] = items[k];
+    }
+    fft_apply_impl(all, nk, v_zyx, nb, st);
+}
+
 void launch_fft_apply(const SphereDev &sp, const double *v_zyx, const cd *X, int64_t ldx, cd *Y,
                       int64_t ldy, int nb, cd *S, hipStream_t st) {
-    fft_apply_impl(sp, v_zyx, X, ldx, Y, ldy, nb, S, st);
+    const FftApplyItem<double> it{sp, X, ldx, Y, ldy, S};
+    fft_apply_batch(&it, 1, v_zyx, nb, st);
 }
 void launch_fft_apply(const SphereDev &sp, const float *v_zyx, const cf *X, int64_t ldx, cf *Y,
                       int64_t ldy, int nb, cf *S, hipStream_t st) {
-    fft_apply_impl(sp, v_zyx, X, ldx, Y, ldy, nb, S, st);
+    const FftApplyItem<float> it{sp, X, ldx, Y, ldy, S};
+    fft_apply_batch(&it, 1, v_zyx, nb, st);
+}
+void launch_fft_apply_batch(const FftApplyItem<double> *items, int nk, const double *v_zyx, int nb,
+                            hipStream_t st) {
+    fft_apply_batch(items, nk, v_zyx, nb, st);
+}
+void launch_fft_apply_batch(const FftApplyItem<float> *items, int nk, const float *v_zyx, int nb,
+                            hipStream_t st) {
+    fft_apply_batch(items, nk, v_zyx, nb, st);
 }
 
 }  // namespace pw

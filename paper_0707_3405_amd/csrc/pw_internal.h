@@ -83,6 +83,24 @@ void launch_density_accumulate(const SphereDev &sp, const cd *X, int64_t ldx, in
 void launch_density_finish(const double *rho_zyx, int n, double scale, double *rho, hipStream_t st);
 bool fft_size_supported(int n);
 std::vector<int> fft_supported_sizes();
+// One k-point of a multi-k-point apply: its sphere, X and Y, its stick buffer.
+// All items share the FFT grid, the radix split and the potential.
+template <class T>
+struct FftApplyItem {
+    SphereDev sp;
+    const cpx<T> *X;
+    int64_t ldx;
+    cpx<T> *Y;
+    int64_t ldy;
+    cpx<T> *S;
+};
+constexpr int kMaxApplyBatch = 16;   // k-points per launch (the items travel as kernel arguments)
+// Y_k = T_k X_k + (V psi_k)(G) for nb columns of every item: each pass is one
+// launch over all (k-point, band) work items.
+void launch_fft_apply_batch(const FftApplyItem<double> *items, int nk, const double *v_zyx, int nb,
+                            hipStream_t st);
+void launch_fft_apply_batch(const FftApplyItem<float> *items, int nk, const float *v_zyx, int nb,
+                            hipStream_t st);
 
 // Launch parameters of the FFT passes and the split-K GEMM chosen per context
 // (pw_autotune / pw_set_tuning; 0 = built-in default).  The launchers read the

@@ -1146,6 +1146,39 @@ pw_status block_update_impl(pw_ctx c, const void *A, int64_t lda, const void *C,
 
 }  // namespace
 
+namespace {
+// the local part of every context in one launch per FFT pass, then each
+// context's projector products, chunk by chunk (the stream is the contexts' one)
+template <class S>
+void apply_batch_impl(pw_ctx const *ctxs, int nk, const void *const *X, const int64_t *ldx,
+                      void *const *Y, const int64_t *ldy, int nb, int chunk, pw_precision prec) {
+    using T = decltype(S{}.x);
+    pw_ctx c0 = ctxs[0];
+    std::vector<Plan<S>> plans;
+    plans.reserve(nk);
+    for (int k = 0; k < nk; ++k) {
+        pw_ctx c = ctxs[k];
+        plans.push_back(ready_plan<S>(c, std::max(c->plan_nbands, 1), chunk));
+        if constexpr (std::is_same<S, pw::cf>::value) {
+            ensure_mixed_tables(c);
+            c->proj_bf16 = prec == PW_PREC_MIXED_BF16 || prec == PW_PREC_MIXED_BF16_GRAM;
+        }
+    }
+    std::vector<pw::FftApplyItem<T>> items(nk);
+    for (int b0 = 0; b0 < nb; b0 += chunk) {
+        const int nc = std::min(chunk, nb - b0);
+        for (int k = 0; k < nk; ++k)
+            items[k] = pw::FftApplyItem<T>{ctxs[k]->sp, static_cast<const S *>(X[k]) + (int64_t)b0 * ldx[k], ldx[k],
+                                           static_cast<S *>(Y[k]) + (int64_t)b0 * ldy[k], ldy[k], plans[k].Sb};
+        pw::launch_fft_apply_batch(items.data(), nk, potential_of(c0, (const S *)nullptr), nc, c0->stream);
+        for (int k = 0; k < nk; ++k)
+            if (ctxs[k]->nproj() > 0)
+                proj_add(ctxs[k], plans[k], ctxs[k]->d_D, static_cast<const S *>(X[k]) + (int64_t)b0 * ldx[k], ldx[k],
+                         static_cast<S *>(Y[k]) + (int64_t)b0 * ldy[k], ldy[k], nc);
+    }
+}
+}  // namespace
+
 extern "C" {
 
 pw_status pw_create(int device, void *hip_stream, pw_ctx *out) {
@@ -1315,6 +1348,39 @@ pw_status pw_apply_H(pw_ctx c, const void *X, int64_t ldx, void *Y, int64_t ldy,
 pw_status pw_apply_O(pw_ctx c, const void *X, int64_t ldx, void *Y, int64_t ldy, int32_t nb,
                      pw_precision prec) {
     return apply_entry(c, X, ldx, Y, ldy, nb, prec, true);
+}
+
+
+pw_status pw_apply_H_batch(pw_ctx const *ctxs, int32_t nk, const void *const *X, const int64_t *ldx,
+                           void *const *Y, const int64_t *ldy, int32_t nb, pw_precision prec) {
+    if (!ctxs || nk < 1 || !ctxs[0]) return PW_ERR_ARG;
+    pw_ctx c0 = ctxs[0];
+    return guard(c0, [&] {
+        require_precision(prec);
+        PW_REQUIRE(nk <= pw::kMaxApplyBatch, PW_ERR_ARG, "at most 16 contexts per batched apply");
+        PW_REQUIRE(X && Y && ldx && ldy, PW_ERR_ARG, "null argument");
+        PW_REQUIRE(nb >= 0, PW_ERR_ARG, "negative column count");
+        require_basis(c0);
+        require_device(c0);
+        PW_REQUIRE(c0->has_v, PW_ERR_STATE, "pw_set_local_potential has not been called");
+        int chunk = 1 << 30;
+        for (int k = 0; k < nk; ++k) {
+            pw_ctx c = ctxs[k];
+            PW_REQUIRE(c != nullptr, PW_ERR_ARG, "null context");
+            require_basis(c);
+            PW_REQUIRE(c->device == c0->device && c->stream == c0->stream, PW_ERR_ARG,
+                       "the contexts of a batched apply share one device and one stream");
+            PW_REQUIRE(c->n == c0->n, PW_ERR_ARG, "the contexts of a batched apply share one FFT grid");
+            PW_REQUIRE(X[k] && Y[k], PW_ERR_ARG, "null block");
+            PW_REQUIRE(ldx[k] >= c->npw && ldy[k] >= c->npw, PW_ERR_ARG, "leading dimension < npw");
+            for (int q = 0; q < k; ++q) PW_REQUIRE(ctxs[q] != c, PW_ERR_ARG, "a context appears twice");
+            chunk = std::min(chunk, c->plan_block > 0 ? c->plan_block : 1);
+        }
+        if (nb == 0) return PW_OK;
+        if (prec != PW_PREC_FP64) apply_batch_impl<pw::cf>(ctxs, nk, X, ldx, Y, ldy, nb, chunk, prec);
+        else apply_batch_impl<cd>(ctxs, nk, X, ldx, Y, ldy, nb, chunk, prec);
+        return PW_OK;
+    });
 }
 
 pw_status pw_lobpcg_solve(pw_ctx c, int32_t nbands, int32_t block, double tol, int32_t max_iter,

@@ -191,3 +191,24 @@ def test_radix_split_tuning_is_checked_on_the_host():
     ctx.init_basis(w3.cell, w3.kfrac, w3.ecut, (w3.n,) * 3)
     ctx.set_tuning(fft_radix2=5)
     ctx.close()
+
+
+def test_apply_batch_argument_checks():
+    """pw_apply_H_batch refuses a bad batch before touching a device: no contexts,
+    more than 16, a null context, and host-only contexts (no device to run on)."""
+    import ctypes
+    from paper_0707_3405_amd import Context, PW_ERR_ARG, PW_ERR_STATE
+    from workloads import make_workload
+    w = make_workload("gamma_l10")
+    c = Context(-1)
+    c.init_basis(w.cell, w.kfrac, w.ecut, (w.n,) * 3)
+    lib = c.lib
+    one = (ctypes.c_void_p * 17)(*([c.h.value] * 17))
+    ptrs = (ctypes.c_void_p * 17)(*([1] * 17))
+    lds = (ctypes.c_int64 * 17)(*([c.npw] * 17))
+    assert lib.pw_apply_H_batch(one, 0, ptrs, lds, ptrs, lds, 4, 0) == PW_ERR_ARG
+    assert lib.pw_apply_H_batch(one, 17, ptrs, lds, ptrs, lds, 4, 0) == PW_ERR_ARG
+    nul = (ctypes.c_void_p * 2)(c.h.value, None)
+    assert lib.pw_apply_H_batch(nul, 2, ptrs, lds, ptrs, lds, 4, 0) in (PW_ERR_ARG, PW_ERR_STATE)
+    assert lib.pw_apply_H_batch(one, 1, ptrs, lds, ptrs, lds, 4, 0) == PW_ERR_STATE   # host-only
+    c.close()

@@ -73,3 +73,91 @@ def test_batch_ten_kpoints(torch_cuda, prec_name):
     assert np.array_equal(solo, eigs[1])
     print(f"{prec_name}: batch of 10 k-points {t_batch:.2f} s, one k-point alone {t_solo:.2f} s, "
           f"{10 * 256 / t_batch:.1f} eigenpairs/s batched")
+
+
+def _batch_setup(torch, wl, prec, nb):
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_FP64
+    from workloads import start_block
+    s = torch.cuda.Stream()   # one stream for every context of the batched apply
+    probs = [PlaneWaveProblem.from_workload(w, device=0, stream=s, prec=prec) for w in wl]
+    dt = torch.complex128 if prec == PW_PREC_FP64 else torch.complex64
+    Xs = [torch.from_numpy(np.ascontiguousarray(start_block(40 + k, p.npw, nb).T)).to("cuda").to(dt)
+          for k, p in enumerate(probs)]
+    return s, probs, Xs
+
+
+@pytest.mark.parametrize("prec_name,nb", [("fp64", 40), ("mixed", 32), ("fp64", 7)])
+def test_apply_batch_matches_per_context(torch_cuda, prec_name, nb):
+    """pw_apply_H_batch over the ten k-points of the L = 16 bohr cell (uneven npw,
+    one launch per FFT pass for every (k-point, band) item, the potential of the
+    first context shared) gives every context's pw_apply_H result bitwise; 40
+    columns are two chunks of the 32-band workspace."""
+    torch = torch_cuda
+    from paper_0707_3405_amd import apply_H_batch, PW_PREC_FP64, PW_PREC_MIXED
+    from workloads import make_kpoint_workloads
+    prec = PW_PREC_FP64 if prec_name == "fp64" else PW_PREC_MIXED
+    wl = make_kpoint_workloads()
+    s, probs, Xs = _batch_setup(torch, wl, prec, nb)
+    assert len({p.npw for p in probs}) > 1
+    Ys = [torch.empty_like(X) for X in Xs]
+    Yr = [torch.empty_like(X) for X in Xs]
+    with torch.cuda.stream(s):
+        apply_H_batch([p.ctx for p in probs], Xs, Ys, prec=prec)
+        for p, X, Y in zip(probs, Xs, Yr):
+            p.ctx.apply_H(X, Y, prec=prec)
+    s.synchronize()
+    for k, (Y, R) in enumerate(zip(Ys, Yr)):
+        assert torch.equal(Y, R), k
+
+
+def test_apply_batch_matches_oracle(torch_cuda):
+    """The batched apply against the oracle's dense H at three k-points of the
+    mid-size cell: 1e-13 ||H|| ||x|| per column."""
+    torch = torch_cuda
+    from oracle import pw
+    from paper_0707_3405_amd import apply_H_batch, PW_PREC_FP64
+    from workloads import make_kpoint_workloads
+    wl = make_kpoint_workloads("mid_nl", kpts=[(0, 0, 0), (0.25, 0, 0.5), (0.5, 0.5, 0.5)])
+    s, probs, Xs = _batch_setup(torch, wl, PW_PREC_FP64, 12)
+    Ys = [torch.empty_like(X) for X in Xs]
+    with torch.cuda.stream(s):
+        apply_H_batch([p.ctx for p in probs], Xs, Ys)
+    s.synchronize()
+    for w, p, X, Y in zip(wl, probs, Xs, Ys):
+        mil = pw.sphere(w.cell, w.kfrac, w.ecut)
+        H = pw.dense_hamiltonian(w.cell, w.kfrac, mil, w.vgrid, w.pos, w.lm, w.D)
+        x = X.cpu().numpy().T
+        err = np.linalg.norm(Y.cpu().numpy().T - H @ x, axis=0) / (np.linalg.norm(H, 2) * np.linalg.norm(x, axis=0))
+        assert err.max() <= 1e-13, err.max()
+
+
+def test_apply_batch_graph_replay(torch_cuda):
+    """The batched apply recorded into a graph (kernel launches only) replays to
+    the eager result bitwise, three times, with eager work and synchronisations
+    between the replays."""
+    torch = torch_cuda
+    from paper_0707_3405_amd import apply_H_batch, PW_PREC_FP64
+    from workloads import make_kpoint_workloads
+    wl = make_kpoint_workloads()[:4]
+    s, probs, Xs = _batch_setup(torch, wl, PW_PREC_FP64, 32)
+    ctxs = [p.ctx for p in probs]
+    Ys = [torch.empty_like(X) for X in Xs]
+    with torch.cuda.stream(s):
+        apply_H_batch(ctxs, Xs, Ys)   # eager: also sets the kernels' LDS limits
+    s.synchronize()
+    ref = [Y.clone() for Y in Ys]
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        apply_H_batch(ctxs, Xs, Ys)
+    scratch = [torch.empty_like(X) for X in Xs]
+    for rep in range(3):
+        with torch.cuda.stream(s):
+            for Y in Ys:
+                Y.zero_()
+            for p, X, Z in zip(probs, Xs, scratch):   # eager work between the replays
+                p.ctx.apply_H(X, Z)
+        s.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k, (Y, R) in enumerate(zip(Ys, ref)):
+            assert torch.equal(Y, R), (rep, k)
