@@ -171,12 +171,13 @@ pw_status pw_apply_H(pw_ctx ctx, const void *X, int64_t ldx, void *Y, int64_t ld
  * (sec. 5.2: the k-points are the third level of parallelism; one GPU takes
  * them together).  The contexts share one device, one stream and one FFT
  * grid; their spheres, kinetic energies, projectors and stick buffers are
- * their own, and the local potential of ctxs[0] (its radix split too) serves
- * them all.  Each of the three FFT passes is one launch over every (k-point,
+ * their own, and the local potential of ctxs[0] serves them all, as do its
+ * launch parameters (pw_set_tuning: radix split, FFT tiling, split-K target).  Each of the three FFT passes is one launch over every (k-point,
  * band) work item; the projector products of each context follow on the same
  * stream.  X[k], Y[k]: device, column-major [npw_k x nb], ldx[k], ldy[k] >=
  * npw_k, complex128 for PW_PREC_FP64 and complex64 for the mixed forms, as in
- * pw_apply_H, whose result it gives for every context bitwise.  Every context
+ * pw_apply_H, whose result it gives for every context bitwise when the
+ * contexts hold the same potential and launch parameters.  Every context
  * needs a workspace sized for prec; none may be in use elsewhere during the
  * call.  Errors (bad argument, mismatched contexts) are recorded on ctxs[0].
  * Only kernel launches go to the stream (no allocation, copy or
