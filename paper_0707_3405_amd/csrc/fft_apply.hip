@@ -155,8 +155,10 @@ __global__ void __launch_bounds__((plane_threads<P::N, T>())) k_plane(const Appl
         const int nr = min(rb, N - y0);
         // first inverse x stage, its inputs read straight from the kept columns
         // of A (the other x are zero): no row buffer fill, no barrier for it
+        // (n2 runs fastest over the lanes: the reads of A then step by whole
+        // columns, conflict-free, where rows of one x stepped by R2 and collided)
         for (int it = threadIdx.x; it < nr * R2; it += blockDim.x) {
-            const int r = it % nr, n2 = it / nr;
+            const int n2 = it % R2, r = it / R2;
             const int ypos = digit_rev<P>(y0 + r);
             cpx<T> u[R1];
 #pragma unroll
@@ -184,8 +186,8 @@ __global__ void __launch_bounds__((plane_threads<P::N, T>())) k_plane(const Appl
             for (int n2 = 0; n2 < R2; ++n2) R[r * LD + k1 * R2 + n2] = out[n2];
         }
         __syncthreads();
-        for (int it = threadIdx.x; it < nr * R2; it += blockDim.x) {
-            const int r = it % nr, n2 = it / nr;
+        for (int it = threadIdx.x; it < nr * R2; it += blockDim.x) {   // n2 fastest, as above
+            const int n2 = it % R2, r = it / R2;
             cpx<T> out[R1];
             dif_a<P, -1>(R + r * LD, n2, tw, out);
             const int ypos = digit_rev<P>(y0 + r);

@@ -37,6 +37,7 @@
 // scheme of Henry, Tang and Heinecke, ARITH 2019); the dropped lo*lo term and
 // the rounding of lo leave a relative error near 2^-16 per product.
 #include <atomic>
+#include <type_traits>
 
 #include "pw_internal.h"
 
@@ -65,16 +66,36 @@ struct Mfma<float> {
 constexpr int kTile = 64;      // workgroup tile (complex elements) per dimension
 constexpr int kThreads = 256;  // 4 waves in a 2 x 2 arrangement, 32 x 32 each
 
+
+// Loading operand tiles.  complex64: the loads carry no condition, their
+// addresses are clamped into the operand, and values outside it are replaced
+// by zero only where they are written to LDS (a load under a branch is waited
+// on inside that branch, which turned the prefetch of the next k-block into a
+// stall: the complex64 Gram 138 -> 89 us).  FP64 keeps the zero chosen at the
+// load, which measured 2-7 % faster there (its MFMA takes twice the cycles, so
+// the loads are off the critical path).
 template <class T>
-__device__ __forceinline__ cpx<T> ldg_or_zero(const cpx<T> *p, bool ok) {
-    return ok ? *p : cpx<T>{T(0), T(0)};
+constexpr bool kZeroAtLoad = sizeof(T) == 8;
+template <class T>
+__device__ __forceinline__ cpx<T> tile_load(const cpx<T> *p, bool ok) {
+    if constexpr (kZeroAtLoad<T>) return ok ? *p : cpx<T>{T(0), T(0)};
+    return *p;
 }
-// coefficient element rounded to the block type
 template <class T>
-__device__ __forceinline__ cpx<T> ldc_or_zero(const cd *p, bool ok) {
-    if (!ok) return cpx<T>{T(0), T(0)};
-    const cd v = *p;
-    return cpx<T>{T(v.x), T(v.y)};
+__device__ __forceinline__ cpx<T> tile_keep(const cpx<T> &v, bool ok) {
+    if constexpr (kZeroAtLoad<T>) return v;
+    return cpx<T>{ok ? v.x : T(0), ok ? v.y : T(0)};
+}
+// coefficient elements (complex128), rounded to the block type at the store
+template <class T>
+__device__ __forceinline__ cd coef_load(const cd *p, bool ok) {
+    if constexpr (kZeroAtLoad<T>) return ok ? *p : cd{0.0, 0.0};
+    return *p;
+}
+template <class T>
+__device__ __forceinline__ cpx<T> coef_keep(const cd &v, bool ok) {
+    if constexpr (kZeroAtLoad<T>) return cpx<T>{T(v.x), T(v.y)};
+    return cpx<T>{ok ? T(v.x) : T(0), ok ? T(v.y) : T(0)};
 }
 
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
@@ -176,21 +197,22 @@ __global__ void __launch_bounds__(kThreads)
         Bg[u] = B + (int64_t)(bok[u] ? cb : 0) * ldb;
     }
     cpx<T> ra[4], rb[4];
-    auto gload = [&](int64_t kb) {
-        const int64_t k = kb + li;
-        const bool kin = k < kend;
+    auto gload = [&](int64_t kb) {   // clamped addresses
+        const int64_t k = min(kb + li, kend - 1);
+        const bool kin = kb + li < kend;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            ra[u] = ldg_or_zero(Ag[u] + k, kin && aok[u]);
-            rb[u] = ldg_or_zero(Bg[u] + k, kin && bok[u]);
+            ra[u] = tile_load(Ag[u] + k, kin && aok[u]);
+            rb[u] = tile_load(Bg[u] + k, kin && bok[u]);
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, int64_t kb) {
+        const bool kin = kb + li < kend;
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = 16 * wave + 4 * u + g;
-            sA[buf][c * LDC + li] = ra[u];
-            sB[buf][c * LDC + li] = rb[u];
+            sA[buf][c * LDC + li] = tile_keep(ra[u], kin && aok[u]);
+            sB[buf][c * LDC + li] = tile_keep(rb[u], kin && bok[u]);
         }
     };
 
@@ -210,7 +232,10 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
         for (int nj = 0; nj < 2; ++nj)
             live[mi][nj] = tm * kTile + ia + 16 * mi < p && tn * kTile + jb + 16 * nj < q;
-    auto mma = [&](int buf) {
+    // FULL: every sub-tile of the wave lies inside p x q (all but edge tiles),
+    // so the MFMAs run without the per-sub-tile branches
+    auto mma_t = [&](int buf, auto full) {
+        constexpr bool FULL = decltype(full)::value;
         cpx<T> a[2][4], b[2][4];
 #pragma unroll
         for (int t = 0; t < 2; ++t)
@@ -220,7 +245,8 @@ __global__ void __launch_bounds__(kThreads)
                 b[t][s] = sB[buf][(jb + 16 * t + li) * LDC + 4 * g + s];
             }
         if constexpr (BF) {
-            mma_bf16<-1>(a, b, live, t1, t2, t3);
+            constexpr bool kAll[2][2] = {{true, true}, {true, true}};
+            mma_bf16<-1>(a, b, FULL ? kAll : live, t1, t2, t3);
         } else {
 #pragma unroll
             for (int s = 0; s < 4; ++s)
@@ -228,23 +254,31 @@ __global__ void __launch_bounds__(kThreads)
                 for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
                     for (int nj = 0; nj < 2; ++nj) {
-                        if (!live[mi][nj]) continue;
+                        if (!FULL && !live[mi][nj]) continue;
                         t1[mi][nj] = M::op(a[mi][s].x, b[nj][s].x, t1[mi][nj]);
                         t2[mi][nj] = M::op(a[mi][s].y, b[nj][s].y, t2[mi][nj]);
                         t3[mi][nj] = M::op(a[mi][s].x - a[mi][s].y, b[nj][s].x + b[nj][s].y, t3[mi][nj]);
                     }
         }
     };
+    // (complex64 only: the FP64 kernel measured slower with it)
+    const bool all_live = sizeof(T) == 4 && live[0][0] && live[0][1] && live[1][0] && live[1][1];
+    auto mma = [&](int buf) {
+        if (all_live)
+            mma_t(buf, std::true_type{});
+        else
+            mma_t(buf, std::false_type{});
+    };
     if (kbeg < kend) {
         gload(kbeg);
-        lstore(0);
+        lstore(0, kbeg);
         __syncthreads();
         int buf = 0;
         for (int64_t kb = kbeg; kb < kend; kb += KB) {
             const bool more = kb + KB < kend;
-            if (more) gload(kb + KB);
+            gload(kb + KB);   // past the chunk end: clamped, never stored
             mma(buf);
-            if (more) lstore(buf ^ 1);
+            if (more) lstore(buf ^ 1, kb + KB);
             __syncthreads();
             buf ^= 1;
         }
@@ -335,21 +369,23 @@ __global__ void __launch_bounds__(kThreads)
         cok[u] = col < q;
         Cc[u] = Cm + (int64_t)(cok[u] ? col : 0) * ldc;
     }
-    cpx<T> ra[4], rc[4];
-    auto gload = [&](int kb) {
+    cpx<T> ra[4];
+    cd rc[4];
+    auto gload = [&](int kb) {   // clamped addresses
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int kk = kb + 4 * wave + u;
-            ra[u] = ldg_or_zero(Arow + (int64_t)(kk < p ? kk : 0) * lda, arow && kk < p);
+            ra[u] = tile_load(Arow + (int64_t)(kk < p ? kk : 0) * lda, arow && kk < p);
             const int kc = kb + li;
-            rc[u] = ldc_or_zero<T>(Cc[u] + (kc < p ? kc : 0), cok[u] && kc < p);
+            rc[u] = coef_load<T>(Cc[u] + (kc < p ? kc : 0), cok[u] && kc < p);
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, int kb) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            sA[buf][(4 * wave + u) * LDA + lane] = ra[u];
-            sC[buf][(16 * wave + 4 * u + g) * LDCC + li] = rc[u];
+            const int kk = kb + 4 * wave + u;
+            sA[buf][(4 * wave + u) * LDA + lane] = tile_keep(ra[u], arow && kk < p);
+            sC[buf][(16 * wave + 4 * u + g) * LDCC + li] = coef_keep<T>(rc[u], cok[u] && kb + li < p);
         }
     };
     // 3-multiplication complex product: with t1 = sum ar cr, t2 = sum ai ci,
@@ -392,14 +428,14 @@ __global__ void __launch_bounds__(kThreads)
     };
     if (p > 0) {
         gload(0);
-        lstore(0);
+        lstore(0, 0);
         __syncthreads();
         int buf = 0;
         for (int kb = 0; kb < p; kb += KB) {
             const bool more = kb + KB < p;
-            if (more) gload(kb + KB);
+            gload(kb + KB);   // past p: clamped, never stored
             mma(buf);
-            if (more) lstore(buf ^ 1);
+            if (more) lstore(buf ^ 1, kb + KB);
             __syncthreads();
             buf ^= 1;
         }
@@ -437,7 +473,7 @@ __global__ void __launch_bounds__(kThreads)
 // double buffering as k_gemm_nn_lds.
 constexpr int kNnMaxRb = 5;
 template <class T>
-__global__ void __launch_bounds__(kThreads)
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 8 ? 1 : 3)))
     k_gemm_nn_rows(const cpx<T> *__restrict__ A, int64_t lda, const cd *__restrict__ Cm, int64_t ldc,
                    int64_t K, int p, int q, double alpha, double beta, cpx<T> *Y, int64_t ldy,
                    int groups) {
@@ -470,84 +506,109 @@ __global__ void __launch_bounds__(kThreads)
         cok[u] = col < q;
         Cc[u] = Cm + (int64_t)(cok[u] ? col : 0) * ldc;
     }
-    cpx<T> ra0[4], ra1[4], rc[4];
-    auto gload = [&](int kb) {
+    cpx<T> ra0[4], ra1[4];
+    cd rc[4];
+    auto gload = [&](int kb) {   // clamped addresses
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int kk = kb + 4 * wave + u;
             const int64_t ko = (int64_t)(kk < p ? kk : 0) * lda;
-            ra0[u] = ldg_or_zero(Arow0 + ko, arow0 && kk < p);
-            ra1[u] = ldg_or_zero(Arow1 + ko, arow1 && kk < p);
+            ra0[u] = tile_load(Arow0 + ko, arow0 && kk < p);
+            ra1[u] = tile_load(Arow1 + ko, arow1 && kk < p);
             const int kc = kb + li;
-            rc[u] = ldc_or_zero<T>(Cc[u] + (kc < p ? kc : 0), cok[u] && kc < p);
+            rc[u] = coef_load<T>(Cc[u] + (kc < p ? kc : 0), cok[u] && kc < p);
         }
     };
-    auto lstore = [&](int buf) {
+    auto lstore = [&](int buf, int kb) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            sA[buf][(4 * wave + u) * LDA + lane] = ra0[u];
-            if (lane < NRW - 64) sA[buf][(4 * wave + u) * LDA + 64 + lane] = ra1[u];
-            sC[buf][(16 * wave + 4 * u + gq) * LDCC + li] = rc[u];
+            const int kk = kb + 4 * wave + u;
+            sA[buf][(4 * wave + u) * LDA + lane] = tile_keep(ra0[u], arow0 && kk < p);
+            if (lane < NRW - 64)
+                sA[buf][(4 * wave + u) * LDA + 64 + lane] = tile_keep(ra1[u], arow1 && kk < p);
+            sC[buf][(16 * wave + 4 * u + gq) * LDCC + li] = coef_keep<T>(rc[u], cok[u] && kb + li < p);
         }
     };
-    // 3-multiplication complex product (as in k_gemm_nn_lds)
-    v4 t1[kNnMaxRb], t2[kNnMaxRb], t3[kNnMaxRb];
-#pragma unroll
-    for (int i = 0; i < kNnMaxRb; ++i) t1[i] = t2[i] = t3[i] = v4{0, 0, 0, 0};
     const bool colv = cbase + 16 * wave < q;   // this wave's 16 columns (uniform per wave)
-    auto mma = [&](int buf) {
+    // For complex64 the k loop and the output are instantiated per row-block
+    // count NB, so that the MFMA sequence has no branches (the LDS reads are
+    // issued ahead of the MFMAs) and each instance holds only its own
+    // accumulators; FP64 (NB = 0) keeps one loop over the runtime count, which
+    // measured faster there (the FP32 MFMA takes half the cycles and leaves
+    // the LDS latency exposed).
+    auto run = [&](auto nbc) {
+        constexpr int NB = decltype(nbc)::value;
+        constexpr int NA = NB ? NB : kNnMaxRb;
+        // 3-multiplication complex product (as in k_gemm_nn_lds)
+        v4 t1[NA], t2[NA], t3[NA];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const cpx<T> b = sC[buf][(16 * wave + li) * LDCC + 4 * gq + s];
-            const T bs = b.x + b.y;
+        for (int i = 0; i < NA; ++i) t1[i] = t2[i] = t3[i] = v4{0, 0, 0, 0};
+        auto mma = [&](int buf) {
 #pragma unroll
-            for (int i = 0; i < kNnMaxRb; ++i) {
-                if (i >= nrb) break;
-                const cpx<T> a = sA[buf][(4 * gq + s) * LDA + 16 * i + li];
-                t1[i] = M::op(a.x, b.x, t1[i]);
-                t2[i] = M::op(a.y, b.y, t2[i]);
-                t3[i] = M::op(a.x + a.y, bs, t3[i]);
+            for (int s = 0; s < 4; ++s) {
+                const cpx<T> b = sC[buf][(16 * wave + li) * LDCC + 4 * gq + s];
+                const T bs = b.x + b.y;
+#pragma unroll
+                for (int i = 0; i < NA; ++i) {
+                    if (!NB && i >= nrb) break;
+                    const cpx<T> a = sA[buf][(4 * gq + s) * LDA + 16 * i + li];
+                    t1[i] = M::op(a.x, b.x, t1[i]);
+                    t2[i] = M::op(a.y, b.y, t2[i]);
+                    t3[i] = M::op(a.x + a.y, bs, t3[i]);
+                }
+            }
+        };
+        if (p > 0) {   // every wave stages its share of A, also when its columns are idle
+            gload(0);
+            lstore(0, 0);
+        }
+        __syncthreads();
+        if (p > 0) {
+            int buf = 0;
+            for (int kb = 0; kb < p; kb += KB) {
+                const bool more = kb + KB < p;
+                gload(kb + KB);   // past p: clamped, never stored
+                if (colv) mma(buf);
+                if (more) lstore(buf ^ 1, kb + KB);
+                __syncthreads();
+                buf ^= 1;
+            }
+        }
+        // every read of A finished before the last barrier: Y == A is safe when
+        // one workgroup spans all q (each workgroup writes only its own rows)
+        if (!colv) return;
+#pragma unroll
+        for (int i = 0; i < NA; ++i) {
+            if (!NB && i >= nrb) break;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t row = rbase + 16 * i + M::row(gq, r);
+                const int j = cbase + 16 * wave + li;
+                if (row < K && j < q) {
+                    cpx<T> *y = Y + (int64_t)j * ldy + row;
+                    T yr = T(alpha) * (t1[i][r] - t2[i][r]);
+                    T yi = T(alpha) * (t3[i][r] - t1[i][r] - t2[i][r]);
+                    if (beta != 0.0) {
+                        const cpx<T> o = *y;
+                        yr += T(beta) * o.x;
+                        yi += T(beta) * o.y;
+                    }
+                    *y = cpx<T>{yr, yi};
+                }
             }
         }
     };
-    if (p > 0) {   // every wave stages its share of A, also when its columns are idle
-        gload(0);
-        lstore(0);
+    static_assert(kNnMaxRb == 5, "row-block cases below");
+    if constexpr (sizeof(T) == 8) {
+        run(std::integral_constant<int, 0>{});
+        return;
     }
-    __syncthreads();
-    if (p > 0) {
-        int buf = 0;
-        for (int kb = 0; kb < p; kb += KB) {
-            const bool more = kb + KB < p;
-            if (more) gload(kb + KB);
-            if (colv) mma(buf);
-            if (more) lstore(buf ^ 1);
-            __syncthreads();
-            buf ^= 1;
-        }
-    }
-    // every read of A finished before the last barrier: Y == A is safe when
-    // one workgroup spans all q (each workgroup writes only its own rows)
-    if (!colv) return;
-#pragma unroll
-    for (int i = 0; i < kNnMaxRb; ++i) {
-        if (i >= nrb) break;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int64_t row = rbase + 16 * i + M::row(gq, r);
-            const int j = cbase + 16 * wave + li;
-            if (row < K && j < q) {
-                cpx<T> *y = Y + (int64_t)j * ldy + row;
-                T yr = T(alpha) * (t1[i][r] - t2[i][r]);
-                T yi = T(alpha) * (t3[i][r] - t1[i][r] - t2[i][r]);
-                if (beta != 0.0) {
-                    const cpx<T> o = *y;
-                    yr += T(beta) * o.x;
-                    yi += T(beta) * o.y;
-                }
-                *y = cpx<T>{yr, yi};
-            }
-        }
+    switch (nrb) {
+    case 5: run(std::integral_constant<int, 5>{}); break;
+    case 4: run(std::integral_constant<int, 4>{}); break;
+    case 3: run(std::integral_constant<int, 3>{}); break;
+    case 2: run(std::integral_constant<int, 2>{}); break;
+    default: run(std::integral_constant<int, 1>{}); break;
     }
 }
 
