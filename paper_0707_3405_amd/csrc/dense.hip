@@ -18,6 +18,8 @@ namespace {
 
 __device__ __forceinline__ cd cconj(cd a) { return {a.x, -a.y}; }
 __device__ __forceinline__ cd cmulz(cd a, cd b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
+__device__ __forceinline__ cf cconj(cf a) { return {a.x, -a.y}; }
+__device__ __forceinline__ cf cmulz(cf a, cf b) { return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 
 // 1 / d to within an ulp without the division sequence: the hardware
 // reciprocal refined by two Newton steps (d finite and normal).  Measured on
@@ -30,10 +32,18 @@ __device__ __forceinline__ double rcp_nr(double d) {
     return r;
 }
 
+// FP32: the hardware reciprocal (within 1 ulp) and square root
+__device__ __forceinline__ float rcp_nr(float d) { return __builtin_amdgcn_rcpf(d); }
+__device__ __forceinline__ double sqrt_r(double x) { return sqrt(x); }
+__device__ __forceinline__ float sqrt_r(float x) { return __builtin_sqrtf(x); }
+
 // value of v in lane `lane` (uniform), as a wave-uniform value
 __device__ __forceinline__ double lane_read(double v, int lane) {
     return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
                             __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+__device__ __forceinline__ float lane_read(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 
 // Block-wide sum of one double per thread: wave shuffles, then the wave
@@ -407,15 +417,21 @@ __device__ __forceinline__ double dpp_f64(double x) {
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_f64(float x) {   // the FP32 form (one 32-bit move)
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
+}
 // sum over the 16 lanes of a DPP row; every lane of the row gets the same value
-__device__ __forceinline__ double row16_sum(double x) {
+template <class R>
+__device__ __forceinline__ R row16_sum(R x) {
     x += dpp_f64<0xB1>(x);    // quad_perm [1,0,3,2]
     x += dpp_f64<0x4E>(x);    // quad_perm [2,3,0,1]
     x += dpp_f64<0x141>(x);   // row_half_mirror
     x += dpp_f64<0x140>(x);   // row_mirror
     return x;
 }
-__device__ __forceinline__ double quad_sum(double x) {
+template <class R>
+__device__ __forceinline__ R quad_sum(R x) {
     x += dpp_f64<0xB1>(x);
     x += dpp_f64<0x4E>(x);
     return x;
@@ -427,16 +443,20 @@ __device__ __forceinline__ double dpp_f64_rows(double x) {
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, false);
     return __hiloint2double(hi, lo);
 }
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_f64_rows(float x) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
+}
 // Wave sum returned as a wave-uniform value, without LDS: the row sums, then
 // row_bcast:15 adds row 0 into row 1 and row 2 into row 3, row_bcast:31 adds
 // rows 0 + 1 into rows 2 and 3, and lane 63 holds the total (same order of
 // additions in every wave).
-__device__ __forceinline__ double wave_total(double x) {
+template <class R>
+__device__ __forceinline__ R wave_total(R x) {
     x = row16_sum(x);
     x += dpp_f64_rows<0x142, 0xA>(x);   // row_bcast:15
     x += dpp_f64_rows<0x143, 0xC>(x);   // row_bcast:31
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), 63),
-                            __builtin_amdgcn_readlane(__double2loint(x), 63));
+    return lane_read(x, 63);
 }
 
 // Look-ahead form of the register-resident reduction (same Householder
@@ -449,63 +469,68 @@ __device__ __forceinline__ double wave_total(double x) {
 // updating.  Then the partials of y = A v (row partials one per half-wave,
 // column partials summed over lane quads by DPP, both in LDS) and w = tau y -
 // nu v by four threads per row: three barriers per column instead of four.
-template <int T>
+// R is the arithmetic type: double, or float for the Rayleigh-Ritz problems of
+// the complex64 stage of the mixed iteration (the input is rounded to float,
+// the outputs are stored as double).
+template <int T, class R>
 __global__ void __launch_bounds__(1024)
     k_hetrd_la(cd *__restrict__ A, int64_t lda, int n, double *__restrict__ dd,
                double *__restrict__ ee, cd *__restrict__ tau_out) {
+    using C = cpx<R>;
     constexpr int NR = 32 * T;
     constexpr int NE = T * (T + 1) / 2;
-    __shared__ cd vs[2][NR];          // reflectors of steps of both parities
-    __shared__ cd ws[NR];             // w of the last step, zero outside its live rows
-    __shared__ cd pr[32][NR + 1];     // row sums of y, one per half-wave (padded)
-    __shared__ cd pc[8][NR + 1];      // column sums of y, one per lane quad (padded)
-    __shared__ double sv[16];         // per-wave partials of Re(v^H A v)
-    __shared__ cd s_tau[2];
+    __shared__ C vs[2][NR];          // reflectors of steps of both parities
+    __shared__ C ws[NR];             // w of the last step, zero outside its live rows
+    __shared__ C pr[32][NR + 1];     // row sums of y, one per half-wave (padded)
+    __shared__ C pc[8][NR + 1];      // column sums of y, one per lane quad (padded)
+    __shared__ R sv[16];         // per-wave partials of Re(v^H A v)
+    __shared__ C s_tau[2];
     const int t = threadIdx.x, ti = t & 31, tj = t >> 5, wave = t >> 6, lane = t & 63;
 
-    cd E[NE];
+    C E[NE];
     unroll_for<0, T>([&](auto a_) {
         constexpr int a = a_;
         unroll_for<0, a + 1>([&](auto b_) {
             constexpr int b = b_;
             const int i = ti + 32 * a, c = tj + 32 * b;
-            cd m = {0.0, 0.0};
+            C m = {R(0), R(0)};
             if (i < n && c < n) {   // exact Hermitian part (A + A^H) / 2
                 const cd x = A[(int64_t)c * lda + i], y = A[(int64_t)i * lda + c];
-                m = cd{0.5 * (x.x + y.x), 0.5 * (x.y - y.y)};
-                if (i == c) m.y = 0.0;
+                m = C{R(0.5 * (x.x + y.x)), R(0.5 * (x.y - y.y))};
+                if (i == c) m.y = R(0);
             }
             E[a * (a + 1) / 2 + b] = m;
         });
     });
-    for (int i = t; i < NR; i += 1024) vs[0][i] = vs[1][i] = ws[i] = cd{0.0, 0.0};
+    for (int i = t; i < NR; i += 1024) vs[0][i] = vs[1][i] = ws[i] = C{R(0), R(0)};
     __syncthreads();
     // A -= w v^H + v w^H on the live tiles of step jm (v = vs[par], w = ws)
     auto update = [&](int jm, int par) {
         unroll_for<0, T>([&](auto a_) {
             constexpr int a = a_;
             if (32 * a + 31 <= jm) return;
-            const cd vi = vs[par][ti + 32 * a], wi = ws[ti + 32 * a];
+            const C vi = vs[par][ti + 32 * a], wi = ws[ti + 32 * a];
             unroll_for<0, a + 1>([&](auto b_) {
                 constexpr int b = b_;
                 if (32 * b + 31 <= jm) return;
-                const cd vj = cconj(vs[par][tj + 32 * b]), wj = cconj(ws[tj + 32 * b]);
-                const cd u1 = cmulz(wi, vj), u2 = cmulz(vi, wj);
-                cd &e = E[a * (a + 1) / 2 + b];
-                e.x -= u1.x + u2.x;
-                e.y -= u1.y + u2.y;
+                const C vj = cconj(vs[par][tj + 32 * b]), wj = cconj(ws[tj + 32 * b]);
+                const C u1 = cmulz(wi, vj), u2 = cmulz(vi, wj);
+                const C e = E[a * (a + 1) / 2 + b];   // whole-element update: member writes
+                E[a * (a + 1) / 2 + b] = C{e.x - (u1.x + u2.x), e.y - (u1.y + u2.y)};   // kept FP32 E in scratch
             });
         });
     };
     // entry (ti + 32 a, col) of this lane for the column tile jb (zero above it)
-    auto col_entry = [&](auto a_, int jb) -> cd {
+    auto col_entry = [&](auto a_, int jb) -> C {
         constexpr int a = decltype(a_)::value;
-        cd x = {0.0, 0.0};
-        unroll_for<0, a + 1>([&](auto b_) {
+        R xr = R(0), xi = R(0);   // selects by component (an element-wise pick became
+        unroll_for<0, a + 1>([&](auto b_) {   // a dynamically indexed stack array in FP32)
             constexpr int b = b_;
-            if (b == jb) x = E[a * (a + 1) / 2 + b];
+            const bool hit = b == jb;
+            xr = hit ? E[a * (a + 1) / 2 + b].x : xr;
+            xi = hit ? E[a * (a + 1) / 2 + b].y : xi;
         });
-        return x;
+        return C{xr, xi};
     };
     for (int j = 0; j + 1 < n; ++j) {
         const int par = j & 1, own = j & 31, jb = j >> 5;
@@ -515,55 +540,55 @@ __global__ void __launch_bounds__(1024)
         if (owner) {
             // ---- reflector j from column j, held by half-wave `own` ----
             const int base = (own & 1) * 32;
-            double sg = 0.0;
+            R sg = R(0);
             unroll_for<0, T>([&](auto a_) {
                 constexpr int a = a_;
                 const int r = ti + 32 * a;
                 if (r >= j + 2 && r < n) {
-                    const cd x = col_entry(a_, jb);
+                    const C x = col_entry(a_, jb);
                     sg += x.x * x.x + x.y * x.y;
                 }
             });
             sg = row16_sum(sg);
             sg += dpp_f64_rows<0x142, 0xA>(sg);   // lanes 31 and 63: the two half-wave totals
-            const double sigma = lane_read(sg, base + 31);
+            const R sigma = lane_read(sg, base + 31);
             const int a1 = (j + 1) >> 5;
-            cd xa = {0.0, 0.0}, xd = {0.0, 0.0};
+            C xa = {R(0), R(0)}, xd = {R(0), R(0)};
             unroll_for<0, T>([&](auto a_) {
                 constexpr int a = a_;
                 if (a == a1) xa = col_entry(a_, jb);
                 if (a == jb) xd = col_entry(a_, jb);
             });
-            const cd alpha = {lane_read(xa.x, base + ((j + 1) & 31)), lane_read(xa.y, base + ((j + 1) & 31))};
-            const double djj = lane_read(xd.x, base + own);
-            cd tau, scale;
-            double beta;
-            if (sigma == 0.0 && alpha.y == 0.0) {
-                tau = cd{0.0, 0.0};
+            const C alpha = {lane_read(xa.x, base + ((j + 1) & 31)), lane_read(xa.y, base + ((j + 1) & 31))};
+            const R djj = lane_read(xd.x, base + own);
+            C tau, scale;
+            R beta;
+            if (sigma == R(0) && alpha.y == R(0)) {
+                tau = C{R(0), R(0)};
                 beta = alpha.x;
-                scale = cd{0.0, 0.0};
+                scale = C{R(0), R(0)};
             } else {
-                const double nrm = sqrt(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
-                beta = alpha.x >= 0.0 ? -nrm : nrm;
-                const double dr = alpha.x - beta, di = alpha.y;
-                const double ib = rcp_nr(beta), iden = rcp_nr(dr * dr + di * di);
-                tau = cd{-dr * ib, -alpha.y * ib};
-                scale = cd{dr * iden, -di * iden};
+                const R nrm = sqrt_r(alpha.x * alpha.x + alpha.y * alpha.y + sigma);
+                beta = alpha.x >= R(0) ? -nrm : nrm;
+                const R dr = alpha.x - beta, di = alpha.y;
+                const R ib = rcp_nr(beta), iden = rcp_nr(dr * dr + di * di);
+                tau = C{-dr * ib, -alpha.y * ib};
+                scale = C{dr * iden, -di * iden};
             }
-            const bool reflect = !(tau.x == 0.0 && tau.y == 0.0);
+            const bool reflect = !(tau.x == R(0) && tau.y == R(0));
             if (tj == own) {   // the owning half-wave writes the whole reflector
                 unroll_for<0, T>([&](auto a_) {
                     constexpr int a = a_;
                     const int r = ti + 32 * a;
-                    cd vv = {0.0, 0.0};
-                    if (reflect && r > j && r < n) vv = r == j + 1 ? cd{1.0, 0.0} : cmulz(col_entry(a_, jb), scale);
+                    C vv = {R(0), R(0)};
+                    if (reflect && r > j && r < n) vv = r == j + 1 ? C{R(1), R(0)} : cmulz(col_entry(a_, jb), scale);
                     vs[par][r] = vv;
-                    if (r > j + 1 && r < n) A[(int64_t)j * lda + r] = vv;   // kept for the back-transform
+                    if (r > j + 1 && r < n) A[(int64_t)j * lda + r] = cd{vv.x, vv.y};   // kept for the back-transform
                 });
                 if (ti == own) {
                     dd[j] = djj;
                     ee[j] = beta;
-                    tau_out[j] = tau;
+                    tau_out[j] = cd{tau.x, tau.y};
                     A[(int64_t)j * lda + j + 1] = cd{beta, 0.0};
                     s_tau[par] = tau;
                 }
@@ -573,39 +598,39 @@ __global__ void __launch_bounds__(1024)
         __syncthreads();
         // ---- partials of y = A v ----
         {
-            double vpart = 0.0;
+            R vpart = R(0);
             unroll_for<0, T>([&](auto a_) {   // row sums over this lane's tiles of row ti + 32a
                 constexpr int a = a_;
                 if (32 * a + 31 <= j) return;
-                double rr = 0.0, ri = 0.0;
+                R rr = R(0), ri = R(0);
                 unroll_for<0, a + 1>([&](auto b_) {
                     constexpr int b = b_;
                     if (32 * b + 31 <= j) return;
-                    const cd e = E[a * (a + 1) / 2 + b];
-                    const cd vj = vs[par][tj + 32 * b];
+                    const C e = E[a * (a + 1) / 2 + b];
+                    const C vj = vs[par][tj + 32 * b];
                     rr += e.x * vj.x - e.y * vj.y;
                     ri += e.x * vj.y + e.y * vj.x;
                 });
-                const cd vi = vs[par][ti + 32 * a];
+                const C vi = vs[par][ti + 32 * a];
                 vpart += vi.x * rr + vi.y * ri;
-                pr[tj][ti + 32 * a] = cd{rr, ri};
+                pr[tj][ti + 32 * a] = C{rr, ri};
             });
             unroll_for<0, T - 1>([&](auto b_) {   // conj(e) v_i into y_j, off-diagonal tiles
                 constexpr int b = b_;
                 if (32 * b + 31 <= j) return;
-                double cr = 0.0, ci = 0.0;
+                R cr = R(0), ci = R(0);
                 unroll_for<b + 1, T>([&](auto a_) {
                     constexpr int a = a_;
-                    const cd e = E[a * (a + 1) / 2 + b];
-                    const cd vi = vs[par][ti + 32 * a];
+                    const C e = E[a * (a + 1) / 2 + b];
+                    const C vi = vs[par][ti + 32 * a];
                     cr += e.x * vi.x + e.y * vi.y;
                     ci += e.x * vi.y - e.y * vi.x;
                 });
-                const cd vj = vs[par][tj + 32 * b];
+                const C vj = vs[par][tj + 32 * b];
                 vpart += vj.x * cr + vj.y * ci;
                 cr = quad_sum(cr);   // the eight quad sums of a column are added in the w step
                 ci = quad_sum(ci);
-                if ((ti & 3) == 0) pc[ti >> 2][tj + 32 * b] = cd{cr, ci};
+                if ((ti & 3) == 0) pc[ti >> 2][tj + 32 * b] = C{cr, ci};
             });
             vpart = wave_total(vpart);
             if (lane == 0) sv[wave] = vpart;
@@ -615,9 +640,9 @@ __global__ void __launch_bounds__(1024)
         if (t < 4 * NR) {
             const int r = t >> 2, q = t & 3;
             const bool live = r > j && r < n;
-            double sr = 0.0, si = 0.0;
+            R sr = R(0), si = R(0);
             if (live) {
-                double er = 0.0, ei = 0.0;
+                R er = R(0), ei = R(0);
 #pragma unroll
                 for (int h = 0; h < 8; h += 2) {
                     sr += pr[8 * q + h][r].x;
@@ -636,16 +661,16 @@ __global__ void __launch_bounds__(1024)
             }
             sr = quad_sum(sr);
             si = quad_sum(si);
-            double vhy = (sv[4 * q] + sv[4 * q + 1]) + (sv[4 * q + 2] + sv[4 * q + 3]);
+            R vhy = (sv[4 * q] + sv[4 * q + 1]) + (sv[4 * q + 2] + sv[4 * q + 3]);
             vhy = quad_sum(vhy);
-            const cd tau = s_tau[par];
-            const double nu = 0.5 * (tau.x * tau.x + tau.y * tau.y) * vhy;
+            const C tau = s_tau[par];
+            const R nu = R(0.5) * (tau.x * tau.x + tau.y * tau.y) * vhy;
             if (q == 0) {
-                cd wr = {0.0, 0.0};
+                C wr = {R(0), R(0)};
                 if (live) {
-                    const cd ty = cmulz(tau, cd{sr, si});
-                    const cd vr = vs[par][r];
-                    wr = cd{ty.x - nu * vr.x, ty.y - nu * vr.y};
+                    const C ty = cmulz(tau, C{sr, si});
+                    const C vr = vs[par][r];
+                    wr = C{ty.x - nu * vr.x, ty.y - nu * vr.y};
                 }
                 ws[r] = wr;
             }
@@ -765,10 +790,13 @@ __global__ void __launch_bounds__(kStebzThreads) k_stebz(const double *__restric
 // (entry i in lane i % 64, slot i / 64) and read with readlane, so the Sturm
 // chains never wait on LDS; the bounds come from wave reductions (min / max,
 // exact in any order).  Same points, counts and rounds as k_stebz.  n <= 64 RPL.
+// rel_tol: relative width at which a bracket stops (DBL_EPSILON; FLT_EPSILON
+// for a tridiagonal matrix from the FP32 reduction, whose eigenvalues carry
+// FP32 rounding anyway: 3 rounds instead of 6)
 template <int RPL>
 __global__ void __launch_bounds__(kStebzThreads) k_stebz_w(const double *__restrict__ dd,
                                                            const double *__restrict__ ee, int n, int /*k*/,
-                                                           double *__restrict__ w) {
+                                                           double *__restrict__ w, double rel_tol) {
     __shared__ int wfirst[2][kStebzThreads / 64];
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
     constexpr int NP = 2 * kStebzThreads;
@@ -801,7 +829,7 @@ __global__ void __launch_bounds__(kStebzThreads) k_stebz_w(const double *__restr
     double lo = gl, hi = gu;
     for (int round = 0; round < 16; ++round) {
         const double width = hi - lo;
-        if (width <= 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+        if (width <= 2.0 * rel_tol * fmax(fabs(lo), fabs(hi)) + pivmin) break;
         const double x1 = lo + width * (double)(t + 1) / (double)(NP + 1);
         const double x2 = lo + width * (double)(t + 1 + kStebzThreads) / (double)(NP + 1);
         // Sturm counts at x1 and x2 (the recurrence of sturm_count2)
@@ -1605,7 +1633,7 @@ size_t heev_scratch_bytes(int n, int k) {
 }
 
 void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t ldv, void *scratch,
-                     int *status, hipStream_t st) {
+                     int *status, hipStream_t st, bool fp32_reduction) {
     PW_REQUIRE(n >= 1 && n <= 1024 && k >= 1 && k <= n, PW_ERR_ARG, "heev: need 1 <= k <= n <= 1024");
     auto align = [](size_t x) { return (x + 255) & ~size_t(255); };
     char *p = static_cast<char *>(scratch);
@@ -1620,14 +1648,21 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     // 1. tridiagonalisation (the trailing block of A is overwritten in both triangles)
     if (n <= 32 * kRfMaxT) {
         const int T = (n + 31) / 32;
-        switch (T) {
-            case 1: hipLaunchKernelGGL(k_hetrd_la<1>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
-            case 2: hipLaunchKernelGGL(k_hetrd_la<2>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
-            case 3: hipLaunchKernelGGL(k_hetrd_la<3>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
-            case 4: hipLaunchKernelGGL(k_hetrd_la<4>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
-            case 5: hipLaunchKernelGGL(k_hetrd_la<5>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
-            default: hipLaunchKernelGGL(k_hetrd_la<6>, dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
-        }
+        auto go = [&](auto r_) {
+            using R = decltype(r_);
+            switch (T) {
+                case 1: hipLaunchKernelGGL((k_hetrd_la<1, R>), dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+                case 2: hipLaunchKernelGGL((k_hetrd_la<2, R>), dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+                case 3: hipLaunchKernelGGL((k_hetrd_la<3, R>), dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+                case 4: hipLaunchKernelGGL((k_hetrd_la<4, R>), dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+                case 5: hipLaunchKernelGGL((k_hetrd_la<5, R>), dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+                default: hipLaunchKernelGGL((k_hetrd_la<6, R>), dim3(1), dim3(1024), 0, st, A, lda, n, d, e, tau); break;
+            }
+        };
+        if (fp32_reduction)
+            go(0.0f);
+        else
+            go(0.0);
     } else {
         TrdState S;
         S.v[0] = reinterpret_cast<cd *>(p);
@@ -1651,11 +1686,13 @@ void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t
     // 2. eigenvalues
     const size_t sm2 = 2 * (size_t)n * 8;
     // one workgroup per eigenvalue, spread over k CUs
+    const bool lowp = fp32_reduction && n <= 32 * kRfMaxT;
+    const double tol = lowp ? (double)FLT_EPSILON : DBL_EPSILON;
     switch ((n + 63) / 64) {
-        case 1: hipLaunchKernelGGL(k_stebz_w<1>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w); break;
-        case 2: hipLaunchKernelGGL(k_stebz_w<2>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w); break;
-        case 3: hipLaunchKernelGGL(k_stebz_w<3>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w); break;
-        case 4: hipLaunchKernelGGL(k_stebz_w<4>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w); break;
+        case 1: hipLaunchKernelGGL(k_stebz_w<1>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w, tol); break;
+        case 2: hipLaunchKernelGGL(k_stebz_w<2>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w, tol); break;
+        case 3: hipLaunchKernelGGL(k_stebz_w<3>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w, tol); break;
+        case 4: hipLaunchKernelGGL(k_stebz_w<4>, dim3(k), dim3(kStebzThreads), 0, st, d, e, n, k, w, tol); break;
         default: hipLaunchKernelGGL(k_stebz, dim3(k), dim3(kStebzThreads), sm2, st, d, e, n, k, w); break;
     }
     // 3. inverse iteration

@@ -140,10 +140,14 @@ void launch_gemm_tn_bf16(const cf *A, int64_t lda, const cf *B, int64_t ldb, int
 void launch_gemm_nn_bf16(const cf *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
                          double alpha, double beta, cf *Y, int64_t ldy, hipStream_t st);
 
-// Small dense FP64 (single workgroup).
+// Small dense FP64 (single workgroup).  fp32_reduction: the Householder
+// reduction (n <= 192) runs in FP32 on the input rounded to float (the
+// Rayleigh-Ritz problems of the complex64 stage of the mixed iteration); the
+// eigenvalues, inverse iteration, orthogonalisation and back-transform stay
+// FP64.
 size_t heev_scratch_bytes(int n, int k);
 void launch_heev_f64(cd *A, int64_t lda, int n, int k, double *w, cd *V, int64_t ldv,
-                     void *scratch, int *status, hipStream_t st);
+                     void *scratch, int *status, hipStream_t st, bool fp32_reduction = false);
 // Library-owned device scratch of the entry point that allocates nothing
 // (noalloc.hip): a fixed array per GPU.  static_scratch_setup resolves its
 // device address with `device` current (once per device, from pw_create);

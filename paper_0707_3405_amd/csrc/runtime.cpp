@@ -471,6 +471,10 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
                  int floor_iters = 0, bool *final_res_above_tol = nullptr) {
     hipStream_t st = c->stream;
     const int64_t ld = c->ldp, npw = c->npw;
+    // complex64 blocks carry FP32 rounding: their Rayleigh-Ritz problems are
+    // reduced to tridiagonal form in FP32 as well (the FP64 stage that ends a
+    // mixed solve, and every FP64 solve, reduce in FP64)
+    constexpr bool kLowpReduction = std::is_same<S, pw::cf>::value;
     PhaseTimer tm;
     tm.st = st;
     hipEvent_t t_begin, t_end;
@@ -570,7 +574,8 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
             rr_gram(c, p, Z, HZ, ld, mb);
             tm.end(PhaseTimer::kGemm, e0);
             auto e1 = tm.begin();
-            pw::launch_heev_f64(p.Agram, mb, mb, mb, p.w, p.Cc, 3 * m, p.heev_scratch, c->d_status, st);
+            pw::launch_heev_f64(p.Agram, mb, mb, mb, p.w, p.Cc, 3 * m, p.heev_scratch, c->d_status, st,
+                                kLowpReduction);
             tm.end(PhaseTimer::kDense, e1);
             auto e2 = tm.begin();
             pw::launch_gemm_nn(Z, ld, p.Cc, 3 * m, npw, mb, mb, 1.0, 0.0, p.Z[1 - cur], ld, st);
@@ -691,7 +696,7 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
                 tm.end(PhaseTimer::kGemm, e0);
                 auto e1 = tm.begin();
                 pw::launch_heev_f64(p.Agram, nz, nz, mb, p.w, p.Cc, 3 * m, p.heev_scratch, c->d_status,
-                                    st);
+                                    st, kLowpReduction);
                 tm.end(PhaseTimer::kDense, e1);
             }
             // P coefficients for the active columns: C with the X rows removed,
