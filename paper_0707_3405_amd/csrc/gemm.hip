@@ -168,16 +168,29 @@ template <class T, bool BF>
 __global__ void __launch_bounds__(kThreads)
     k_gemm_tn_lds(const cpx<T> *__restrict__ A, int64_t lda, const cpx<T> *__restrict__ B,
                   int64_t ldb, int64_t K, int p, int q, int64_t kchunk, int tiles_m, int tiles_n,
-                  int nsplit, cpx<T> *__restrict__ part) {
+                  int nsplit, cpx<T> *__restrict__ part, int herm) {
     using M = Mfma<T>;
     using v4 = typename M::v4;
     constexpr int KB = 16, LDC = KB + 1;
     __shared__ cpx<T> sA[2][kTile * LDC], sB[2][kTile * LDC];
-    const int total = tiles_m * tiles_n * nsplit;
+    // herm: the product is Hermitian (A^H B with p = q), only the tiles on and
+    // above the diagonal are formed, column by column, and the partials are
+    // packed per tile (64 x 64 each)
+    const int ntile = herm ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+    const int total = ntile * nsplit;
     const int lid = xcd_logical(blockIdx.x, total);
-    const int split = lid / (tiles_m * tiles_n);
-    const int tile = lid % (tiles_m * tiles_n);
-    const int tm = tile % tiles_m, tn = tile / tiles_m;
+    const int split = lid / ntile;
+    const int tile = lid % ntile;
+    int tm, tn;
+    if (herm) {
+        int t = tile;
+        tn = 0;
+        while (t > tn) t -= ++tn;
+        tm = t;
+    } else {
+        tm = tile % tiles_m;
+        tn = tile / tiles_m;
+    }
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int li = lane & 15, g = lane >> 4;
     const int64_t kbeg = (int64_t)split * kchunk;
@@ -283,7 +296,7 @@ __global__ void __launch_bounds__(kThreads)
             buf ^= 1;
         }
     }
-    cpx<T> *P = part + (size_t)split * p * q;
+    cpx<T> *P = part + (size_t)split * (herm ? (size_t)ntile * kTile * kTile : (size_t)p * q);
     const int i0 = tm * kTile + ia, j0 = tn * kTile + jb;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -293,9 +306,10 @@ __global__ void __launch_bounds__(kThreads)
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + 16 * mi + M::row(g, r);
                 const int j = j0 + 16 * nj + li;
+                const size_t at = herm ? ((size_t)tile * kTile + (j - tn * kTile)) * kTile + (i - tm * kTile)
+                                       : (size_t)j * p + i;
                 if (i < p && j < q)
-                    P[(size_t)j * p + i] = cpx<T>{t1[mi][nj][r] + t2[mi][nj][r],
-                                                  t3[mi][nj][r] - t1[mi][nj][r] + t2[mi][nj][r]};
+                    P[at] = cpx<T>{t1[mi][nj][r] + t2[mi][nj][r], t3[mi][nj][r] - t1[mi][nj][r] + t2[mi][nj][r]};
             }
 }
 
@@ -305,13 +319,30 @@ __global__ void __launch_bounds__(kThreads)
 template <class T>
 __global__ void __launch_bounds__(256)
     k_reduce_parts(const cpx<T> *__restrict__ part, int nsplit, int p, int q, cd *C, int64_t ldc,
-                   const double *__restrict__ scale_row, double beta) {
+                   const double *__restrict__ scale_row, double beta, int ntile_herm) {
     __shared__ cd red[4][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t n = (int64_t)p * q;
+    // herm (ntile_herm > 0): partials packed per upper tile; element e of tile
+    // t is (ii, jj) = (e % 64, e / 64) of the tile's (tm, tn), and the sum is
+    // also stored, conjugated, at the mirrored position below the diagonal
+    const bool herm = ntile_herm > 0;
+    const int64_t n = herm ? (int64_t)ntile_herm * kTile * kTile : (int64_t)p * q;
     const int64_t idx = (int64_t)blockIdx.x * 64 + lane;
+    int i = 0, j = 0;
+    bool ok = idx < n;
+    if (ok && herm) {
+        int t = (int)(idx / (kTile * kTile)), tn = 0;
+        const int e = (int)(idx % (kTile * kTile));
+        while (t > tn) t -= ++tn;
+        i = t * kTile + e % kTile;
+        j = tn * kTile + e / kTile;
+        ok = i < p && j < q;
+    } else if (ok) {
+        i = (int)(idx % p);
+        j = (int)(idx / p);
+    }
     double sr = 0.0, si = 0.0;
-    if (idx < n)
+    if (ok)
         for (int s = wave; s < nsplit; s += 4) {
             const cpx<T> v = part[(size_t)s * n + idx];
             sr += (double)v.x;
@@ -319,10 +350,9 @@ __global__ void __launch_bounds__(256)
         }
     red[wave][lane] = cd{sr, si};
     __syncthreads();
-    if (wave != 0 || idx >= n) return;
+    if (wave != 0 || !ok) return;
     sr = ((red[0][lane].x + red[1][lane].x) + red[2][lane].x) + red[3][lane].x;
     si = ((red[0][lane].y + red[1][lane].y) + red[2][lane].y) + red[3][lane].y;
-    const int i = (int)(idx % p), j = (int)(idx / p);
     if (scale_row) {
         sr *= scale_row[i];
         si *= scale_row[i];
@@ -333,6 +363,7 @@ __global__ void __launch_bounds__(256)
         si += beta * c->y;
     }
     *c = cd{sr, si};
+    if (herm && i / kTile < j / kTile) C[(int64_t)i * ldc + j] = cd{sr, -si};
 }
 
 // NN: the k-blocks are staged through LDS: per 16-wide k-block the workgroup
@@ -659,29 +690,34 @@ size_t gemm_tn_part_elems(int64_t K, int p, int q, int *nsplit_out) {
     return (size_t)ns * p * q;
 }
 
+// herm: A^H B is Hermitian (B = H A for a Hermitian H, p = q); only the
+// tiles on and above the diagonal are formed and the rest is mirrored
 template <class T, bool BF = false>
 void gemm_tn_impl(const cpx<T> *A, int64_t lda, const cpx<T> *B, int64_t ldb, int64_t K, int p, int q,
                   cd *C, int64_t ldc, const double *scale_row, double beta, cd *part, size_t part_elems,
-                  hipStream_t st) {
+                  hipStream_t st, bool herm = false) {
     if (p <= 0 || q <= 0) return;
     PW_REQUIRE(K > 0, PW_ERR_ARG, "empty contraction (callers form a zero product themselves)");
     const int tiles_m = (p + kTile - 1) / kTile, tiles_n = (q + kTile - 1) / kTile;
+    herm = herm && p == q && tiles_m >= 2 && !scale_row && beta == 0.0;
+    const int ntile = herm ? tiles_m * (tiles_m + 1) / 2 : tiles_m * tiles_n;
+    const size_t per_split = herm ? (size_t)ntile * kTile * kTile : (size_t)p * q;
     const int target = thread_tuning().tn_split_wgs > 0 ? thread_tuning().tn_split_wgs : PW_SPLIT_WGS;
-    int ns = choose_split(K, tiles_m * tiles_n, target);
-    if ((size_t)ns * p * q > part_elems) ns = (int)(part_elems / ((size_t)p * q));
+    int ns = choose_split(K, ntile, target);
+    if ((size_t)ns * per_split > part_elems) ns = (int)(part_elems / per_split);
     PW_REQUIRE(ns >= 1, PW_ERR_NOMEM, "GEMM partial buffer too small");
     int64_t kchunk = (K + ns - 1) / ns;
     kchunk = (kchunk + 15) / 16 * 16;
     ns = (int)((K + kchunk - 1) / kchunk);
     if (ns < 1) ns = 1;
-    const int total = tiles_m * tiles_n * ns;
+    const int total = ntile * ns;
     // partials in the block type (the buffer is sized for complex128)
     cpx<T> *pt = reinterpret_cast<cpx<T> *>(part);
     hipLaunchKernelGGL((k_gemm_tn_lds<T, BF>), dim3(total), dim3(kThreads), 0, st, A, lda, B, ldb, K, p, q,
-                       kchunk, tiles_m, tiles_n, ns, pt);
-    const int64_t n = (int64_t)p * q;
+                       kchunk, tiles_m, tiles_n, ns, pt, herm ? 1 : 0);
+    const int64_t n = (int64_t)per_split;
     hipLaunchKernelGGL(k_reduce_parts<T>, dim3((unsigned)((n + 63) / 64)), dim3(256), 0, st, pt, ns, p,
-                       q, C, ldc, scale_row, beta);
+                       q, C, ldc, scale_row, beta, herm ? ntile : 0);
     PW_HIP(hipGetLastError());
 }
 
@@ -742,8 +778,16 @@ void launch_gemm_nn(const cf *A, int64_t lda, const cd *C, int64_t ldc, int64_t 
 }
 void launch_gemm_tn_bf16(const cf *A, int64_t lda, const cf *B, int64_t ldb, int64_t K, int p, int q,
                          cd *C, int64_t ldc, const double *scale_row, double beta, cd *part,
-                         size_t part_elems, hipStream_t st) {
-    gemm_tn_impl<float, true>(A, lda, B, ldb, K, p, q, C, ldc, scale_row, beta, part, part_elems, st);
+                         size_t part_elems, hipStream_t st, bool herm) {
+    gemm_tn_impl<float, true>(A, lda, B, ldb, K, p, q, C, ldc, scale_row, beta, part, part_elems, st, herm);
+}
+void launch_gemm_herm(const cd *A, int64_t lda, const cd *B, int64_t ldb, int64_t K, int p, cd *C,
+                      int64_t ldc, cd *part, size_t part_elems, hipStream_t st) {
+    gemm_tn_impl(A, lda, B, ldb, K, p, p, C, ldc, nullptr, 0.0, part, part_elems, st, true);
+}
+void launch_gemm_herm(const cf *A, int64_t lda, const cf *B, int64_t ldb, int64_t K, int p, cd *C,
+                      int64_t ldc, cd *part, size_t part_elems, hipStream_t st) {
+    gemm_tn_impl(A, lda, B, ldb, K, p, p, C, ldc, nullptr, 0.0, part, part_elems, st, true);
 }
 void launch_gemm_nn_bf16(const cf *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
                          double alpha, double beta, cf *Y, int64_t ldy, hipStream_t st) {

@@ -136,7 +136,13 @@ void launch_gemm_nn(const cf *A, int64_t lda, const cd *C, int64_t ldc, int64_t 
 //   the same two products on complex64 blocks with split-bf16 MFMA products
 void launch_gemm_tn_bf16(const cf *A, int64_t lda, const cf *B, int64_t ldb, int64_t K, int p, int q,
                          cd *C, int64_t ldc, const double *scale_row, double beta, cd *part,
-                         size_t part_elems, hipStream_t st);
+                         size_t part_elems, hipStream_t st, bool herm = false);
+// A^H B for a Hermitian product (B = H A, H Hermitian): the p x p result with
+// only the tiles on and above the diagonal formed, the others mirrored
+void launch_gemm_herm(const cd *A, int64_t lda, const cd *B, int64_t ldb, int64_t K, int p, cd *C,
+                      int64_t ldc, cd *part, size_t part_elems, hipStream_t st);
+void launch_gemm_herm(const cf *A, int64_t lda, const cf *B, int64_t ldb, int64_t K, int p, cd *C,
+                      int64_t ldc, cd *part, size_t part_elems, hipStream_t st);
 void launch_gemm_nn_bf16(const cf *A, int64_t lda, const cd *C, int64_t ldc, int64_t K, int p, int q,
                          double alpha, double beta, cf *Y, int64_t ldy, hipStream_t st);
 

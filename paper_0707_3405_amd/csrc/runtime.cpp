@@ -387,12 +387,12 @@ void rr_gram(pw_ctx_s *c, const Plan<S> &p, const S *Z, const S *HZ, int64_t ld,
     if constexpr (std::is_same<S, pw::cf>::value) {
         if (c->gram_bf16) {
             pw::launch_gemm_tn_bf16(Z, ld, HZ, ld, c->npw, nz, nz, p.Agram, nz, nullptr, 0.0, p.part,
-                                    p.part_elems, c->stream);
+                                    p.part_elems, c->stream, true);
             return;
         }
     }
-    pw::launch_gemm_tn(Z, ld, HZ, ld, c->npw, nz, nz, p.Agram, nz, nullptr, 0.0, p.part, p.part_elems,
-                       c->stream);
+    // Z^H H Z is Hermitian: the tiles below the diagonal are mirrored
+    pw::launch_gemm_herm(Z, ld, HZ, ld, c->npw, nz, p.Agram, nz, p.part, p.part_elems, c->stream);
 }
 
 template <class S>
@@ -749,8 +749,7 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
 
     if (final_rr) {   // Rayleigh-Ritz over all M bands
         auto ef = tm.begin();
-        pw::launch_gemm_tn(X, ldx, p.HXall, ld, npw, M, M, p.Agram, M, nullptr, 0.0, p.part,
-                           p.part_elems, st);
+        pw::launch_gemm_herm(X, ldx, p.HXall, ld, npw, M, p.Agram, M, p.part, p.part_elems, st);
         pw::launch_heev_f64(p.Agram, M, M, M, p.w, p.U, M, p.heev_scratch, c->d_status, st);
         pw::launch_gemm_nn(X, ldx, p.U, M, npw, M, M, 1.0, 0.0, p.T, ld, st);
         pw::launch_copy_cols(p.T, ld, X, ldx, npw, M, st);
@@ -1491,8 +1490,7 @@ pw_status pw_autotune(pw_ctx c, int32_t nb, pw_tuning *out) {
         const double *vapply = c->d_v;   // the potential in the layout of the split being timed
         auto apply = [&] { pw::launch_fft_apply(c->sp, vapply, p.Z[0], ld, p.HZ[0] + 0, ld, nb, p.Sb, st); };
         auto gemm = [&] {
-            pw::launch_gemm_tn(p.Z[0], ld, p.HZ[0], ld, npw, nz, nz, p.Agram, nz, nullptr, 0.0, p.part,
-                               p.part_elems, st);
+            pw::launch_gemm_herm(p.Z[0], ld, p.HZ[0], ld, npw, nz, p.Agram, nz, p.part, p.part_elems, st);
             if (np > 0)
                 pw::launch_gemm_tn(c->d_B, c->ldp, p.Z[0], ld, npw, np, m, p.Pj, np, c->d_D, 0.0, p.part,
                                    p.part_elems, st);
