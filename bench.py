@@ -191,7 +191,8 @@ def main():
 
     import torch
     from paper_0707_3405_amd import (PlaneWaveProblem, PW_PREC_FP64, PW_PREC_MIXED,
-                                     PW_PREC_MIXED_BF16, PW_PREC_MIXED_BF16_GRAM, solve_batch)
+                                     PW_PREC_MIXED_BF16, PW_PREC_MIXED_BF16_GRAM, PW_PREC_MIXED_FP32_RR,
+                                     solve_batch)
     from workloads import make_workload, make_kpoint_workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -235,7 +236,8 @@ def main():
 
         # ---- the same cell in the mixed forms (complex64 iteration + FP64 refinement;
         # the BF16 forms also run the projector products, and the second one the
-        # Rayleigh-Ritz Gram, on split-bf16 matrix cores)
+        # Rayleigh-Ritz Gram, on split-bf16 matrix cores; the FP32-RR form reduces the
+        # complex64 stage's Rayleigh-Ritz problems to tridiagonal form in FP32)
         def run_mixed(prec, label):
             solve(prec)
             torch.cuda.synchronize()
@@ -263,11 +265,12 @@ def main():
                     "phase_ms": {k: mst[k] for k in ("ms_apply", "ms_gemm", "ms_dense", "ms_vec",
                                                      "ms_final_rr")}}
 
-        mixed = mixed_bf16 = mixed_bf16_gram = None
+        mixed = mixed_bf16 = mixed_bf16_gram = mixed_fp32_rr = None
         if args.mixed_steps > 0:
             mixed = run_mixed(PW_PREC_MIXED, "mixed")
             mixed_bf16 = run_mixed(PW_PREC_MIXED_BF16, "mixed-bf16")
             mixed_bf16_gram = run_mixed(PW_PREC_MIXED_BF16_GRAM, "mixed-bf16-gram")
+            mixed_fp32_rr = run_mixed(PW_PREC_MIXED_FP32_RR, "mixed-fp32-rr")
 
         # ---- the same cell as the pencil (H, O), O = I + sum_p q_p |beta_p><beta_p|
         generalized = None
@@ -553,6 +556,7 @@ def main():
         "mixed": mixed,
         "mixed_bf16": mixed_bf16,
         "mixed_bf16_gram": mixed_bf16_gram,
+        "mixed_fp32_rr": mixed_fp32_rr,
         "generalized": generalized,
         "autotuned": tuned,
         "hx_full_ms_per_64_bands": hx_full,

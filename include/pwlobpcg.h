@@ -66,7 +66,12 @@ typedef enum {
  * GEMMs of H X); PW_PREC_MIXED_BF16_GRAM also forms the Rayleigh-Ritz Gram
  * matrix Z^H (H Z) of the complex64 stage on BF16 matrix cores (the CholQR
  * Grams, constraint products and block updates stay FP32).  Both BF16 forms
- * refine in FP64 exactly like PW_PREC_MIXED. */
+ * refine in FP64 exactly like PW_PREC_MIXED.  PW_PREC_MIXED_FP32_RR is
+ * PW_PREC_MIXED with the Householder reduction of the complex64 stage's
+ * Rayleigh-Ritz eigenproblems (sizes up to 192) in FP32 on the FP64 Gram
+ * rounded to float, and their eigenvalues bisected to FP32 width; inverse
+ * iteration, orthogonalisation and back-transform stay FP64, and the FP64
+ * stage is that of PW_PREC_MIXED. */
 typedef enum {
     PW_PREC_FP64 = 0,          /* every step in complex128 / float64 */
     PW_PREC_MIXED = 1,         /* complex64 iteration, FP64 small dense steps and refinement */
@@ -74,8 +79,10 @@ typedef enum {
                                   B (D B^H X)) on BF16 matrix cores: complex64 operands
                                   split into hi + lo bf16 pairs, three products per real
                                   product, FP32 accumulation */
-    PW_PREC_MIXED_BF16_GRAM = 3  /* PW_PREC_MIXED_BF16 with the Rayleigh-Ritz Gram of the
+    PW_PREC_MIXED_BF16_GRAM = 3, /* PW_PREC_MIXED_BF16 with the Rayleigh-Ritz Gram of the
                                     complex64 stage on the same split-bf16 products */
+    PW_PREC_MIXED_FP32_RR = 4    /* PW_PREC_MIXED with the complex64 stage's Rayleigh-Ritz
+                                    tridiagonal reduction in FP32 */
 } pw_precision;
 
 /* Per-solve counters and phase times (milliseconds, measured with HIP events

@@ -20,7 +20,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpwlobpc
 PW_OK, PW_ERR_ARG, PW_ERR_STATE, PW_ERR_NOMEM, PW_ERR_DEVICE, PW_ERR_NOT_CONVERGED, PW_ERR_NUMERIC = range(7)
 STATUS_NAMES = {0: "PW_OK", 1: "PW_ERR_ARG", 2: "PW_ERR_STATE", 3: "PW_ERR_NOMEM",
                 4: "PW_ERR_DEVICE", 5: "PW_ERR_NOT_CONVERGED", 6: "PW_ERR_NUMERIC"}
-PW_PREC_FP64, PW_PREC_MIXED, PW_PREC_MIXED_BF16, PW_PREC_MIXED_BF16_GRAM = 0, 1, 2, 3
+PW_PREC_FP64, PW_PREC_MIXED, PW_PREC_MIXED_BF16, PW_PREC_MIXED_BF16_GRAM, PW_PREC_MIXED_FP32_RR = 0, 1, 2, 3, 4
 
 EXPORTS = ("pw_create", "pw_destroy", "pw_last_error", "pw_init_basis", "pw_fft_sizes",
            "pw_get_miller", "pw_get_kinetic", "pw_set_local_potential", "pw_set_projectors",

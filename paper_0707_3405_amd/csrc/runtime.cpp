@@ -130,6 +130,7 @@ struct pw_ctx_s {
     pw::cf *d_B32 = nullptr;   // complex64 copy for the mixed form
     bool proj_bf16 = false;    // complex64 projector products on split-bf16 MFMA
     bool gram_bf16 = false;    // complex64 Rayleigh-Ritz Gram on split-bf16 MFMA
+    bool rr_fp32 = false;      // complex64 stage: Rayleigh-Ritz tridiagonal reduction in FP32
     pw::Tuning tune;           // launch parameters (pw_autotune / pw_set_tuning)
     double *d_D = nullptr;
     double *d_Q = nullptr;     // overlap coefficients (generalized form); null: O = I
@@ -296,7 +297,7 @@ size_t plan_bytes(const pw_ctx_s &c, int M, int m, pw_precision prec) {
 
 void require_precision(pw_precision prec) {
     PW_REQUIRE(prec == PW_PREC_FP64 || prec == PW_PREC_MIXED || prec == PW_PREC_MIXED_BF16 ||
-                   prec == PW_PREC_MIXED_BF16_GRAM,
+                   prec == PW_PREC_MIXED_BF16_GRAM || prec == PW_PREC_MIXED_FP32_RR,
                PW_ERR_ARG, "unknown precision");
 }
 
@@ -471,10 +472,10 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
                  int floor_iters = 0, bool *final_res_above_tol = nullptr) {
     hipStream_t st = c->stream;
     const int64_t ld = c->ldp, npw = c->npw;
-    // complex64 blocks carry FP32 rounding: their Rayleigh-Ritz problems are
-    // reduced to tridiagonal form in FP32 as well (the FP64 stage that ends a
-    // mixed solve, and every FP64 solve, reduce in FP64)
-    constexpr bool kLowpReduction = std::is_same<S, pw::cf>::value;
+    // PW_PREC_MIXED_FP32_RR: the complex64 stage, whose blocks carry FP32
+    // rounding, reduces its Rayleigh-Ritz problems to tridiagonal form in FP32
+    // as well (its FP64 stage, and every other form, reduce in FP64)
+    const bool kLowpReduction = std::is_same<S, pw::cf>::value && c->rr_fp32;
     PhaseTimer tm;
     tm.st = st;
     hipEvent_t t_begin, t_end;
@@ -828,6 +829,7 @@ pw_status solve(pw_ctx_s *c, int M, int m, double tol, int max_iter, pw_precisio
         ensure_mixed_tables(c);
         c->proj_bf16 = prec == PW_PREC_MIXED_BF16 || prec == PW_PREC_MIXED_BF16_GRAM;
         c->gram_bf16 = prec == PW_PREC_MIXED_BF16_GRAM;
+        c->rr_fp32 = prec == PW_PREC_MIXED_FP32_RR;
         Plan<pw::cf> p32 = ready_plan<pw::cf>(c, M, m);
         if (use_guess) pw::launch_copy_cols(X, ldx, p32.Xs, c->ldp, c->npw, M, c->stream);
         // an unconverged block here is not an error: the FP64 stage continues from it

@@ -173,12 +173,13 @@ def test_apply_bf16_paper_scale(torch_cuda, oracle_problem):
     assert np.all(err <= bound), np.max(err / bound)
 
 
-@pytest.mark.parametrize("prec_name", ["PW_PREC_MIXED_BF16", "PW_PREC_MIXED_BF16_GRAM"])
+@pytest.mark.parametrize("prec_name", ["PW_PREC_MIXED_BF16", "PW_PREC_MIXED_BF16_GRAM", "PW_PREC_MIXED_FP32_RR"])
 @pytest.mark.parametrize("name", ["mid_nl", "fcc32_l12", "fcc108_l20"])
 def test_solve_bf16_vs_oracle(torch_cuda, name, prec_name):
-    """Both BF16 forms: projector products on split-bf16 matrix cores, and in
-    the second also the Rayleigh-Ritz Gram of the complex64 stage; the FP64
-    refinement brings every eigenvalue to the oracle's."""
+    """The BF16 forms (projector products on split-bf16 matrix cores, and in
+    the second also the Rayleigh-Ritz Gram of the complex64 stage) and the
+    FP32-RR form (the complex64 stage's Rayleigh-Ritz tridiagonal reduction in
+    FP32): the FP64 refinement brings every eigenvalue to the oracle's."""
     torch = torch_cuda
     import paper_0707_3405_amd as pkg
     from workloads import make_workload
@@ -210,6 +211,26 @@ def test_bf16_gram_is_its_own_path(torch_cuda):
         torch.cuda.synchronize()
         out[prec] = (eig, X.clone())
     (e1, x1), (e2, x2) = out[PW_PREC_MIXED_BF16], out[PW_PREC_MIXED_BF16_GRAM]
+    assert not torch.equal(x1, x2)
+    assert np.abs(e1 - e2).max() <= 1e-8
+
+
+def test_fp32_rr_is_its_own_path(torch_cuda):
+    """PW_PREC_MIXED_FP32_RR runs another complex64 stage than PW_PREC_MIXED
+    (the FP32 reduction changes its vectors) and reaches the same eigenvalues;
+    the FP64 small-eigensolver entry point is untouched by it (bitwise)."""
+    torch = torch_cuda
+    from paper_0707_3405_amd import PlaneWaveProblem, PW_PREC_MIXED, PW_PREC_MIXED_FP32_RR
+    from workloads import make_workload
+    w = make_workload("mid_nl")
+    out = {}
+    for prec in (PW_PREC_MIXED, PW_PREC_MIXED_FP32_RR):
+        prob = PlaneWaveProblem.from_workload(w, device=0, prec=prec)
+        eig, X, _ = prob.solve(w.tol, max_iter=300)
+        torch.cuda.synchronize()
+        out[prec] = (eig, X.clone(), prob.ctx.get_stats())
+    (e1, x1, s1), (e2, x2, s2) = out[PW_PREC_MIXED], out[PW_PREC_MIXED_FP32_RR]
+    assert s1["mixed_iterations"] > 0 and s2["mixed_iterations"] > 0
     assert not torch.equal(x1, x2)
     assert np.abs(e1 - e2).max() <= 1e-8
 
