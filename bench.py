@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # calibration; profiles/hbm_bytes_fcc108_l20.txt) for the kernels as they were profiled,
 # over the same kernels as the launch time (the Grams include k_reduce_parts);
 # set an entry to None when its kernels change.
-TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 3.63e8, "gemm_complex64": 1.84e8, "dense": 5.42e6}
+TRAFFIC_MEASURED = {"apply": 6.15e8, "gemm": 3.63e8, "gemm_complex64": 1.84e8, "dense": 5.43e6}
 FP64_PEAK_TFLOPS = 78.6        # MI355X dense FP64 (vector and matrix)
 FP32_PEAK_TFLOPS = 157.3       # MI355X dense FP32 (matrix)
 WORKLOAD = "fcc108_l20"
@@ -378,7 +378,7 @@ def main():
     eig_tflops = eig_flops / (t_eig * 1e-3) / 1e12
 
     roofs = {
-        "dense": dict(bound="alu", kernel="pw_small_eigh 192x192 lowest 64 (k_hetrd_la<6>, k_stebz_w<3>, "
+        "dense": dict(bound="alu", kernel="pw_small_eigh 192x192 lowest 64 (k_hetrd_la<6, double>, k_stebz_w<3>, "
                       "k_stein_w<3>, k_orth_chol2, k_unmtr_w<3>, k_check_w)", achieved=eig_tflops, peak=FP64_PEAK_TFLOPS, unit="TFLOP/s",
                       frac=eig_tflops / FP64_PEAK_TFLOPS, traffic=TRAFFIC_MEASURED["dense"],
                       algorithmic=f"{eig_flops:.3e} FLOP per call (16/3 n^3 + 8 n^2 k)", launch_ms=t_eig,
