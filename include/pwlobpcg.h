@@ -86,7 +86,8 @@ typedef enum {
 } pw_precision;
 
 /* Per-solve counters and phase times (milliseconds, measured with HIP events
- * on the context stream). */
+ * on the context stream).  The five phase times are measured only while
+ * pw_set_phase_timing is on (they read 0 otherwise); ms_total always is. */
 typedef struct {
     int32_t iterations;        /* LOBPCG iterations summed over blocks */
     int32_t blocks;            /* number of blocks */
@@ -291,6 +292,14 @@ pw_status pw_density(pw_ctx ctx, const void *X, int64_t ldx, int32_t nb, const d
 pw_status pw_get_residuals(pw_ctx ctx, double *res);
 /* Counters and phase times of the last solve. */
 pw_status pw_get_stats(pw_ctx ctx, pw_stats *stats);
+/* Phase timing of the solves on ctx: on != 0 records a pair of HIP events
+ * around every phase of every iteration (the ms_apply .. ms_final_rr of
+ * pw_stats).  Each record is a marker packet between two kernels on the
+ * stream; at the paper-scale cell (12 phases per iteration, ~600 iterations)
+ * they lengthen a solve by ~5 %, so timing is off by default and the phase
+ * times then read 0.  Applies to every later solve on ctx (pw_lobpcg_solve,
+ * pw_lobpcg_solve_batch). */
+pw_status pw_set_phase_timing(pw_ctx ctx, int32_t on);
 
 /* ---- Building blocks of the iteration, exported for per-step parity tests ----
  * All pointers are device pointers; complex128 column-major; asynchronous on

@@ -28,7 +28,7 @@ EXPORTS = ("pw_create", "pw_destroy", "pw_last_error", "pw_init_basis", "pw_fft_
            "pw_get_residuals", "pw_get_stats", "pw_gram", "pw_block_update", "pw_small_eigh",
            "pw_residuals", "pw_gram_mixed", "pw_block_update_mixed", "pw_lobpcg_solve_batch",
            "pw_density", "pw_set_overlap", "pw_apply_O", "pw_chol_inv", "pw_autotune",
-           "pw_set_tuning", "pw_small_eigh_noalloc", "pw_apply_H_batch")
+           "pw_set_tuning", "pw_small_eigh_noalloc", "pw_apply_H_batch", "pw_set_phase_timing")
 
 
 class PWError(RuntimeError):
@@ -99,6 +99,7 @@ def load_library():
         "pw_lobpcg_solve": (ctypes.c_int, [P, I32, I32, D, I32, ctypes.c_int, P, I64, I32, P]),
         "pw_get_residuals": (ctypes.c_int, [P, P]),
         "pw_get_stats": (ctypes.c_int, [P, ctypes.POINTER(PWStats)]),
+        "pw_set_phase_timing": (ctypes.c_int, [P, I32]),
         "pw_gram": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, P, I64]),
         "pw_block_update": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, D, D, P, I64]),
         "pw_gram_mixed": (ctypes.c_int, [P, P, I64, P, I64, I64, I32, I32, P, I64]),
@@ -347,6 +348,10 @@ class Context:
         out = np.zeros(nbands, np.float64)
         self._check(self.lib.pw_get_residuals(self.h, out.ctypes.data))
         return out
+
+    def set_phase_timing(self, on=True):
+        """Per-phase HIP events in later solves (pw_stats phase times; ~5 % slower)."""
+        self._check(self.lib.pw_set_phase_timing(self.h, 1 if on else 0))
 
     def get_stats(self):
         s = PWStats()

@@ -38,6 +38,7 @@ struct Arena {
 struct PhaseTimer {
     enum Phase { kApply = 0, kGemm, kDense, kVec, kFinal, kCount };
     hipStream_t st = nullptr;
+    bool on = true;   // off: no events are recorded (each one is a marker between kernels)
     std::vector<hipEvent_t> pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> open;
     size_t next = 0;
@@ -51,11 +52,13 @@ struct PhaseTimer {
         return pool[next++];
     }
     hipEvent_t begin() {
+        if (!on) return nullptr;
         hipEvent_t e = get();
         PW_HIP(hipEventRecord(e, st));
         return e;
     }
     void end(int phase, hipEvent_t b) {
+        if (!on) return;
         hipEvent_t e = get();
         PW_HIP(hipEventRecord(e, st));
         open.push_back({phase, {b, e}});
@@ -131,6 +134,7 @@ struct pw_ctx_s {
     bool proj_bf16 = false;    // complex64 projector products on split-bf16 MFMA
     bool gram_bf16 = false;    // complex64 Rayleigh-Ritz Gram on split-bf16 MFMA
     bool rr_fp32 = false;      // complex64 stage: Rayleigh-Ritz tridiagonal reduction in FP32
+    bool phase_timing = false; // per-phase HIP events in the solves (pw_set_phase_timing)
     pw::Tuning tune;           // launch parameters (pw_autotune / pw_set_tuning)
     double *d_D = nullptr;
     double *d_Q = nullptr;     // overlap coefficients (generalized form); null: O = I
@@ -478,6 +482,7 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
     const bool kLowpReduction = std::is_same<S, pw::cf>::value && c->rr_fp32;
     PhaseTimer tm;
     tm.st = st;
+    tm.on = c->phase_timing;
     hipEvent_t t_begin, t_end;
     PW_HIP(hipEventCreate(&t_begin));
     PW_HIP(hipEventCreate(&t_end));
@@ -1603,6 +1608,13 @@ pw_status pw_get_stats(pw_ctx c, pw_stats *stats) {
     return guard(c, [&] {
         PW_REQUIRE(stats, PW_ERR_ARG, "null output");
         *stats = c->stats;
+        return PW_OK;
+    });
+}
+
+pw_status pw_set_phase_timing(pw_ctx c, int32_t on) {
+    return guard(c, [&] {
+        c->phase_timing = on != 0;
         return PW_OK;
     });
 }

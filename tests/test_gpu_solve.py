@@ -98,6 +98,26 @@ def test_solve_warm_restart_converges_immediately(torch_cuda):
     assert np.abs(eig2 - eig).max() <= 1e-10
 
 
+def test_phase_timing_switch(torch_cuda):
+    """Phase times are measured only with pw_set_phase_timing on (off by
+    default: the per-phase events lengthen a solve); the eigenpairs are the
+    same either way, bitwise."""
+    torch = torch_cuda
+    w, prob, eig, X, status, res = _solve(torch, "gamma_l10")
+    X = X.clone()
+    off = prob.ctx.get_stats()
+    phase_keys = ("ms_apply", "ms_gemm", "ms_dense", "ms_vec", "ms_final_rr")
+    assert off["ms_total"] > 0 and all(off[k] == 0 for k in phase_keys)
+    prob.ctx.set_phase_timing(True)
+    eig2, X2, _ = prob.solve(w.tol, max_iter=300)
+    on = prob.ctx.get_stats()
+    prob.ctx.set_phase_timing(False)
+    assert all(on[k] >= 0 for k in phase_keys) and on["ms_apply"] > 0 and on["ms_dense"] > 0
+    assert sum(on[k] for k in phase_keys) <= 1.05 * on["ms_total"]
+    assert on["iterations"] == off["iterations"]
+    assert np.array_equal(eig2, eig) and torch.equal(X2, X)
+
+
 def test_not_converged_status(torch_cuda):
     torch = torch_cuda
     from paper_0707_3405_amd import PW_ERR_NOT_CONVERGED
