@@ -180,10 +180,12 @@ void launch_band_dots(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, cons
                       const cf *OX = nullptr, int64_t ldox = 0);
 void launch_resid_precond(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
                           int64_t npw, int nb, const double *theta, const double *ekin_nrm, cd *W,
-                          int64_t ldw, double *part, double *res, hipStream_t st);
+                          int64_t ldw, double *part, double *res, hipStream_t st,
+                          const int *status = nullptr);   // status: also stored as res[nb]
 void launch_resid_precond(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, const double *kin,
                           int64_t npw, int nb, const double *theta, const double *ekin_nrm, cf *W,
-                          int64_t ldw, double *part, double *res, hipStream_t st);
+                          int64_t ldw, double *part, double *res, hipStream_t st,
+                          const int *status = nullptr);   // status: also stored as res[nb]
 void launch_build_projectors_f64(const double *qvec, int64_t npw, int natom, const double *pos,
                                  int nlm, const int *lm, double pref, cd *B, int64_t ldb,
                                  hipStream_t st);

@@ -618,13 +618,13 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
                 pw::launch_band_dots(Z, ld, HZ, ld, c->sp.kin, npw, mb, p.rpart, p.theta, p.ekin, st, OZ,
                                      ld);
                 pw::launch_resid_precond(gen ? OZ : Z, ld, HZ, ld, c->sp.kin, npw, mb, p.theta, p.ekin,
-                                         (S *)nullptr, 0, p.rpart, p.res, st);
+                                         (S *)nullptr, 0, p.rpart, p.res, st, c->d_status);
                 tm.end(PhaseTimer::kVec, e);
             }
-            PW_HIP(hipMemcpyAsync(hres, p.res, sizeof(double) * mb, hipMemcpyDeviceToHost, st));
-            PW_HIP(hipMemcpyAsync(hstat, c->d_status, sizeof(int), hipMemcpyDeviceToHost, st));
+            // the norms and, in res[mb], the status word: one copy per iteration
+            PW_HIP(hipMemcpyAsync(hres, p.res, sizeof(double) * (mb + 1), hipMemcpyDeviceToHost, st));
             PW_HIP(hipStreamSynchronize(st));
-            const int status = *hstat;
+            const int status = (int)hres[mb];
             tm.collect();
             if (status & 4) throw Error{PW_ERR_NUMERIC, "non-finite value in the iteration"};
             if (status & 1) {

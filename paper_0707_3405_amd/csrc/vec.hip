@@ -142,8 +142,12 @@ __global__ void __launch_bounds__(kThreads)
     W[(int64_t)jj * ldw + r] = narrow<S>(k * (hb.x - th * a.x), k * (hb.y - th * a.y));
 }
 
+// status (optional): the context's status word, appended as res[nb] so that one
+// copy brings the norms and the breakdown flags to the host
 __global__ void k_resid_final(const double *__restrict__ part, int nchunk, int nb,
-                              const double *__restrict__ nrm2, double *__restrict__ res) {
+                              const double *__restrict__ nrm2, double *__restrict__ res,
+                              const int *__restrict__ status) {
+    if (status && threadIdx.x == 0) res[nb] = (double)*status;
     for (int b = threadIdx.x; b < nb; b += blockDim.x) {
         double s = 0.0;
         for (int c = 0; c < nchunk; ++c) s += part[(int64_t)c * nb + b];
@@ -278,23 +282,23 @@ void launch_band_dots(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, cons
 template <class S>
 void resid_impl(const S *X, int64_t ldx, const S *HX, int64_t ldhx, const double *kin, int64_t npw,
                 int nb, const double *theta, const double *ekin, S *W, int64_t ldw, double *part,
-                double *res, hipStream_t st) {
+                double *res, hipStream_t st, const int *status) {
     const int nchunk = (int)((npw + kChunk - 1) / kChunk);
     hipLaunchKernelGGL(k_resid<S>, dim3(nchunk, nb), dim3(kThreads), 0, st, X, ldx, HX, ldhx, kin, npw,
                        nb, theta, ekin, W, ldw, part);
     // ekin array carries |x|^2 in its second half (see k_band_dots_final)
-    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, st, part, nchunk, nb, ekin + nb, res);
+    hipLaunchKernelGGL(k_resid_final, dim3(1), dim3(256), 0, st, part, nchunk, nb, ekin + nb, res, status);
     PW_HIP(hipGetLastError());
 }
 void launch_resid_precond(const cd *X, int64_t ldx, const cd *HX, int64_t ldhx, const double *kin,
                           int64_t npw, int nb, const double *theta, const double *ekin, cd *W,
-                          int64_t ldw, double *part, double *res, hipStream_t st) {
-    resid_impl(X, ldx, HX, ldhx, kin, npw, nb, theta, ekin, W, ldw, part, res, st);
+                          int64_t ldw, double *part, double *res, hipStream_t st, const int *status) {
+    resid_impl(X, ldx, HX, ldhx, kin, npw, nb, theta, ekin, W, ldw, part, res, st, status);
 }
 void launch_resid_precond(const cf *X, int64_t ldx, const cf *HX, int64_t ldhx, const double *kin,
                           int64_t npw, int nb, const double *theta, const double *ekin, cf *W,
-                          int64_t ldw, double *part, double *res, hipStream_t st) {
-    resid_impl(X, ldx, HX, ldhx, kin, npw, nb, theta, ekin, W, ldw, part, res, st);
+                          int64_t ldw, double *part, double *res, hipStream_t st, const int *status) {
+    resid_impl(X, ldx, HX, ldhx, kin, npw, nb, theta, ekin, W, ldw, part, res, st, status);
 }
 
 void launch_build_projectors_f64(const double *qvec, int64_t npw, int natom, const double *pos,
