@@ -412,39 +412,39 @@ __device__ __forceinline__ void unroll_for(F &&f) {
 }
 
 template <int CTRL>
-__device__ __forceinline__ double dpp_f64(double x) {
+__device__ __forceinline__ double dpp_mov(double x) {
     const int lo = __builtin_amdgcn_mov_dpp(__double2loint(x), CTRL, 0xF, 0xF, true);
     const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(x), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
 template <int CTRL>
-__device__ __forceinline__ float dpp_f64(float x) {   // the FP32 form (one 32-bit move)
+__device__ __forceinline__ float dpp_mov(float x) {   // one 32-bit move
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(x), CTRL, 0xF, 0xF, true));
 }
 // sum over the 16 lanes of a DPP row; every lane of the row gets the same value
 template <class R>
 __device__ __forceinline__ R row16_sum(R x) {
-    x += dpp_f64<0xB1>(x);    // quad_perm [1,0,3,2]
-    x += dpp_f64<0x4E>(x);    // quad_perm [2,3,0,1]
-    x += dpp_f64<0x141>(x);   // row_half_mirror
-    x += dpp_f64<0x140>(x);   // row_mirror
+    x += dpp_mov<0xB1>(x);    // quad_perm [1,0,3,2]
+    x += dpp_mov<0x4E>(x);    // quad_perm [2,3,0,1]
+    x += dpp_mov<0x141>(x);   // row_half_mirror
+    x += dpp_mov<0x140>(x);   // row_mirror
     return x;
 }
 template <class R>
 __device__ __forceinline__ R quad_sum(R x) {
-    x += dpp_f64<0xB1>(x);
-    x += dpp_f64<0x4E>(x);
+    x += dpp_mov<0xB1>(x);
+    x += dpp_mov<0x4E>(x);
     return x;
 }
 // lanes whose DPP row is disabled by ROW_MASK read 0
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ double dpp_f64_rows(double x) {
+__device__ __forceinline__ double dpp_rows(double x) {
     const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(x), CTRL, ROW_MASK, 0xF, false);
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(x), CTRL, ROW_MASK, 0xF, false);
     return __hiloint2double(hi, lo);
 }
 template <int CTRL, int ROW_MASK>
-__device__ __forceinline__ float dpp_f64_rows(float x) {
+__device__ __forceinline__ float dpp_rows(float x) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, ROW_MASK, 0xF, false));
 }
 // Wave sum returned as a wave-uniform value, without LDS: the row sums, then
@@ -454,8 +454,8 @@ __device__ __forceinline__ float dpp_f64_rows(float x) {
 template <class R>
 __device__ __forceinline__ R wave_total(R x) {
     x = row16_sum(x);
-    x += dpp_f64_rows<0x142, 0xA>(x);   // row_bcast:15
-    x += dpp_f64_rows<0x143, 0xC>(x);   // row_bcast:31
+    x += dpp_rows<0x142, 0xA>(x);   // row_bcast:15
+    x += dpp_rows<0x143, 0xC>(x);   // row_bcast:31
     return lane_read(x, 63);
 }
 
@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(1024)
     __shared__ C ws[NR];             // w of the last step, zero outside its live rows
     __shared__ C pr[32][NR + 1];     // row sums of y, one per half-wave (padded)
     __shared__ C pc[8][NR + 1];      // column sums of y, one per lane quad (padded)
-    __shared__ R sv[16];         // per-wave partials of Re(v^H A v)
+    __shared__ R sv[16];             // per-wave partials of Re(v^H A v)
     __shared__ C s_tau[2];
     const int t = threadIdx.x, ti = t & 31, tj = t >> 5, wave = t >> 6, lane = t & 63;
 
@@ -515,16 +515,19 @@ __global__ void __launch_bounds__(1024)
                 if (32 * b + 31 <= jm) return;
                 const C vj = cconj(vs[par][tj + 32 * b]), wj = cconj(ws[tj + 32 * b]);
                 const C u1 = cmulz(wi, vj), u2 = cmulz(vi, wj);
-                const C e = E[a * (a + 1) / 2 + b];   // whole-element update: member writes
-                E[a * (a + 1) / 2 + b] = C{e.x - (u1.x + u2.x), e.y - (u1.y + u2.y)};   // kept FP32 E in scratch
+                // whole-element update (member-wise updates kept FP32 elements in scratch)
+                const C e = E[a * (a + 1) / 2 + b];
+                E[a * (a + 1) / 2 + b] = C{e.x - (u1.x + u2.x), e.y - (u1.y + u2.y)};
             });
         });
     };
     // entry (ti + 32 a, col) of this lane for the column tile jb (zero above it)
     auto col_entry = [&](auto a_, int jb) -> C {
         constexpr int a = decltype(a_)::value;
-        R xr = R(0), xi = R(0);   // selects by component (an element-wise pick became
-        unroll_for<0, a + 1>([&](auto b_) {   // a dynamically indexed stack array in FP32)
+        // selects by component (an element-wise pick became a dynamically indexed
+        // stack array in FP32)
+        R xr = R(0), xi = R(0);
+        unroll_for<0, a + 1>([&](auto b_) {
             constexpr int b = b_;
             const bool hit = b == jb;
             xr = hit ? E[a * (a + 1) / 2 + b].x : xr;
@@ -550,7 +553,7 @@ __global__ void __launch_bounds__(1024)
                 }
             });
             sg = row16_sum(sg);
-            sg += dpp_f64_rows<0x142, 0xA>(sg);   // lanes 31 and 63: the two half-wave totals
+            sg += dpp_rows<0x142, 0xA>(sg);   // lanes 31 and 63: the two half-wave totals
             const R sigma = lane_read(sg, base + 31);
             const int a1 = (j + 1) >> 5;
             C xa = {R(0), R(0)}, xd = {R(0), R(0)};

@@ -479,7 +479,7 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
     // PW_PREC_MIXED_FP32_RR: the complex64 stage, whose blocks carry FP32
     // rounding, reduces its Rayleigh-Ritz problems to tridiagonal form in FP32
     // as well (its FP64 stage, and every other form, reduce in FP64)
-    const bool kLowpReduction = std::is_same<S, pw::cf>::value && c->rr_fp32;
+    const bool lowp_reduction = std::is_same<S, pw::cf>::value && c->rr_fp32;
     PhaseTimer tm;
     tm.st = st;
     tm.on = c->phase_timing;
@@ -581,7 +581,7 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
             tm.end(PhaseTimer::kGemm, e0);
             auto e1 = tm.begin();
             pw::launch_heev_f64(p.Agram, mb, mb, mb, p.w, p.Cc, 3 * m, p.heev_scratch, c->d_status, st,
-                                kLowpReduction);
+                                lowp_reduction);
             tm.end(PhaseTimer::kDense, e1);
             auto e2 = tm.begin();
             pw::launch_gemm_nn(Z, ld, p.Cc, 3 * m, npw, mb, mb, 1.0, 0.0, p.Z[1 - cur], ld, st);
@@ -702,7 +702,7 @@ pw_status lobpcg(pw_ctx_s *c, const Plan<S> &p, int M, int m, double tol, int ma
                 tm.end(PhaseTimer::kGemm, e0);
                 auto e1 = tm.begin();
                 pw::launch_heev_f64(p.Agram, nz, nz, mb, p.w, p.Cc, 3 * m, p.heev_scratch, c->d_status,
-                                    st, kLowpReduction);
+                                    st, lowp_reduction);
                 tm.end(PhaseTimer::kDense, e1);
             }
             // P coefficients for the active columns: C with the X rows removed,
